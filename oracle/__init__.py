@@ -1,0 +1,281 @@
+"""Python access to the FP64 CPU oracle (oracle/oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use this module; the GPU library never does.  It shares no
+code with the GPU path.  Functions return numpy arrays; every computation
+happens in the single-threaded double-precision C code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ORC_OK, ORC_DEGENERATE, ORC_FALLBACK_HUBER, ORC_NONFINITE = 0, 1, 2, 3
+MLP_NPARAM = 5185
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c: plain C, -O2, no FP contraction, no vector intrinsics."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                               "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class OrcSensor(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("phi", ctypes.POINTER(ctypes.c_double)),
+                ("theta", ctypes.POINTER(ctypes.c_double)), ("r0", ctypes.c_double)]
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("iters", ctypes.c_int * 8), ("delta", ctypes.c_double),
+                ("edge_rel", ctypes.c_double), ("max_corr_dist", ctypes.c_double),
+                ("init_mode", ctypes.c_int), ("weight_mode", ctypes.c_int),
+                ("mlp", ctypes.POINTER(ctypes.c_double)), ("r_max", ctypes.c_double)]
+
+
+class OrcLevelStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters_run", ctypes.c_int32), ("n_valid", ctypes.c_int32),
+                ("n_inlier", ctypes.c_int32), ("n_proj", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("sum_w", ctypes.c_double), ("sum_w_e2", ctypes.c_double), ("robust_cost", ctypes.c_double),
+                ("step_rot", ctypes.c_double), ("step_trans", ctypes.c_double),
+                ("JtJ", ctypes.c_double * 21), ("Jtr", ctypes.c_double * 6)]
+
+    def to_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("JtJ", "Jtr", "pad")}
+        d["JtJ"] = np.array(self.JtJ[:])
+        d["Jtr"] = np.array(self.Jtr[:])
+        return d
+
+
+class OrcProj(ctypes.Structure):
+    _fields_ = [("valid", ctypes.c_int32), ("u", ctypes.c_int32), ("v", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("r", ctypes.c_double), ("uhat", ctypes.c_double),
+                ("phi", ctypes.c_double), ("theta", ctypes.c_double)]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_F = ctypes.POINTER(ctypes.c_float)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        S = ctypes.POINTER(OrcSensor)
+        P = ctypes.POINTER(OrcParams)
+        ST = ctypes.POINTER(OrcLevelStats)
+        L.orc_unproject.argtypes = [S, ctypes.c_int, ctypes.c_int, ctypes.c_double, _D]
+        L.orc_project.argtypes = [S, ctypes.c_int, _D, ctypes.POINTER(OrcProj)]
+        L.orc_unproject_image.argtypes = [S, _F, _D, _U8]
+        L.orc_project_points.argtypes = [S, ctypes.c_int, _D, ctypes.c_int64, _I32, _I32, _D, _D, _D, _U8]
+        L.orc_normals.argtypes = [S, _F, ctypes.c_double, _D, _U8]
+        L.orc_bf16.argtypes = [ctypes.c_double]
+        L.orc_bf16.restype = ctypes.c_double
+        L.orc_mlp_nparam.restype = ctypes.c_int
+        L.orc_mlp_forward.argtypes = [_D, _F, ctypes.c_int64, _D, _D]
+        L.orc_mlp_loss_grad.argtypes = [_D, _F, _F, ctypes.c_int64, _D]
+        L.orc_mlp_loss_grad.restype = ctypes.c_double
+        L.orc_exp_se3.argtypes = [_D, _D]
+        L.orc_pose_error.argtypes = [_D, _D, _D, _D]
+        L.orc_icp.argtypes = [S, _F, _F, P, _D, _D, ST]
+        L.orc_icp.restype = ctypes.c_int
+        L.orc_system.argtypes = [S, ctypes.c_int, _F, _F, P, _D, ctypes.c_int, _I32, _I32, _U8, _U8,
+                                 _D, _D, _D, _D, _D, _F, ST]
+        L.orc_system.restype = ctypes.c_int
+        L.orc_associate_with_normals.argtypes = [S, ctypes.c_int, _F, _F, _D, _U8, _D, P, _I32, _I32, _U8,
+                                                 _U8, _D, _D, _D, _D, _D]
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+class _SensorHolder:
+    """Keeps the numpy tables alive while the C struct points at them."""
+
+    def __init__(self, sensor):
+        self.phi = np.ascontiguousarray(sensor.phi, dtype=np.float64)
+        self.theta = np.ascontiguousarray(sensor.theta, dtype=np.float64)
+        self.s = OrcSensor(int(sensor.H), int(sensor.W), _p(self.phi, _D), _p(self.theta, _D), float(sensor.r0))
+        self.H, self.W = int(sensor.H), int(sensor.W)
+
+
+def make_params(levels=3, iters=(10, 10, 10), delta=0.5, edge_rel=0.1, max_corr_dist=0.0, init_mode=0,
+                weight_mode=0, mlp=None, r_max=80.0):
+    prm = OrcParams()
+    prm.levels = levels
+    for i in range(8):
+        prm.iters[i] = int(iters[i]) if i < len(iters) else 0
+    prm.delta, prm.edge_rel, prm.max_corr_dist = delta, edge_rel, max_corr_dist
+    prm.init_mode, prm.weight_mode, prm.r_max = init_mode, weight_mode, r_max
+    holder = None
+    if mlp is not None:
+        holder = np.ascontiguousarray(mlp, dtype=np.float64)
+        assert holder.size == MLP_NPARAM
+        prm.mlp = _p(holder, _D)
+    prm._keep = holder  # keep alive
+    return prm
+
+
+def unproject(sensor, u: int, v: int, r: float) -> np.ndarray:
+    h = _SensorHolder(sensor)
+    out = np.zeros(3)
+    lib().orc_unproject(ctypes.byref(h.s), int(u), int(v), float(r), _p(out, _D))
+    return out
+
+
+def unproject_image(sensor, rng_img: np.ndarray):
+    h = _SensorHolder(sensor)
+    r = np.ascontiguousarray(rng_img, dtype=np.float32)
+    xyz = np.zeros((h.H, h.W, 3))
+    valid = np.zeros((h.H, h.W), np.uint8)
+    lib().orc_unproject_image(ctypes.byref(h.s), _p(r, _F), _p(xyz, _D), _p(valid, _U8))
+    return xyz, valid.astype(bool)
+
+
+def project_points(sensor, level: int, xyz: np.ndarray) -> dict:
+    h = _SensorHolder(sensor)
+    pts = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    n = pts.shape[0]
+    u = np.zeros(n, np.int32)
+    v = np.zeros(n, np.int32)
+    r = np.zeros(n)
+    uh = np.zeros(n)
+    ph = np.zeros(n)
+    valid = np.zeros(n, np.uint8)
+    lib().orc_project_points(ctypes.byref(h.s), int(level), _p(pts, _D), n, _p(u, _I32), _p(v, _I32),
+                             _p(r, _D), _p(uh, _D), _p(ph, _D), _p(valid, _U8))
+    return {"u": u, "v": v, "r": r, "uhat": uh, "phi": ph, "valid": valid.astype(bool)}
+
+
+def normals(sensor, rng_img: np.ndarray, edge_rel: float = 0.1):
+    h = _SensorHolder(sensor)
+    r = np.ascontiguousarray(rng_img, dtype=np.float32)
+    n = np.zeros((h.H, h.W, 3))
+    valid = np.zeros((h.H, h.W), np.uint8)
+    lib().orc_normals(ctypes.byref(h.s), _p(r, _F), float(edge_rel), _p(n, _D), _p(valid, _U8))
+    return n, valid.astype(bool)
+
+
+def bf16(x: float) -> float:
+    return lib().orc_bf16(float(x))
+
+
+def exp_se3(xi) -> np.ndarray:
+    x = np.ascontiguousarray(xi, dtype=np.float64)
+    T = np.zeros((4, 4))
+    lib().orc_exp_se3(_p(x, _D), _p(T, _D))
+    return T
+
+
+def pose_error(T: np.ndarray, Tref: np.ndarray):
+    a = np.ascontiguousarray(T, dtype=np.float64)
+    b = np.ascontiguousarray(Tref, dtype=np.float64)
+    er, et = ctypes.c_double(), ctypes.c_double()
+    lib().orc_pose_error(_p(a, _D), _p(b, _D), ctypes.byref(er), ctypes.byref(et))
+    return er.value, et.value
+
+
+def icp(sensor, src: np.ndarray, dst: np.ndarray, params: OrcParams, T_init=None):
+    """Run the full multi-scale ICP; returns (pose 4x4, list of per-level stats dicts)."""
+    h = _SensorHolder(sensor)
+    s = np.ascontiguousarray(src, dtype=np.float32)
+    d = np.ascontiguousarray(dst, dtype=np.float32)
+    Ti = np.eye(4) if T_init is None else np.ascontiguousarray(T_init, dtype=np.float64)
+    To = np.zeros((4, 4))
+    stats = (OrcLevelStats * 8)()
+    rc = lib().orc_icp(ctypes.byref(h.s), _p(s, _F), _p(d, _F), ctypes.byref(params), _p(Ti, _D), _p(To, _D),
+                       stats)
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return To, [stats[i].to_dict() for i in range(params.levels)]
+
+
+def system(sensor, level: int, src, dst, params: OrcParams, T, use_learned=False, with_features=False) -> dict:
+    """Per-pixel association terms and the normal equations at a fixed pose."""
+    h = _SensorHolder(sensor)
+    s = np.ascontiguousarray(src, dtype=np.float32)
+    d = np.ascontiguousarray(dst, dtype=np.float32)
+    Tm = np.ascontiguousarray(T, dtype=np.float64)
+    st = 1 << level
+    Hl, Wl = h.H // st, h.W // st
+    n = Hl * Wl
+    out = {"u": np.zeros(n, np.int32), "v": np.zeros(n, np.int32), "mask": np.zeros(n, np.uint8),
+           "proj_valid": np.zeros(n, np.uint8), "e": np.zeros(n), "w": np.zeros(n), "J": np.zeros((n, 6)),
+           "uhat": np.zeros(n), "phi": np.zeros(n)}
+    feat = np.zeros((n, 14), np.float32) if with_features else None
+    ls = OrcLevelStats()
+    rc = lib().orc_system(ctypes.byref(h.s), int(level), _p(s, _F), _p(d, _F), ctypes.byref(params), _p(Tm, _D),
+                          int(bool(use_learned)), _p(out["u"], _I32), _p(out["v"], _I32), _p(out["mask"], _U8),
+                          _p(out["proj_valid"], _U8), _p(out["e"], _D), _p(out["w"], _D), _p(out["J"], _D),
+                          _p(out["uhat"], _D), _p(out["phi"], _D), _p(feat, _F) if feat is not None else None,
+                          ctypes.byref(ls))
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    for k in ("mask", "proj_valid"):
+        out[k] = out[k].astype(bool)
+    for k in ("u", "v", "mask", "proj_valid", "e", "w", "uhat", "phi"):
+        out[k] = out[k].reshape(Hl, Wl)
+    out["J"] = out["J"].reshape(Hl, Wl, 6)
+    if feat is not None:
+        out["feat"] = feat.reshape(Hl, Wl, 14)
+    out["stats"] = ls.to_dict()
+    return out
+
+
+def associate_with_normals(sensor, level, src, dst, nrm, nvalid, params, T) -> dict:
+    h = _SensorHolder(sensor)
+    s = np.ascontiguousarray(src, dtype=np.float32)
+    d = np.ascontiguousarray(dst, dtype=np.float32)
+    nr = np.ascontiguousarray(nrm, dtype=np.float64)
+    nv = np.ascontiguousarray(nvalid, dtype=np.uint8)
+    Tm = np.ascontiguousarray(T, dtype=np.float64)
+    st = 1 << level
+    Hl, Wl = h.H // st, h.W // st
+    n = Hl * Wl
+    out = {"u": np.zeros(n, np.int32), "v": np.zeros(n, np.int32), "mask": np.zeros(n, np.uint8),
+           "proj_valid": np.zeros(n, np.uint8), "e": np.zeros(n), "w": np.zeros(n), "J": np.zeros((n, 6)),
+           "uhat": np.zeros(n), "phi": np.zeros(n)}
+    lib().orc_associate_with_normals(ctypes.byref(h.s), int(level), _p(s, _F), _p(d, _F), _p(nr, _D), _p(nv, _U8),
+                                     _p(Tm, _D), ctypes.byref(params), _p(out["u"], _I32), _p(out["v"], _I32),
+                                     _p(out["mask"], _U8), _p(out["proj_valid"], _U8), _p(out["e"], _D),
+                                     _p(out["w"], _D), _p(out["J"], _D), _p(out["uhat"], _D), _p(out["phi"], _D))
+    out["mask"] = out["mask"].astype(bool)
+    out["proj_valid"] = out["proj_valid"].astype(bool)
+    return out
+
+
+def mlp_forward(params: np.ndarray, feats: np.ndarray):
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 14)
+    B = f.shape[0]
+    z = np.zeros(B)
+    w = np.zeros(B)
+    lib().orc_mlp_forward(_p(P, _D), _p(f, _F), B, _p(z, _D), _p(w, _D))
+    return z, w
+
+
+def mlp_loss_grad(params: np.ndarray, feats: np.ndarray, labels: np.ndarray):
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 14)
+    y = np.ascontiguousarray(labels, dtype=np.float32).reshape(-1)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().orc_mlp_loss_grad(_p(P, _D), _p(f, _F), _p(y, _F), f.shape[0], _p(g, _D))
+    return loss, g

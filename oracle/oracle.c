@@ -1,0 +1,893 @@
+/*
+ * FP64 CPU oracle for multi-scale projective point-to-plane ICP on cylindrical
+ * range images (Dong, Ryu, Kaess, Park: "Revisiting LiDAR Registration and
+ * Reconstruction: A Range Image Perspective", Sec. 3 and Sec. 4.1).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, single-threaded
+ * reference that the GPU library is checked against.  It shares no code,
+ * header, table or helper with the GPU library and is never called by it.
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg load it.
+ *
+ * Everything is double precision, built with -ffp-contract=off, with no
+ * blocking, fusion or reordering beyond what the paper's equations state:
+ *   Eq. (1)-(2)  unprojection of pixel (u, v) with range r,
+ *   Eq. (3)-(4)  projection with the iterative receiver-offset compensation
+ *                and the elevation argmin over the beam table,
+ *   Eq. (5)-(6)  projective data association,
+ *   Eq. (7)      robust point-to-plane objective solved by Gauss-Newton,
+ *   Sec. 4.1     multi-scale registration on strided images with the
+ *                original intrinsics.
+ * Readings of silent or ambiguous passages are listed next to the code that
+ * takes them.  The learned per-pixel weight (a small MLP) is not part of the
+ * paper; its forward and backward passes are written out here with the same
+ * bf16 rounding points the GPU uses, so that the GPU can be checked.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846264338327950288
+#define ORC_TWO_PI 6.28318530717958647692528676655900577
+
+enum { ORC_OK = 0, ORC_DEGENERATE = 1, ORC_FALLBACK_HUBER = 2, ORC_NONFINITE = 3 };
+
+/* Sensor intrinsics (Sec. 3): H beams, W columns, per-beam elevation phi[H]
+ * (strictly decreasing, v = 0 is the top beam), per-beam azimuth offset
+ * theta[H] (NULL means all zero) and receiver radius r0. */
+typedef struct {
+    int H, W;
+    const double *phi;
+    const double *theta;
+    double r0;
+} orc_sensor;
+
+typedef struct {
+    int levels;
+    int iters[8];          /* Gauss-Newton iterations per level, index 0 = finest */
+    double delta;          /* pseudo-Huber kernel size (m) */
+    double edge_rel;       /* normal validity: |r_nbr - r_c| <= edge_rel * r_c */
+    double max_corr_dist;  /* <= 0: no distance gate */
+    int init_mode;         /* 0: given initial pose, 1: align point-set centres */
+    int weight_mode;       /* 0: pseudo-Huber, 1: learned */
+    const double *mlp;     /* learned-weight parameters (see orc_mlp_*) */
+    double r_max;          /* range scale of the first learned feature */
+} orc_params;
+
+typedef struct {
+    int32_t status, iters_run, n_valid, n_inlier, n_proj, pad;
+    double sum_w, sum_w_e2, robust_cost, step_rot, step_trans;
+    double JtJ[21], Jtr[6];
+} orc_level_stats;
+
+static double th_lut(const orc_sensor *s, int v) { return s->theta ? s->theta[v] : 0.0; }
+
+static int range_ok(double r) { return isfinite(r) && r > 0.0; }
+
+/* ------------------------------------------------------------------ Eq. (1)-(2) */
+
+/* Unprojection Pi^{-1}(u, v, r): the receiver sits on a cylinder of radius r0
+ * at encoder angle 2 pi u / W, and the ray leaves it at azimuth
+ * theta(u, v) = 2 pi u / W + theta_lut[v] and elevation phi(v) = phi_lut[v]. */
+void orc_unproject(const orc_sensor *s, int u, int v, double r, double out[3])
+{
+    double a = ORC_TWO_PI * (double)u / (double)s->W;
+    double th = a + th_lut(s, v);
+    double ph = s->phi[v];
+    out[0] = r * cos(th) * cos(ph) + s->r0 * cos(a);
+    out[1] = r * sin(th) * cos(ph) + s->r0 * sin(a);
+    out[2] = r * sin(ph);
+}
+
+/* Unit ray direction of pixel (u, v) (the r-coefficient of Eq. (1)). */
+static void ray_dir(const orc_sensor *s, int u, int v, double d[3])
+{
+    double th = ORC_TWO_PI * (double)u / (double)s->W + th_lut(s, v);
+    double ph = s->phi[v];
+    d[0] = cos(th) * cos(ph);
+    d[1] = sin(th) * cos(ph);
+    d[2] = sin(ph);
+}
+
+/* ------------------------------------------------------------------ Eq. (3)-(4) */
+
+static double atan2_wrapped(double y, double x)
+{
+    /* arctan2 lands in [-pi, pi]; the paper wraps it to [0, 2 pi] (Sec. 3.2 footnote) */
+    double a = atan2(y, x);
+    if (a < 0.0)
+        a += ORC_TWO_PI;
+    return a;
+}
+
+/* Eq. (4): v = argmin_t |phi_lut[t] - phi| over the rows 0, s, 2s, ... of the
+ * table (s = 1 at the finest level); ties go to the smaller index.  Returns
+ * the level row index t. */
+static int elevation_argmin(const orc_sensor *s, int stride, double phi)
+{
+    int Hl = s->H / stride;
+    int best = 0;
+    double bd = fabs(s->phi[0] - phi);
+    for (int t = 1; t < Hl; ++t) {
+        double d = fabs(s->phi[t * stride] - phi);
+        if (d < bd) {
+            bd = d;
+            best = t;
+        }
+    }
+    return best;
+}
+
+typedef struct {
+    int32_t valid, u, v, pad;
+    double r, uhat, phi, theta;
+} orc_proj;
+
+/*
+ * Projection Pi at pyramid level `level` (stride s = 2^level), Eq. (3)-(4).
+ *
+ * Readings (the paper is brief here):
+ *  - Receiver-offset compensation: starting from the azimuth of (x, y), the
+ *    encoder angle a is refined by rounds of: remove the receiver offset
+ *    r0 (cos a, sin a, 0), re-estimate the ray azimuth and elevation, take the
+ *    finest-level beam v_k by Eq. (4), and set a = theta - theta_lut[v_k],
+ *    repeated until a stops changing (|change| <= 1e-15 rad, at most 100
+ *    rounds).  The paper omits theta_lut while iterating; including it makes
+ *    the fixed point the exact inverse of Eq. (1).  With r0 = 0 no round is
+ *    needed.
+ *  - Level indices (Sec. 4.1, "projective transforms at the finest level,
+ *    down-sampled on coordinates at the given stride"): v_l is the Eq. (4)
+ *    argmin over the strided rows s*t; u_hat_l = W/(2 pi) (theta -
+ *    theta_lut[s v_l]) / s wrapped to [0, W/s) and u_l = floor(u_hat_l + 1/2)
+ *    mod W/s (round half up).
+ *  - Validity (the paper skips the boundary check for clarity): r > 0 and the
+ *    elevation lies within half a row spacing beyond the end rows of the
+ *    finest table.
+ */
+void orc_project(const orc_sensor *s, int level, const double x[3], orc_proj *out)
+{
+    int stride = 1 << level;
+    int Wl = s->W / stride;
+    double xp = x[0], yp = x[1], z = x[2];
+    if (s->r0 > 0.0) {
+        double a = atan2_wrapped(x[1], x[0]);
+        for (int k = 0; k < 100; ++k) {
+            xp = x[0] - s->r0 * cos(a);
+            yp = x[1] - s->r0 * sin(a);
+            double thk = atan2_wrapped(yp, xp);
+            double rk = sqrt(xp * xp + yp * yp + z * z);
+            double sk = rk > 0.0 ? z / rk : 0.0;
+            if (sk > 1.0) sk = 1.0;
+            if (sk < -1.0) sk = -1.0;
+            int vk = elevation_argmin(s, 1, asin(sk));
+            double an = thk - th_lut(s, vk);
+            double change = fabs(an - a);
+            if (change > ORC_PI)
+                change = ORC_TWO_PI - change;
+            a = an;
+            if (change <= 1e-15)
+                break;
+        }
+        xp = x[0] - s->r0 * cos(a);
+        yp = x[1] - s->r0 * sin(a);
+    }
+    double r = sqrt(xp * xp + yp * yp + z * z);
+    out->r = r;
+    out->valid = 0;
+    out->u = out->v = -1;
+    out->uhat = out->phi = out->theta = 0.0;
+    if (!(r > 0.0))
+        return;
+    double sz = z / r;
+    if (sz > 1.0) sz = 1.0;
+    if (sz < -1.0) sz = -1.0;
+    double phi = asin(sz);
+    double theta = atan2_wrapped(yp, xp);
+    out->phi = phi;
+    out->theta = theta;
+    int H = s->H;
+    double phi_hi = s->phi[0] + 0.5 * (s->phi[0] - s->phi[1]);
+    double phi_lo = s->phi[H - 1] - 0.5 * (s->phi[H - 2] - s->phi[H - 1]);
+    int vl = elevation_argmin(s, stride, phi);
+    double uh = (theta - th_lut(s, vl * stride)) * (double)s->W / ORC_TWO_PI / (double)stride;
+    uh = uh - (double)Wl * floor(uh / (double)Wl);
+    int ul = (int)floor(uh + 0.5);
+    if (ul >= Wl)
+        ul -= Wl;
+    out->uhat = uh;
+    out->u = ul;
+    out->v = vl;
+    out->valid = (phi <= phi_hi && phi >= phi_lo) ? 1 : 0;
+}
+
+/* Batch helpers used by the tests. */
+void orc_unproject_image(const orc_sensor *s, const float *range, double *xyz, uint8_t *valid)
+{
+    for (int v = 0; v < s->H; ++v)
+        for (int u = 0; u < s->W; ++u) {
+            size_t i = (size_t)v * s->W + u;
+            double r = range[i];
+            valid[i] = (uint8_t)range_ok(r);
+            if (valid[i])
+                orc_unproject(s, u, v, r, xyz + 3 * i);
+            else
+                xyz[3 * i] = xyz[3 * i + 1] = xyz[3 * i + 2] = 0.0;
+        }
+}
+
+void orc_project_points(const orc_sensor *s, int level, const double *xyz, int64_t n, int32_t *u,
+                        int32_t *v, double *r, double *uhat, double *phi, uint8_t *valid)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        orc_proj p;
+        orc_project(s, level, xyz + 3 * i, &p);
+        u[i] = p.u;
+        v[i] = p.v;
+        r[i] = p.r;
+        uhat[i] = p.uhat;
+        phi[i] = p.phi;
+        valid[i] = (uint8_t)p.valid;
+    }
+}
+
+/* ------------------------------------------------------------------ normal image */
+
+/*
+ * Target normals by the cross product of neighbour-pixel differences
+ * (Sec. 4.1: "simply a cross product of two neighbor pixels"; Sec. 6.1 notes
+ * the normal map can be computed directly from the range image).
+ *
+ * Readings: central differences n = (P(u+1,v) - P(u-1,v)) x (P(u,v+1) -
+ * P(u,v-1)); u wraps around the cylinder, v does not (rows 0 and H-1 are
+ * invalid); a pixel is valid iff its own and its four neighbours' ranges are
+ * finite and positive and each neighbour differs from the centre by at most
+ * edge_rel times the centre range; |n|^2 <= 1e-24 is invalid; n is oriented
+ * towards the sensor (n . d <= 0 for the pixel's ray direction d).
+ */
+void orc_normals(const orc_sensor *s, const float *range, double edge_rel, double *nrm, uint8_t *valid)
+{
+    int H = s->H, W = s->W;
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            size_t i = (size_t)v * W + u;
+            valid[i] = 0;
+            nrm[3 * i] = nrm[3 * i + 1] = nrm[3 * i + 2] = 0.0;
+            if (v == 0 || v == H - 1)
+                continue;
+            int ul = (u + W - 1) % W, ur = (u + 1) % W;
+            double rc = range[i];
+            double rl = range[(size_t)v * W + ul], rr = range[(size_t)v * W + ur];
+            double ru = range[(size_t)(v - 1) * W + u], rd = range[(size_t)(v + 1) * W + u];
+            if (!range_ok(rc) || !range_ok(rl) || !range_ok(rr) || !range_ok(ru) || !range_ok(rd))
+                continue;
+            double lim = edge_rel * rc;
+            if (fabs(rl - rc) > lim || fabs(rr - rc) > lim || fabs(ru - rc) > lim || fabs(rd - rc) > lim)
+                continue;
+            double pl[3], pr[3], pu[3], pd[3];
+            orc_unproject(s, ul, v, rl, pl);
+            orc_unproject(s, ur, v, rr, pr);
+            orc_unproject(s, u, v - 1, ru, pu);
+            orc_unproject(s, u, v + 1, rd, pd);
+            double a[3] = {pr[0] - pl[0], pr[1] - pl[1], pr[2] - pl[2]};
+            double b[3] = {pd[0] - pu[0], pd[1] - pu[1], pd[2] - pu[2]};
+            double n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+            double n2 = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+            if (!(n2 > 1e-24))
+                continue;
+            double inv = 1.0 / sqrt(n2);
+            n[0] *= inv;
+            n[1] *= inv;
+            n[2] *= inv;
+            double d[3];
+            ray_dir(s, u, v, d);
+            if (n[0] * d[0] + n[1] * d[1] + n[2] * d[2] > 0.0) {
+                n[0] = -n[0];
+                n[1] = -n[1];
+                n[2] = -n[2];
+            }
+            nrm[3 * i] = n[0];
+            nrm[3 * i + 1] = n[1];
+            nrm[3 * i + 2] = n[2];
+            valid[i] = 1;
+        }
+}
+
+/* ------------------------------------------------------------------ learned weight (not in the paper) */
+
+/* Round a double to the nearest bfloat16 value (ties to even), via float. */
+double orc_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    if ((b & 0x7f800000u) == 0x7f800000u) {
+        /* inf / nan pass through (nan kept quiet) */
+        if (b & 0x007fffffu)
+            b |= 0x00400000u;
+        b &= 0xffff0000u;
+    } else {
+        uint32_t lsb = (b >> 16) & 1u;
+        b += 0x7fffu + lsb;
+        b &= 0xffff0000u;
+    }
+    memcpy(&f, &b, 4);
+    return (double)f;
+}
+
+/* Parameter layout (5185 doubles): W1[64][14], b1[64], W2[64][64], b2[64], W3[64], b3. */
+#define MLP_IN 14
+#define MLP_H 64
+#define OFF_W1 0
+#define OFF_B1 (OFF_W1 + MLP_H * MLP_IN)
+#define OFF_W2 (OFF_B1 + MLP_H)
+#define OFF_B2 (OFF_W2 + MLP_H * MLP_H)
+#define OFF_W3 (OFF_B2 + MLP_H)
+#define OFF_B3 (OFF_W3 + MLP_H)
+#define MLP_NPARAM (OFF_B3 + 1)
+
+int orc_mlp_nparam(void) { return MLP_NPARAM; }
+
+/*
+ * Forward pass of the 14-64-64-1 weight network for one feature vector.
+ * Rounding points shared with the GPU: the inputs f, and the hidden
+ * activations h1 and h2 after ReLU, are rounded to bfloat16; the weights are
+ * given as their exact bfloat16 values; everything else is exact FP64 here.
+ * Returns the logit z; the weight is sigmoid(z).
+ */
+static double mlp_forward1(const double *P, const double *f_in, double *fb, double *a1, double *h1,
+                           double *a2, double *h2)
+{
+    for (int k = 0; k < MLP_IN; ++k)
+        fb[k] = orc_bf16(f_in[k]);
+    for (int j = 0; j < MLP_H; ++j) {
+        double acc = P[OFF_B1 + j];
+        for (int k = 0; k < MLP_IN; ++k)
+            acc += P[OFF_W1 + j * MLP_IN + k] * fb[k];
+        a1[j] = acc;
+        h1[j] = orc_bf16(acc > 0.0 ? acc : 0.0);
+    }
+    for (int j = 0; j < MLP_H; ++j) {
+        double acc = P[OFF_B2 + j];
+        for (int k = 0; k < MLP_H; ++k)
+            acc += P[OFF_W2 + j * MLP_H + k] * h1[k];
+        a2[j] = acc;
+        h2[j] = orc_bf16(acc > 0.0 ? acc : 0.0);
+    }
+    double z = P[OFF_B3];
+    for (int k = 0; k < MLP_H; ++k)
+        z += P[OFF_W3 + k] * h2[k];
+    return z;
+}
+
+static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+void orc_mlp_forward(const double *P, const float *feats, int64_t B, double *z_out, double *w_out)
+{
+    double f[MLP_IN], fb[MLP_IN], a1[MLP_H], h1[MLP_H], a2[MLP_H], h2[MLP_H];
+    for (int64_t b = 0; b < B; ++b) {
+        for (int k = 0; k < MLP_IN; ++k)
+            f[k] = feats[b * MLP_IN + k];
+        double z = mlp_forward1(P, f, fb, a1, h1, a2, h2);
+        if (z_out)
+            z_out[b] = z;
+        if (w_out)
+            w_out[b] = sigmoid(z);
+    }
+}
+
+/*
+ * Mean binary cross-entropy of sigmoid(z) against labels y in {0, 1}, and its
+ * gradient with respect to every parameter (layout as above).
+ * Backward rounding points shared with the GPU: the output delta
+ * dz = (sigmoid(z) - y) / B and the hidden deltas (after the ReLU mask,
+ * ReLU'(0) = 0) are rounded to bfloat16 before they multiply activations or
+ * weights; bias gradients are sums of those rounded deltas.
+ */
+double orc_mlp_loss_grad(const double *P, const float *feats, const float *labels, int64_t B, double *grad)
+{
+    double f[MLP_IN], fb[MLP_IN], a1[MLP_H], h1[MLP_H], a2[MLP_H], h2[MLP_H];
+    double g2[MLP_H], g1[MLP_H];
+    memset(grad, 0, sizeof(double) * MLP_NPARAM);
+    double loss = 0.0;
+    for (int64_t b = 0; b < B; ++b) {
+        for (int k = 0; k < MLP_IN; ++k)
+            f[k] = feats[b * MLP_IN + k];
+        double z = mlp_forward1(P, f, fb, a1, h1, a2, h2);
+        double y = labels[b];
+        /* BCE(sigmoid(z), y) = log(1 + e^z) - y z, written stably */
+        double sp = z > 0.0 ? z + log1p(exp(-z)) : log1p(exp(z));
+        loss += sp - y * z;
+        double dz = orc_bf16((sigmoid(z) - y) / (double)B);
+        for (int k = 0; k < MLP_H; ++k)
+            grad[OFF_W3 + k] += dz * h2[k];
+        grad[OFF_B3] += dz;
+        for (int j = 0; j < MLP_H; ++j) {
+            double d = a2[j] > 0.0 ? P[OFF_W3 + j] * dz : 0.0;
+            g2[j] = orc_bf16(d);
+        }
+        for (int j = 0; j < MLP_H; ++j) {
+            for (int k = 0; k < MLP_H; ++k)
+                grad[OFF_W2 + j * MLP_H + k] += g2[j] * h1[k];
+            grad[OFF_B2 + j] += g2[j];
+        }
+        for (int k = 0; k < MLP_H; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < MLP_H; ++j)
+                acc += P[OFF_W2 + j * MLP_H + k] * g2[j];
+            g1[k] = orc_bf16(a1[k] > 0.0 ? acc : 0.0);
+        }
+        for (int j = 0; j < MLP_H; ++j) {
+            for (int k = 0; k < MLP_IN; ++k)
+                grad[OFF_W1 + j * MLP_IN + k] += g1[j] * fb[k];
+            grad[OFF_B1 + j] += g1[j];
+        }
+    }
+    return loss / (double)B;
+}
+
+/* ------------------------------------------------------------------ SE(3) */
+
+static void skew(const double w[3], double K[9])
+{
+    K[0] = 0.0;   K[1] = -w[2]; K[2] = w[1];
+    K[3] = w[2];  K[4] = 0.0;   K[5] = -w[0];
+    K[6] = -w[1]; K[7] = w[0];  K[8] = 0.0;
+}
+
+static void mat3_mul(const double *A, const double *B, double *C)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+/* Exponential map of a twist xi = (omega, tau) to a 4x4 row-major rigid
+ * transform: Rodrigues' rotation and t = V tau with
+ * V = I + (1 - cos a)/a^2 K + (a - sin a)/a^3 K^2, a = |omega|, K = [omega]x.
+ * Taylor coefficients below a = 1e-6. */
+void orc_exp_se3(const double xi[6], double T[16])
+{
+    const double *w = xi, *tau = xi + 3;
+    double a2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double a = sqrt(a2);
+    double A, Bc, C;
+    if (a < 1e-6) {
+        A = 1.0 - a2 / 6.0;
+        Bc = 0.5 - a2 / 24.0;
+        C = 1.0 / 6.0 - a2 / 120.0;
+    } else {
+        A = sin(a) / a;
+        Bc = (1.0 - cos(a)) / a2;
+        C = (a - sin(a)) / (a2 * a);
+    }
+    double K[9], K2[9];
+    skew(w, K);
+    mat3_mul(K, K, K2);
+    double R[9], V[9];
+    for (int i = 0; i < 9; ++i) {
+        double I = (i % 4 == 0) ? 1.0 : 0.0;
+        R[i] = I + A * K[i] + Bc * K2[i];
+        V[i] = I + Bc * K[i] + C * K2[i];
+    }
+    memset(T, 0, 16 * sizeof(double));
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+            T[4 * i + j] = R[3 * i + j];
+        T[4 * i + 3] = V[3 * i] * tau[0] + V[3 * i + 1] * tau[1] + V[3 * i + 2] * tau[2];
+    }
+    T[15] = 1.0;
+}
+
+static void mat4_mul(const double *A, const double *B, double *C)
+{
+    double tmp[16];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 4; ++k)
+                acc += A[4 * i + k] * B[4 * k + j];
+            tmp[4 * i + j] = acc;
+        }
+    memcpy(C, tmp, sizeof(tmp));
+}
+
+/* Registration error metrics (Sec. 6.1), read with the trace and an
+ * unsquared norm: e_R = arccos((tr(R R_ref^T) - 1) / 2), e_t = |t - t_ref|. */
+void orc_pose_error(const double T[16], const double Tref[16], double *e_rot, double *e_trans)
+{
+    double tr = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+            tr += T[4 * i + k] * Tref[4 * i + k];
+    double c = (tr - 1.0) / 2.0;
+    if (c > 1.0) c = 1.0;
+    if (c < -1.0) c = -1.0;
+    *e_rot = acos(c);
+    double dx = T[3] - Tref[3], dy = T[7] - Tref[7], dz = T[11] - Tref[11];
+    *e_trans = sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* ------------------------------------------------------------------ Eq. (5)-(7) */
+
+/* Pseudo-Huber robust kernel (Barron's general kernel with alpha = 1), the
+ * kernel of the paper's experiments (Sec. 6.1): rho(e) = d^2 (sqrt(1 +
+ * (e/d)^2) - 1); the IRLS weight is rho'(e) / e = (1 + (e/d)^2)^(-1/2). */
+static double huber_weight(double e, double d) { return 1.0 / sqrt(1.0 + (e / d) * (e / d)); }
+static double huber_cost(double e, double d) { return d * d * (sqrt(1.0 + (e / d) * (e / d)) - 1.0); }
+
+static double clamp4(double x) { return x < -4.0 ? -4.0 : (x > 4.0 ? 4.0 : x); }
+
+/* Per-pixel output of one association pass. */
+typedef struct {
+    int32_t *u, *v;       /* level indices of the association (or -1) */
+    uint8_t *mask;        /* 1: valid correspondence */
+    uint8_t *proj_valid;  /* 1: the source pixel projected inside the image */
+    double *e, *w, *J;    /* residual, weight, Jacobian row [6] */
+    double *uhat, *phi;   /* continuous column and elevation (for tie analysis) */
+    float *feat;          /* learned-weight features [14] or NULL */
+} orc_assoc_out;
+
+/*
+ * Learned-weight features of a correspondence (not in the paper; a reading of
+ * "3x3 range patch + normal + residual"): f0 = range at the associated
+ * target pixel / r_max; f1..f8 = clamp((neighbour - centre) / delta, -4, 4)
+ * for the 8 level-l neighbours of the associated target pixel in raster order,
+ * u wrapping and rows outside the image or neighbours without a return
+ * reading +4; f9..f11 = target normal; f12 = clamp(e / delta, -4, 4);
+ * f13 = clamp((target range - projected range) / delta, -4, 4), the
+ * projective signed distance of Eq. (8)-(9).
+ */
+static void features(const orc_sensor *s, int level, const float *dst, int ul, int vl, double rproj,
+                     const double n[3], double e, double delta, double r_max, double f[14])
+{
+    int st = 1 << level, Wl = s->W / st, Hl = s->H / st;
+    double rc = dst[(size_t)(st * vl) * s->W + st * ul];
+    f[0] = rc / r_max;
+    int k = 1;
+    for (int dv = -1; dv <= 1; ++dv)
+        for (int du = -1; du <= 1; ++du) {
+            if (du == 0 && dv == 0)
+                continue;
+            int vv = vl + dv, uu = (ul + du + Wl) % Wl;
+            double val = 4.0;
+            if (vv >= 0 && vv < Hl) {
+                double rn = dst[(size_t)(st * vv) * s->W + st * uu];
+                if (range_ok(rn))
+                    val = clamp4((rn - rc) / delta);
+            }
+            f[k++] = val;
+        }
+    f[9] = n[0];
+    f[10] = n[1];
+    f[11] = n[2];
+    f[12] = clamp4(e / delta);
+    f[13] = clamp4((rc - rproj) / delta);
+}
+
+/*
+ * Projective data association at level l (Eq. (5)-(6)) and per-pixel
+ * residual, Jacobian and weight for Eq. (7) at pose T (dst <- src).
+ * Source pixel (u', v') of level l is full-resolution pixel (s u', s v').
+ * A correspondence is rejected when the source has no return, the projection
+ * is invalid, the target pixel has no return or no valid normal, or (if
+ * enabled) |x - q| exceeds max_corr_dist.
+ * e = n^T (x - q); J = [(x cross n)^T, n^T] is de/dxi for the left update
+ * x <- Exp(xi) x with xi = (omega, tau).
+ */
+void orc_associate(const orc_sensor *s, int level, const float *src, const float *dst, const double *nrm,
+                   const uint8_t *nvalid, const double T[16], const orc_params *prm, int use_learned,
+                   orc_assoc_out *out)
+{
+    int st = 1 << level, Wl = s->W / st, Hl = s->H / st;
+    for (int vp = 0; vp < Hl; ++vp)
+        for (int up = 0; up < Wl; ++up) {
+            size_t o = (size_t)vp * Wl + up;
+            out->u[o] = out->v[o] = -1;
+            out->mask[o] = 0;
+            out->proj_valid[o] = 0;
+            out->e[o] = out->w[o] = 0.0;
+            for (int k = 0; k < 6; ++k)
+                out->J[6 * o + k] = 0.0;
+            out->uhat[o] = out->phi[o] = 0.0;
+            if (out->feat)
+                for (int k = 0; k < 14; ++k)
+                    out->feat[14 * o + k] = 0.0f;
+            double rs = src[(size_t)(st * vp) * s->W + st * up];
+            if (!range_ok(rs))
+                continue;
+            double p[3], x[3];
+            orc_unproject(s, st * up, st * vp, rs, p);
+            for (int i = 0; i < 3; ++i)
+                x[i] = T[4 * i] * p[0] + T[4 * i + 1] * p[1] + T[4 * i + 2] * p[2] + T[4 * i + 3];
+            orc_proj pr;
+            orc_project(s, level, x, &pr);
+            out->uhat[o] = pr.uhat;
+            out->phi[o] = pr.phi;
+            if (!pr.valid)
+                continue;
+            out->proj_valid[o] = 1;
+            out->u[o] = pr.u;
+            out->v[o] = pr.v;
+            size_t di = (size_t)(st * pr.v) * s->W + st * pr.u;
+            double rd = dst[di];
+            if (!range_ok(rd) || !nvalid[di])
+                continue;
+            const double *n = nrm + 3 * di;
+            double q[3];
+            orc_unproject(s, st * pr.u, st * pr.v, rd, q);
+            double dx[3] = {x[0] - q[0], x[1] - q[1], x[2] - q[2]};
+            if (prm->max_corr_dist > 0.0 &&
+                sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]) > prm->max_corr_dist)
+                continue;
+            double e = n[0] * dx[0] + n[1] * dx[1] + n[2] * dx[2];
+            double *J = out->J + 6 * o;
+            J[0] = x[1] * n[2] - x[2] * n[1];
+            J[1] = x[2] * n[0] - x[0] * n[2];
+            J[2] = x[0] * n[1] - x[1] * n[0];
+            J[3] = n[0];
+            J[4] = n[1];
+            J[5] = n[2];
+            out->mask[o] = 1;
+            out->e[o] = e;
+            double w;
+            if (use_learned) {
+                double f[14];
+                features(s, level, dst, pr.u, pr.v, pr.r, n, e, prm->delta, prm->r_max, f);
+                float ff[14];
+                for (int k = 0; k < 14; ++k)
+                    ff[k] = (float)f[k];
+                if (out->feat)
+                    memcpy(out->feat + 14 * o, ff, sizeof(ff));
+                double z;
+                orc_mlp_forward(prm->mlp, ff, 1, &z, &w);
+            } else {
+                w = huber_weight(e, prm->delta);
+                if (out->feat) {
+                    double f[14];
+                    features(s, level, dst, pr.u, pr.v, pr.r, n, e, prm->delta, prm->r_max, f);
+                    for (int k = 0; k < 14; ++k)
+                        out->feat[14 * o + k] = (float)f[k];
+                }
+            }
+            out->w[o] = w;
+        }
+}
+
+/* Weighted normal equations of Eq. (7) from per-pixel terms:
+ * H = sum w J J^T (21 upper entries, row-major), g = sum w J e, plus the
+ * residual statistics of the pass. */
+static void accumulate(int n, const orc_assoc_out *a, double delta, double Hm[36], double g[6],
+                       orc_level_stats *st)
+{
+    memset(Hm, 0, 36 * sizeof(double));
+    memset(g, 0, 6 * sizeof(double));
+    st->n_valid = st->n_inlier = st->n_proj = 0;
+    st->sum_w = st->sum_w_e2 = st->robust_cost = 0.0;
+    for (int o = 0; o < n; ++o) {
+        st->n_proj += a->proj_valid[o];
+        if (!a->mask[o])
+            continue;
+        const double *J = a->J + 6 * o;
+        double w = a->w[o], e = a->e[o];
+        for (int i = 0; i < 6; ++i) {
+            for (int j = 0; j < 6; ++j)
+                Hm[6 * i + j] += w * J[i] * J[j];
+            g[i] += w * J[i] * e;
+        }
+        st->n_valid += 1;
+        st->n_inlier += fabs(e) < delta ? 1 : 0;
+        st->sum_w += w;
+        st->sum_w_e2 += w * e * e;
+        st->robust_cost += huber_cost(e, delta);
+    }
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j)
+            st->JtJ[k++] = Hm[6 * i + j];
+    for (int i = 0; i < 6; ++i)
+        st->Jtr[i] = g[i];
+}
+
+/* Cholesky solve of H xi = -g.  Fails (returns 0) when a pivot is not above
+ * 1e-12 times the largest diagonal entry. */
+static int cholesky_solve(const double Hm[36], const double g[6], double xi[6])
+{
+    double L[36] = {0};
+    double dmax = 0.0;
+    for (int i = 0; i < 6; ++i)
+        if (Hm[7 * i] > dmax)
+            dmax = Hm[7 * i];
+    if (!(dmax > 0.0))
+        return 0;
+    for (int j = 0; j < 6; ++j) {
+        double d = Hm[7 * j];
+        for (int k = 0; k < j; ++k)
+            d -= L[6 * j + k] * L[6 * j + k];
+        if (!(d > 1e-12 * dmax))
+            return 0;
+        L[7 * j] = sqrt(d);
+        for (int i = j + 1; i < 6; ++i) {
+            double acc = Hm[6 * i + j];
+            for (int k = 0; k < j; ++k)
+                acc -= L[6 * i + k] * L[6 * j + k];
+            L[6 * i + j] = acc / L[7 * j];
+        }
+    }
+    double y[6];
+    for (int i = 0; i < 6; ++i) {
+        double acc = -g[i];
+        for (int k = 0; k < i; ++k)
+            acc -= L[6 * i + k] * y[k];
+        y[i] = acc / L[7 * i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double acc = y[i];
+        for (int k = i + 1; k < 6; ++k)
+            acc -= L[6 * k + i] * xi[k];
+        xi[i] = acc / L[7 * i];
+    }
+    return 1;
+}
+
+static int all_finite(const double *a, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(a[i]))
+            return 0;
+    return 1;
+}
+
+typedef struct {
+    orc_assoc_out a;
+    void *mem;
+} assoc_buf;
+
+static int assoc_alloc(assoc_buf *b, size_t n)
+{
+    size_t bytes = n * (10 * sizeof(double) + 2 * sizeof(int32_t) + 2);
+    char *m = (char *)malloc(bytes > 0 ? bytes : 1);
+    if (!m)
+        return 0;
+    b->mem = m;
+    b->a.e = (double *)m; m += n * sizeof(double);
+    b->a.w = (double *)m; m += n * sizeof(double);
+    b->a.J = (double *)m; m += 6 * n * sizeof(double);
+    b->a.uhat = (double *)m; m += n * sizeof(double);
+    b->a.phi = (double *)m; m += n * sizeof(double);
+    b->a.u = (int32_t *)m; m += n * sizeof(int32_t);
+    b->a.v = (int32_t *)m; m += n * sizeof(int32_t);
+    b->a.mask = (uint8_t *)m; m += n;
+    b->a.proj_valid = (uint8_t *)m;
+    b->a.feat = NULL;
+    return 1;
+}
+
+/*
+ * Multi-scale projective ICP (Sec. 4.1).  For levels l = L-1 down to 0 and
+ * iters[l] Gauss-Newton iterations each: associate (Eq. (5)-(6)), build the
+ * weighted normal equations of Eq. (7), solve by Cholesky, and update
+ * T <- Exp(xi) T.  A level stops early (status DEGENERATE) when fewer than 6
+ * correspondences remain or the Cholesky pivot test fails.  With learned
+ * weights, an iteration whose weights sum below 0.1 n_valid or whose system
+ * fails is redone with pseudo-Huber weights (status FALLBACK_HUBER).
+ * The statistics of a level are those of its last evaluated iteration.
+ *
+ * Initial pose: T_init as given, or (init_mode 1) R = I and t = mean of the
+ * valid target points minus mean of the valid source points (Sec. 4.1).
+ * Returns 0 on success, -1 on an allocation failure.
+ */
+int orc_icp(const orc_sensor *s, const float *src, const float *dst, const orc_params *prm,
+            const double T_init[16], double T_out[16], orc_level_stats *stats)
+{
+    int H = s->H, W = s->W;
+    size_t N = (size_t)H * W;
+    double *nrm = (double *)malloc(3 * N * sizeof(double));
+    uint8_t *nv = (uint8_t *)malloc(N);
+    assoc_buf ab;
+    if (!nrm || !nv || !assoc_alloc(&ab, N)) {
+        free(nrm);
+        free(nv);
+        return -1;
+    }
+    orc_normals(s, dst, prm->edge_rel, nrm, nv);
+    double T[16];
+    memcpy(T, T_init, sizeof(T));
+    if (prm->init_mode == 1) {
+        double cs[3] = {0}, cd[3] = {0}, p[3];
+        size_t ns = 0, nd = 0;
+        for (int v = 0; v < H; ++v)
+            for (int u = 0; u < W; ++u) {
+                size_t i = (size_t)v * W + u;
+                if (range_ok(src[i])) {
+                    orc_unproject(s, u, v, src[i], p);
+                    cs[0] += p[0]; cs[1] += p[1]; cs[2] += p[2];
+                    ns++;
+                }
+                if (range_ok(dst[i])) {
+                    orc_unproject(s, u, v, dst[i], p);
+                    cd[0] += p[0]; cd[1] += p[1]; cd[2] += p[2];
+                    nd++;
+                }
+            }
+        memset(T, 0, sizeof(T));
+        T[0] = T[5] = T[10] = T[15] = 1.0;
+        if (ns > 0 && nd > 0)
+            for (int i = 0; i < 3; ++i)
+                T[4 * i + 3] = cd[i] / (double)nd - cs[i] / (double)ns;
+    }
+    for (int l = prm->levels - 1; l >= 0; --l) {
+        int st = 1 << l;
+        int n = (H / st) * (W / st);
+        orc_level_stats *ls = &stats[l];
+        memset(ls, 0, sizeof(*ls));
+        for (int it = 0; it < prm->iters[l]; ++it) {
+            double Hm[36], g[6], xi[6];
+            int learned = prm->weight_mode == 1;
+            orc_associate(s, l, src, dst, nrm, nv, T, prm, learned, &ab.a);
+            accumulate(n, &ab.a, prm->delta, Hm, g, ls);
+            ls->iters_run = it + 1;
+            ls->status = ORC_OK;
+            int ok = ls->n_valid >= 6 && all_finite(Hm, 36) && all_finite(g, 6) && cholesky_solve(Hm, g, xi);
+            if (learned && (!ok || ls->sum_w < 0.1 * ls->n_valid)) {
+                orc_associate(s, l, src, dst, nrm, nv, T, prm, 0, &ab.a);
+                accumulate(n, &ab.a, prm->delta, Hm, g, ls);
+                ok = ls->n_valid >= 6 && all_finite(Hm, 36) && all_finite(g, 6) && cholesky_solve(Hm, g, xi);
+                ls->status = ORC_FALLBACK_HUBER;
+            }
+            if (!ok) {
+                ls->status = (all_finite(Hm, 36) && all_finite(g, 6)) ? ORC_DEGENERATE : ORC_NONFINITE;
+                ls->step_rot = ls->step_trans = 0.0;
+                break;
+            }
+            double D[16];
+            orc_exp_se3(xi, D);
+            mat4_mul(D, T, T);
+            ls->step_rot = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+            ls->step_trans = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+        }
+    }
+    memcpy(T_out, T, sizeof(T));
+    free(nrm);
+    free(nv);
+    free(ab.mem);
+    return 0;
+}
+
+/* One association + normal-equation pass at a fixed pose, for the tests:
+ * writes the per-pixel terms and the level statistics (JtJ, Jtr, counts). */
+int orc_system(const orc_sensor *s, int level, const float *src, const float *dst, const orc_params *prm,
+               const double T[16], int use_learned, int32_t *u, int32_t *v, uint8_t *mask, uint8_t *proj_valid,
+               double *e, double *w, double *J, double *uhat, double *phi, float *feat, orc_level_stats *st)
+{
+    size_t N = (size_t)s->H * s->W;
+    int sd = 1 << level;
+    int n = (s->H / sd) * (s->W / sd);
+    double *nrm = (double *)malloc(3 * N * sizeof(double));
+    uint8_t *nv = (uint8_t *)malloc(N);
+    if (!nrm || !nv) {
+        free(nrm);
+        free(nv);
+        return -1;
+    }
+    orc_normals(s, dst, prm->edge_rel, nrm, nv);
+    orc_assoc_out a = {u, v, mask, proj_valid, e, w, J, uhat, phi, feat};
+    orc_associate(s, level, src, dst, nrm, nv, T, prm, use_learned, &a);
+    double Hm[36], g[6];
+    memset(st, 0, sizeof(*st));
+    accumulate(n, &a, prm->delta, Hm, g, st);
+    free(nrm);
+    free(nv);
+    return 0;
+}
+
+/* Association with caller-given normals (for the strided-sensor invariant). */
+void orc_associate_with_normals(const orc_sensor *s, int level, const float *src, const float *dst,
+                                const double *nrm, const uint8_t *nvalid, const double T[16],
+                                const orc_params *prm, int32_t *u, int32_t *v, uint8_t *mask,
+                                uint8_t *proj_valid, double *e, double *w, double *J, double *uhat,
+                                double *phi)
+{
+    orc_assoc_out a = {u, v, mask, proj_valid, e, w, J, uhat, phi, NULL};
+    orc_associate(s, level, src, dst, nrm, nvalid, T, prm, 0, &a);
+}
