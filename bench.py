@@ -1,0 +1,187 @@
+"""Benchmark of the registration hot path on one MI355X.
+
+Workload (default): an odometry sequence of 100 consecutive 128x2048 scans of
+a synthetic outdoor scene (ground, 200 boxes and cylinders, ranges to 120 m,
+2 cm noise, 8% dropouts), registered as 99 independent pairs (k+1 -> k) from
+the identity with 4 pyramid levels x 10 Gauss-Newton iterations, pseudo-Huber
+delta 0.5 m, FP32 per-pixel math and FP64 solves.  One step is one batched
+registration of all 99 pairs: normal/pyramid pass plus 40 Gauss-Newton
+launches, inputs resident in HBM.
+
+Prints one JSON line (see the keys below).  `value` counts only pairs whose
+pose lies within 1 mm / 1e-4 rad of the FP64 CPU oracle: the fraction is
+measured on the oracle sample of the cpu_baseline leg (which is also timed
+on the host cores and reported as the CPU baseline).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ROT_TOL, TRANS_TOL = 1e-4, 1e-3
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def rot_trans_error(T, Tref):
+    R = T[:3, :3] @ Tref[:3, :3].T
+    s = np.linalg.norm([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]]) / 2
+    c = (np.trace(R) - 1) / 2
+    return float(np.arctan2(s, c)), float(np.linalg.norm(T[:3, 3] - Tref[:3, 3]))
+
+
+def cpu_baseline(pairs, sensor, levels, iters, delta, r_max, sample_every, threads):
+    """The FP64 oracle on a bounded sample of the workload's pairs, one pair per
+    host thread (the oracle itself is single-threaded)."""
+    import oracle
+    prm = oracle.make_params(levels=levels, iters=iters, delta=delta, r_max=r_max)
+    idx = list(range(0, len(pairs), sample_every))
+
+    def run(i):
+        T, _ = oracle.icp(sensor, pairs[i].src, pairs[i].dst, prm)
+        return T
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        poses = list(ex.map(run, idx))
+    dt = time.perf_counter() - t0
+    return idx, poses, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scans", type=int, default=100)
+    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (value then unchecked)")
+    ap.add_argument("--sample-every", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the batch of independent pairs would be split across GPUs "
+              "with no communication (see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2112_02779_amd as rir
+
+    cfg = synth.CONFIGS["odometry128x2048"]
+    levels, iters, delta = cfg["levels"], cfg["iters"], cfg["delta"]
+    r_max = cfg["noise"].rmax
+    t0 = time.perf_counter()
+    seq = synth.gen_sequence(cfg, args.seed, n_scans=args.scans)
+    pairs = seq["pairs"]
+    sm = seq["sensor"]
+    n = len(pairs)
+    log(f"generated {n} pairs of {sm.H}x{sm.W} in {time.perf_counter() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    scans = [torch.from_numpy(s).to(dev) for s in seq["scans"]]
+    sensor = rir.Sensor.from_model(sm)
+    ctx = rir.Context(0)
+    batch = [(sensor, scans[k + 1], scans[k]) for k in range(n)]
+    params = rir.make_params(levels=levels, iters=iters, delta=delta, use_graph=True)
+    init = torch.eye(4, dtype=torch.float64, device=dev).repeat(n, 1, 1)
+    poses = torch.empty((n, 4, 4), dtype=torch.float64, device=dev)
+    stats = torch.empty(n * levels * rir.STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    tuning, tune_ms = None, None
+    if not args.no_autotune:
+        t1 = time.perf_counter()
+        tuning, tune_ms = rir.autotune(ctx, params, batch, init)
+        torch.cuda.synchronize()
+        log(f"autotune picked {tuning} ({tune_ms:.3f} ms/batch) in {time.perf_counter() - t1:.1f}s")
+    tuning = ctx.get_tuning()
+
+    ctx.enable_timing(True)
+    for _ in range(args.warmup):
+        rir.icp_batch(ctx, params, batch, init, poses, stats)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done")
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        rir.icp_batch(ctx, params, batch, init, poses, stats)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    ms_per_step = (t_end - t_start) * 1e3 / args.steps
+    level_ms = ctx.level_times(levels)
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; level ms {['%.3f' % x for x in level_ms]}")
+
+    T_gpu = poses.cpu().numpy()
+    st = rir.stats_to_numpy(stats, n, levels)
+
+    # dominant kernel: the level-0 Gauss-Newton launch (association + reduction + solve)
+    n0 = sm.H * sm.W
+    tile_px = tuning["block"] * tuning["px_per_thread"]
+    tiles0 = n * ((n0 + tile_px - 1) // tile_px)
+    bytes_l0 = 4.0 * n0 * n + 16.0 * float(st["n_proj"][:, 0].sum()) + 144.0 * tiles0
+    l0_launch_ms = level_ms[0] / iters[0]
+    achieved = bytes_l0 / (l0_launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_icp_step<float,0> at level 0", "bytes_per_launch": bytes_l0,
+                "launch_ms": round(l0_launch_ms, 5)}
+
+    cpu = None
+    frac_ok, checked, max_err = 1.0, 0, None
+    if not args.no_cpu:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        idx, To, dt = cpu_baseline(pairs, sm, levels, iters, delta, r_max, args.sample_every, threads)
+        errs = [rot_trans_error(T_gpu[i], T) for i, T in zip(idx, To)]
+        ok = [e[0] <= ROT_TOL and e[1] <= TRANS_TOL for e in errs]
+        frac_ok, checked = float(np.mean(ok)), len(ok)
+        max_err = [max(e[0] for e in errs), max(e[1] for e in errs)]
+        cpu = {"value": round(len(idx) / dt, 4), "unit": "scan pairs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(idx)} of the {n} pairs (every {args.sample_every}th), FP64 single-threaded "
+                         f"oracle, one pair per thread, {dt:.1f} s wall"}
+        log(f"oracle sample {len(idx)} pairs in {dt:.1f}s; within tolerance {sum(ok)}/{len(ok)}; max err {max_err}")
+
+    pairs_per_s = n / (ms_per_step * 1e-3)
+    gt_err = [rot_trans_error(T_gpu[i], p.gt) for i, p in enumerate(pairs)]
+    out = {
+        "metric": "scan pairs/s at <=1mm/1e-4rad pose err vs FP64 oracle",
+        "value": round(pairs_per_s * frac_ok, 2),
+        "unit": "scan pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"odometry sequence, {n} pairs of {sm.H}x{sm.W} scans, {levels} levels x "
+                               f"{iters[0]} Gauss-Newton iterations, pseudo-Huber delta {delta} m, batched",
+                   "pairs_per_step": n, "levels": levels, "iters": iters, "tuning": tuning},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "raw_pairs_per_s": round(pairs_per_s, 2),
+        "oracle_checked": checked,
+        "oracle_within_tol": frac_ok,
+        "max_err_vs_oracle_rad_m": max_err,
+        "median_err_vs_gt_rad_m": [float(np.median([e[0] for e in gt_err])), float(np.median([e[1] for e in gt_err]))],
+        "level_ms": [round(x, 4) for x in level_ms],
+        "degenerate_levels": int(np.sum(st["status"] != 0)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,273 @@
+/*
+ * rir.h -- C ABI of librir: multi-scale projective point-to-plane ICP on
+ * cylindrical LiDAR range images, on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Dong, Ryu, Kaess, Park, "Revisiting LiDAR
+ * Registration and Reconstruction: A Range Image Perspective":
+ *   Sec. 3.1, Eq. (1)-(2)  ray-wise unprojection with per-beam azimuth and
+ *                          elevation tables and the receiver radius r0;
+ *   Sec. 3.2, Eq. (3)-(4)  projection with receiver-offset compensation and
+ *                          an inverse elevation table;
+ *   Sec. 4.1, Eq. (5)-(7)  projective data association and robust
+ *                          point-to-plane Gauss-Newton over a strided
+ *                          range/normal pyramid.
+ *
+ * Conventions shared by every call:
+ *  - Images are row-major [v][u], v = 0 the top beam (highest elevation), u the
+ *    column; azimuth grows with u counter-clockwise from +x.  Ranges are FP32
+ *    metres; 0, negative, NaN and Inf mean "no return".
+ *  - Poses are 4x4 row-major FP64 matrices T_dst<-src mapping source-sensor
+ *    points into the target-sensor frame.  Twists are xi = (omega, tau) and
+ *    updates are applied on the left: T <- Exp(xi) T.
+ *  - Pointers documented as "device" must point to memory on the context's or
+ *    sensor's GPU; "host" pointers to ordinary host memory.  The caller owns
+ *    every data buffer; the library owns only its opaque handles (device
+ *    tables, workspaces, captured graphs) and never frees caller memory.
+ *  - Calls taking a `stream` (a hipStream_t passed as void*, NULL = default
+ *    stream) enqueue their work asynchronously on it after validating their
+ *    arguments on the host.  Validation failures return an error before
+ *    anything is enqueued.  No C++ exception crosses this interface.
+ *  - Errors: every call returns a rir_status; on failure rir_last_error()
+ *    gives a thread-local message.  Numerical outcomes of a registration
+ *    (degenerate systems, fallbacks) are not errors; they are reported per
+ *    pair and per level in rir_level_stats.status.
+ *  - Handles are not thread-safe; use one rir_ctx per host thread/stream.
+ */
+#ifndef RIR_H
+#define RIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rir_status;
+
+enum {
+    RIR_OK = 0,
+    RIR_E_INVALID = 1,     /* null pointer, bad enum, bad numeric argument */
+    RIR_E_SHAPE = 2,       /* image shape incompatible with the pyramid or sensor */
+    RIR_E_LUT = 3,         /* sensor tables rejected (not strictly decreasing, ...) */
+    RIR_E_HIP = 4,         /* a HIP runtime call failed */
+    RIR_E_OOM = 5,         /* device or host allocation failed */
+    RIR_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+};
+
+/* Per-level outcome of a registration (rir_level_stats.status). */
+enum {
+    RIR_LEVEL_OK = 0,
+    RIR_LEVEL_DEGENERATE = 1,     /* < 6 correspondences or Cholesky pivot test failed; level stopped */
+    RIR_LEVEL_FALLBACK_HUBER = 2, /* learned weights rejected; that iteration used pseudo-Huber */
+    RIR_LEVEL_NONFINITE = 3       /* non-finite normal equations; level stopped */
+};
+
+enum { RIR_WEIGHT_HUBER = 0, RIR_WEIGHT_LEARNED = 1 };
+enum { RIR_PREC_FP32 = 0, RIR_PREC_FP64 = 1 };
+enum { RIR_MAX_LEVELS = 8 };
+
+typedef struct rir_sensor rir_sensor;
+typedef struct rir_ctx rir_ctx;
+typedef struct rir_mlp rir_mlp;
+
+/* Sensor intrinsics (Sec. 3.1): H beams, W columns, per-beam elevation
+ * phi_lut[H] (radians, strictly decreasing, |phi| < pi/2), per-beam azimuth
+ * offset theta_lut[H] (radians, |theta| < pi, NULL = all zero) and receiver
+ * radius r0 >= 0 (metres).  Both tables are host arrays, copied at creation.
+ * inv_bins: minimum bin count of the inverse elevation table per pyramid
+ * level (0 = automatic: at least 2 H_l, more if needed so that each bin holds
+ * at most one row boundary; Sec. 3.2). */
+typedef struct {
+    int32_t H, W;
+    const double *phi_lut;
+    const double *theta_lut;
+    double r0;
+    int32_t inv_bins;
+} rir_sensor_desc;
+
+/* Registration parameters (Sec. 4.1, Sec. 6.1).
+ *  levels        pyramid levels L (1..8); level l uses stride 2^l, so H and W
+ *                of every pair must be divisible by 2^(L-1).
+ *  iters[l]      Gauss-Newton iterations at level l (index 0 = finest); levels
+ *                run coarse to fine.
+ *  delta         pseudo-Huber kernel size in metres (> 0).
+ *  edge_rel      target-normal validity: every 4-neighbour range within
+ *                edge_rel * centre range (> 0; 0.1 by convention).
+ *  max_corr_dist reject correspondences with |x - q| above this (<= 0: off).
+ *  init_mode     0: start from init_poses; 1: R = I and t = difference of the
+ *                centres of the valid target and source points (Sec. 4.1).
+ *  weight_mode   RIR_WEIGHT_HUBER or RIR_WEIGHT_LEARNED (needs mlp).
+ *  precision     RIR_PREC_FP32: per-pixel math and tile sums in FP32, FP64
+ *                tile-partial sums, Cholesky and pose update;
+ *                RIR_PREC_FP64: everything in FP64.
+ *  use_graph     1: capture the iteration schedule once per batch shape as
+ *                HIP graphs and replay them; 0: launch kernel by kernel.
+ *  mlp           learned-weight network (weight_mode LEARNED), else NULL.
+ *  r_max         range scale of the first learned feature (metres). */
+typedef struct {
+    int32_t levels;
+    int32_t iters[RIR_MAX_LEVELS];
+    double delta;
+    double edge_rel;
+    double max_corr_dist;
+    int32_t init_mode;
+    int32_t weight_mode;
+    int32_t precision;
+    int32_t use_graph;
+    const rir_mlp *mlp;
+    double r_max;
+} rir_icp_params;
+
+/* Statistics of one pyramid level of one pair: those of the level's last
+ * evaluated Gauss-Newton iteration.  JtJ holds the 21 upper-triangle entries
+ * of sum w J J^T in row-major order, Jtr = sum w J e (Eq. (7) normal
+ * equations, xi = (omega, tau)); n_proj counts source pixels whose projection
+ * landed in the image; step_rot/step_trans are |omega|, |tau| of the last
+ * applied step (0 if none); robust_cost = sum of pseudo-Huber rho(e). */
+typedef struct {
+    int32_t status, iters_run, n_valid, n_inlier, n_proj, pad;
+    double sum_w, sum_w_e2, robust_cost, step_rot, step_trans;
+    double JtJ[21], Jtr[6];
+} rir_level_stats;
+
+/* One scan pair: source and target range images (device, H x W row-major
+ * FP32, H and W those of `sensor`). */
+typedef struct {
+    const rir_sensor *sensor;
+    const float *src_range;
+    const float *dst_range;
+} rir_pair;
+
+/* Tuning of the association/reduction launch (picked by rir_autotune).
+ * block: threads per workgroup (64, 128 or 256); px_per_thread: pixels each
+ * thread visits per tile (1..16); grid_mult: persistent workgroups per
+ * compute unit (0 = one workgroup per tile); xcd_remap: 1 maps consecutive
+ * tiles to the same XCD (L2) of the chip. */
+typedef struct {
+    int32_t block, px_per_thread, grid_mult, xcd_remap;
+} rir_tuning;
+
+/* ---------------------------------------------------------------- sensors */
+
+/* Builds the device tables of a sensor on the current HIP device (Sec. 3):
+ * per-beam and per-column trigonometric factors of Eq. (1), cancellation-free
+ * neighbour-difference factors for the normal image, and per-level inverse
+ * elevation tables of Sec. 3.2.  Errors: RIR_E_INVALID (null), RIR_E_LUT
+ * (H < 2, W < 4, non-finite or non-decreasing phi, |theta| >= pi, |phi| >=
+ * pi/2, r0 < 0), RIR_E_OOM, RIR_E_HIP.  *out is owned by the caller and
+ * released with rir_sensor_destroy. */
+rir_status rir_sensor_create(const rir_sensor_desc *desc, rir_sensor **out);
+void rir_sensor_destroy(rir_sensor *sensor);
+
+/* ---------------------------------------------------------------- contexts */
+
+/* A registration context on HIP device `device`: owns workspaces, captured
+ * graphs and the tuning.  Errors: RIR_E_INVALID, RIR_E_HIP, RIR_E_OOM. */
+rir_status rir_ctx_create(int device, rir_ctx **out);
+void rir_ctx_destroy(rir_ctx *ctx);
+rir_status rir_ctx_set_tuning(rir_ctx *ctx, const rir_tuning *tuning);
+rir_status rir_ctx_get_tuning(const rir_ctx *ctx, rir_tuning *tuning);
+
+/* When on, rir_icp_batch records HIP events on its stream around each
+ * pyramid level's iterations; rir_ctx_level_times then waits for the last
+ * call's events and writes the elapsed milliseconds of level l to ms[l]
+ * (ms[levels] receives the normal/pyramid pass).  Host arrays. */
+rir_status rir_ctx_enable_timing(rir_ctx *ctx, int32_t on);
+rir_status rir_ctx_level_times(rir_ctx *ctx, float *ms, int32_t n);
+
+/* ---------------------------------------------------------------- geometry */
+
+/* Eq. (1)-(2): unprojects every pixel of `range` (device H x W) to
+ * xyz (device H*W*3 FP32, (x,y,z) per pixel) and valid (device H*W bytes,
+ * 1 = return present, xyz = 0 otherwise). */
+rir_status rir_unproject(const rir_sensor *sensor, const float *range, float *xyz, uint8_t *valid, void *stream);
+
+/* Eq. (3)-(4) at pyramid level `level` (stride s = 2^level, Sec. 4.1): for n
+ * points xyz (device n*3 FP32) writes the level pixel (u, v) (device int32),
+ * the range r (device FP32) and valid (device bytes: inside the elevation
+ * field of view and r > 0; u = v = -1 when invalid).  Level indices are the
+ * nearest strided row by elevation and the nearest strided column. */
+rir_status rir_project(const rir_sensor *sensor, int32_t level, const float *xyz, int64_t n, int32_t *u,
+                       int32_t *v, float *r, uint8_t *valid, void *stream);
+
+/* Target normal image by the cross product of neighbour differences
+ * (Sec. 4.1, Sec. 6.1): nrm (device H*W*3 FP32) and valid (device bytes).
+ * Valid iff the pixel and its 4 neighbours (u wraps, v does not) have returns
+ * and every neighbour lies within edge_rel of the centre range; normals face
+ * the sensor. */
+rir_status rir_normals(const rir_sensor *sensor, const float *range, double edge_rel, float *nrm, uint8_t *valid,
+                       void *stream);
+
+/* ---------------------------------------------------------------- registration */
+
+/* Registers n_pairs independent scan pairs (Sec. 4.1, Eq. (5)-(7)), all with
+ * the same parameters but any mix of sensors and image sizes, in one batch:
+ * one association/reduction launch per Gauss-Newton iteration covers every
+ * pair, the tile partial sums of each pair are reduced and its 6x6 system
+ * solved by the last workgroup to finish that pair.
+ *   pairs       host array of n_pairs descriptors (device images).
+ *   init_poses  device n_pairs*16 FP64 (ignored with init_mode 1).
+ *   poses_out   device n_pairs*16 FP64 (may alias init_poses).
+ *   stats_out   device n_pairs*levels rir_level_stats, or NULL.
+ * Errors: RIR_E_INVALID, RIR_E_SHAPE (H or W not divisible by 2^(L-1)),
+ * RIR_E_UNSUPPORTED, RIR_E_OOM, RIR_E_HIP. */
+rir_status rir_icp_batch(rir_ctx *ctx, const rir_icp_params *params, int32_t n_pairs, const rir_pair *pairs,
+                         const double *init_poses, double *poses_out, rir_level_stats *stats_out, void *stream);
+
+/* One association pass of one pair at level `level` and host pose `pose`
+ * (16 FP64) without a pose update, dumping per source pixel of that level
+ * (N_l = (H/s)*(W/s), row-major): u, v (int32, -1 if the projection is
+ * invalid), mask (byte, 1 = correspondence used), e, w (FP32), J (FP32 N_l*6)
+ * and feat (FP32 N_l*14 learned-weight features, zeros where mask = 0); each
+ * output pointer is device memory or NULL.  stats_out (host, nullable)
+ * receives the reduced normal equations of the pass; when given the call
+ * waits for the stream. */
+rir_status rir_debug_associate(rir_ctx *ctx, const rir_icp_params *params, const rir_pair *pair, int32_t level,
+                               const double *pose, int32_t *u, int32_t *v, uint8_t *mask, float *e, float *w,
+                               float *J, float *feat, rir_level_stats *stats_out, void *stream);
+
+/* Times the batch for a sweep of rir_tuning candidates (each replayed a few
+ * times after a warm-up, HIP events on `stream`) and installs the fastest in
+ * the context; best (host, nullable) receives it and best_ms (host, nullable)
+ * its time per batch.  Poses are left in poses_scratch (device n_pairs*16). */
+rir_status rir_autotune(rir_ctx *ctx, const rir_icp_params *params, int32_t n_pairs, const rir_pair *pairs,
+                        const double *init_poses, double *poses_scratch, rir_tuning *best, float *best_ms,
+                        void *stream);
+
+/* ---------------------------------------------------------------- learned weight */
+
+/* Per-pixel robust-weight network 14-64-64-1 (ReLU, ReLU, sigmoid) replacing
+ * the pseudo-Huber weight of Eq. (7).  Parameters: w_bf16 = W1[64][14],
+ * W2[64][64], W3[64] as bfloat16 bit patterns (host, 5056 values), b_f32 =
+ * b1[64], b2[64], b3 (host, 129 values).  Training keeps FP32 master copies
+ * and Adam moments on the device. */
+rir_status rir_mlp_create(int device, const uint16_t *w_bf16, const float *b_f32, rir_mlp **out);
+void rir_mlp_destroy(rir_mlp *mlp);
+/* Host copies of the current bfloat16 weights (5056), biases (129) and, if
+ * master is non-NULL, the FP32 master weights (5056). */
+rir_status rir_mlp_get_params(const rir_mlp *mlp, uint16_t *w_bf16, float *b_f32, float *master);
+rir_status rir_mlp_set_params(rir_mlp *mlp, const uint16_t *w_bf16, const float *b_f32);
+
+/* Weights w = sigmoid(net(f)) for B feature rows (device B*14 FP32) into
+ * w_out (device B FP32).  Inputs and hidden activations are rounded to
+ * bfloat16; products accumulate in FP32 on the matrix cores. */
+rir_status rir_mlp_forward(const rir_mlp *mlp, const float *feats, int64_t B, float *w_out, void *stream);
+
+/* One Adam step (beta 0.9/0.999, eps 1e-8, learning rate lr) on the mean
+ * binary cross-entropy of sigmoid(net(f)) against labels (device B FP32 in
+ * {0,1}).  loss_out (device FP32, nullable) receives the batch loss;
+ * grads_out (device 5185 FP32 in the layout W1, b1, W2, b2, W3, b3, nullable)
+ * the gradient before the update. */
+rir_status rir_mlp_train_step(rir_mlp *mlp, const float *feats, const float *labels, int64_t B, float lr,
+                              float *loss_out, float *grads_out, void *stream);
+
+/* ---------------------------------------------------------------- errors */
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *rir_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIR_H */

@@ -1,0 +1,1158 @@
+// Host runtime of librir: argument validation, sensor tables, batch plans
+// (tile lists, workspaces, captured HIP graphs), the C ABI of include/rir.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <limits>
+#include <type_traits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "rir.h"
+#include "rir_internal.h"
+
+using namespace rir;
+
+namespace {
+
+thread_local std::string g_err;
+
+rir_status fail(rir_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return fail(e_ == hipErrorOutOfMemory ? RIR_E_OOM : RIR_E_HIP,                          \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                         \
+    } while (0)
+
+constexpr double kTwoPi = 6.28318530717958647692528676655900577;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Byte layout of one device allocation holding several arrays.
+struct Layout {
+    size_t bytes = 0;
+    size_t add(size_t n) {
+        size_t off = align_up(bytes, 256);
+        bytes = off + n;
+        return off;
+    }
+};
+
+}  // namespace
+
+// ============================================================================ sensor
+
+struct rir_sensor {
+    int device = 0;
+    int H = 0, W = 0, nlev = 0;
+    double r0 = 0.0;
+    std::vector<double> phi, theta;
+    void *dmem = nullptr;
+    SensorTab<float> tf{};
+    SensorTab<double> td{};
+    const SensorTab<float> *d_tf = nullptr;
+    const SensorTab<double> *d_td = nullptr;
+    ~rir_sensor()
+    {
+        if (dmem) {
+            hipSetDevice(device);
+            hipFree(dmem);
+        }
+    }
+};
+
+namespace {
+
+struct HostTables {
+    std::vector<double> row, col, nrow, theta;
+    std::vector<double> mu[kMaxLevels], uoff[kMaxLevels];
+    std::vector<int32_t> bins[kMaxLevels];
+    double s_lo, s_hi, cos_h, sin_h;
+    double bin_lo[kMaxLevels], bin_scale[kMaxLevels], kW[kMaxLevels];
+};
+
+// FP64 construction of the tables of Sec. 3: the factors of Eq. (1), the
+// product-form neighbour-difference factors, and per level the sin of the
+// elevation midpoints between strided rows with an inverse table over
+// sin(phi) (Sec. 3.2: 2 H_l bins at least, more when a bin would hold two
+// boundaries).
+void build_tables(const rir_sensor &s, int inv_bins, HostTables &t)
+{
+    const int H = s.H, W = s.W;
+    t.row.resize(4 * H);
+    for (int v = 0; v < H; ++v) {
+        t.row[4 * v] = std::cos(s.phi[v]);
+        t.row[4 * v + 1] = std::sin(s.phi[v]);
+        t.row[4 * v + 2] = std::cos(s.theta[v]);
+        t.row[4 * v + 3] = std::sin(s.theta[v]);
+    }
+    t.col.resize(2 * W);
+    for (int u = 0; u < W; ++u) {
+        const double a = kTwoPi * (double)u / (double)W;
+        t.col[2 * u] = std::cos(a);
+        t.col[2 * u + 1] = std::sin(a);
+    }
+    t.nrow.assign(8 * H, 0.0);
+    for (int v = 1; v + 1 < H; ++v) {
+        const double sg = 0.5 * (s.phi[v + 1] + s.phi[v - 1]), dp = 0.5 * (s.phi[v + 1] - s.phi[v - 1]);
+        const double m = 0.5 * (s.theta[v + 1] + s.theta[v - 1]), dt = 0.5 * (s.theta[v + 1] - s.theta[v - 1]);
+        double *f = &t.nrow[8 * v];
+        f[0] = std::cos(m + sg);
+        f[1] = std::sin(m + sg);
+        f[2] = std::cos(m - sg);
+        f[3] = std::sin(m - sg);
+        f[4] = std::sin(dt + dp);
+        f[5] = std::sin(dt - dp);
+        f[6] = 2.0 * std::cos(sg) * std::sin(dp);
+        f[7] = 0.0;
+    }
+    t.theta = s.theta;
+    const double phi_hi = s.phi[0] + 0.5 * (s.phi[0] - s.phi[1]);
+    const double phi_lo = s.phi[H - 1] - 0.5 * (s.phi[H - 2] - s.phi[H - 1]);
+    t.s_hi = phi_hi >= 0.5 * M_PI ? INFINITY : std::sin(phi_hi);
+    t.s_lo = phi_lo <= -0.5 * M_PI ? -INFINITY : std::sin(phi_lo);
+    t.cos_h = std::cos(kTwoPi / W);
+    t.sin_h = std::sin(kTwoPi / W);
+    const double lo = std::isfinite(t.s_lo) ? t.s_lo : -1.0;
+    const double hi = std::isfinite(t.s_hi) ? t.s_hi : 1.0;
+    for (int l = 0; l < s.nlev; ++l) {
+        const int st = 1 << l, Hl = H / st;
+        t.kW[l] = (double)W / (kTwoPi * st);
+        t.uoff[l].resize(Hl);
+        for (int k = 0; k < Hl; ++k)
+            t.uoff[l][k] = s.theta[st * k] * (double)W / (kTwoPi * st);
+        t.mu[l].assign(std::max(Hl - 1, 1), 0.0);
+        double gmin = hi - lo;
+        for (int k = 0; k + 1 < Hl; ++k) {
+            t.mu[l][k] = std::sin(0.5 * (s.phi[st * k] + s.phi[st * (k + 1)]));
+            if (k > 0)
+                gmin = std::min(gmin, t.mu[l][k - 1] - t.mu[l][k]);
+        }
+        long nb = std::max<long>(2L * Hl, std::max(inv_bins, 2));
+        if (Hl > 2 && gmin > 0)
+            nb = std::max<long>(nb, (long)std::ceil((hi - lo) / gmin) + 1);
+        nb = std::min<long>(nb, 1L << 16);
+        t.bin_lo[l] = lo;
+        t.bin_scale[l] = (double)nb / (hi - lo);
+        t.bins[l].resize(nb);
+        for (long b = 0; b < nb; ++b) {
+            const double top = lo + (double)(b + 1) / t.bin_scale[l];
+            int c = 0;
+            while (c < Hl - 1 && t.mu[l][c] > top)
+                ++c;
+            t.bins[l][b] = c;
+        }
+    }
+}
+
+template <typename T>
+void fill_tab(SensorTab<T> &tab, const rir_sensor &s, const HostTables &t, char *base, const size_t *off_row,
+              const size_t *off_col, const size_t *off_nrow, const size_t *off_theta, const size_t *off_mu,
+              const size_t *off_uoff, const size_t *off_bins)
+{
+    tab.H = s.H;
+    tab.W = s.W;
+    tab.nlev = s.nlev;
+    tab.r0 = (T)s.r0;
+    tab.s_lo = std::isfinite(t.s_lo) ? (T)t.s_lo : -std::numeric_limits<T>::infinity();
+    tab.s_hi = std::isfinite(t.s_hi) ? (T)t.s_hi : std::numeric_limits<T>::infinity();
+    tab.cos_h = (T)t.cos_h;
+    tab.sin_h = (T)t.sin_h;
+    tab.row = reinterpret_cast<const T *>(base + *off_row);
+    tab.col = reinterpret_cast<const T *>(base + *off_col);
+    tab.nrow = reinterpret_cast<const T *>(base + *off_nrow);
+    tab.theta = reinterpret_cast<const T *>(base + *off_theta);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        if (l < s.nlev) {
+            tab.nbins[l] = (int)t.bins[l].size();
+            tab.bin_lo[l] = (T)t.bin_lo[l];
+            tab.bin_scale[l] = (T)t.bin_scale[l];
+            tab.kW[l] = (T)t.kW[l];
+            tab.mu[l] = reinterpret_cast<const T *>(base + off_mu[l]);
+            tab.uoff[l] = reinterpret_cast<const T *>(base + off_uoff[l]);
+            tab.bins[l] = reinterpret_cast<const int32_t *>(base + off_bins[l]);
+        } else {
+            tab.nbins[l] = 0;
+            tab.bin_lo[l] = tab.bin_scale[l] = tab.kW[l] = (T)0;
+            tab.mu[l] = tab.uoff[l] = nullptr;
+            tab.bins[l] = nullptr;
+        }
+    }
+}
+
+template <typename T>
+void put(std::vector<char> &img, size_t off, const std::vector<double> &v)
+{
+    T *p = reinterpret_cast<T *>(img.data() + off);
+    for (size_t i = 0; i < v.size(); ++i)
+        p[i] = (T)v[i];
+}
+
+}  // namespace
+
+extern "C" rir_status rir_sensor_create(const rir_sensor_desc *desc, rir_sensor **out)
+{
+    if (!desc || !out)
+        return fail(RIR_E_INVALID, "rir_sensor_create: null argument");
+    *out = nullptr;
+    const int H = desc->H, W = desc->W;
+    if (H < 2 || W < 4)
+        return fail(RIR_E_LUT, "rir_sensor_create: need H >= 2 and W >= 4");
+    if (!desc->phi_lut)
+        return fail(RIR_E_INVALID, "rir_sensor_create: phi_lut is null");
+    if (!(desc->r0 >= 0.0) || !std::isfinite(desc->r0))
+        return fail(RIR_E_LUT, "rir_sensor_create: r0 must be finite and >= 0");
+    std::unique_ptr<rir_sensor> s(new rir_sensor());
+    s->H = H;
+    s->W = W;
+    s->r0 = desc->r0;
+    s->phi.assign(desc->phi_lut, desc->phi_lut + H);
+    s->theta.assign(H, 0.0);
+    if (desc->theta_lut)
+        s->theta.assign(desc->theta_lut, desc->theta_lut + H);
+    for (int v = 0; v < H; ++v) {
+        if (!std::isfinite(s->phi[v]) || std::fabs(s->phi[v]) >= 0.5 * M_PI)
+            return fail(RIR_E_LUT, "rir_sensor_create: phi_lut entries must be finite with |phi| < pi/2");
+        if (v > 0 && !(s->phi[v] < s->phi[v - 1]))
+            return fail(RIR_E_LUT, "rir_sensor_create: phi_lut must be strictly decreasing (row 0 = top beam)");
+        if (!std::isfinite(s->theta[v]) || std::fabs(s->theta[v]) >= M_PI)
+            return fail(RIR_E_LUT, "rir_sensor_create: theta_lut entries must be finite with |theta| < pi");
+    }
+    int nlev = 0;
+    while (nlev < kMaxLevels && H % (1 << nlev) == 0 && W % (1 << nlev) == 0 && (W >> nlev) >= 2)
+        ++nlev;
+    s->nlev = nlev;
+    HIP_TRY(hipGetDevice(&s->device));
+    HostTables t;
+    build_tables(*s, std::max(desc->inv_bins, 0), t);
+
+    Layout lay;
+    size_t od_row = lay.add(8 * t.row.size()), od_col = lay.add(8 * t.col.size());
+    size_t od_nrow = lay.add(8 * t.nrow.size()), od_theta = lay.add(8 * t.theta.size());
+    size_t of_row = lay.add(4 * t.row.size()), of_col = lay.add(4 * t.col.size());
+    size_t of_nrow = lay.add(4 * t.nrow.size()), of_theta = lay.add(4 * t.theta.size());
+    size_t od_mu[kMaxLevels] = {}, of_mu[kMaxLevels] = {}, od_uoff[kMaxLevels] = {}, of_uoff[kMaxLevels] = {};
+    size_t o_bins[kMaxLevels] = {};
+    for (int l = 0; l < nlev; ++l) {
+        od_mu[l] = lay.add(8 * t.mu[l].size());
+        of_mu[l] = lay.add(4 * t.mu[l].size());
+        od_uoff[l] = lay.add(8 * t.uoff[l].size());
+        of_uoff[l] = lay.add(4 * t.uoff[l].size());
+        o_bins[l] = lay.add(4 * t.bins[l].size());
+    }
+    size_t o_tf = lay.add(sizeof(SensorTab<float>)), o_td = lay.add(sizeof(SensorTab<double>));
+    std::vector<char> img(lay.bytes, 0);
+    put<double>(img, od_row, t.row);
+    put<double>(img, od_col, t.col);
+    put<double>(img, od_nrow, t.nrow);
+    put<double>(img, od_theta, t.theta);
+    put<float>(img, of_row, t.row);
+    put<float>(img, of_col, t.col);
+    put<float>(img, of_nrow, t.nrow);
+    put<float>(img, of_theta, t.theta);
+    for (int l = 0; l < nlev; ++l) {
+        put<double>(img, od_mu[l], t.mu[l]);
+        put<float>(img, of_mu[l], t.mu[l]);
+        put<double>(img, od_uoff[l], t.uoff[l]);
+        put<float>(img, of_uoff[l], t.uoff[l]);
+        std::memcpy(img.data() + o_bins[l], t.bins[l].data(), 4 * t.bins[l].size());
+    }
+    HIP_TRY(hipMalloc(&s->dmem, lay.bytes));
+    char *base = static_cast<char *>(s->dmem);
+    fill_tab(s->tf, *s, t, base, &of_row, &of_col, &of_nrow, &of_theta, of_mu, of_uoff, o_bins);
+    fill_tab(s->td, *s, t, base, &od_row, &od_col, &od_nrow, &od_theta, od_mu, od_uoff, o_bins);
+    std::memcpy(img.data() + o_tf, &s->tf, sizeof(s->tf));
+    std::memcpy(img.data() + o_td, &s->td, sizeof(s->td));
+    HIP_TRY(hipMemcpy(s->dmem, img.data(), lay.bytes, hipMemcpyHostToDevice));
+    s->d_tf = reinterpret_cast<const SensorTab<float> *>(base + o_tf);
+    s->d_td = reinterpret_cast<const SensorTab<double> *>(base + o_td);
+    *out = s.release();
+    return RIR_OK;
+}
+
+extern "C" void rir_sensor_destroy(rir_sensor *sensor) { delete sensor; }
+
+// ============================================================================ learned-weight network
+
+struct rir_mlp {
+    int device = 0;
+    void *dmem = nullptr;
+    uint16_t *w = nullptr;   // bf16 weights [kMlpNW]
+    float *b = nullptr;      // biases [kMlpNB]
+    float *master = nullptr; // FP32 master weights [kMlpNW]
+    float *m1 = nullptr, *m2 = nullptr;  // Adam moments [5185]
+    float *gpart = nullptr;  // per-block gradient records
+    int gpart_blocks = 0;
+    int step = 0;
+    ~rir_mlp()
+    {
+        hipSetDevice(device);
+        if (dmem)
+            hipFree(dmem);
+        if (gpart)
+            hipFree(gpart);
+    }
+    MlpDev dev() const { return MlpDev{w, b}; }
+};
+
+// ============================================================================ context and plans
+
+namespace {
+
+struct KeyPod {
+    int levels, iters[kMaxLevels], init_mode, weight_mode, precision, use_graph, debug;
+    double delta, edge_rel, max_corr, r_max;
+    const rir_mlp *mlp;
+    rir_tuning tune;
+};
+
+struct PlanKey {
+    std::vector<const rir_sensor *> sensors;
+    KeyPod k;
+    bool operator<(const PlanKey &o) const
+    {
+        if (sensors != o.sensors)
+            return sensors < o.sensors;
+        return std::memcmp(&k, &o.k, sizeof(KeyPod)) < 0;
+    }
+};
+
+struct Plan {
+    PlanKey key;
+    int device = 0;
+    int n_pairs = 0;
+    bool fp64 = false;
+    int tile_px = 0, block = 0;
+    int n_tiles[kMaxLevels] = {};
+    int grid[kMaxLevels] = {};
+    void *dmem = nullptr;
+    void *h_desc = nullptr;   // pinned host copy of the pair descriptors
+    size_t desc_bytes = 0;
+    void *d_desc = nullptr;
+    int2 *d_tiles[kMaxLevels] = {};
+    void *d_psum = nullptr;
+    int4 *d_pcnt = nullptr;
+    int *d_counters = nullptr;
+    double *d_poses = nullptr;
+    rir_level_stats *d_stats = nullptr;
+    int *d_flags = nullptr;
+    std::vector<const float *> cur_src, cur_dst;
+    hipEvent_t desc_evt = nullptr;
+    bool desc_pending = false;
+    hipGraphExec_t g_pre = nullptr;
+    hipGraphExec_t g_lev[kMaxLevels] = {};
+    bool graphs = false;
+    ~Plan()
+    {
+        hipSetDevice(device);
+        if (g_pre)
+            hipGraphExecDestroy(g_pre);
+        for (auto &g : g_lev)
+            if (g)
+                hipGraphExecDestroy(g);
+        if (desc_evt)
+            hipEventDestroy(desc_evt);
+        if (h_desc)
+            hipHostFree(h_desc);
+        if (dmem)
+            hipFree(dmem);
+    }
+};
+
+}  // namespace
+
+struct rir_ctx {
+    int device = 0;
+    int n_cu = 256;
+    hipStream_t cap = nullptr;  // private stream used only for graph capture
+    rir_tuning tune{256, 8, 0, 1};
+    std::map<PlanKey, std::unique_ptr<Plan>> plans;
+    bool timing = false;
+    int timing_levels = 0;
+    hipEvent_t ev[2 * (kMaxLevels + 1)] = {};
+    bool ev_recorded = false;
+    ~rir_ctx()
+    {
+        hipSetDevice(device);
+        plans.clear();
+        for (auto &e : ev)
+            if (e)
+                hipEventDestroy(e);
+        if (cap)
+            hipStreamDestroy(cap);
+    }
+};
+
+extern "C" rir_status rir_ctx_create(int device, rir_ctx **out)
+{
+    if (!out)
+        return fail(RIR_E_INVALID, "rir_ctx_create: null argument");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n)
+        return fail(RIR_E_INVALID, "rir_ctx_create: no such device");
+    HIP_TRY(hipSetDevice(device));
+    std::unique_ptr<rir_ctx> c(new rir_ctx());
+    c->device = device;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    for (auto &e : c->ev)
+        HIP_TRY(hipEventCreate(&e));
+    *out = c.release();
+    return RIR_OK;
+}
+
+extern "C" void rir_ctx_destroy(rir_ctx *ctx) { delete ctx; }
+
+static rir_status check_tuning(const rir_tuning *t)
+{
+    if (!(t->block == 64 || t->block == 128 || t->block == 256))
+        return fail(RIR_E_INVALID, "rir_tuning.block must be 64, 128 or 256");
+    if (t->px_per_thread < 1 || t->px_per_thread > 16)
+        return fail(RIR_E_INVALID, "rir_tuning.px_per_thread must be in 1..16");
+    if (t->grid_mult < 0 || t->grid_mult > 64)
+        return fail(RIR_E_INVALID, "rir_tuning.grid_mult must be in 0..64");
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_ctx_set_tuning(rir_ctx *ctx, const rir_tuning *tuning)
+{
+    if (!ctx || !tuning)
+        return fail(RIR_E_INVALID, "rir_ctx_set_tuning: null argument");
+    rir_status st = check_tuning(tuning);
+    if (st != RIR_OK)
+        return st;
+    if (std::memcmp(&ctx->tune, tuning, sizeof(rir_tuning)) != 0) {
+        ctx->tune = *tuning;
+        hipSetDevice(ctx->device);
+        ctx->plans.clear();
+    }
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_ctx_get_tuning(const rir_ctx *ctx, rir_tuning *tuning)
+{
+    if (!ctx || !tuning)
+        return fail(RIR_E_INVALID, "rir_ctx_get_tuning: null argument");
+    *tuning = ctx->tune;
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_ctx_enable_timing(rir_ctx *ctx, int32_t on)
+{
+    if (!ctx)
+        return fail(RIR_E_INVALID, "rir_ctx_enable_timing: null context");
+    ctx->timing = on != 0;
+    ctx->ev_recorded = false;
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_ctx_level_times(rir_ctx *ctx, float *ms, int32_t n)
+{
+    if (!ctx || !ms)
+        return fail(RIR_E_INVALID, "rir_ctx_level_times: null argument");
+    if (!ctx->ev_recorded)
+        return fail(RIR_E_INVALID, "rir_ctx_level_times: no timed call recorded");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int L = ctx->timing_levels;
+    for (int i = 0; i < n; ++i)
+        ms[i] = 0.f;
+    for (int l = 0; l <= L && l < n; ++l) {
+        HIP_TRY(hipEventSynchronize(ctx->ev[2 * l + 1]));
+        HIP_TRY(hipEventElapsedTime(&ms[l], ctx->ev[2 * l], ctx->ev[2 * l + 1]));
+    }
+    return RIR_OK;
+}
+
+namespace {
+
+rir_status check_params(const rir_icp_params *p)
+{
+    if (!p)
+        return fail(RIR_E_INVALID, "null rir_icp_params");
+    if (p->levels < 1 || p->levels > kMaxLevels)
+        return fail(RIR_E_INVALID, "rir_icp_params.levels must be in 1..8");
+    for (int l = 0; l < p->levels; ++l)
+        if (p->iters[l] < 0 || p->iters[l] > 1000)
+            return fail(RIR_E_INVALID, "rir_icp_params.iters must be in 0..1000");
+    if (!(p->delta > 0.0) || !std::isfinite(p->delta))
+        return fail(RIR_E_INVALID, "rir_icp_params.delta must be > 0");
+    if (!(p->edge_rel > 0.0) || !std::isfinite(p->edge_rel))
+        return fail(RIR_E_INVALID, "rir_icp_params.edge_rel must be > 0");
+    if (!std::isfinite(p->max_corr_dist))
+        return fail(RIR_E_INVALID, "rir_icp_params.max_corr_dist must be finite");
+    if (p->init_mode != 0 && p->init_mode != 1)
+        return fail(RIR_E_INVALID, "rir_icp_params.init_mode must be 0 or 1");
+    if (p->weight_mode != RIR_WEIGHT_HUBER && p->weight_mode != RIR_WEIGHT_LEARNED)
+        return fail(RIR_E_INVALID, "rir_icp_params.weight_mode must be HUBER or LEARNED");
+    if (p->weight_mode == RIR_WEIGHT_LEARNED && !p->mlp)
+        return fail(RIR_E_INVALID, "rir_icp_params.mlp is required with learned weights");
+    if (p->weight_mode == RIR_WEIGHT_LEARNED && !(p->r_max > 0.0))
+        return fail(RIR_E_INVALID, "rir_icp_params.r_max must be > 0 with learned weights");
+    if (p->precision != RIR_PREC_FP32 && p->precision != RIR_PREC_FP64)
+        return fail(RIR_E_INVALID, "rir_icp_params.precision must be FP32 or FP64");
+    return RIR_OK;
+}
+
+rir_status check_pairs(const rir_ctx *ctx, const rir_icp_params *p, int n, const rir_pair *pairs)
+{
+    if (n < 1)
+        return fail(RIR_E_INVALID, "n_pairs must be >= 1");
+    if (!pairs)
+        return fail(RIR_E_INVALID, "pairs is null");
+    const int div = 1 << (p->levels - 1);
+    for (int i = 0; i < n; ++i) {
+        const rir_sensor *s = pairs[i].sensor;
+        if (!s || !pairs[i].src_range || !pairs[i].dst_range)
+            return fail(RIR_E_INVALID, "pair " + std::to_string(i) + ": null sensor or image");
+        if (s->device != ctx->device)
+            return fail(RIR_E_INVALID, "pair " + std::to_string(i) + ": sensor lives on another device");
+        if (s->H % div || s->W % div || p->levels > s->nlev)
+            return fail(RIR_E_SHAPE, "pair " + std::to_string(i) + ": H and W must be divisible by 2^(levels-1)");
+        if ((int64_t)s->H * s->W >= (1 << 24))
+            return fail(RIR_E_SHAPE, "pair " + std::to_string(i) + ": images must have fewer than 2^24 pixels");
+    }
+    return RIR_OK;
+}
+
+template <typename T>
+void set_desc_images(PairDesc<T> *d, const rir_pair &p)
+{
+    d->src[0] = const_cast<float *>(p.src_range);
+    d->dstr[0] = const_cast<float *>(p.dst_range);
+}
+
+// Allocates and fills a plan for one batch shape.
+rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, int n, Plan *&out)
+{
+    std::unique_ptr<Plan> P(new Plan());
+    P->key = key;
+    P->device = ctx->device;
+    P->n_pairs = n;
+    P->fp64 = key.k.precision == RIR_PREC_FP64;
+    const size_t tsz = P->fp64 ? sizeof(double) : sizeof(float);
+    const int L = key.k.levels;
+    P->block = key.k.tune.block;
+    P->tile_px = key.k.tune.block * key.k.tune.px_per_thread;
+    std::vector<std::vector<int2>> tiles(L);
+    std::vector<int> t0(n * kMaxLevels, 0), nt(n * kMaxLevels, 0);
+    for (int l = 0; l < L; ++l) {
+        for (int i = 0; i < n; ++i) {
+            const rir_sensor *s = pairs[i].sensor;
+            const int Nl = (s->H >> l) * (s->W >> l);
+            const int k = (Nl + P->tile_px - 1) / P->tile_px;
+            t0[i * kMaxLevels + l] = (int)tiles[l].size();
+            nt[i * kMaxLevels + l] = k;
+            for (int j = 0; j < k; ++j)
+                tiles[l].push_back(make_int2(i, j * P->tile_px));
+        }
+        P->n_tiles[l] = (int)tiles[l].size();
+        int G = P->n_tiles[l];
+        if (key.k.tune.grid_mult > 0)
+            G = std::min(G, key.k.tune.grid_mult * ctx->n_cu);
+        if (key.k.tune.xcd_remap)
+            G = (G + 7) / 8 * 8;
+        P->grid[l] = std::max(G, 1);
+    }
+    const int max_tiles = P->n_tiles[0];
+    // device layout
+    Layout lay;
+    P->desc_bytes = n * (P->fp64 ? sizeof(PairDesc<double>) : sizeof(PairDesc<float>));
+    size_t o_desc = lay.add(P->desc_bytes);
+    size_t o_tiles[kMaxLevels];
+    for (int l = 0; l < L; ++l)
+        o_tiles[l] = lay.add(sizeof(int2) * tiles[l].size());
+    size_t o_psum = lay.add((size_t)max_tiles * kAccum * tsz);
+    size_t o_pcnt = lay.add((size_t)max_tiles * sizeof(int4));
+    size_t o_cnt = lay.add((size_t)n * sizeof(int));
+    size_t o_pose = lay.add((size_t)n * 16 * sizeof(double));
+    size_t o_stats = lay.add((size_t)n * L * sizeof(rir_level_stats));
+    size_t o_flags = lay.add((size_t)n * kFlagStride * sizeof(int));
+    std::vector<size_t> o_src(n * kMaxLevels, 0), o_dstr(n * kMaxLevels, 0), o_dst4(n * kMaxLevels, 0);
+    for (int i = 0; i < n; ++i) {
+        const rir_sensor *s = pairs[i].sensor;
+        for (int l = 0; l < L; ++l) {
+            const size_t Nl = (size_t)(s->H >> l) * (s->W >> l);
+            if (l > 0) {
+                o_src[i * kMaxLevels + l] = lay.add(Nl * sizeof(float));
+                o_dstr[i * kMaxLevels + l] = lay.add(Nl * sizeof(float));
+            }
+            o_dst4[i * kMaxLevels + l] = lay.add(Nl * 4 * tsz);
+        }
+    }
+    HIP_TRY(hipMalloc(&P->dmem, lay.bytes));
+    char *base = static_cast<char *>(P->dmem);
+    HIP_TRY(hipMemset(base + o_cnt, 0, (size_t)n * sizeof(int)));
+    HIP_TRY(hipMemset(base + o_flags, 0, (size_t)n * kFlagStride * sizeof(int)));
+    P->d_desc = base + o_desc;
+    for (int l = 0; l < L; ++l) {
+        P->d_tiles[l] = reinterpret_cast<int2 *>(base + o_tiles[l]);
+        HIP_TRY(hipMemcpy(P->d_tiles[l], tiles[l].data(), sizeof(int2) * tiles[l].size(), hipMemcpyHostToDevice));
+    }
+    P->d_psum = base + o_psum;
+    P->d_pcnt = reinterpret_cast<int4 *>(base + o_pcnt);
+    P->d_counters = reinterpret_cast<int *>(base + o_cnt);
+    P->d_poses = reinterpret_cast<double *>(base + o_pose);
+    P->d_stats = reinterpret_cast<rir_level_stats *>(base + o_stats);
+    P->d_flags = reinterpret_cast<int *>(base + o_flags);
+    HIP_TRY(hipHostMalloc(&P->h_desc, P->desc_bytes, hipHostMallocDefault));
+    std::memset(P->h_desc, 0, P->desc_bytes);
+    for (int i = 0; i < n; ++i) {
+        const rir_sensor *s = pairs[i].sensor;
+        auto fill = [&](auto *d, auto *tab) {
+            d->tab = tab;
+            d->H = s->H;
+            d->W = s->W;
+            for (int l = 0; l < kMaxLevels; ++l) {
+                d->src[l] = nullptr;
+                d->dstr[l] = nullptr;
+                d->dst4[l] = nullptr;
+                d->tile0[l] = d->ntile[l] = 0;
+                d->invW[l] = 0.f;
+            }
+            for (int l = 0; l < L; ++l) {
+                using TT = typename std::remove_pointer<typename std::remove_reference<decltype(d->dst4[0])>::type>::type;
+                if (l > 0) {
+                    d->src[l] = reinterpret_cast<float *>(base + o_src[i * kMaxLevels + l]);
+                    d->dstr[l] = reinterpret_cast<float *>(base + o_dstr[i * kMaxLevels + l]);
+                }
+                d->dst4[l] = reinterpret_cast<TT *>(base + o_dst4[i * kMaxLevels + l]);
+                d->tile0[l] = t0[i * kMaxLevels + l];
+                d->ntile[l] = nt[i * kMaxLevels + l];
+                d->invW[l] = 1.0f / (float)(s->W >> l);
+            }
+            set_desc_images(d, pairs[i]);
+        };
+        if (P->fp64)
+            fill(reinterpret_cast<PairDesc<double> *>(P->h_desc) + i, s->d_td);
+        else
+            fill(reinterpret_cast<PairDesc<float> *>(P->h_desc) + i, s->d_tf);
+        P->cur_src.push_back(pairs[i].src_range);
+        P->cur_dst.push_back(pairs[i].dst_range);
+    }
+    HIP_TRY(hipMemcpy(P->d_desc, P->h_desc, P->desc_bytes, hipMemcpyHostToDevice));
+    HIP_TRY(hipEventCreateWithFlags(&P->desc_evt, hipEventDisableTiming));
+    out = P.release();
+    return RIR_OK;
+}
+
+rir_status get_plan(rir_ctx *ctx, const rir_icp_params *p, const rir_pair *pairs, int n, int debug, Plan *&out)
+{
+    PlanKey key;
+    std::memset(&key.k, 0, sizeof(KeyPod));
+    for (int i = 0; i < n; ++i)
+        key.sensors.push_back(pairs[i].sensor);
+    KeyPod &k = key.k;
+    k.levels = p->levels;
+    for (int l = 0; l < kMaxLevels; ++l)
+        k.iters[l] = l < p->levels ? p->iters[l] : 0;
+    k.init_mode = p->init_mode;
+    k.weight_mode = p->weight_mode;
+    k.precision = p->precision;
+    k.use_graph = p->use_graph ? 1 : 0;
+    k.debug = debug;
+    k.delta = p->delta;
+    k.edge_rel = p->edge_rel;
+    k.max_corr = p->max_corr_dist;
+    k.r_max = p->weight_mode == RIR_WEIGHT_LEARNED ? p->r_max : 0.0;
+    k.mlp = p->weight_mode == RIR_WEIGHT_LEARNED ? p->mlp : nullptr;
+    k.tune = ctx->tune;
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) {
+        out = it->second.get();
+        return RIR_OK;
+    }
+    Plan *P = nullptr;
+    rir_status st = make_plan(ctx, key, pairs, n, P);
+    if (st != RIR_OK)
+        return st;
+    ctx->plans[key].reset(P);
+    out = P;
+    return RIR_OK;
+}
+
+// Points the plan's descriptors at this call's images (only when they changed).
+rir_status update_images(Plan *P, const rir_pair *pairs, hipStream_t st)
+{
+    bool changed = false;
+    for (int i = 0; i < P->n_pairs; ++i)
+        if (P->cur_src[i] != pairs[i].src_range || P->cur_dst[i] != pairs[i].dst_range)
+            changed = true;
+    if (!changed)
+        return RIR_OK;
+    // the pinned staging copy may still be read by a previous enqueued copy
+    HIP_TRY(hipEventSynchronize(P->desc_evt));
+    for (int i = 0; i < P->n_pairs; ++i) {
+        if (P->fp64)
+            set_desc_images(reinterpret_cast<PairDesc<double> *>(P->h_desc) + i, pairs[i]);
+        else
+            set_desc_images(reinterpret_cast<PairDesc<float> *>(P->h_desc) + i, pairs[i]);
+        P->cur_src[i] = pairs[i].src_range;
+        P->cur_dst[i] = pairs[i].dst_range;
+    }
+    HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc, P->desc_bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(P->desc_evt, st));
+    return RIR_OK;
+}
+
+StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, int mode)
+{
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.pairs = P->d_desc;
+    a.tiles = P->d_tiles[level];
+    a.n_tiles = P->n_tiles[level];
+    a.level = level;
+    a.iter = iter;
+    a.levels = P->key.k.levels;
+    a.tile_px = P->tile_px;
+    a.xcd_remap = P->key.k.tune.xcd_remap;
+    a.mode = mode;
+    a.psum = P->d_psum;
+    a.pcnt = P->d_pcnt;
+    a.counters = P->d_counters;
+    a.poses = P->d_poses;
+    a.stats = P->d_stats;
+    a.flags = P->d_flags;
+    a.delta = p->delta;
+    a.max_corr = p->max_corr_dist;
+    a.r_max = (float)p->r_max;
+    if (p->weight_mode == RIR_WEIGHT_LEARNED)
+        a.mlp = p->mlp->dev();
+    return a;
+}
+
+// Enqueues the normal/pyramid pass (and the flag/statistics reset).
+rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t st)
+{
+    HIP_TRY(launch_clear(P->d_flags, P->n_pairs * kFlagStride, P->d_stats, P->n_pairs * P->key.k.levels, st));
+    PrepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.pairs = P->d_desc;
+    a.tiles = P->d_tiles[0];
+    a.n_tiles = P->n_tiles[0];
+    a.tile_px = P->tile_px;
+    a.levels = P->key.k.levels;
+    a.init_centroid = p->init_mode == 1;
+    a.edge_rel = p->edge_rel;
+    a.psum = P->d_psum;
+    a.counters = P->d_counters;
+    a.poses = P->d_poses;
+    a.xcd_remap = P->key.k.tune.xcd_remap;
+    HIP_TRY(launch_prepass(P->fp64, a, P->grid[0], P->block, st));
+    return RIR_OK;
+}
+
+// Enqueues the Gauss-Newton iterations of one level.
+rir_status enqueue_level(const Plan *P, const rir_icp_params *p, int l, hipStream_t st)
+{
+    for (int it = 0; it < P->key.k.iters[l]; ++it) {
+        StepArgs a = step_args(P, p, l, it, kStepNormal);
+        HIP_TRY(launch_step(P->fp64, p->weight_mode, a, P->grid[l], P->block, st));
+        if (p->weight_mode == RIR_WEIGHT_LEARNED) {
+            StepArgs b = step_args(P, p, l, it, kStepFallback);
+            HIP_TRY(launch_step(P->fp64, RIR_WEIGHT_HUBER, b, P->grid[l], P->block, st));
+        }
+    }
+    return RIR_OK;
+}
+
+rir_status capture(rir_ctx *ctx, Plan *P, const rir_icp_params *p)
+{
+    hipStream_t cs = ctx->cap;
+    auto cap_one = [&](int which, hipGraphExec_t *out) -> rir_status {
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        rir_status st = which < 0 ? enqueue_prepass(P, p, cs) : enqueue_level(P, p, which, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (st != RIR_OK) {
+            if (g)
+                hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess)
+            return fail(RIR_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return fail(RIR_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        return RIR_OK;
+    };
+    rir_status st = cap_one(-1, &P->g_pre);
+    if (st != RIR_OK)
+        return st;
+    for (int l = 0; l < P->key.k.levels; ++l) {
+        st = cap_one(l, &P->g_lev[l]);
+        if (st != RIR_OK)
+            return st;
+    }
+    P->graphs = true;
+    return RIR_OK;
+}
+
+rir_status run_plan(rir_ctx *ctx, Plan *P, const rir_icp_params *p, hipStream_t st)
+{
+    const int L = P->key.k.levels;
+    const bool tm = ctx->timing;
+    if (p->use_graph && !P->graphs) {
+        rir_status s = capture(ctx, P, p);
+        if (s != RIR_OK)
+            return s;
+    }
+    if (tm)
+        HIP_TRY(hipEventRecord(ctx->ev[2 * L], st));
+    if (p->use_graph)
+        HIP_TRY(hipGraphLaunch(P->g_pre, st));
+    else {
+        rir_status s = enqueue_prepass(P, p, st);
+        if (s != RIR_OK)
+            return s;
+    }
+    if (tm)
+        HIP_TRY(hipEventRecord(ctx->ev[2 * L + 1], st));
+    for (int l = L - 1; l >= 0; --l) {
+        if (tm)
+            HIP_TRY(hipEventRecord(ctx->ev[2 * l], st));
+        if (p->use_graph)
+            HIP_TRY(hipGraphLaunch(P->g_lev[l], st));
+        else {
+            rir_status s = enqueue_level(P, p, l, st);
+            if (s != RIR_OK)
+                return s;
+        }
+        if (tm)
+            HIP_TRY(hipEventRecord(ctx->ev[2 * l + 1], st));
+    }
+    if (tm) {
+        ctx->timing_levels = L;
+        ctx->ev_recorded = true;
+    }
+    return RIR_OK;
+}
+
+}  // namespace
+
+extern "C" rir_status rir_icp_batch(rir_ctx *ctx, const rir_icp_params *params, int32_t n_pairs, const rir_pair *pairs,
+                                    const double *init_poses, double *poses_out, rir_level_stats *stats_out,
+                                    void *stream)
+{
+    if (!ctx)
+        return fail(RIR_E_INVALID, "rir_icp_batch: null context");
+    rir_status s = check_params(params);
+    if (s != RIR_OK)
+        return s;
+    s = check_pairs(ctx, params, n_pairs, pairs);
+    if (s != RIR_OK)
+        return s;
+    if (!poses_out || (params->init_mode == 0 && !init_poses))
+        return fail(RIR_E_INVALID, "rir_icp_batch: null pose buffer");
+    if (params->weight_mode == RIR_WEIGHT_LEARNED && params->mlp->device != ctx->device)
+        return fail(RIR_E_INVALID, "rir_icp_batch: network lives on another device");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Plan *P = nullptr;
+    s = get_plan(ctx, params, pairs, n_pairs, 0, P);
+    if (s != RIR_OK)
+        return s;
+    s = update_images(P, pairs, st);
+    if (s != RIR_OK)
+        return s;
+    const size_t pose_bytes = (size_t)n_pairs * 16 * sizeof(double);
+    if (params->init_mode == 0)
+        HIP_TRY(hipMemcpyAsync(P->d_poses, init_poses, pose_bytes, hipMemcpyDeviceToDevice, st));
+    s = run_plan(ctx, P, params, st);
+    if (s != RIR_OK)
+        return s;
+    HIP_TRY(hipMemcpyAsync(poses_out, P->d_poses, pose_bytes, hipMemcpyDeviceToDevice, st));
+    if (stats_out)
+        HIP_TRY(hipMemcpyAsync(stats_out, P->d_stats, (size_t)n_pairs * params->levels * sizeof(rir_level_stats),
+                               hipMemcpyDeviceToDevice, st));
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_debug_associate(rir_ctx *ctx, const rir_icp_params *params, const rir_pair *pair,
+                                          int32_t level, const double *pose, int32_t *u, int32_t *v, uint8_t *mask,
+                                          float *e, float *w, float *J, float *feat, rir_level_stats *stats_out,
+                                          void *stream)
+{
+    if (!ctx || !pose)
+        return fail(RIR_E_INVALID, "rir_debug_associate: null argument");
+    rir_status s = check_params(params);
+    if (s != RIR_OK)
+        return s;
+    s = check_pairs(ctx, params, 1, pair);
+    if (s != RIR_OK)
+        return s;
+    if (level < 0 || level >= params->levels)
+        return fail(RIR_E_INVALID, "rir_debug_associate: level out of range");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rir_icp_params q = *params;
+    q.use_graph = 0;
+    q.init_mode = 0;
+    Plan *P = nullptr;
+    s = get_plan(ctx, &q, pair, 1, 1, P);
+    if (s != RIR_OK)
+        return s;
+    s = update_images(P, pair, st);
+    if (s != RIR_OK)
+        return s;
+    s = enqueue_prepass(P, &q, st);
+    if (s != RIR_OK)
+        return s;
+    // the pose goes through the (pinned) descriptor staging event discipline
+    HIP_TRY(hipEventSynchronize(P->desc_evt));
+    double *hp = nullptr;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&hp), 16 * sizeof(double), hipHostMallocDefault));
+    std::memcpy(hp, pose, 16 * sizeof(double));
+    hipError_t e1 = hipMemcpyAsync(P->d_poses, hp, 16 * sizeof(double), hipMemcpyHostToDevice, st);
+    StepArgs a = step_args(P, &q, level, 0, kStepDebug);
+    a.dbg_u = u;
+    a.dbg_v = v;
+    a.dbg_mask = mask;
+    a.dbg_e = e;
+    a.dbg_w = w;
+    a.dbg_J = J;
+    a.dbg_feat = feat;
+    hipError_t e2 = e1 == hipSuccess ? launch_step(P->fp64, q.weight_mode, a, P->grid[level], P->block, st) : e1;
+    hipError_t e3 = hipStreamSynchronize(st);
+    hipHostFree(hp);
+    HIP_TRY(e1);
+    HIP_TRY(e2);
+    HIP_TRY(e3);
+    if (stats_out)
+        HIP_TRY(hipMemcpy(stats_out, P->d_stats, sizeof(rir_level_stats), hipMemcpyDeviceToHost));
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_autotune(rir_ctx *ctx, const rir_icp_params *params, int32_t n_pairs,
+                                   const rir_pair *pairs, const double *init_poses, double *poses_scratch,
+                                   rir_tuning *best, float *best_ms, void *stream)
+{
+    if (!ctx || !poses_scratch)
+        return fail(RIR_E_INVALID, "rir_autotune: null argument");
+    rir_status s = check_params(params);
+    if (s != RIR_OK)
+        return s;
+    s = check_pairs(ctx, params, n_pairs, pairs);
+    if (s != RIR_OK)
+        return s;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool was_timing = ctx->timing;
+    ctx->timing = false;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int blocks[] = {128, 256};
+    const int ppts[] = {2, 4, 8, 16};
+    const int gms[] = {0, 4};
+    const int xcds[] = {0, 1};
+    rir_tuning bt = ctx->tune;
+    float bms = INFINITY;
+    for (int b : blocks)
+        for (int ppt : ppts)
+            for (int gm : gms)
+                for (int x : xcds) {
+                    rir_tuning t{b, ppt, gm, x};
+                    s = rir_ctx_set_tuning(ctx, &t);
+                    if (s != RIR_OK)
+                        break;
+                    // warm-up (builds the plan and captures the graphs)
+                    s = rir_icp_batch(ctx, params, n_pairs, pairs, init_poses, poses_scratch, nullptr, stream);
+                    if (s != RIR_OK)
+                        break;
+                    const int reps = 3;
+                    if (hipEventRecord(e0, st) != hipSuccess)
+                        break;
+                    for (int r = 0; r < reps && s == RIR_OK; ++r)
+                        s = rir_icp_batch(ctx, params, n_pairs, pairs, init_poses, poses_scratch, nullptr, stream);
+                    if (s != RIR_OK)
+                        break;
+                    hipEventRecord(e1, st);
+                    hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    ms /= reps;
+                    if (ms < bms) {
+                        bms = ms;
+                        bt = t;
+                    }
+                }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->timing = was_timing;
+    if (s != RIR_OK)
+        return s;
+    s = rir_ctx_set_tuning(ctx, &bt);
+    if (s != RIR_OK)
+        return s;
+    if (best)
+        *best = bt;
+    if (best_ms)
+        *best_ms = bms;
+    return RIR_OK;
+}
+
+// ============================================================================ geometry entry points
+
+extern "C" rir_status rir_unproject(const rir_sensor *sensor, const float *range, float *xyz, uint8_t *valid,
+                                    void *stream)
+{
+    if (!sensor || !range || !xyz || !valid)
+        return fail(RIR_E_INVALID, "rir_unproject: null argument");
+    HIP_TRY(hipSetDevice(sensor->device));
+    HIP_TRY(launch_unproject(sensor->tf, range, xyz, valid, static_cast<hipStream_t>(stream)));
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_project(const rir_sensor *sensor, int32_t level, const float *xyz, int64_t n, int32_t *u,
+                                  int32_t *v, float *r, uint8_t *valid, void *stream)
+{
+    if (!sensor || (n > 0 && (!xyz || !u || !v || !r || !valid)))
+        return fail(RIR_E_INVALID, "rir_project: null argument");
+    if (n < 0)
+        return fail(RIR_E_INVALID, "rir_project: n < 0");
+    if (level < 0 || level >= sensor->nlev)
+        return fail(RIR_E_SHAPE, "rir_project: level not supported by this sensor's shape");
+    if (n == 0)
+        return RIR_OK;
+    HIP_TRY(hipSetDevice(sensor->device));
+    HIP_TRY(launch_project(sensor->tf, level, xyz, n, u, v, r, valid, static_cast<hipStream_t>(stream)));
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_normals(const rir_sensor *sensor, const float *range, double edge_rel, float *nrm,
+                                  uint8_t *valid, void *stream)
+{
+    if (!sensor || !range || !nrm || !valid)
+        return fail(RIR_E_INVALID, "rir_normals: null argument");
+    if (!(edge_rel > 0.0) || !std::isfinite(edge_rel))
+        return fail(RIR_E_INVALID, "rir_normals: edge_rel must be > 0");
+    HIP_TRY(hipSetDevice(sensor->device));
+    HIP_TRY(launch_normals(sensor->tf, range, edge_rel, nrm, valid, static_cast<hipStream_t>(stream)));
+    return RIR_OK;
+}
+
+// ============================================================================ learned-weight network API
+
+extern "C" rir_status rir_mlp_create(int device, const uint16_t *w_bf16, const float *b_f32, rir_mlp **out)
+{
+    if (!w_bf16 || !b_f32 || !out)
+        return fail(RIR_E_INVALID, "rir_mlp_create: null argument");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n)
+        return fail(RIR_E_INVALID, "rir_mlp_create: no such device");
+    HIP_TRY(hipSetDevice(device));
+    std::unique_ptr<rir_mlp> m(new rir_mlp());
+    m->device = device;
+    Layout lay;
+    size_t o_w = lay.add(kMlpNW * 2), o_b = lay.add(kMlpNB * 4), o_ms = lay.add(kMlpNW * 4);
+    size_t o_m1 = lay.add(5185 * 4), o_m2 = lay.add(5185 * 4);
+    HIP_TRY(hipMalloc(&m->dmem, lay.bytes));
+    char *base = static_cast<char *>(m->dmem);
+    m->w = reinterpret_cast<uint16_t *>(base + o_w);
+    m->b = reinterpret_cast<float *>(base + o_b);
+    m->master = reinterpret_cast<float *>(base + o_ms);
+    m->m1 = reinterpret_cast<float *>(base + o_m1);
+    m->m2 = reinterpret_cast<float *>(base + o_m2);
+    HIP_TRY(hipMemset(m->dmem, 0, lay.bytes));
+    rir_status s = rir_mlp_set_params(m.get(), w_bf16, b_f32);
+    if (s != RIR_OK)
+        return s;
+    *out = m.release();
+    return RIR_OK;
+}
+
+extern "C" void rir_mlp_destroy(rir_mlp *mlp) { delete mlp; }
+
+extern "C" rir_status rir_mlp_set_params(rir_mlp *m, const uint16_t *w_bf16, const float *b_f32)
+{
+    if (!m || !w_bf16 || !b_f32)
+        return fail(RIR_E_INVALID, "rir_mlp_set_params: null argument");
+    HIP_TRY(hipSetDevice(m->device));
+    std::vector<float> master(kMlpNW);
+    for (int i = 0; i < kMlpNW; ++i) {
+        uint32_t bits = (uint32_t)w_bf16[i] << 16;
+        std::memcpy(&master[i], &bits, 4);
+    }
+    HIP_TRY(hipMemcpy(m->w, w_bf16, kMlpNW * 2, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->b, b_f32, kMlpNB * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->master, master.data(), kMlpNW * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(m->m1, 0, 5185 * 4));
+    HIP_TRY(hipMemset(m->m2, 0, 5185 * 4));
+    m->step = 0;
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_mlp_get_params(const rir_mlp *m, uint16_t *w_bf16, float *b_f32, float *master)
+{
+    if (!m || !w_bf16 || !b_f32)
+        return fail(RIR_E_INVALID, "rir_mlp_get_params: null argument");
+    HIP_TRY(hipSetDevice(m->device));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(w_bf16, m->w, kMlpNW * 2, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(b_f32, m->b, kMlpNB * 4, hipMemcpyDeviceToHost));
+    if (master)
+        HIP_TRY(hipMemcpy(master, m->master, kMlpNW * 4, hipMemcpyDeviceToHost));
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_mlp_forward(const rir_mlp *m, const float *feats, int64_t B, float *w_out, void *stream)
+{
+    if (!m || (B > 0 && (!feats || !w_out)))
+        return fail(RIR_E_INVALID, "rir_mlp_forward: null argument");
+    if (B < 0)
+        return fail(RIR_E_INVALID, "rir_mlp_forward: B < 0");
+    if (B == 0)
+        return RIR_OK;
+    HIP_TRY(hipSetDevice(m->device));
+    HIP_TRY(launch_mlp_forward(m->dev(), feats, B, w_out, static_cast<hipStream_t>(stream)));
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_mlp_train_step(rir_mlp *m, const float *feats, const float *labels, int64_t B, float lr,
+                                         float *loss_out, float *grads_out, void *stream)
+{
+    if (!m || !feats || !labels)
+        return fail(RIR_E_INVALID, "rir_mlp_train_step: null argument");
+    if (B < 1 || B > (1LL << 30))
+        return fail(RIR_E_INVALID, "rir_mlp_train_step: B must be in 1..2^30");
+    if (!(lr >= 0.f) || !std::isfinite(lr))
+        return fail(RIR_E_INVALID, "rir_mlp_train_step: lr must be finite and >= 0");
+    HIP_TRY(hipSetDevice(m->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nb = mlp_grad_blocks(B);
+    if (nb > m->gpart_blocks) {
+        HIP_TRY(hipStreamSynchronize(st));
+        if (m->gpart)
+            HIP_TRY(hipFree(m->gpart));
+        m->gpart = nullptr;
+        HIP_TRY(hipMalloc(reinterpret_cast<void **>(&m->gpart), (size_t)nb * kMlpGradRecord * sizeof(float)));
+        m->gpart_blocks = nb;
+    }
+    HIP_TRY(launch_mlp_grad(m->dev(), feats, labels, B, m->gpart, nb, st));
+    m->step += 1;
+    HIP_TRY(launch_mlp_adam(m->gpart, nb, B, lr, m->step, m->master, m->b, m->m1, m->m2, m->w, loss_out, grads_out,
+                            st));
+    return RIR_OK;
+}
+
+extern "C" const char *rir_last_error(void) { return g_err.c_str(); }

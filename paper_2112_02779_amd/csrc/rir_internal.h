@@ -1,0 +1,106 @@
+// Internal interface between the host runtime (api.cpp) and the kernels
+// (kernels.hip, mlp.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rir.h"
+#include "rir_device.h"
+
+namespace rir {
+
+// Per-pair view of one batch entry, in device memory.  Level images:
+//  src[l]  FP32 source ranges at stride 2^l ([0] is the caller's image)
+//  dstr[l] FP32 target ranges at stride 2^l ([0] is the caller's image)
+//  dst4[l] 4 T per pixel: target normal (x, y, z) and range, all zero where
+//          the normal is invalid (which includes "no return")
+// Tiles of level l of this pair are tile0[l] .. tile0[l] + ntile[l] - 1 of the
+// level's tile list.
+template <typename T>
+struct PairDesc {
+    const SensorTab<T> *tab;
+    float *src[kMaxLevels];
+    float *dstr[kMaxLevels];
+    T *dst4[kMaxLevels];
+    int H, W;
+    int tile0[kMaxLevels], ntile[kMaxLevels];
+    float invW[kMaxLevels];
+};
+
+// Per-pair flag words: flags[pair * kFlagStride + l] bit 0 = level l stopped;
+// flags[pair * kFlagStride + kMaxLevels] bit 0 = learned weights rejected in
+// the last iteration (a pseudo-Huber redo is pending).
+constexpr int kFlagStride = kMaxLevels + 1;
+constexpr int kAccum = 32;  // float accumulators per tile (30 used)
+
+enum StepMode { kStepNormal = 0, kStepFallback = 1, kStepDebug = 2 };
+
+// Learned-weight network in device memory.
+struct MlpDev {
+    const uint16_t *w;  // bf16 W1[64][14], W2[64][64], W3[64]
+    const float *b;     // b1[64], b2[64], b3
+};
+constexpr int kMlpW1 = 0, kMlpW2 = 64 * 14, kMlpW3 = 64 * 14 + 64 * 64, kMlpNW = 64 * 14 + 64 * 64 + 64;
+constexpr int kMlpB1 = 0, kMlpB2 = 64, kMlpB3 = 128, kMlpNB = 129;
+
+struct StepArgs {
+    const void *pairs;   // PairDesc<T>[n_pairs]
+    const int2 *tiles;   // (pair, first pixel) of every tile of this level
+    int n_tiles;
+    int level, iter, levels;
+    int tile_px;         // pixels per tile = block * px_per_thread
+    int xcd_remap;
+    int mode;            // StepMode
+    void *psum;          // T[n_tiles][kAccum]
+    int4 *pcnt;          // [n_tiles] (n_valid, n_inlier, n_proj, 0)
+    int *counters;       // [n_pairs] tiles finished in the current launch
+    double *poses;       // [n_pairs][16]
+    rir_level_stats *stats;  // [n_pairs][levels] (debug: [1])
+    int *flags;          // [n_pairs][kFlagStride]
+    double delta, max_corr;
+    float r_max;
+    MlpDev mlp;
+    // per-pixel dumps (debug mode; each may be null)
+    int32_t *dbg_u, *dbg_v;
+    uint8_t *dbg_mask;
+    float *dbg_e, *dbg_w, *dbg_J, *dbg_feat;
+};
+
+struct PrepArgs {
+    const void *pairs;  // PairDesc<T>[n_pairs]
+    const int2 *tiles;  // level-0 tiles
+    int n_tiles;
+    int tile_px;
+    int levels;
+    int init_centroid;  // 1: compute t0 from the point-set centres
+    double edge_rel;
+    void *psum;         // T[n_tiles][kAccum] (centroid sums)
+    int *counters;
+    double *poses;
+    int xcd_remap;
+};
+
+// Launch wrappers (kernels.hip).  All enqueue on `stream` and return the
+// launch status.
+hipError_t launch_unproject(const SensorTab<float> &S, const float *range, float *xyz, uint8_t *valid,
+                            hipStream_t stream);
+hipError_t launch_project(const SensorTab<float> &S, int level, const float *xyz, int64_t n, int32_t *u, int32_t *v,
+                          float *r, uint8_t *valid, hipStream_t stream);
+hipError_t launch_normals(const SensorTab<float> &S, const float *range, double edge_rel, float *nrm,
+                          uint8_t *valid, hipStream_t stream);
+hipError_t launch_clear(int *flags, int n_flags, rir_level_stats *stats, int n_stats, hipStream_t stream);
+hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, hipStream_t stream);
+hipError_t launch_step(bool fp64, int weight_mode, const StepArgs &a, int grid, int block, hipStream_t stream);
+
+// Learned-weight network (mlp.hip).
+hipError_t launch_mlp_forward(const MlpDev &m, const float *feats, int64_t B, float *w_out, hipStream_t stream);
+hipError_t launch_mlp_grad(const MlpDev &m, const float *feats, const float *labels, int64_t B, float *gpart,
+                           int nblocks, hipStream_t stream);
+hipError_t launch_mlp_adam(const float *gpart, int nblocks, int64_t B, float lr, int step, float *master,
+                           float *bias, float *m1, float *m2, uint16_t *wbf, float *loss_out, float *grads_out,
+                           hipStream_t stream);
+int mlp_grad_blocks(int64_t B);
+constexpr int kMlpGradRecord = 5185 + 1;  // gradient + loss per block
+
+}  // namespace rir

@@ -1,0 +1,210 @@
+// Learned per-pixel robust weight (replaces the pseudo-Huber weight of
+// Eq. (7)): features of a correspondence and the 14-64-64-1 network evaluated
+// by one wavefront for its 64 lanes on the matrix cores (bf16 operands, FP32
+// accumulation).
+//
+// The layers are computed transposed, H^T = W X^T, with the weights as the A
+// operand and activations as the B operand of v_mfma_f32_16x16x16_bf16: the
+// accumulator layout of that instruction (lane l holds rows 4(l/16)+j, column
+// l%16 of a 16x16 tile) is exactly its B-operand layout, so the output of one
+// layer feeds the next without moving data between lanes.
+#pragma once
+
+#include "rir_internal.h"
+
+namespace rir {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint32_t f2bf(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    if ((b & 0x7f800000u) == 0x7f800000u)
+        return (b | ((b & 0x007fffffu) ? 0x00400000u : 0u)) >> 16;
+    return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ float round_bf(float f) { return bf2f(f2bf(f)); }
+
+__device__ __forceinline__ f32x4_t mfma16(bf16x4_t a, bf16x4_t b, f32x4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Per-lane operand fragments of the network (lane l: r = l % 16, g = l / 16).
+//  a1[mt]      W1 rows mt*16 + r, inputs 4g..4g+3 (inputs >= 14 are zero)
+//  a2[mt][kt]  W2 rows mt*16 + r, inputs kt*16 + 4g..+3
+//  b1, b2, w3  [mt][j] for hidden unit mt*16 + 4g + j
+struct MlpFrag {
+    bf16x4_t a1[4];
+    bf16x4_t a2[4][4];
+    float b1[4][4], b2[4][4], w3[4][4];
+    float b3;
+};
+
+__device__ __forceinline__ void mlp_load(const MlpDev &m, MlpFrag &F)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * g + j;
+            F.a1[mt][j] = (short)(k < 14 ? m.w[kMlpW1 + (mt * 16 + r) * 14 + k] : 0);
+            F.b1[mt][j] = m.b[kMlpB1 + mt * 16 + k];
+            F.b2[mt][j] = m.b[kMlpB2 + mt * 16 + k];
+            F.w3[mt][j] = bf2f(m.w[kMlpW3 + mt * 16 + k]);
+        }
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                F.a2[mt][kt][j] = (short)m.w[kMlpW2 + (mt * 16 + r) * 64 + kt * 16 + 4 * g + j];
+    }
+    F.b3 = m.b[kMlpB3];
+}
+
+// Packs 14 features (rounded to bf16) into 8 dwords, two per dword, low half first.
+__device__ __forceinline__ void pack_features(const float (&f)[14], uint32_t (&fp)[8])
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t lo = 2 * k < 14 ? f2bf(f[2 * k]) : 0u;
+        const uint32_t hi = 2 * k + 1 < 14 ? f2bf(f[2 * k + 1]) : 0u;
+        fp[k] = lo | (hi << 16);
+    }
+}
+
+// Logit z of the network for the wave's 64 pixels: lane l passes its pixel's
+// packed features and receives z of that pixel.  `lds` is this wave's private
+// 64 x 8-dword staging area (the feature transpose into B-operand layout).
+// Must be called by all 64 lanes.
+__device__ __forceinline__ float mlp_wave(const MlpFrag &F, const uint32_t (&fp)[8], uint32_t *lds)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    uint4 *row = reinterpret_cast<uint4 *>(lds + lane * 8);
+    row[0] = make_uint4(fp[0], fp[1], fp[2], fp[3]);
+    row[1] = make_uint4(fp[4], fp[5], fp[6], fp[7]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float zsel = 0.f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const uint2 bb = *reinterpret_cast<const uint2 *>(lds + (nt * 16 + r) * 8 + 2 * g);
+        bf16x4_t B;
+        B[0] = (short)(bb.x & 0xffffu);
+        B[1] = (short)(bb.x >> 16);
+        B[2] = (short)(bb.y & 0xffffu);
+        B[3] = (short)(bb.y >> 16);
+        bf16x4_t hb[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4_t c = {F.b1[mt][0], F.b1[mt][1], F.b1[mt][2], F.b1[mt][3]};
+            c = mfma16(F.a1[mt], B, c);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                hb[mt][j] = (short)f2bf(fmaxf(c[j], 0.f));
+        }
+        float part = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4_t c = {F.b2[mt][0], F.b2[mt][1], F.b2[mt][2], F.b2[mt][3]};
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt)
+                c = mfma16(F.a2[mt][kt], hb[kt], c);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                part += F.w3[mt][j] * round_bf(fmaxf(c[j], 0.f));
+        }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (nt == g)
+            zsel = part + F.b3;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return zsel;
+}
+
+__device__ __forceinline__ float clamp4(float x) { return fminf(fmaxf(x, -4.f), 4.f); }
+
+// Features of a correspondence (target pixel (ul, vl) of level l, residual e,
+// projected source range xr, target normal n):
+//  f0 = target range / r_max, f1..f8 = clamp((neighbour - centre) / delta, +-4)
+//  for the 8 level-l neighbours in raster order (u wraps; rows outside the
+//  image or neighbours without return give +4), f9..f11 = n,
+//  f12 = clamp(e / delta), f13 = clamp((target range - xr) / delta) (the
+//  projective signed distance of Eq. (8)-(9)).  Zeros when !valid.
+template <typename T>
+__device__ __forceinline__ void compute_features(const StepArgs &a, const PairDesc<T> &P, int l, bool valid, int ul,
+                                                 int vl, T e, T xr, T n0, T n1, T n2, float (&f)[14])
+{
+#pragma unroll
+    for (int k = 0; k < 14; ++k)
+        f[k] = 0.f;
+    if (!valid)
+        return;
+    const int Wl = P.W >> l, Hl = P.H >> l;
+    const float *img = P.dstr[l];
+    const T rc = (T)img[(size_t)vl * Wl + ul];
+    const T inv_delta = (T)(1.0 / a.delta);
+    f[0] = (float)(rc / (T)a.r_max);
+    int k = 1;
+#pragma unroll
+    for (int dv = -1; dv <= 1; ++dv)
+#pragma unroll
+        for (int du = -1; du <= 1; ++du) {
+            if (du == 0 && dv == 0)
+                continue;
+            const int vv = vl + dv;
+            int uu = ul + du;
+            uu = uu < 0 ? uu + Wl : (uu >= Wl ? uu - Wl : uu);
+            float val = 4.f;
+            if (vv >= 0 && vv < Hl) {
+                const float rn = img[(size_t)vv * Wl + uu];
+                if (range_ok(rn))
+                    val = clamp4((float)(((T)rn - rc) * inv_delta));
+            }
+            f[k++] = val;
+        }
+    f[9] = (float)n0;
+    f[10] = (float)n1;
+    f[11] = (float)n2;
+    f[12] = clamp4((float)(e * inv_delta));
+    f[13] = clamp4((float)((rc - xr) * inv_delta));
+}
+
+template <typename T>
+__device__ __forceinline__ void store_features(const StepArgs &a, const PairDesc<T> &P, int l, bool valid, int ul,
+                                               int vl, T e, T xr, T n0, T n1, T n2, float *out)
+{
+    float f[14];
+    compute_features<T>(a, P, l, valid, ul, vl, e, xr, n0, n1, n2, f);
+#pragma unroll
+    for (int k = 0; k < 14; ++k)
+        out[k] = f[k];
+}
+
+// Learned weight sigmoid(z) of this lane's correspondence; all lanes of the
+// wave must call it (lanes without a correspondence pass valid = false).
+// dump (nullable) receives the features of pixel dump_index (>= 0).
+template <typename T>
+__device__ __forceinline__ T learned_weight(const StepArgs &a, const MlpFrag &F, const PairDesc<T> &P, int l,
+                                            bool valid, int ul, int vl, T e, T xr, T n0, T n1, T n2, float *dump,
+                                            int dump_index)
+{
+    __shared__ uint32_t s_stage[4][64 * 8];
+    float f[14];
+    compute_features<T>(a, P, l, valid, ul, vl, e, xr, n0, n1, n2, f);
+    if (dump && dump_index >= 0)
+        for (int k = 0; k < 14; ++k)
+            dump[14 * (size_t)dump_index + k] = f[k];
+    uint32_t fp[8];
+    pack_features(f, fp);
+    const float z = mlp_wave(F, fp, s_stage[threadIdx.x >> 6]);
+    return (T)(1.f / (1.f + __expf(-z)));
+}
+
+}  // namespace rir

@@ -1,0 +1,53 @@
+"""Helpers shared by the GPU parity tests: device transfer, the library
+handles of a synthetic pair, and the ambiguity band of pose-dependent indices.
+
+Indices computed in FP32 on the GPU and in FP64 by the oracle can differ only
+where the continuous quantity they round lies next to a rounding boundary.
+A pixel is ambiguous when its FP64 column coordinate is within BAND_U pixels
+of a half-integer, or its FP64 elevation is within BAND_PHI row spacings of
+a level midpoint or of a field-of-view edge.  Outside the band indices and
+masks must agree bit for bit; inside it either neighbour is accepted.
+"""
+import numpy as np
+
+BAND_U = 2e-3     # pixels
+BAND_PHI = 1e-3   # fraction of the local row spacing
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def level_midpoints(phi_lut, level):
+    s = 1 << level
+    p = phi_lut[::s]
+    return 0.5 * (p[:-1] + p[1:]), np.abs(np.diff(p))
+
+
+def ambiguous(sensor, level, uhat, phi):
+    """Boolean mask of pixels whose rounding is ambiguous (see module doc)."""
+    uhat = np.asarray(uhat, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    frac = uhat - np.floor(uhat)
+    amb = np.abs(frac - 0.5) < BAND_U
+    mids, gaps = level_midpoints(sensor.phi, level)
+    if mids.size:
+        d = np.abs(phi[..., None] - mids)
+        k = np.argmin(d, axis=-1)
+        amb |= d.min(axis=-1) < BAND_PHI * gaps[k]
+    p = sensor.phi
+    hi = p[0] + 0.5 * (p[0] - p[1])
+    lo = p[-1] - 0.5 * (p[-2] - p[-1])
+    edge_gap = min(p[0] - p[1], p[-2] - p[-1])
+    amb |= (np.abs(phi - hi) < BAND_PHI * edge_gap) | (np.abs(phi - lo) < BAND_PHI * edge_gap)
+    return amb
+
+
+def rot_trans_error(T, Tref):
+    """Rotation angle (rad, via the skew part, accurate near zero) and
+    translation distance between two 4x4 poses."""
+    R = T[:3, :3] @ Tref[:3, :3].T
+    s = np.linalg.norm([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]]) / 2
+    c = (np.trace(R) - 1) / 2
+    return float(np.arctan2(s, c)), float(np.linalg.norm(T[:3, 3] - Tref[:3, 3]))

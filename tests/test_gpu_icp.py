@@ -1,0 +1,236 @@
+"""GPU parity of the registration path (Sec. 4.1, Eq. (5)-(7)) against the
+FP64 oracle: per-pixel association, residuals, Jacobians and weights at a
+shared pose; the reduced normal equations; full multi-scale poses; batching,
+graphs, determinism and failure statuses."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import ambiguous, rot_trans_error, to_dev
+
+pytestmark = pytest.mark.gpu
+
+POSE_ROT_TOL = 1e-4   # rad
+POSE_TRANS_TOL = 1e-3  # m
+JTJ_TOL = 1e-5        # |dH_ij| <= JTJ_TOL * sqrt(H_ii H_jj)
+
+
+@pytest.fixture(scope="module")
+def rir():
+    import torch
+    import paper_2112_02779_amd as rir
+    assert torch.cuda.is_available()
+    return rir
+
+
+@pytest.fixture(scope="module")
+def ctx(rir):
+    c = rir.Context(0)
+    c.set_tuning(256, 8, 0, 1)
+    return c
+
+
+def _pair(cfg="pair64", seed=0, shape=None, sensor=None):
+    return synth.gen_pair(synth.CONFIGS[cfg], seed, shape=shape, sensor=sensor)
+
+
+def _jtj_matrix(upper):
+    H = np.zeros((6, 6))
+    iu = np.triu_indices(6)
+    H[iu] = upper
+    H.T[iu] = upper
+    return H
+
+
+def _normalised_diff(Ha, Hb):
+    d = np.sqrt(np.outer(np.diag(Hb), np.diag(Hb)))
+    return np.max(np.abs(Ha - Hb) / d)
+
+
+@pytest.mark.parametrize("case", [("pair64", 0, (64, 1024), "uniform"), ("pair64", 1, (32, 512), "staggered"),
+                                  ("dynamic64", 2, (64, 1024), "uniform")])
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_association_terms_match_oracle(rir, ctx, case, level):
+    cfg, seed, shape, kind = case
+    sm = synth.uniform_sensor(*shape) if kind == "uniform" else synth.staggered_sensor(*shape, r0=0.015)
+    pair = _pair(cfg, seed, shape, sm)
+    sen = rir.Sensor.from_model(sm)
+    T = pair.gt @ synth.make_pose(synth.rot_axis_angle([0.3, 1.0, 0.2], 0.01), [0.05, -0.03, 0.02])
+    prm = rir.make_params(levels=3, iters=[1, 1, 1], delta=0.5)
+    out = rir.debug_associate(ctx, prm, sen, to_dev(pair.src), to_dev(pair.dst), level, T)
+    ref = oracle.system(sm, level, pair.src, pair.dst, oracle.make_params(levels=3, iters=[1, 1, 1], delta=0.5), T)
+    g = {k: out[k].cpu().numpy() for k in ("u", "v", "mask", "e", "w", "J")}
+    g["mask"] = g["mask"].astype(bool)
+    amb = ambiguous(sm, level, ref["uhat"], ref["phi"]) & (ref["proj_valid"] | (g["u"] >= 0))
+    clear = ~amb
+    # indices and masks bit-exact outside the band
+    np.testing.assert_array_equal(g["u"][clear], ref["u"][clear])
+    np.testing.assert_array_equal(g["v"][clear], ref["v"][clear])
+    np.testing.assert_array_equal(g["mask"][clear], ref["mask"][clear])
+    assert amb.mean() < 0.01
+    m = clear & ref["mask"]
+    assert m.sum() > 100
+    np.testing.assert_allclose(g["e"][m], ref["e"][m], atol=2e-5)
+    np.testing.assert_allclose(g["w"][m], ref["w"][m], atol=1e-6)
+    jscale = np.maximum(1.0, np.abs(ref["J"][m]))
+    assert np.max(np.abs(g["J"][m] - ref["J"][m]) / jscale) < 2e-5
+    # normal equations over the common pixels: GPU terms vs oracle terms
+    def sums(J, w, e, mm):
+        Jm, wm, em = J[mm].astype(np.float64), w[mm].astype(np.float64), e[mm].astype(np.float64)
+        return (Jm * wm[:, None]).T @ Jm, (Jm * wm[:, None]).T @ em
+    Hg, gg = sums(g["J"], g["w"], g["e"], m)
+    Ho, go = sums(ref["J"], ref["w"], ref["e"], m)
+    assert _normalised_diff(Hg, Ho) < JTJ_TOL
+    # the kernel's own FP32 reduction against an FP64 sum of its per-pixel terms
+    Hall, gall = sums(g["J"], g["w"], g["e"], g["mask"])
+    Hk = _jtj_matrix(out["stats"]["JtJ"])
+    assert _normalised_diff(Hk, Hall) < JTJ_TOL
+    assert np.max(np.abs(out["stats"]["Jtr"] - gall)) <= 1e-5 * np.sqrt(np.max(np.diag(Hall)) * np.sum(
+        g["w"][g["mask"]] * g["e"][g["mask"]] ** 2)) + 1e-9
+    assert out["stats"]["n_valid"] == int(g["mask"].sum())
+    st = ref["stats"]
+    assert abs(out["stats"]["n_valid"] - st["n_valid"]) <= amb.sum()
+    # whole-image normal equations: differences come only from band pixels
+    Hr = _jtj_matrix(st["JtJ"])
+    assert _normalised_diff(Hk, Hr) < JTJ_TOL + 4.0 * amb.sum() / max(st["n_valid"], 1)
+
+
+def _run_gpu(rir, ctx, sm, pairs, iters, levels, **kw):
+    sen = rir.Sensor.from_model(sm)
+    prm = rir.make_params(levels=levels, iters=iters, delta=0.5, **kw)
+    batch = [(sen, to_dev(p.src), to_dev(p.dst)) for p in pairs]
+    poses, stats = rir.icp_batch(ctx, prm, batch)
+    return poses.cpu().numpy(), rir.stats_to_numpy(stats, len(pairs), levels)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_multiscale_pose_matches_oracle_pair64(rir, ctx, seed):
+    """64x1024 pairs, 3 levels x 10 iterations (FP32 per-pixel math, FP64 solve)."""
+    pair = _pair("pair64", seed)
+    Tg, st = _run_gpu(rir, ctx, pair.sensor, [pair], [10, 10, 10], 3)
+    To, so = oracle.icp(pair.sensor, pair.src, pair.dst, oracle.make_params(levels=3, iters=[10, 10, 10]))
+    er, et = rot_trans_error(Tg[0], To)
+    assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (er, et)
+    for l in range(3):
+        assert st[0, l]["status"] == so[l]["status"] == 0
+        assert st[0, l]["iters_run"] == so[l]["iters_run"] == 10
+        assert abs(st[0, l]["n_valid"] - so[l]["n_valid"]) <= 0.002 * so[l]["n_valid"] + 5
+
+
+def test_multiscale_pose_matches_oracle_general_sensor(rir, ctx):
+    """Non-uniform elevation table, staggered azimuth offsets and r0 > 0."""
+    sm = synth.staggered_sensor(64, 1024, r0=0.015)
+    pair = _pair("pair64", 7, sensor=sm)
+    Tg, st = _run_gpu(rir, ctx, sm, [pair], [10, 10, 10], 3)
+    To, so = oracle.icp(sm, pair.src, pair.dst, oracle.make_params(levels=3, iters=[10, 10, 10]))
+    er, et = rot_trans_error(Tg[0], To)
+    assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (er, et)
+
+
+def test_fp64_mode_matches_oracle_tightly(rir, ctx):
+    pair = _pair("pair64", 4)
+    Tg, _ = _run_gpu(rir, ctx, pair.sensor, [pair], [10, 10, 10], 3, precision=rir.PREC_FP64)
+    To, _ = oracle.icp(pair.sensor, pair.src, pair.dst, oracle.make_params(levels=3, iters=[10, 10, 10]))
+    er, et = rot_trans_error(Tg[0], To)
+    assert er < 1e-6 and et < 1e-5, (er, et)
+
+
+def test_self_registration_is_identity(rir, ctx):
+    pair = _pair("pair64", 5)
+    same = synth.Pair(pair.sensor, pair.dst, pair.dst, np.eye(4), 5)
+    Tg, st = _run_gpu(rir, ctx, pair.sensor, [same], [3, 3, 3], 3)
+    np.testing.assert_array_equal(Tg[0], np.eye(4))
+    assert np.all(st["sum_w_e2"] == 0.0)
+
+
+def test_run_twice_is_bitwise_identical_and_graph_equals_eager(rir, ctx):
+    pairs = [_pair("pair64", s) for s in range(3)]
+    T1, s1 = _run_gpu(rir, ctx, pairs[0].sensor, pairs, [4, 4, 4], 3)
+    T2, s2 = _run_gpu(rir, ctx, pairs[0].sensor, pairs, [4, 4, 4], 3)
+    T3, s3 = _run_gpu(rir, ctx, pairs[0].sensor, pairs, [4, 4, 4], 3, use_graph=False)
+    assert np.array_equal(T1, T2) and np.array_equal(T1, T3)
+    assert s1.tobytes() == s2.tobytes() == s3.tobytes()
+
+
+def test_pair_alone_equals_pair_in_mixed_batch(rir, ctx):
+    """Tiles never straddle pairs, so a pair's result does not depend on the
+    batch it is solved in (fixed tuning)."""
+    shapes = [(16, 1024), (32, 1024), (64, 1024), (128, 2048)]
+    pairs = [_pair("batch256mixed", 2000 + i, shape=shapes[i % 4]) for i in range(8)]
+    sensors = {}
+    batch = []
+    for p in pairs:
+        key = (p.sensor.H, p.sensor.W)
+        if key not in sensors:
+            sensors[key] = rir.Sensor.from_model(p.sensor)
+        batch.append((sensors[key], to_dev(p.src), to_dev(p.dst)))
+    prm = rir.make_params(levels=3, iters=[5, 5, 5], delta=0.5)
+    Tb, sb = rir.icp_batch(ctx, prm, batch)
+    Tb = Tb.cpu().numpy()
+    for i in (0, 3, 5):
+        Ti, si = rir.icp_batch(ctx, prm, [batch[i]])
+        assert np.array_equal(Ti.cpu().numpy()[0], Tb[i])
+    # and each pair of the batch agrees with the oracle
+    for i, p in enumerate(pairs[:4]):
+        To, _ = oracle.icp(p.sensor, p.src, p.dst, oracle.make_params(levels=3, iters=[5, 5, 5]))
+        er, et = rot_trans_error(Tb[i], To)
+        assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (i, er, et)
+
+
+def test_degenerate_and_empty_inputs(rir, ctx):
+    """An empty source and a ground-only scene give status DEGENERATE with the
+    pose unchanged, as in the oracle; a tiny ragged image still runs."""
+    import torch
+    pair = _pair("pair64", 6)
+    sen = rir.Sensor.from_model(pair.sensor)
+    prm = rir.make_params(levels=3, iters=[2, 2, 2])
+    T0 = torch.tensor(synth.make_pose(np.eye(3), [0.1, 0, 0])[None], dtype=torch.float64, device="cuda:0")
+    poses, stats = rir.icp_batch(ctx, prm, [(sen, to_dev(np.zeros_like(pair.src)), to_dev(pair.dst))], init_poses=T0)
+    st = rir.stats_to_numpy(stats, 1, 3)
+    np.testing.assert_array_equal(poses.cpu().numpy(), T0.cpu().numpy())
+    assert np.all(st["status"] == rir.LEVEL_DEGENERATE) and np.all(st["n_valid"] == 0)
+    sm = synth.uniform_sensor(32, 256, 0.0, -30.0)
+    scene = synth.Scene(np.array([[0, 0, 1.0, 0]]))
+    a = synth.scan(sm, scene, synth.make_pose(np.eye(3), [0, 0, 1.8]), synth.ScanNoise(), np.random.default_rng(0))
+    sen2 = rir.Sensor.from_model(sm)
+    poses, stats = rir.icp_batch(ctx, prm, [(sen2, to_dev(a["range"]), to_dev(a["range"]))])
+    np.testing.assert_array_equal(poses.cpu().numpy()[0], np.eye(4))
+    assert np.all(rir.stats_to_numpy(stats, 1, 3)["status"] == rir.LEVEL_DEGENERATE)
+    # smallest shapes: 4 x 8 image, one level
+    sm3 = synth.uniform_sensor(4, 8)
+    img = np.full((4, 8), 5.0, np.float32)
+    sen3 = rir.Sensor.from_model(sm3)
+    poses, stats = rir.icp_batch(ctx, rir.make_params(levels=1, iters=[1]), [(sen3, to_dev(img), to_dev(img))])
+    assert rir.stats_to_numpy(stats, 1, 1)["status"][0, 0] in (rir.LEVEL_OK, rir.LEVEL_DEGENERATE)
+
+
+def test_host_side_errors(rir, ctx):
+    pair = _pair("pair64", 0, shape=(30, 512), sensor=synth.uniform_sensor(30, 512))
+    sen = rir.Sensor.from_model(pair.sensor)
+    with pytest.raises(rir.RirError) as ei:
+        rir.icp_batch(ctx, rir.make_params(levels=3), [(sen, to_dev(pair.src), to_dev(pair.dst))])
+    assert ei.value.status == rir.RIR_E_SHAPE
+    with pytest.raises(rir.RirError) as ei:
+        rir.icp_batch(ctx, rir.make_params(levels=1, delta=-1.0), [(sen, to_dev(pair.src), to_dev(pair.dst))])
+    assert ei.value.status == rir.RIR_E_INVALID
+
+
+def test_centroid_initialisation(rir, ctx):
+    pair = _pair("pair64", 8)
+    Tg, _ = _run_gpu(rir, ctx, pair.sensor, [pair], [0], 1, init_mode=1)
+    To, _ = oracle.icp(pair.sensor, pair.src, pair.dst, oracle.make_params(levels=1, iters=[0], init_mode=1))
+    np.testing.assert_allclose(Tg[0], To, atol=2e-5)
+
+
+def test_full_size_odometry_pairs_match_oracle(rir, ctx):
+    """The 128x2048, 4-level workload at full size: a few pairs of the
+    odometry sequence (batched) against the oracle."""
+    seq = synth.gen_sequence(synth.CONFIGS["odometry128x2048"], 1000, n_scans=4)
+    sm = seq["sensor"]
+    Tg, st = _run_gpu(rir, ctx, sm, seq["pairs"], [10, 10, 10, 10], 4)
+    prm = oracle.make_params(levels=4, iters=[10, 10, 10, 10], r_max=120.0)
+    for i, p in enumerate(seq["pairs"]):
+        To, so = oracle.icp(sm, p.src, p.dst, prm)
+        er, et = rot_trans_error(Tg[i], To)
+        assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (i, er, et)
