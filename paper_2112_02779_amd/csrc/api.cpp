@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <limits>
 #include <type_traits>
 #include <cmath>
@@ -21,6 +22,11 @@ using namespace rir;
 namespace {
 
 thread_local std::string g_err;
+
+// Identity of sensors and networks inside cached plans.  Ids are never reused,
+// so a plan built for an object that has since been destroyed can never be
+// matched by a new object that happens to get the same address.
+std::atomic<uint64_t> g_next_uid{1};
 
 rir_status fail(rir_status s, const std::string &msg)
 {
@@ -55,6 +61,7 @@ struct Layout {
 // ============================================================================ sensor
 
 struct rir_sensor {
+    uint64_t uid = g_next_uid.fetch_add(1);
     int device = 0;
     int H = 0, W = 0, nlev = 0;
     double r0 = 0.0;
@@ -287,6 +294,7 @@ extern "C" void rir_sensor_destroy(rir_sensor *sensor) { delete sensor; }
 // ============================================================================ learned-weight network
 
 struct rir_mlp {
+    uint64_t uid = g_next_uid.fetch_add(1);
     int device = 0;
     void *dmem = nullptr;
     uint16_t *w = nullptr;   // bf16 weights [kMlpNW]
@@ -314,12 +322,12 @@ namespace {
 struct KeyPod {
     int levels, iters[kMaxLevels], init_mode, weight_mode, precision, use_graph, debug;
     double delta, edge_rel, max_corr, r_max;
-    const rir_mlp *mlp;
+    uint64_t mlp;
     rir_tuning tune;
 };
 
 struct PlanKey {
-    std::vector<const rir_sensor *> sensors;
+    std::vector<uint64_t> sensors;
     KeyPod k;
     bool operator<(const PlanKey &o) const
     {
@@ -331,6 +339,8 @@ struct PlanKey {
 
 struct Plan {
     PlanKey key;
+    uint64_t last_use = 0;
+    std::vector<int> shapes;  // H, W per pair (checked on every reuse)
     int device = 0;
     int n_pairs = 0;
     bool fp64 = false;
@@ -379,6 +389,7 @@ struct rir_ctx {
     hipStream_t cap = nullptr;  // private stream used only for graph capture
     rir_tuning tune{256, 8, 0, 1};
     std::map<PlanKey, std::unique_ptr<Plan>> plans;
+    uint64_t use_clock = 0;
     bool timing = false;
     int timing_levels = 0;
     hipEvent_t ev[2 * (kMaxLevels + 1)] = {};
@@ -439,7 +450,8 @@ extern "C" rir_status rir_ctx_set_tuning(rir_ctx *ctx, const rir_tuning *tuning)
         return st;
     if (std::memcmp(&ctx->tune, tuning, sizeof(rir_tuning)) != 0) {
         ctx->tune = *tuning;
-        hipSetDevice(ctx->device);
+        HIP_TRY(hipSetDevice(ctx->device));
+        HIP_TRY(hipDeviceSynchronize());  // captured graphs of the old plans may still run
         ctx->plans.clear();
     }
     return RIR_OK;
@@ -656,7 +668,7 @@ rir_status get_plan(rir_ctx *ctx, const rir_icp_params *p, const rir_pair *pairs
     PlanKey key;
     std::memset(&key.k, 0, sizeof(KeyPod));
     for (int i = 0; i < n; ++i)
-        key.sensors.push_back(pairs[i].sensor);
+        key.sensors.push_back(pairs[i].sensor->uid);
     KeyPod &k = key.k;
     k.levels = p->levels;
     for (int l = 0; l < kMaxLevels; ++l)
@@ -670,17 +682,40 @@ rir_status get_plan(rir_ctx *ctx, const rir_icp_params *p, const rir_pair *pairs
     k.edge_rel = p->edge_rel;
     k.max_corr = p->max_corr_dist;
     k.r_max = p->weight_mode == RIR_WEIGHT_LEARNED ? p->r_max : 0.0;
-    k.mlp = p->weight_mode == RIR_WEIGHT_LEARNED ? p->mlp : nullptr;
+    k.mlp = p->weight_mode == RIR_WEIGHT_LEARNED ? p->mlp->uid : 0;
     k.tune = ctx->tune;
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) {
-        out = it->second.get();
+        Plan *P = it->second.get();
+        for (int i = 0; i < n; ++i)
+            if (P->shapes[2 * i] != pairs[i].sensor->H || P->shapes[2 * i + 1] != pairs[i].sensor->W)
+                return fail(RIR_E_SHAPE, "internal: cached plan does not match the batch shape");
+        P->last_use = ++ctx->use_clock;
+        out = P;
         return RIR_OK;
+    }
+    // keep at most kMaxPlans plans: evict the least recently used (plans of
+    // destroyed sensors are never used again and age out this way)
+    constexpr size_t kMaxPlans = 8;
+    if (ctx->plans.size() >= kMaxPlans) {
+        HIP_TRY(hipDeviceSynchronize());
+        while (ctx->plans.size() >= kMaxPlans) {
+            auto victim = ctx->plans.begin();
+            for (auto jt = ctx->plans.begin(); jt != ctx->plans.end(); ++jt)
+                if (jt->second->last_use < victim->second->last_use)
+                    victim = jt;
+            ctx->plans.erase(victim);
+        }
     }
     Plan *P = nullptr;
     rir_status st = make_plan(ctx, key, pairs, n, P);
     if (st != RIR_OK)
         return st;
+    for (int i = 0; i < n; ++i) {
+        P->shapes.push_back(pairs[i].sensor->H);
+        P->shapes.push_back(pairs[i].sensor->W);
+    }
+    P->last_use = ++ctx->use_clock;
     ctx->plans[key].reset(P);
     out = P;
     return RIR_OK;

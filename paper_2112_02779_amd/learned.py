@@ -1,0 +1,217 @@
+"""Learned per-pixel robust weight: training data, training and evaluation.
+
+Everything here runs on the GPU through librir (the same kernels as
+registration); nothing calls the test oracle.
+
+Labels (a reading of "labels from the converged residuals"): each pair is
+first registered from its ground-truth pose with pseudo-Huber weights; at
+that converged pose a source pixel whose correspondence has |e*| <= 3 sigma
+(sigma = the scans' range noise) is labelled 1 (reliable), otherwise 0
+(moving objects, spurious returns, occlusion edges).  Labels therefore do not
+depend on the current pose.  Features are taken where the network will see
+them: at the poses a plain pseudo-Huber registration from the initial pose
+passes through (start, after each coarse level, end) and at every pyramid
+level.
+
+CLI:  python -m paper_2112_02779_amd.learned train  [--pairs N] [--out FILE]
+      python -m paper_2112_02779_amd.learned eval   [--pairs N] [--weights FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(_HERE, "weights", "robust_mlp_dynamic64.npz")
+
+
+def _rir():
+    import paper_2112_02779_amd as rir
+    return rir
+
+
+def _log(msg):
+    print(f"[learned] {msg}", file=sys.stderr, flush=True)
+
+
+class DeviceBatch:
+    """Pairs uploaded to the GPU with one sensor handle per distinct model."""
+
+    def __init__(self, pairs, device="cuda:0"):
+        import torch
+        rir = _rir()
+        self.pairs = pairs
+        self.sensors = {}
+        self.items = []
+        for p in pairs:
+            key = (p.sensor.H, p.sensor.W, p.sensor.r0, p.sensor.phi.tobytes(), p.sensor.theta.tobytes())
+            if key not in self.sensors:
+                self.sensors[key] = rir.Sensor.from_model(p.sensor)
+            self.items.append((self.sensors[key], torch.from_numpy(p.src).to(device),
+                               torch.from_numpy(p.dst).to(device)))
+
+    def __len__(self):
+        return len(self.items)
+
+
+def register(ctx, batch: DeviceBatch, levels, iters, init=None, mlp=None, delta=0.5, r_max=80.0, chunk=256):
+    """Batched registration; returns host poses [n, 4, 4] and stats [n, levels]."""
+    import torch
+    rir = _rir()
+    prm = rir.make_params(levels=levels, iters=iters, delta=delta, r_max=r_max,
+                          weight_mode=rir.WEIGHT_LEARNED if mlp is not None else rir.WEIGHT_HUBER, mlp=mlp)
+    n = len(batch)
+    poses = np.zeros((n, 4, 4))
+    stats = []
+    for a in range(0, n, chunk):
+        items = batch.items[a:a + chunk]
+        T0 = None
+        if init is not None:
+            T0 = torch.from_numpy(np.ascontiguousarray(init[a:a + chunk])).to("cuda:0")
+        P, S = rir.icp_batch(ctx, prm, items, init_poses=T0)
+        poses[a:a + len(items)] = P.cpu().numpy()
+        stats.append(rir.stats_to_numpy(S, len(items), levels))
+    return poses, np.concatenate(stats)
+
+
+def make_samples(ctx, batch: DeviceBatch, sigma: float, levels=3, iters=(10, 10, 10), delta=0.5, r_max=80.0,
+                 per_view=2048, seed=0):
+    """(features [M, 14] float32, labels [M] float32) for the pairs of `batch`."""
+    rir = _rir()
+    rng = np.random.default_rng(seed)
+    n = len(batch)
+    gts = np.stack([p.gt for p in batch.pairs])
+    T_conv, _ = register(ctx, batch, levels, list(iters), init=gts, delta=delta)
+    # poses along the plain trajectory from the identity
+    views = [np.tile(np.eye(4), (n, 1, 1))]
+    for stop in range(levels - 1, 0, -1):
+        sched = [0 if l < stop else iters[l] for l in range(levels)]
+        views.append(register(ctx, batch, levels, sched, delta=delta)[0])
+    views.append(register(ctx, batch, levels, list(iters), delta=delta)[0])
+    prm = rir.make_params(levels=levels, iters=list(iters), delta=delta, r_max=r_max)
+    feats, labels = [], []
+    for i, (sensor, src, dst) in enumerate(batch.items):
+        d0 = rir.debug_associate(ctx, prm, sensor, src, dst, 0, T_conv[i])
+        m0 = d0["mask"].cpu().numpy().astype(bool)
+        y0 = (np.abs(d0["e"].cpu().numpy()) <= 3.0 * sigma) & m0
+        for V in views:
+            for lvl in range(levels):
+                s = 1 << lvl
+                d = rir.debug_associate(ctx, prm, sensor, src, dst, lvl, V[i], features=True)
+                m = d["mask"].cpu().numpy().astype(bool)
+                lab_ok = m & m0[::s, ::s]
+                idx = np.flatnonzero(lab_ok)
+                if idx.size == 0:
+                    continue
+                if idx.size > per_view:
+                    idx = rng.choice(idx, per_view, replace=False)
+                f = d["feat"].cpu().numpy().reshape(-1, 14)[idx]
+                y = y0[::s, ::s].reshape(-1)[idx]
+                feats.append(f)
+                labels.append(y.astype(np.float32))
+    return np.concatenate(feats), np.concatenate(labels)
+
+
+def train(mlp, feats, labels, steps=3000, batch=8192, lr=2e-3, seed=0, log_every=500):
+    """Adam on minibatches drawn with replacement; returns the loss history."""
+    import torch
+    rng = np.random.default_rng(seed)
+    F = torch.from_numpy(np.ascontiguousarray(feats, dtype=np.float32)).to("cuda:0")
+    Y = torch.from_numpy(np.ascontiguousarray(labels, dtype=np.float32)).to("cuda:0")
+    hist = []
+    for k in range(steps):
+        idx = torch.from_numpy(rng.integers(0, F.shape[0], size=batch)).to("cuda:0")
+        cur_lr = lr * (0.1 ** (k / max(steps, 1)))
+        loss, _ = mlp.train_step(F[idx].contiguous(), Y[idx].contiguous(), cur_lr)
+        if k % log_every == 0 or k == steps - 1:
+            hist.append((k, float(loss.cpu())))
+            _log(f"step {k} loss {hist[-1][1]:.4f}")
+    return hist
+
+
+def pose_errors(poses, refs):
+    out = []
+    for T, R in zip(poses, refs):
+        D = T[:3, :3] @ R[:3, :3].T
+        s = np.linalg.norm([D[2, 1] - D[1, 2], D[0, 2] - D[2, 0], D[1, 0] - D[0, 1]]) / 2
+        out.append((float(np.arctan2(s, (np.trace(D) - 1) / 2)), float(np.linalg.norm(T[:3, 3] - R[:3, 3]))))
+    return np.array(out)
+
+
+def summarize(err, rot_ok=np.deg2rad(0.25), trans_ok=0.05):
+    return {"median_rot_rad": float(np.median(err[:, 0])), "median_trans_m": float(np.median(err[:, 1])),
+            "p90_rot_rad": float(np.percentile(err[:, 0], 90)), "p90_trans_m": float(np.percentile(err[:, 1], 90)),
+            "success_rate": float(np.mean((err[:, 0] <= rot_ok) & (err[:, 1] <= trans_ok)))}
+
+
+def evaluate(ctx, mlp, batch: DeviceBatch, levels=3, iters=(10, 10, 10), repeats=3):
+    """Learned vs plain pseudo-Huber on the same pairs: pose error against the
+    ground truth and batched throughput (pairs/s) on this GPU."""
+    import torch
+    gts = np.stack([p.gt for p in batch.pairs])
+    res = {}
+    for name, net in (("huber", None), ("learned", mlp)):
+        register(ctx, batch, levels, list(iters), mlp=net)  # warm-up (plans, graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            T, st = register(ctx, batch, levels, list(iters), mlp=net)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / repeats
+        s = summarize(pose_errors(T, gts))
+        s["pairs_per_s"] = len(batch) / dt
+        s["goodput_pairs_per_s"] = s["pairs_per_s"] * s["success_rate"]
+        s["fallback_levels"] = int(np.sum(st["status"] == 2))
+        res[name] = s
+    return res
+
+
+def save(mlp, path=WEIGHTS, meta=None):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, params=mlp.get_params(), meta=json.dumps(meta or {}))
+
+
+def load(path=WEIGHTS) -> np.ndarray:
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"].astype(np.float64)
+
+
+def main(argv=None):
+    import synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("--pairs", type=int, default=1000)
+    ap.add_argument("--eval-pairs", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--weights", default=WEIGHTS)
+    args = ap.parse_args(argv)
+    rir = _rir()
+    cfg = synth.CONFIGS["dynamic64"]
+    ctx = rir.Context(0)
+    if args.cmd == "train":
+        t0 = time.perf_counter()
+        pairs = [synth.gen_pair(cfg, 3000 + i) for i in range(args.pairs)]
+        _log(f"generated {len(pairs)} training pairs in {time.perf_counter() - t0:.1f}s")
+        batch = DeviceBatch(pairs)
+        t0 = time.perf_counter()
+        F, Y = make_samples(ctx, batch, sigma=cfg["noise"].sigma)
+        _log(f"{len(Y)} samples ({Y.mean():.3f} positive) in {time.perf_counter() - t0:.1f}s")
+        mlp = rir.Mlp(rir.init_mlp_params(0))
+        hist = train(mlp, F, Y, steps=args.steps)
+        save(mlp, args.out, {"train_pairs": args.pairs, "samples": int(len(Y)), "loss": hist})
+        _log(f"saved {args.out}")
+    params = load(args.out if args.cmd == "train" else args.weights)
+    mlp = rir.Mlp(params)
+    pairs = [synth.gen_pair(cfg, 13000 + i) for i in range(args.eval_pairs)]
+    res = evaluate(ctx, mlp, DeviceBatch(pairs))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

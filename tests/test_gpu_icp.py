@@ -71,8 +71,10 @@ def test_association_terms_match_oracle(rir, ctx, case, level):
     assert amb.mean() < 0.01
     m = clear & ref["mask"]
     assert m.sum() > 100
+    # FP32 points at up to ~40 m carry ~1e-5 m of rounding, so e agrees to
+    # 2e-5 m and w (|dw/de| <= 0.77 / delta) to 4e-5
     np.testing.assert_allclose(g["e"][m], ref["e"][m], atol=2e-5)
-    np.testing.assert_allclose(g["w"][m], ref["w"][m], atol=1e-6)
+    np.testing.assert_allclose(g["w"][m], ref["w"][m], atol=4e-5)
     jscale = np.maximum(1.0, np.abs(ref["J"][m]))
     assert np.max(np.abs(g["J"][m] - ref["J"][m]) / jscale) < 2e-5
     # normal equations over the common pixels: GPU terms vs oracle terms
@@ -86,8 +88,10 @@ def test_association_terms_match_oracle(rir, ctx, case, level):
     Hall, gall = sums(g["J"], g["w"], g["e"], g["mask"])
     Hk = _jtj_matrix(out["stats"]["JtJ"])
     assert _normalised_diff(Hk, Hall) < JTJ_TOL
-    assert np.max(np.abs(out["stats"]["Jtr"] - gall)) <= 1e-5 * np.sqrt(np.max(np.diag(Hall)) * np.sum(
-        g["w"][g["mask"]] * g["e"][g["mask"]] ** 2)) + 1e-9
+    # |(J^T W e)_i| <= sqrt(H_ii * sum w e^2) bounds each entry (Cauchy-Schwarz)
+    we2 = float(np.sum(g["w"][g["mask"]].astype(np.float64) * g["e"][g["mask"]].astype(np.float64) ** 2))
+    jtr_scale = np.sqrt(np.diag(Hall) * we2) + 1e-12
+    assert np.max(np.abs(out["stats"]["Jtr"] - gall) / jtr_scale) < JTJ_TOL
     assert out["stats"]["n_valid"] == int(g["mask"].sum())
     st = ref["stats"]
     assert abs(out["stats"]["n_valid"] - st["n_valid"]) <= amb.sum()
@@ -234,3 +238,31 @@ def test_full_size_odometry_pairs_match_oracle(rir, ctx):
         To, so = oracle.icp(sm, p.src, p.dst, prm)
         er, et = rot_trans_error(Tg[i], To)
         assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (i, er, et)
+
+
+def test_plans_never_outlive_their_sensors(rir, ctx):
+    """Regression: cached plans were keyed by the sensor's address, so a new
+    sensor of another shape allocated at a freed sensor's address reused a
+    plan sized for the old shape.  Sensors of different shapes are now
+    created and destroyed in turn through one context; every pass must write
+    exactly its own image's pixels and match a fresh context."""
+    import torch
+    shapes = [(64, 1024), (16, 256), (32, 512), (64, 1024), (16, 256)]
+    prm = rir.make_params(levels=3, iters=[1, 1, 1])
+    fresh = rir.Context(0)
+    fresh.set_tuning(256, 8, 0, 1)
+    for k, shape in enumerate(shapes):
+        sm = synth.uniform_sensor(*shape)
+        pair = _pair("pair64", 40 + k, shape=shape, sensor=sm)
+        sen = rir.Sensor.from_model(sm)
+        src, dst = to_dev(pair.src), to_dev(pair.dst)
+        guard = torch.full((1 << 16,), 7, dtype=torch.int32, device="cuda:0")
+        a = rir.debug_associate(ctx, prm, sen, src, dst, 0, pair.gt)
+        b = rir.debug_associate(fresh, prm, sen, src, dst, 0, pair.gt)
+        assert a["u"].shape == (shape[0], shape[1])
+        assert torch.equal(a["u"], b["u"]) and torch.equal(a["e"], b["e"])
+        assert int((guard != 7).sum()) == 0
+        P1, _ = rir.icp_batch(ctx, prm, [(sen, src, dst)])
+        P2, _ = rir.icp_batch(fresh, prm, [(sen, src, dst)])
+        assert torch.equal(P1, P2)
+        del sen
