@@ -143,13 +143,22 @@ typedef struct {
  *    mod W/s (round half up).
  *  - Validity (the paper skips the boundary check for clarity): r > 0 and the
  *    elevation lies within half a row spacing beyond the end rows of the
- *    finest table.
+ *    finest table.  With r0 > 0 the point must also lie farther than 2 r0
+ *    from the sensor axis: the compensation assumes r0 << r, has no fixed
+ *    point inside the receiver circle, and beyond 2 r0 contracts at least
+ *    twofold per round, so it converges.
  */
 void orc_project(const orc_sensor *s, int level, const double x[3], orc_proj *out)
 {
     int stride = 1 << level;
     int Wl = s->W / stride;
     double xp = x[0], yp = x[1], z = x[2];
+    out->valid = 0;
+    out->u = out->v = -1;
+    out->r = sqrt(xp * xp + yp * yp + z * z);
+    out->uhat = out->phi = out->theta = 0.0;
+    if (s->r0 > 0.0 && !(xp * xp + yp * yp > 4.0 * s->r0 * s->r0))
+        return;
     if (s->r0 > 0.0) {
         double a = atan2_wrapped(x[1], x[0]);
         for (int k = 0; k < 100; ++k) {

@@ -498,3 +498,23 @@ def test_centroid_initialisation(orc):
     xd, vd = orc.unproject_image(p.sensor, p.dst)
     np.testing.assert_allclose(T[:3, :3], np.eye(3))
     np.testing.assert_allclose(T[:3, 3], xd[vd].mean(0) - xs[vs].mean(0), rtol=1e-9, atol=1e-12)
+
+
+def test_points_near_the_axis_do_not_project(orc):
+    """Reading of Sec. 3.2 (r0 << r): with r0 > 0 a point within 2 r0 of the
+    sensor axis does not project (the compensation has no fixed point inside
+    the receiver circle); just beyond it the round trip is still exact."""
+    sen = synth.staggered_sensor(32, 512, r0=0.05)
+    r0 = sen.r0
+    pts = np.array([[0, 0, 0], [r0, 0, 0], [1.5 * r0, 0.5 * r0, 0.0], [0, 1.99 * r0, 0.0]])
+    assert not orc.project_points(sen, 0, pts)["valid"].any()
+    # pixels whose points lie just beyond 2 r0: smallest range for the middle rows
+    img = np.full((32, 512), 3.1 * r0, np.float32)
+    xyz, _ = orc.unproject_image(sen, img)
+    rho = np.hypot(xyz[..., 0], xyz[..., 1])
+    ok = rho > 2 * r0
+    pr = orc.project_points(sen, 0, xyz.reshape(-1, 3))
+    vv, uu = np.meshgrid(np.arange(32), np.arange(512), indexing="ij")
+    np.testing.assert_array_equal(pr["valid"], ok.ravel())
+    np.testing.assert_array_equal(pr["u"][ok.ravel()], uu[ok])
+    np.testing.assert_array_equal(pr["v"][ok.ravel()], vv[ok])
