@@ -66,8 +66,12 @@ def main():
     ap.add_argument("--scans", type=int, default=100)
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="block,px_per_thread,grid_mult,xcd_remap,chunk to use instead of autotuning")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (value then unchecked)")
     ap.add_argument("--sample-every", type=int, default=3)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the batch of independent pairs would be split across GPUs "
@@ -89,6 +93,14 @@ def main():
     log(f"generated {n} pairs of {sm.H}x{sm.W} in {time.perf_counter() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x 1 GiB device copies done")
+        del a, b
     scans = [torch.from_numpy(s).to(dev) for s in seq["scans"]]
     sensor = rir.Sensor.from_model(sm)
     ctx = rir.Context(0)
@@ -100,7 +112,10 @@ def main():
     torch.cuda.synchronize()
 
     tuning, tune_ms = None, None
-    if not args.no_autotune:
+    if args.tuning:
+        b, ppt, gm, xcd, ch = (int(x) for x in args.tuning.split(","))
+        ctx.set_tuning(b, ppt, gm, xcd, ch)
+    elif not args.no_autotune:
         t1 = time.perf_counter()
         tuning, tune_ms = rir.autotune(ctx, params, batch, init)
         torch.cuda.synchronize()
@@ -128,14 +143,14 @@ def main():
 
     # dominant kernel: the level-0 Gauss-Newton launch (association + reduction + solve)
     n0 = sm.H * sm.W
-    tile_px = tuning["block"] * tuning["px_per_thread"]
+    tile_px = tuning["block"] * tuning["px_per_thread"]  # finest level
     tiles0 = n * ((n0 + tile_px - 1) // tile_px)
     bytes_l0 = 4.0 * n0 * n + 16.0 * float(st["n_proj"][:, 0].sum()) + 144.0 * tiles0
     l0_launch_ms = level_ms[0] / iters[0]
     achieved = bytes_l0 / (l0_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_icp_step<float,0> at level 0", "bytes_per_launch": bytes_l0,
+                "kernel": "rir::k_icp_step<float, 0, true> (finest level)", "bytes_per_launch": bytes_l0,
                 "launch_ms": round(l0_launch_ms, 5)}
 
     cpu = None

@@ -140,11 +140,13 @@ typedef struct {
 
 /* Tuning of the association/reduction launch (picked by rir_autotune).
  * block: threads per workgroup (64, 128 or 256); px_per_thread: pixels each
- * thread visits per tile (1..16); grid_mult: persistent workgroups per
- * compute unit (0 = one workgroup per tile); xcd_remap: 1 maps consecutive
- * tiles to the same XCD (L2) of the chip. */
+ * thread visits per finest-level tile (1..16; level l uses px_per_thread /
+ * 4^l, at least 1); grid_mult: persistent workgroups per compute unit (0 =
+ * one workgroup per tile); xcd_remap: 1 maps consecutive tiles to the same
+ * XCD (L2) of the chip; chunk: pixels whose loads each thread keeps in
+ * flight together (1, 2 or 4). */
 typedef struct {
-    int32_t block, px_per_thread, grid_mult, xcd_remap;
+    int32_t block, px_per_thread, grid_mult, xcd_remap, chunk;
 } rir_tuning;
 
 /* ---------------------------------------------------------------- sensors */

@@ -344,7 +344,7 @@ struct Plan {
     int device = 0;
     int n_pairs = 0;
     bool fp64 = false;
-    int tile_px = 0, block = 0;
+    int tile_px[kMaxLevels] = {}, block = 0;
     int n_tiles[kMaxLevels] = {};
     int grid[kMaxLevels] = {};
     void *dmem = nullptr;
@@ -354,7 +354,6 @@ struct Plan {
     int2 *d_tiles[kMaxLevels] = {};
     void *d_psum = nullptr;
     int4 *d_pcnt = nullptr;
-    int *d_counters = nullptr;
     double *d_poses = nullptr;
     rir_level_stats *d_stats = nullptr;
     int *d_flags = nullptr;
@@ -387,7 +386,7 @@ struct rir_ctx {
     int device = 0;
     int n_cu = 256;
     hipStream_t cap = nullptr;  // private stream used only for graph capture
-    rir_tuning tune{256, 8, 0, 1};
+    rir_tuning tune{256, 8, 0, 1, 4};
     std::map<PlanKey, std::unique_ptr<Plan>> plans;
     uint64_t use_clock = 0;
     bool timing = false;
@@ -438,6 +437,10 @@ static rir_status check_tuning(const rir_tuning *t)
         return fail(RIR_E_INVALID, "rir_tuning.px_per_thread must be in 1..16");
     if (t->grid_mult < 0 || t->grid_mult > 64)
         return fail(RIR_E_INVALID, "rir_tuning.grid_mult must be in 0..64");
+    if (!(t->chunk == 1 || t->chunk == 2 || t->chunk == 4))
+        return fail(RIR_E_INVALID, "rir_tuning.chunk must be 1, 2 or 4");
+    if (t->xcd_remap != 0 && t->xcd_remap != 1)
+        return fail(RIR_E_INVALID, "rir_tuning.xcd_remap must be 0 or 1");
     return RIR_OK;
 }
 
@@ -560,18 +563,21 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     const size_t tsz = P->fp64 ? sizeof(double) : sizeof(float);
     const int L = key.k.levels;
     P->block = key.k.tune.block;
-    P->tile_px = key.k.tune.block * key.k.tune.px_per_thread;
+    // coarser levels have 4x fewer pixels each: shrink the pixels per thread
+    // with them (down to one) so that they still spread over the whole chip
+    for (int l = 0; l < L; ++l)
+        P->tile_px[l] = key.k.tune.block * std::max(1, key.k.tune.px_per_thread >> (2 * l));
     std::vector<std::vector<int2>> tiles(L);
     std::vector<int> t0(n * kMaxLevels, 0), nt(n * kMaxLevels, 0);
     for (int l = 0; l < L; ++l) {
         for (int i = 0; i < n; ++i) {
             const rir_sensor *s = pairs[i].sensor;
             const int Nl = (s->H >> l) * (s->W >> l);
-            const int k = (Nl + P->tile_px - 1) / P->tile_px;
+            const int k = (Nl + P->tile_px[l] - 1) / P->tile_px[l];
             t0[i * kMaxLevels + l] = (int)tiles[l].size();
             nt[i * kMaxLevels + l] = k;
             for (int j = 0; j < k; ++j)
-                tiles[l].push_back(make_int2(i, j * P->tile_px));
+                tiles[l].push_back(make_int2(i, j * P->tile_px[l]));
         }
         P->n_tiles[l] = (int)tiles[l].size();
         int G = P->n_tiles[l];
@@ -581,7 +587,9 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
             G = (G + 7) / 8 * 8;
         P->grid[l] = std::max(G, 1);
     }
-    const int max_tiles = P->n_tiles[0];
+    int max_tiles = 0;
+    for (int l = 0; l < L; ++l)
+        max_tiles = std::max(max_tiles, P->n_tiles[l]);
     // device layout
     Layout lay;
     P->desc_bytes = n * (P->fp64 ? sizeof(PairDesc<double>) : sizeof(PairDesc<float>));
@@ -591,7 +599,6 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
         o_tiles[l] = lay.add(sizeof(int2) * tiles[l].size());
     size_t o_psum = lay.add((size_t)max_tiles * kAccum * tsz);
     size_t o_pcnt = lay.add((size_t)max_tiles * sizeof(int4));
-    size_t o_cnt = lay.add((size_t)n * sizeof(int));
     size_t o_pose = lay.add((size_t)n * 16 * sizeof(double));
     size_t o_stats = lay.add((size_t)n * L * sizeof(rir_level_stats));
     size_t o_flags = lay.add((size_t)n * kFlagStride * sizeof(int));
@@ -609,7 +616,6 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     }
     HIP_TRY(hipMalloc(&P->dmem, lay.bytes));
     char *base = static_cast<char *>(P->dmem);
-    HIP_TRY(hipMemset(base + o_cnt, 0, (size_t)n * sizeof(int)));
     HIP_TRY(hipMemset(base + o_flags, 0, (size_t)n * kFlagStride * sizeof(int)));
     P->d_desc = base + o_desc;
     for (int l = 0; l < L; ++l) {
@@ -618,7 +624,6 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     }
     P->d_psum = base + o_psum;
     P->d_pcnt = reinterpret_cast<int4 *>(base + o_pcnt);
-    P->d_counters = reinterpret_cast<int *>(base + o_cnt);
     P->d_poses = reinterpret_cast<double *>(base + o_pose);
     P->d_stats = reinterpret_cast<rir_level_stats *>(base + o_stats);
     P->d_flags = reinterpret_cast<int *>(base + o_flags);
@@ -755,12 +760,13 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
     a.level = level;
     a.iter = iter;
     a.levels = P->key.k.levels;
-    a.tile_px = P->tile_px;
+    a.tile_px = P->tile_px[level];
+    a.chunk = P->key.k.tune.chunk;
     a.xcd_remap = P->key.k.tune.xcd_remap;
     a.mode = mode;
+    a.learned = p->weight_mode == RIR_WEIGHT_LEARNED;
     a.psum = P->d_psum;
     a.pcnt = P->d_pcnt;
-    a.counters = P->d_counters;
     a.poses = P->d_poses;
     a.stats = P->d_stats;
     a.flags = P->d_flags;
@@ -781,15 +787,14 @@ rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t s
     a.pairs = P->d_desc;
     a.tiles = P->d_tiles[0];
     a.n_tiles = P->n_tiles[0];
-    a.tile_px = P->tile_px;
+    a.tile_px = P->tile_px[0];
     a.levels = P->key.k.levels;
     a.init_centroid = p->init_mode == 1;
     a.edge_rel = p->edge_rel;
     a.psum = P->d_psum;
-    a.counters = P->d_counters;
     a.poses = P->d_poses;
     a.xcd_remap = P->key.k.tune.xcd_remap;
-    HIP_TRY(launch_prepass(P->fp64, a, P->grid[0], P->block, st));
+    HIP_TRY(launch_prepass(P->fp64, a, P->grid[0], P->block, P->n_pairs, st));
     return RIR_OK;
 }
 
@@ -799,9 +804,11 @@ rir_status enqueue_level(const Plan *P, const rir_icp_params *p, int l, hipStrea
     for (int it = 0; it < P->key.k.iters[l]; ++it) {
         StepArgs a = step_args(P, p, l, it, kStepNormal);
         HIP_TRY(launch_step(P->fp64, p->weight_mode, a, P->grid[l], P->block, st));
+        HIP_TRY(launch_solve(P->fp64, a, P->n_pairs, st));
         if (p->weight_mode == RIR_WEIGHT_LEARNED) {
             StepArgs b = step_args(P, p, l, it, kStepFallback);
             HIP_TRY(launch_step(P->fp64, RIR_WEIGHT_HUBER, b, P->grid[l], P->block, st));
+            HIP_TRY(launch_solve(P->fp64, b, P->n_pairs, st));
         }
     }
     return RIR_OK;
@@ -965,6 +972,8 @@ extern "C" rir_status rir_debug_associate(rir_ctx *ctx, const rir_icp_params *pa
     a.dbg_J = J;
     a.dbg_feat = feat;
     hipError_t e2 = e1 == hipSuccess ? launch_step(P->fp64, q.weight_mode, a, P->grid[level], P->block, st) : e1;
+    if (e2 == hipSuccess)
+        e2 = launch_solve(P->fp64, a, 1, st);
     hipError_t e3 = hipStreamSynchronize(st);
     hipHostFree(hp);
     HIP_TRY(e1);
@@ -995,16 +1004,16 @@ extern "C" rir_status rir_autotune(rir_ctx *ctx, const rir_icp_params *params, i
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const int blocks[] = {128, 256};
-    const int ppts[] = {2, 4, 8, 16};
+    const int ppts[] = {4, 8, 16};
     const int gms[] = {0, 4};
-    const int xcds[] = {0, 1};
+    const int chunks[] = {1, 2, 4};
     rir_tuning bt = ctx->tune;
     float bms = INFINITY;
     for (int b : blocks)
         for (int ppt : ppts)
             for (int gm : gms)
-                for (int x : xcds) {
-                    rir_tuning t{b, ppt, gm, x};
+                for (int ch : chunks) {
+                    rir_tuning t{b, ppt, gm, 1, ch};
                     s = rir_ctx_set_tuning(ctx, &t);
                     if (s != RIR_OK)
                         break;

@@ -114,11 +114,12 @@ __global__ void k_unproject(SensorTab<float> S, const float *range, float *xyz, 
 __global__ void k_project(SensorTab<float> S, int level, const float *xyz, int64_t n, int32_t *uo, int32_t *vo,
                           float *ro, uint8_t *valid)
 {
+    const LevelView<float> V = level_view(S, level);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
         int u = -1, v = -1;
         float r = sqrtf(x * x + y * y + z * z);
-        const bool ok = project(S, level, x, y, z, u, v, r);
+        const bool ok = project(V, x, y, z, u, v, r);
         uo[i] = ok ? u : -1;
         vo[i] = ok ? v : -1;
         ro[i] = r;
@@ -128,11 +129,12 @@ __global__ void k_project(SensorTab<float> S, int level, const float *xyz, int64
 
 __global__ void k_normals(SensorTab<float> S, const float *range, double edge_rel, float *nrm, uint8_t *valid)
 {
+    const NormalView<float> NV = normal_view(S);
     const int N = S.H * S.W;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
         const int v = i / S.W, u = i - v * S.W;
         V3<float> n = {0.f, 0.f, 0.f};
-        const bool ok = normal_at(S, range, u, v, edge_rel, n);
+        const bool ok = normal_at(NV, range, u, v, edge_rel, n);
         nrm[3 * (size_t)i] = ok ? n.x : 0.f;
         nrm[3 * (size_t)i + 1] = ok ? n.y : 0.f;
         nrm[3 * (size_t)i + 2] = ok ? n.z : 0.f;
@@ -156,59 +158,81 @@ __global__ void k_clear(int *flags, int n_flags, rir_level_stats *stats, int n_s
 // Normal image and pyramid (Sec. 4.1): one thread per level-0 pixel writes the
 // (normal, range) record of the target at level 0 and, for pixels on the grid
 // of level l, the strided copies of the target record, target range and
-// source range.  With init_centroid the same pass sums the valid source and
-// target points per tile, and the last workgroup of a pair sets
-// T0 = [I | mean(dst) - mean(src)] (Sec. 4.1).
+// source range.  With init_centroid each tile also records the sums of its
+// valid source and target points (reduced per pair by k_centroid).
+constexpr int kPrepChunk = 4;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
 {
-    __shared__ double s_red[8][kAccum];
-    __shared__ int s_last;
+    __shared__ T s_red[4][kAccum];
     const PairDesc<T> *pairs = reinterpret_cast<const PairDesc<T> *>(a.pairs);
     T *psum = reinterpret_cast<T *>(a.psum);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step) {
         const int2 tl = a.tiles[it.cur];
         const PairDesc<T> &P = pairs[tl.x];
-        const SensorTab<T> &S = *P.tab;
+        const NormalView<T> NV = normal_view(*P.tab);
         const int W = P.W, N = P.H * P.W;
         const int end = min(tl.y + a.tile_px, N);
+        const float invW = P.invW[0];
+        const float *dr = P.dstr[0], *sr = P.src[0];
+        T *d40 = P.dst4[0];
         T acc[kAccum];
 #pragma unroll
         for (int k = 0; k < kAccum; ++k)
             acc[k] = (T)0;
-        for (int i = tl.y + tid; i < end; i += blockDim.x) {
-            int u, v;
-            split_index(i, W, P.invW[0], u, v);
-            V3<T> n;
-            const float rc = P.dstr[0][i];
-            const bool ok = normal_at(S, P.dstr[0], u, v, a.edge_rel, n);
-            V4<T> rec = ok ? V4<T>{n.x, n.y, n.z, (T)rc} : V4<T>{(T)0, (T)0, (T)0, (T)0};
-            st4(P.dst4[0] + 4 * (size_t)i, rec);
-            const float rs = P.src[0][i];
-            for (int l = 1; l < a.levels; ++l) {
-                const int msk = (1 << l) - 1;
-                if ((u & msk) == 0 && (v & msk) == 0) {
-                    const size_t j = (size_t)(v >> l) * (W >> l) + (u >> l);
-                    st4(P.dst4[l] + 4 * j, rec);
-                    P.dstr[l][j] = rc;
-                    P.src[l][j] = rs;
+        const int bd = blockDim.x;
+        for (int i0 = tl.y + tid; i0 - tid < end; i0 += kPrepChunk * bd) {
+            V4<T> rec[kPrepChunk];
+            float rcv[kPrepChunk], rsv[kPrepChunk];
+            int uu[kPrepChunk], vv[kPrepChunk];
+#pragma unroll
+            for (int j = 0; j < kPrepChunk; ++j) {
+                const int i = i0 + j * bd;
+                rec[j] = V4<T>{(T)0, (T)0, (T)0, (T)0};
+                rcv[j] = rsv[j] = 0.f;
+                uu[j] = vv[j] = 0;
+                if (i < end) {
+                    split_index(i, W, invW, uu[j], vv[j]);
+                    V3<T> n;
+                    rcv[j] = dr[i];
+                    rsv[j] = sr[i];
+                    if (normal_at(NV, dr, uu[j], vv[j], a.edge_rel, n))
+                        rec[j] = V4<T>{n.x, n.y, n.z, (T)rcv[j]};
                 }
             }
-            if (a.init_centroid) {
-                if (range_ok(rs)) {
-                    V3<T> p = unproject(S, u, v, (T)rs);
-                    acc[0] += p.x;
-                    acc[1] += p.y;
-                    acc[2] += p.z;
-                    acc[3] += (T)1;
+#pragma unroll
+            for (int j = 0; j < kPrepChunk; ++j) {
+                const int i = i0 + j * bd;
+                if (i >= end)
+                    continue;
+                const int u = uu[j], v = vv[j];
+                st4(d40 + 4 * (size_t)i, rec[j]);
+                for (int l = 1; l < a.levels; ++l) {
+                    const int msk = (1 << l) - 1;
+                    if ((u & msk) == 0 && (v & msk) == 0) {
+                        const size_t q = (size_t)(v >> l) * (W >> l) + (u >> l);
+                        st4(P.dst4[l] + 4 * q, rec[j]);
+                        P.dstr[l][q] = rcv[j];
+                        P.src[l][q] = rsv[j];
+                    }
                 }
-                if (range_ok(rc)) {
-                    V3<T> q = unproject(S, u, v, (T)rc);
-                    acc[4] += q.x;
-                    acc[5] += q.y;
-                    acc[6] += q.z;
-                    acc[7] += (T)1;
+                if (a.init_centroid) {
+                    if (range_ok(rsv[j])) {
+                        V3<T> pp = unproject(NV.row, NV.col, NV.r0, u, v, (T)rsv[j]);
+                        acc[0] += pp.x;
+                        acc[1] += pp.y;
+                        acc[2] += pp.z;
+                        acc[3] += (T)1;
+                    }
+                    if (range_ok(rcv[j])) {
+                        V3<T> q = unproject(NV.row, NV.col, NV.r0, u, v, (T)rcv[j]);
+                        acc[4] += q.x;
+                        acc[5] += q.y;
+                        acc[6] += q.z;
+                        acc[7] += (T)1;
+                    }
                 }
             }
         }
@@ -216,239 +240,60 @@ __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
             continue;
         const T tot = wave_sum32(acc, lane);
         if (lane < 32)
-            s_red[wave][bitrev5(lane)] = (double)tot;
+            s_red[wave][bitrev5(lane)] = tot;
         __syncthreads();
         if (tid < kAccum) {
-            double s = 0.0;
+            T sum = (T)0;
             for (int w = 0; w < nwave; ++w)
-                s += s_red[w][tid];
-            psum[(size_t)it.cur * kAccum + tid] = (T)s;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            __threadfence();
-            const int prev = atomicAdd(&a.counters[tl.x], 1);
-            s_last = prev == P.ntile[0] - 1;
-        }
-        __syncthreads();
-        if (s_last) {
-            __threadfence();
-            if (tid == 0) {
-                double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                for (int k = 0; k < P.ntile[0]; ++k)
-                    for (int j = 0; j < 8; ++j)
-                        c[j] += (double)psum[(size_t)(P.tile0[0] + k) * kAccum + j];
-                double *T0 = a.poses + 16 * (size_t)tl.x;
-                for (int j = 0; j < 16; ++j)
-                    T0[j] = (j % 5 == 0) ? 1.0 : 0.0;
-                if (c[3] > 0.0 && c[7] > 0.0) {
-                    T0[3] = c[4] / c[7] - c[0] / c[3];
-                    T0[7] = c[5] / c[7] - c[1] / c[3];
-                    T0[11] = c[6] / c[7] - c[2] / c[3];
-                }
-                a.counters[tl.x] = 0;
-            }
+                sum += s_red[w][tid];
+            psum[(size_t)it.cur * kAccum + tid] = sum;
         }
         __syncthreads();
     }
 }
 
-// ----------------------------------------------------------------------------- solve
-
-// Index of entry (i, j), i <= j, of the row-major packed upper triangle.
-__device__ __forceinline__ int up6(int i, int j) { return 6 * i - (i * (i - 1)) / 2 + (j - i); }
-
-// Solves H xi = -g in FP64 with H = U^T U (U upper triangular, computed in
-// place over the 21 packed entries of H).  Fails when a pivot is not above
-// 1e-12 times the largest diagonal entry.
-__device__ __noinline__ bool cholesky6(double *U, const double *g, double *xi)
+// Initial pose from the point-set centres (Sec. 4.1): R = I and
+// t = mean(valid target points) - mean(valid source points), from the tile
+// sums of the prepass, added in FP64 in tile order.  One wave per pair.
+template <typename T>
+__global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
 {
-    double dmax = 0.0;
-    for (int i = 0; i < 6; ++i)
-        dmax = U[up6(i, i)] > dmax ? U[up6(i, i)] : dmax;
-    if (!(dmax > 0.0))
-        return false;
-#pragma unroll 1
-    for (int j = 0; j < 6; ++j) {
-        double d = U[up6(j, j)];
-        for (int k = 0; k < j; ++k)
-            d -= U[up6(k, j)] * U[up6(k, j)];
-        if (!(d > 1e-12 * dmax))
-            return false;
-        d = sqrt(d);
-        U[up6(j, j)] = d;
-        for (int i = j + 1; i < 6; ++i) {
-            double acc = U[up6(j, i)];
-            for (int k = 0; k < j; ++k)
-                acc -= U[up6(k, j)] * U[up6(k, i)];
-            U[up6(j, i)] = acc / d;
-        }
-    }
-    double y[6];
-#pragma unroll 1
-    for (int i = 0; i < 6; ++i) {
-        double acc = -g[i];
-        for (int k = 0; k < i; ++k)
-            acc -= U[up6(k, i)] * y[k];
-        y[i] = acc / U[up6(i, i)];
-    }
-#pragma unroll 1
-    for (int i = 5; i >= 0; --i) {
-        double acc = y[i];
-        for (int k = i + 1; k < 6; ++k)
-            acc -= U[up6(i, k)] * xi[k];
-        xi[i] = acc / U[up6(i, i)];
-    }
-    return true;
-}
-
-// T <- Exp(xi) T with Exp(xi) = [R, V tau]: R = I + A K + B K^2,
-// V = I + B K + C K^2, K = [omega]x, K^2 = omega omega^T - |omega|^2 I,
-// A = sin a / a, B = (1 - cos a) / a^2, C = (a - sin a) / a^3 (Taylor below
-// a = 1e-6).  T is updated row by row in place.
-__device__ __noinline__ void se3_left_update(const double *xi, double *T)
-{
-    const double w[3] = {xi[0], xi[1], xi[2]};
-    const double a2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], a = sqrt(a2);
-    double A, B, C;
-    if (a < 1e-6) {
-        A = 1.0 - a2 / 6.0;
-        B = 0.5 - a2 / 24.0;
-        C = 1.0 / 6.0 - a2 / 120.0;
-    } else {
-        double s, c;
-        sincos(a, &s, &c);
-        A = s / a;
-        B = (1.0 - c) / a2;
-        C = (a - s) / (a2 * a);
-    }
-    const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
-    double E[12];
-    for (int i = 0; i < 3; ++i) {
-        double t = 0.0;
-        for (int j = 0; j < 3; ++j) {
-            const double I = i == j ? 1.0 : 0.0;
-            const double K2 = w[i] * w[j] - I * a2;
-            E[4 * i + j] = I + A * K[3 * i + j] + B * K2;
-            t += (I + B * K[3 * i + j] + C * K2) * xi[3 + j];
-        }
-        E[4 * i + 3] = t;
-    }
-    double Tn[12];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 4; ++j) {
-            double acc = j == 3 ? E[4 * i + 3] : 0.0;
-            for (int k = 0; k < 3; ++k)
-                acc += E[4 * i + k] * T[4 * k + j];
-            Tn[4 * i + j] = acc;
-        }
-    for (int i = 0; i < 12; ++i)
-        T[i] = Tn[i];
-}
-
-__device__ __forceinline__ bool finite_all(const double *v, int n)
-{
-    bool ok = true;
-    for (int i = 0; i < n; ++i)
-        ok = ok && isfinite(v[i]);
-    return ok;
-}
-
-// Reduction of one pair's tile records in FP64 (fixed order for a given block
-// size) and the Gauss-Newton update, run by every thread of the last
-// workgroup to finish the pair; thread 0 solves.
-template <typename T, int WMODE>
-__device__ void finish_pair(const StepArgs &a, const PairDesc<T> &P, int pair, double (*s_red)[kAccum],
-                            long long (*s_cnt)[4])
-{
-    const int tid = threadIdx.x, comp = tid & 31, grp = tid >> 5, ngrp = blockDim.x >> 5;
-    const int l = a.level, nt = P.ntile[l], t0 = P.tile0[l];
+    __shared__ double s_c[8];
+    const PairDesc<T> &P = reinterpret_cast<const PairDesc<T> *>(a.pairs)[blockIdx.x];
     const T *psum = reinterpret_cast<const T *>(a.psum);
-    double s = 0.0;
-    for (int k = grp; k < nt; k += ngrp)
-        s += (double)psum[(size_t)(t0 + k) * kAccum + comp];
-    s_red[grp][comp] = s;
-    if (comp < 3) {
-        long long c = 0;
-        for (int k = grp; k < nt; k += ngrp) {
-            const int4 pc = a.pcnt[t0 + k];
-            c += comp == 0 ? pc.x : (comp == 1 ? pc.y : pc.z);
-        }
-        s_cnt[grp][comp] = c;
+    const int lane = threadIdx.x;
+    if (lane < 8) {
+        double s = 0.0;
+        for (int k = 0; k < P.ntile[0]; ++k)
+            s += (double)psum[(size_t)(P.tile0[0] + k) * kAccum + lane];
+        s_c[lane] = s;
     }
     __syncthreads();
-    if (tid != 0)
-        return;
-    double tot[30];
-    for (int c = 0; c < 30; ++c) {
-        double acc = 0.0;
-        for (int g = 0; g < ngrp; ++g)
-            acc += s_red[g][c];
-        tot[c] = acc;
+    if (lane < 16) {
+        double *T0 = a.poses + 16 * (size_t)blockIdx.x;
+        double val = (lane % 5 == 0) ? 1.0 : 0.0;
+        if ((lane == 3 || lane == 7 || lane == 11) && s_c[3] > 0.0 && s_c[7] > 0.0) {
+            const int c = lane / 4;
+            val = s_c[4 + c] / s_c[7] - s_c[c] / s_c[3];
+        }
+        T0[lane] = val;
     }
-    long long cnt[3] = {0, 0, 0};
-    for (int c = 0; c < 3; ++c)
-        for (int g = 0; g < ngrp; ++g)
-            cnt[c] += s_cnt[g][c];
-    int *fl = a.flags + (size_t)pair * kFlagStride;
-    rir_level_stats *out = a.stats + (a.mode == kStepDebug ? 0 : (size_t)pair * a.levels + l);
-    for (int k = 0; k < 21; ++k)
-        out->JtJ[k] = tot[k];
-    const int n_valid = (int)cnt[0];
-    const bool finite = finite_all(tot, 30);
-    double xi[6] = {0, 0, 0, 0, 0, 0};
-    double g6[6];
-    for (int k = 0; k < 6; ++k)
-        g6[k] = tot[21 + k];
-    const bool ok = n_valid >= 6 && finite && cholesky6(tot, g6, xi);
-    if (WMODE == 1 && a.mode == kStepNormal && (!ok || tot[27] < 0.1 * (double)n_valid)) {
-        // learned weights rejected: the pseudo-Huber pass that follows redoes
-        // this iteration and rewrites the statistics
-        fl[kMaxLevels] = 1;
-        a.counters[pair] = 0;
-        return;
-    }
-    int status = a.mode == kStepFallback ? RIR_LEVEL_FALLBACK_HUBER : RIR_LEVEL_OK;
-    double srot = 0.0, stra = 0.0;
-    if (a.mode == kStepFallback)
-        fl[kMaxLevels] = 0;
-    if (!ok) {
-        status = finite ? RIR_LEVEL_DEGENERATE : RIR_LEVEL_NONFINITE;
-        if (a.mode != kStepDebug)
-            fl[l] = 1;
-    } else {
-        srot = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
-        stra = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
-        if (a.mode != kStepDebug)
-            se3_left_update(xi, a.poses + 16 * (size_t)pair);
-    }
-    out->status = status;
-    out->iters_run = a.iter + 1;
-    out->n_valid = n_valid;
-    out->n_inlier = (int)cnt[1];
-    out->n_proj = (int)cnt[2];
-    out->pad = 0;
-    out->sum_w = tot[27];
-    out->sum_w_e2 = tot[28];
-    out->robust_cost = tot[29];
-    out->step_rot = srot;
-    out->step_trans = stra;
-    for (int k = 0; k < 6; ++k)
-        out->Jtr[k] = g6[k];
-    a.counters[pair] = 0;
 }
+
+// ----------------------------------------------------------------------------- step
 
 // One Gauss-Newton iteration at level l for every pair of the batch (Eq. (5)-(7),
 // Sec. 4.1).  Each workgroup walks its tiles; a tile is a run of tile_px
-// consecutive source pixels of one pair's level-l image.
-template <typename T, int WMODE>
+// consecutive source pixels of one pair's level-l image, and each thread takes
+// CHUNK of them at a time (pixels i0 + j * blockDim) so that CHUNK source
+// loads, then CHUNK target gathers, are in flight together.  The tile's sums
+// go to one record (k_solve reduces them).  FINE tags the finest-level
+// instance (same code) so that profiles report it separately.
+template <typename T, int WMODE, bool FINE, int CHUNK>
 __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
 {
     __shared__ T s_wave[4][kAccum];
     __shared__ int s_wcnt[4][4];
-    __shared__ double s_red[8][kAccum];
-    __shared__ long long s_cnt[8][4];
-    __shared__ int s_last;
     const PairDesc<T> *pairs = reinterpret_cast<const PairDesc<T> *>(a.pairs);
     T *psum = reinterpret_cast<T *>(a.psum);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
@@ -470,13 +315,14 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
                 continue;
         }
         const PairDesc<T> &P = pairs[pair];
-        const SensorTab<T> &S = *P.tab;
+        const LevelView<T> V = level_view(*P.tab, l);
         const double *Tp = a.poses + 16 * (size_t)pair;
         const T r00 = (T)Tp[0], r01 = (T)Tp[1], r02 = (T)Tp[2], t0 = (T)Tp[3];
         const T r10 = (T)Tp[4], r11 = (T)Tp[5], r12 = (T)Tp[6], t1 = (T)Tp[7];
         const T r20 = (T)Tp[8], r21 = (T)Tp[9], r22 = (T)Tp[10], t2 = (T)Tp[11];
         const int Wl = P.W >> l, Nl = (P.H >> l) * Wl;
         const int end = min(tl.y + a.tile_px, Nl);
+        const float invW = P.invW[l];
         const float *srcl = P.src[l];
         const T *d4 = P.dst4[l];
         T acc[kAccum];
@@ -484,84 +330,99 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
         for (int k = 0; k < kAccum; ++k)
             acc[k] = (T)0;
         int c_valid = 0, c_in = 0, c_proj = 0;
-        for (int i0 = tl.y; i0 < end; i0 += blockDim.x) {
-            const int i = i0 + tid;
-            bool proj = false, valid = false;
-            T e = (T)0, J0 = (T)0, J1 = (T)0, J2 = (T)0, J3 = (T)0, J4 = (T)0, J5 = (T)0;
-            T xr = (T)0;
-            int ul = -1, vl = -1;
-            if (i < end) {
-                const float rs = srcl[i];
-                if (range_ok(rs)) {
+        const int bd = blockDim.x;
+        for (int i0 = tl.y + tid; i0 - tid < end; i0 += CHUNK * bd) {
+            float rs[CHUNK];
+#pragma unroll
+            for (int j = 0; j < CHUNK; ++j) {
+                const int i = i0 + j * bd;
+                rs[j] = i < end ? srcl[i] : 0.f;
+            }
+            bool proj[CHUNK];
+            int ul[CHUNK], vl[CHUNK];
+            T xx[CHUNK], xy[CHUNK], xz[CHUNK], xr[CHUNK];
+#pragma unroll
+            for (int j = 0; j < CHUNK; ++j) {
+                proj[j] = false;
+                ul[j] = vl[j] = -1;
+                xx[j] = xy[j] = xz[j] = xr[j] = (T)0;
+                if (range_ok(rs[j])) {
                     int up, vp;
-                    split_index(i, Wl, P.invW[l], up, vp);
-                    const V3<T> p = unproject(S, s * up, s * vp, (T)rs);
-                    const T x = r00 * p.x + r01 * p.y + r02 * p.z + t0;
-                    const T y = r10 * p.x + r11 * p.y + r12 * p.z + t1;
-                    const T z = r20 * p.x + r21 * p.y + r22 * p.z + t2;
-                    if (project(S, l, x, y, z, ul, vl, xr)) {
-                        proj = true;
-                        const V4<T> D = ld4(d4 + 4 * ((size_t)vl * Wl + ul));
-                        if (D.w > (T)0) {
-                            const V3<T> q = unproject(S, s * ul, s * vl, D.w);
-                            const T dx = x - q.x, dy = y - q.y, dz = z - q.z;
-                            if (!(mc2 >= (T)0 && dx * dx + dy * dy + dz * dz > mc2)) {
-                                valid = true;
-                                e = D.x * dx + D.y * dy + D.z * dz;
-                                J0 = y * D.z - z * D.y;
-                                J1 = z * D.x - x * D.z;
-                                J2 = x * D.y - y * D.x;
-                                J3 = D.x;
-                                J4 = D.y;
-                                J5 = D.z;
-                            }
-                        }
-                    } else {
-                        ul = vl = -1;
-                    }
+                    split_index(i0 + j * bd, Wl, invW, up, vp);
+                    const V3<T> p = unproject(V, s * up, s * vp, (T)rs[j]);
+                    xx[j] = r00 * p.x + r01 * p.y + r02 * p.z + t0;
+                    xy[j] = r10 * p.x + r11 * p.y + r12 * p.z + t1;
+                    xz[j] = r20 * p.x + r21 * p.y + r22 * p.z + t2;
+                    proj[j] = project(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]);
+                    if (!proj[j])
+                        ul[j] = vl[j] = -1;
                 }
             }
-            const T tq = e * inv_delta;
-            const T wh = d_rsqrt((T)1 + tq * tq);
-            T w = wh;
-            if constexpr (WMODE == 1) {
-                if (a.mode != kStepFallback)
-                    w = learned_weight<T>(a, F, P, l, valid, ul, vl, e, xr, J3, J4, J5, dbg ? a.dbg_feat : nullptr,
-                                          i < end ? i : -1);
-            }
-            w = valid ? w : (T)0;
-            const T rho = valid ? e * e * wh / (wh + (T)1) : (T)0;
-            c_proj += wave_count(proj);
-            c_valid += wave_count(valid);
-            c_in += wave_count(valid && fabs(e) < delta);
-            const T J[6] = {J0, J1, J2, J3, J4, J5};
-            T wJ[6];
+            V4<T> D[CHUNK];
 #pragma unroll
-            for (int k = 0; k < 6; ++k)
-                wJ[k] = w * J[k];
-            int k = 0;
+            for (int j = 0; j < CHUNK; ++j)
+                D[j] = proj[j] ? ld4(d4 + 4 * ((size_t)vl[j] * Wl + ul[j])) : V4<T>{(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
+            for (int j = 0; j < CHUNK; ++j) {
+                const int i = i0 + j * bd;
+                bool valid = false;
+                T e = (T)0, J0 = (T)0, J1 = (T)0, J2 = (T)0;
+                const T n0 = D[j].x, n1 = D[j].y, n2 = D[j].z;
+                if (D[j].w > (T)0) {
+                    const V3<T> q = unproject(V, s * ul[j], s * vl[j], D[j].w);
+                    const T dx = xx[j] - q.x, dy = xy[j] - q.y, dz = xz[j] - q.z;
+                    if (!(mc2 >= (T)0 && dx * dx + dy * dy + dz * dz > mc2)) {
+                        valid = true;
+                        e = n0 * dx + n1 * dy + n2 * dz;
+                        J0 = xy[j] * n2 - xz[j] * n1;
+                        J1 = xz[j] * n0 - xx[j] * n2;
+                        J2 = xx[j] * n1 - xy[j] * n0;
+                    }
+                }
+                const T J3 = valid ? n0 : (T)0, J4 = valid ? n1 : (T)0, J5 = valid ? n2 : (T)0;
+                const T tq = e * inv_delta;
+                const T wh = d_rsqrt((T)1 + tq * tq);
+                T w = wh;
+                if constexpr (WMODE == 1) {
+                    if (a.mode != kStepFallback)
+                        w = learned_weight<T>(a, F, P, l, valid, ul[j], vl[j], e, xr[j], J3, J4, J5,
+                                              dbg ? a.dbg_feat : nullptr, i < end ? i : -1);
+                }
+                w = valid ? w : (T)0;
+                const T rho = valid ? e * e * wh / (wh + (T)1) : (T)0;
+                c_proj += wave_count(proj[j]);
+                c_valid += wave_count(valid);
+                c_in += wave_count(valid && fabs(e) < delta);
+                const T J[6] = {J0, J1, J2, J3, J4, J5};
+                T wJ[6];
 #pragma unroll
-                for (int c = r; c < 6; ++c)
-                    acc[k++] += wJ[r] * J[c];
+                for (int k = 0; k < 6; ++k)
+                    wJ[k] = w * J[k];
+                int k = 0;
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
-                acc[21 + r] += wJ[r] * e;
-            acc[27] += w;
-            acc[28] += w * e * e;
-            acc[29] += rho;
-            if (dbg && i < end) {
-                if (a.dbg_u) a.dbg_u[i] = proj ? ul : -1;
-                if (a.dbg_v) a.dbg_v[i] = proj ? vl : -1;
-                if (a.dbg_mask) a.dbg_mask[i] = valid ? 1 : 0;
-                if (a.dbg_e) a.dbg_e[i] = (float)e;
-                if (a.dbg_w) a.dbg_w[i] = (float)w;
-                if (a.dbg_J)
-                    for (int q = 0; q < 6; ++q)
-                        a.dbg_J[6 * (size_t)i + q] = (float)J[q];
-                if (WMODE == 0 && a.dbg_feat)
-                    store_features<T>(a, P, l, valid, ul, vl, e, xr, J3, J4, J5, a.dbg_feat + 14 * (size_t)i);
+                for (int r = 0; r < 6; ++r)
+#pragma unroll
+                    for (int c = r; c < 6; ++c)
+                        acc[k++] += wJ[r] * J[c];
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+                    acc[21 + r] += wJ[r] * e;
+                acc[27] += w;
+                acc[28] += w * e * e;
+                acc[29] += rho;
+                if (dbg && i < end) {
+                    if (a.dbg_u) a.dbg_u[i] = ul[j];
+                    if (a.dbg_v) a.dbg_v[i] = vl[j];
+                    if (a.dbg_mask) a.dbg_mask[i] = valid ? 1 : 0;
+                    if (a.dbg_e) a.dbg_e[i] = (float)e;
+                    if (a.dbg_w) a.dbg_w[i] = (float)w;
+                    if (a.dbg_J)
+                        for (int q = 0; q < 6; ++q)
+                            a.dbg_J[6 * (size_t)i + q] = (float)J[q];
+                    if (WMODE == 0 && a.dbg_feat)
+                        store_features<T>(a, P, l, valid, ul[j], vl[j], e, xr[j], J3, J4, J5,
+                                          a.dbg_feat + 14 * (size_t)i);
+                }
             }
         }
         const T tot = wave_sum32(acc, lane);
@@ -588,18 +449,225 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
             a.pcnt[it.cur] = c;
         }
         __syncthreads();
-        if (tid == 0) {
-            __threadfence();
-            const int prev = atomicAdd(&a.counters[pair], 1);
-            s_last = prev == P.ntile[l] - 1;
-        }
-        __syncthreads();
-        if (s_last) {
-            __threadfence();
-            finish_pair<T, WMODE>(a, P, pair, s_red, s_cnt);
-        }
-        __syncthreads();
     }
+}
+
+// ----------------------------------------------------------------------------- solve
+
+// Solves H xi = -g in FP64 with H = U^T U (U upper triangular, computed in
+// place over the 21 packed row-major entries of H).  Fails when a pivot is not
+// above 1e-12 times the largest diagonal entry.  Fully unrolled so that every
+// array stays in registers.
+__device__ __forceinline__ bool cholesky6(double (&U)[21], const double (&g)[6], double (&xi)[6])
+{
+    constexpr int off[6] = {0, 6, 11, 15, 18, 20};  // start of row i of the packed triangle
+    double dmax = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        dmax = U[off[i]] > dmax ? U[off[i]] : dmax;
+    if (!(dmax > 0.0))
+        return false;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double d = U[off[j]];
+#pragma unroll
+        for (int k = 0; k < j; ++k)
+            d -= U[off[k] + j - k] * U[off[k] + j - k];
+        ok = ok && (d > 1e-12 * dmax);
+        d = sqrt(d > 0.0 ? d : 1.0);
+        U[off[j]] = d;
+        const double inv = 1.0 / d;
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            double acc = U[off[j] + i - j];
+#pragma unroll
+            for (int k = 0; k < j; ++k)
+                acc -= U[off[k] + j - k] * U[off[k] + i - k];
+            U[off[j] + i - j] = acc * inv;
+        }
+    }
+    if (!ok)
+        return false;
+    double y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double acc = -g[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k)
+            acc -= U[off[k] + i - k] * y[k];
+        y[i] = acc / U[off[i]];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        double acc = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k)
+            acc -= U[off[i] + k - i] * xi[k];
+        xi[i] = acc / U[off[i]];
+    }
+    return true;
+}
+
+// T <- Exp(xi) T with Exp(xi) = [R, V tau]: R = I + A K + B K^2,
+// V = I + B K + C K^2, K = [omega]x, K^2 = omega omega^T - |omega|^2 I,
+// A = sin a / a, B = (1 - cos a) / a^2, C = (a - sin a) / a^3 (Taylor below
+// a = 1e-6).
+__device__ __forceinline__ void se3_left_update(const double (&xi)[6], double *T)
+{
+    const double w[3] = {xi[0], xi[1], xi[2]};
+    const double a2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], a = sqrt(a2);
+    double A, B, C;
+    if (a < 1e-6) {
+        A = 1.0 - a2 / 6.0;
+        B = 0.5 - a2 / 24.0;
+        C = 1.0 / 6.0 - a2 / 120.0;
+    } else {
+        double sn, cs;
+        sincos(a, &sn, &cs);
+        A = sn / a;
+        B = (1.0 - cs) / a2;
+        C = (a - sn) / (a2 * a);
+    }
+    const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+    double E[12];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double I = i == j ? 1.0 : 0.0;
+            const double K2 = w[i] * w[j] - I * a2;
+            E[4 * i + j] = I + A * K[3 * i + j] + B * K2;
+            t += (I + B * K[3 * i + j] + C * K2) * xi[3 + j];
+        }
+        E[4 * i + 3] = t;
+    }
+    double To[12], Tn[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+        To[i] = T[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double acc = j == 3 ? E[4 * i + 3] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                acc += E[4 * i + k] * To[4 * k + j];
+            Tn[4 * i + j] = acc;
+        }
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+        T[i] = Tn[i];
+}
+
+// Reduction of one pair's tile records in FP64 (tile order, independent of
+// the batch) and the Gauss-Newton update of Eq. (7): Cholesky solve,
+// T <- Exp(xi) T, per-level statistics.  One wave per pair.
+template <typename T>
+__global__ __launch_bounds__(256) void k_solve(StepArgs a)
+{
+    __shared__ double s_part[8][kAccum];
+    __shared__ long long s_cpart[8][4];
+    __shared__ double s_tot[32];
+    __shared__ long long s_cnt[4];
+    const int pair = blockIdx.x, lane = threadIdx.x, l = a.level;
+    int *fl = a.flags + (size_t)pair * kFlagStride;
+    if (a.mode != kStepDebug) {
+        if (fl[l] & 1)
+            return;
+        if (a.mode == kStepFallback && !(fl[kMaxLevels] & 1))
+            return;
+    }
+    const PairDesc<T> &P = reinterpret_cast<const PairDesc<T> *>(a.pairs)[pair];
+    const T *psum = reinterpret_cast<const T *>(a.psum);
+    const int nt = P.ntile[l], t0 = P.tile0[l];
+    // group g of 32 threads sums tiles g, g + 8, ... (one coalesced record per step)
+    const int comp = lane & 31, grp = lane >> 5;
+    double sum = 0.0;
+    long long c = 0;
+    for (int k = grp; k < nt; k += 8) {
+        sum += (double)psum[(size_t)(t0 + k) * kAccum + comp];
+        if (comp < 3) {
+            const int4 pc = a.pcnt[t0 + k];
+            c += comp == 0 ? pc.x : (comp == 1 ? pc.y : pc.z);
+        }
+    }
+    s_part[grp][comp] = sum;
+    if (comp < 3)
+        s_cpart[grp][comp] = c;
+    __syncthreads();
+    if (lane < 30) {
+        double t = 0.0;
+        for (int g = 0; g < 8; ++g)
+            t += s_part[g][lane];
+        s_tot[lane] = t;
+    } else if (lane >= 32 && lane < 35) {
+        long long t = 0;
+        for (int g = 0; g < 8; ++g)
+            t += s_cpart[g][lane - 32];
+        s_cnt[lane - 32] = t;
+    }
+    __syncthreads();
+    if (lane != 0)
+        return;
+    double U[21], g[6];
+#pragma unroll
+    for (int k = 0; k < 21; ++k)
+        U[k] = s_tot[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        g[k] = s_tot[21 + k];
+    const double sum_w = s_tot[27], sum_we2 = s_tot[28], rho = s_tot[29];
+    const int n_valid = (int)s_cnt[0];
+    bool finite = isfinite(sum_w) && isfinite(sum_we2) && isfinite(rho);
+#pragma unroll
+    for (int k = 0; k < 21; ++k)
+        finite = finite && isfinite(U[k]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        finite = finite && isfinite(g[k]);
+    rir_level_stats *out = a.stats + (a.mode == kStepDebug ? 0 : (size_t)pair * a.levels + l);
+#pragma unroll
+    for (int k = 0; k < 21; ++k)
+        out->JtJ[k] = U[k];
+    double xi[6] = {0, 0, 0, 0, 0, 0};
+    const bool ok = n_valid >= 6 && finite && cholesky6(U, g, xi);
+    if (a.learned && a.mode == kStepNormal && (!ok || sum_w < 0.1 * (double)n_valid)) {
+        // learned weights rejected: the pseudo-Huber pass that follows redoes
+        // this iteration and rewrites the statistics
+        fl[kMaxLevels] = 1;
+        return;
+    }
+    int status = a.mode == kStepFallback ? RIR_LEVEL_FALLBACK_HUBER : RIR_LEVEL_OK;
+    double srot = 0.0, stra = 0.0;
+    if (a.mode == kStepFallback)
+        fl[kMaxLevels] = 0;
+    if (!ok) {
+        status = finite ? RIR_LEVEL_DEGENERATE : RIR_LEVEL_NONFINITE;
+        if (a.mode != kStepDebug)
+            fl[l] = 1;
+    } else {
+        srot = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+        stra = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+        if (a.mode != kStepDebug)
+            se3_left_update(xi, a.poses + 16 * (size_t)pair);
+    }
+    out->status = status;
+    out->iters_run = a.iter + 1;
+    out->n_valid = n_valid;
+    out->n_inlier = (int)s_cnt[1];
+    out->n_proj = (int)s_cnt[2];
+    out->pad = 0;
+    out->sum_w = sum_w;
+    out->sum_w_e2 = sum_we2;
+    out->robust_cost = rho;
+    out->step_rot = srot;
+    out->step_trans = stra;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        out->Jtr[k] = g[k];
 }
 
 // ----------------------------------------------------------------------------- launchers
@@ -641,27 +709,62 @@ hipError_t launch_clear(int *flags, int n_flags, rir_level_stats *stats, int n_s
     return hipGetLastError();
 }
 
-hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, hipStream_t stream)
+hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, int n_pairs, hipStream_t stream)
 {
     if (fp64)
         hipLaunchKernelGGL(k_prepass<double>, dim3(grid), dim3(block), 0, stream, a);
     else
         hipLaunchKernelGGL(k_prepass<float>, dim3(grid), dim3(block), 0, stream, a);
+    if (a.init_centroid) {
+        if (fp64)
+            hipLaunchKernelGGL(k_centroid<double>, dim3(n_pairs), dim3(64), 0, stream, a);
+        else
+            hipLaunchKernelGGL(k_centroid<float>, dim3(n_pairs), dim3(64), 0, stream, a);
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_solve(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream)
+{
+    if (fp64)
+        hipLaunchKernelGGL(k_solve<double>, dim3(n_pairs), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_solve<float>, dim3(n_pairs), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename T, int WMODE, int CHUNK>
+static void launch_step_c(const StepArgs &a, int grid, int block, hipStream_t stream)
+{
+    if (a.level == 0)
+        hipLaunchKernelGGL((k_icp_step<T, WMODE, true, CHUNK>), dim3(grid), dim3(block), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_icp_step<T, WMODE, false, CHUNK>), dim3(grid), dim3(block), 0, stream, a);
+}
+
+template <typename T, int WMODE>
+static void launch_step_t(const StepArgs &a, int grid, int block, hipStream_t stream)
+{
+    if (a.chunk >= 4)
+        launch_step_c<T, WMODE, 4>(a, grid, block, stream);
+    else if (a.chunk == 2)
+        launch_step_c<T, WMODE, 2>(a, grid, block, stream);
+    else
+        launch_step_c<T, WMODE, 1>(a, grid, block, stream);
 }
 
 hipError_t launch_step(bool fp64, int weight_mode, const StepArgs &a, int grid, int block, hipStream_t stream)
 {
     if (fp64) {
         if (weight_mode == 1)
-            hipLaunchKernelGGL((k_icp_step<double, 1>), dim3(grid), dim3(block), 0, stream, a);
+            launch_step_t<double, 1>(a, grid, block, stream);
         else
-            hipLaunchKernelGGL((k_icp_step<double, 0>), dim3(grid), dim3(block), 0, stream, a);
+            launch_step_t<double, 0>(a, grid, block, stream);
     } else {
         if (weight_mode == 1)
-            hipLaunchKernelGGL((k_icp_step<float, 1>), dim3(grid), dim3(block), 0, stream, a);
+            launch_step_t<float, 1>(a, grid, block, stream);
         else
-            hipLaunchKernelGGL((k_icp_step<float, 0>), dim3(grid), dim3(block), 0, stream, a);
+            launch_step_t<float, 0>(a, grid, block, stream);
     }
     return hipGetLastError();
 }

@@ -10,10 +10,6 @@
 namespace rir {
 
 constexpr int kMaxLevels = 8;
-// Fixed rounds of receiver-offset compensation (Sec. 3.2) when r0 > 0.  The
-// map contracts by about r0 / r per round, so 4 rounds reach FP32 resolution
-// for r0 / r below ~0.03 (r0 = 15 mm, r >= 0.5 m).
-constexpr int kR0Rounds = 4;
 
 // Sensor tables in device memory (pointers) plus scalars, one copy per type.
 //  row  [H][4]  cos phi_v, sin phi_v, cos theta_v, sin theta_v
@@ -86,8 +82,6 @@ __device__ __forceinline__ float d_atan2(float y, float x) { return atan2f(y, x)
 __device__ __forceinline__ double d_atan2(double y, double x) { return atan2(y, x); }
 __device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double d_rsqrt(double x) { return 1.0 / sqrt(x); }
-__device__ __forceinline__ void d_sincos(float a, float *s, float *c) { __sincosf(a, s, c); }
-__device__ __forceinline__ void d_sincos(double a, double *s, double *c) { sincos(a, s, c); }
 template <typename T>
 __device__ __forceinline__ T two_pi();
 template <>
@@ -107,33 +101,78 @@ __device__ __forceinline__ V3<T> ray_dir(V4<T> rw, T ca, T sa)
     return {rw.x * cal, rw.x * sal, rw.y};
 }
 
-// Eq. (1): p = r d(u, v) + r0 (cos a_u, sin a_u, 0).
+// The tables one pyramid level needs, copied out of SensorTab into
+// registers once per tile: the per-pixel code then never re-reads the table
+// descriptor (which, living in global memory next to the kernel's stores,
+// the compiler could not keep in registers).
+template <typename T>
+struct LevelView {
+    const T *row, *col;               // full-resolution factors of Eq. (1)
+    const T *mu, *uoff;               // this level's midpoints and column offsets
+    const int32_t *bins;
+    const SensorTab<T> *tab;          // everything else (receiver-offset search)
+    T r0, s_lo, s_hi, kW, bin_lo, bin_scale;
+    int Hl, Wl, nb;
+};
+
+template <typename T>
+__device__ __forceinline__ LevelView<T> level_view(const SensorTab<T> &S, int l)
+{
+    LevelView<T> V;
+    V.row = S.row;
+    V.col = S.col;
+    V.mu = S.mu[l];
+    V.uoff = S.uoff[l];
+    V.bins = S.bins[l];
+    V.tab = &S;
+    V.r0 = S.r0;
+    V.s_lo = S.s_lo;
+    V.s_hi = S.s_hi;
+    V.kW = S.kW[l];
+    V.bin_lo = S.bin_lo[l];
+    V.bin_scale = S.bin_scale[l];
+    V.Hl = S.H >> l;
+    V.Wl = S.W >> l;
+    V.nb = S.nbins[l];
+    return V;
+}
+
+// Eq. (1): p = r d(u, v) + r0 (cos a_u, sin a_u, 0) for full-resolution pixel (u, v).
+template <typename T>
+__device__ __forceinline__ V3<T> unproject(const T *row, const T *col, T r0, int u, int v, T r)
+{
+    V4<T> rw = ld4(row + 4 * v);
+    T ca, sa;
+    ld2(col + 2 * u, ca, sa);
+    V3<T> d = ray_dir(rw, ca, sa);
+    return {r * d.x + r0 * ca, r * d.y + r0 * sa, r * d.z};
+}
 template <typename T>
 __device__ __forceinline__ V3<T> unproject(const SensorTab<T> &S, int u, int v, T r)
 {
-    V4<T> rw = ld4(S.row + 4 * v);
-    T ca, sa;
-    ld2(S.col + 2 * u, ca, sa);
-    V3<T> d = ray_dir(rw, ca, sa);
-    return {r * d.x + S.r0 * ca, r * d.y + S.r0 * sa, r * d.z};
+    return unproject(S.row, S.col, S.r0, u, v, r);
+}
+template <typename T>
+__device__ __forceinline__ V3<T> unproject(const LevelView<T> &V, int u, int v, T r)
+{
+    return unproject(V.row, V.col, V.r0, u, v, r);
 }
 
-// Eq. (4) at level l on sz = sin(phi): the row t of the strided table whose
-// elevation is nearest (ties to the smaller t), i.e. the number of level
-// midpoints strictly above phi.  The inverse table gives a start row; the two
-// bounded walks make the result exact whatever the bin rounding.
+// Eq. (4) on sz = sin(phi) over a level's rows: the row t whose elevation is
+// nearest (ties to the smaller t), i.e. the number of level midpoints
+// strictly above phi.  The inverse table gives a start row; the two bounded
+// walks make the result exact whatever the bin rounding.
 template <typename T>
-__device__ __forceinline__ int elev_index(const SensorTab<T> &S, int l, T sz)
+__device__ __forceinline__ int elev_index(const T *mu, const int32_t *bins, T bin_lo, T bin_scale, int nb, int Hl,
+                                          T sz)
 {
-    int Hl = S.H >> l;
     if (Hl <= 1)
         return 0;
-    T f = (sz - S.bin_lo[l]) * S.bin_scale[l];
-    const T fmaxb = (T)(S.nbins[l] - 1);
+    T f = (sz - bin_lo) * bin_scale;
+    const T fmaxb = (T)(nb - 1);
     f = f >= (T)0 ? f : (T)0;  // also maps NaN to bin 0
     f = f < fmaxb ? f : fmaxb;
-    int v = S.bins[l][(int)f];
-    const T *mu = S.mu[l];
+    int v = bins[(int)f];
     while (v < Hl - 1 && mu[v] > sz)
         ++v;
     while (v > 0 && mu[v - 1] <= sz)
@@ -141,44 +180,68 @@ __device__ __forceinline__ int elev_index(const SensorTab<T> &S, int l, T sz)
     return v;
 }
 
-// Eq. (3)-(4) at level l: receiver-offset compensation (kR0Rounds rounds when
-// r0 > 0), range, elevation row by the inverse table, column by the azimuth
-// minus the row's offset, rounded half up and wrapped (Sec. 4.1: continuous
-// geometry at the finest level, nearest strided row and column).  Returns
-// false outside the elevation field of view or at r = 0.
+// Eq. (3)-(4) at the view's level.  With r0 > 0 the receiver offset is
+// compensated exactly (Sec. 3.2 iterates towards the same fixed point): for
+// beam v the ray leaving the receiver at encoder angle a reaches p iff, seen
+// from the axis, p = r0 (cos a, sin a) + t (cos(a + th_v), sin(a + th_v))
+// horizontally, so t = sqrt(rho^2 - r0^2 sin^2 th_v) - r0 cos th_v
+// (rho = |p_xy|) and the ray azimuth is atan2(p_y, p_x) - atan2(t sin th_v,
+// r0 + t cos th_v) + th_v; only the beam index is iterated (it changes only
+// near an elevation midpoint).  Points within 2 r0 of the axis do not
+// project.  Then the range, the elevation row by the inverse table and the
+// column from the azimuth minus the row's offset, rounded half up and wrapped
+// (Sec. 4.1: continuous geometry at the finest level, nearest strided row and
+// column).  Returns false outside the elevation field of view or at r = 0.
 template <typename T>
-__device__ __forceinline__ bool project(const SensorTab<T> &S, int l, T x, T y, T z, int &ul, int &vl, T &r)
+__device__ __forceinline__ bool project(const LevelView<T> &V, T x, T y, T z, int &ul, int &vl, T &r)
 {
-    T xp = x, yp = y;
-    if (S.r0 > (T)0) {
-        T a = d_atan2(y, x);
-        for (int k = 0; k < kR0Rounds; ++k) {
-            T sa, ca;
-            d_sincos(a, &sa, &ca);
-            T xk = x - S.r0 * ca, yk = y - S.r0 * sa;
-            T rk2 = xk * xk + yk * yk + z * z;
-            T sk = rk2 > (T)0 ? z * d_rsqrt(rk2) : (T)0;
-            int vk = elev_index(S, 0, sk);
-            a = d_atan2(yk, xk) - S.theta[vk];
+    T r2, th;
+    if (V.r0 > (T)0) {
+        const SensorTab<T> &S = *V.tab;
+        const T *mu0 = S.mu[0], *theta = S.theta;
+        const int32_t *bins0 = S.bins[0];
+        const T lo0 = S.bin_lo[0], sc0 = S.bin_scale[0];
+        const int nb0 = S.nbins[0], H = S.H;
+        const T r0 = V.r0, rho2 = x * x + y * y, z2 = z * z;
+        if (!(rho2 > (T)4 * r0 * r0))
+            return false;
+        T t = sqrt(rho2 - r0 * r0);
+        int v = elev_index(mu0, bins0, lo0, sc0, nb0, H, z * d_rsqrt(t * t + z2));
+        T cth = (T)1, sth = (T)0;
+        for (int k = 0; k < 4; ++k) {
+            cth = V.row[4 * v + 2];
+            sth = V.row[4 * v + 3];
+            t = sqrt(rho2 - r0 * r0 * sth * sth) - r0 * cth;
+            if (k == 3)
+                break;
+            const int vn = elev_index(mu0, bins0, lo0, sc0, nb0, H, z * d_rsqrt(t * t + z2));
+            if (vn == v)
+                break;
+            v = vn;
         }
-        T sa, ca;
-        d_sincos(a, &sa, &ca);
-        xp = x - S.r0 * ca;
-        yp = y - S.r0 * sa;
+        r2 = t * t + z2;
+        th = d_atan2(y, x) - d_atan2(t * sth, r0 + t * cth) + theta[v];
+        if (th < (T)0)
+            th += two_pi<T>();
+        if (th < (T)0)
+            th += two_pi<T>();
+        if (th >= two_pi<T>())
+            th -= two_pi<T>();
+    } else {
+        r2 = x * x + y * y + z * z;
+        th = d_atan2(y, x);
+        if (th < (T)0)
+            th += two_pi<T>();
     }
-    T r2 = xp * xp + yp * yp + z * z;
     if (!(r2 > (T)0))
         return false;
-    T rinv = d_rsqrt(r2);
-    T sz = z * rinv;
-    if (!(sz <= S.s_hi && sz >= S.s_lo))
+    const T rinv = d_rsqrt(r2);
+    const T sz = z * rinv;
+    if (!(sz <= V.s_hi && sz >= V.s_lo))
         return false;
-    int v = elev_index(S, l, sz);
-    T th = d_atan2(yp, xp);
-    if (th < (T)0)
-        th += two_pi<T>();
-    int Wl = S.W >> l;
-    T uh = th * S.kW[l] - S.uoff[l][v];
+    const int v = elev_index(V.mu, V.bins, V.bin_lo, V.bin_scale, V.nb, V.Hl, sz);
+    const int Wl = V.Wl;
+    T uh = th * V.kW - V.uoff[v];
     if (uh < (T)0)
         uh += (T)Wl;
     if (uh >= (T)Wl)
@@ -200,7 +263,20 @@ __device__ __forceinline__ bool project(const SensorTab<T> &S, int l, T x, T y, 
 // validity predicate is evaluated in FP64 on the FP32 ranges.  Returns false
 // (and leaves n untouched) for invalid pixels.
 template <typename T>
-__device__ __forceinline__ bool normal_at(const SensorTab<T> &S, const float *rng, int u, int v, double edge_rel,
+struct NormalView {
+    const T *row, *col, *nrow;
+    T r0, cos_h, sin_h;
+    int H, W;
+};
+
+template <typename T>
+__device__ __forceinline__ NormalView<T> normal_view(const SensorTab<T> &S)
+{
+    return NormalView<T>{S.row, S.col, S.nrow, S.r0, S.cos_h, S.sin_h, S.H, S.W};
+}
+
+template <typename T>
+__device__ __forceinline__ bool normal_at(const NormalView<T> &S, const float *rng, int u, int v, double edge_rel,
                                           V3<T> &n)
 {
     const int H = S.H, W = S.W;

@@ -49,12 +49,13 @@ struct StepArgs {
     const int2 *tiles;   // (pair, first pixel) of every tile of this level
     int n_tiles;
     int level, iter, levels;
-    int tile_px;         // pixels per tile = block * px_per_thread
+    int tile_px;         // pixels per tile = block * px_per_thread at this level
+    int chunk;           // pixels each thread keeps in flight (1, 2 or 4)
     int xcd_remap;
     int mode;            // StepMode
+    int learned;         // the normal pass uses learned weights
     void *psum;          // T[n_tiles][kAccum]
     int4 *pcnt;          // [n_tiles] (n_valid, n_inlier, n_proj, 0)
-    int *counters;       // [n_pairs] tiles finished in the current launch
     double *poses;       // [n_pairs][16]
     rir_level_stats *stats;  // [n_pairs][levels] (debug: [1])
     int *flags;          // [n_pairs][kFlagStride]
@@ -76,7 +77,6 @@ struct PrepArgs {
     int init_centroid;  // 1: compute t0 from the point-set centres
     double edge_rel;
     void *psum;         // T[n_tiles][kAccum] (centroid sums)
-    int *counters;
     double *poses;
     int xcd_remap;
 };
@@ -90,7 +90,8 @@ hipError_t launch_project(const SensorTab<float> &S, int level, const float *xyz
 hipError_t launch_normals(const SensorTab<float> &S, const float *range, double edge_rel, float *nrm,
                           uint8_t *valid, hipStream_t stream);
 hipError_t launch_clear(int *flags, int n_flags, rir_level_stats *stats, int n_stats, hipStream_t stream);
-hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, hipStream_t stream);
+hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, int n_pairs, hipStream_t stream);
+hipError_t launch_solve(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream);
 hipError_t launch_step(bool fp64, int weight_mode, const StepArgs &a, int grid, int block, hipStream_t stream);
 
 // Learned-weight network (mlp.hip).

@@ -141,7 +141,24 @@ def test_fp64_mode_matches_oracle_tightly(rir, ctx):
 
 
 def test_self_registration_is_identity(rir, ctx):
+    """At the identity every source pixel projects onto itself (lossless
+    round trip), so every residual is exactly zero and the pose stays I."""
     pair = _pair("pair64", 5)
+    sen = rir.Sensor.from_model(pair.sensor)
+    img = to_dev(pair.dst)
+    img2 = to_dev(pair.dst)
+    prm = rir.make_params(levels=3, iters=[1, 1, 1])
+    for lvl in range(3):
+        d = rir.debug_associate(ctx, prm, sen, img, img2, lvl, np.eye(4))
+        e = d["e"].cpu().numpy()
+        m = d["mask"].cpu().numpy().astype(bool)
+        s = 1 << lvl
+        vv, uu = np.meshgrid(np.arange(pair.sensor.H // s), np.arange(pair.sensor.W // s), indexing="ij")
+        u, v = d["u"].cpu().numpy(), d["v"].cpu().numpy()
+        src_ok = pair.dst[::s, ::s] > 0
+        moved = src_ok & ((u != uu) | (v != vv))
+        assert not moved.any(), (lvl, np.argwhere(moved)[:5], u[moved][:5], v[moved][:5])
+        assert np.all(e[m] == 0.0), (lvl, np.argwhere(m & (e != 0))[:5], e[m & (e != 0)][:5])
     same = synth.Pair(pair.sensor, pair.dst, pair.dst, np.eye(4), 5)
     Tg, st = _run_gpu(rir, ctx, pair.sensor, [same], [3, 3, 3], 3)
     np.testing.assert_array_equal(Tg[0], np.eye(4))
