@@ -75,8 +75,8 @@ typedef struct rir_mlp rir_mlp;
  * offset theta_lut[H] (radians, |theta| < pi, NULL = all zero) and receiver
  * radius r0 >= 0 (metres).  Both tables are host arrays, copied at creation.
  * inv_bins: minimum bin count of the inverse elevation table per pyramid
- * level (0 = automatic: at least 2 H_l, more if needed so that each bin holds
- * at most one row boundary; Sec. 3.2). */
+ * level (0 = automatic: at least 2 H_l and two per smallest gap between row
+ * boundaries, doubled until no bin holds two distinct boundaries; Sec. 3.2). */
 typedef struct {
     int32_t H, W;
     const double *phi_lut;
@@ -143,8 +143,8 @@ typedef struct {
  * thread visits per finest-level tile (1..16; level l uses px_per_thread /
  * 4^l, at least 1); grid_mult: persistent workgroups per compute unit (0 =
  * one workgroup per tile); xcd_remap: 1 maps consecutive tiles to the same
- * XCD (L2) of the chip; chunk: pixels whose loads each thread keeps in
- * flight together (1, 2 or 4). */
+ * XCD (L2) of the chip; chunk: 64-pixel row segments whose loads each
+ * wavefront keeps in flight together (1, 2 or 4). */
 typedef struct {
     int32_t block, px_per_thread, grid_mult, xcd_remap, chunk;
 } rir_tuning;
@@ -160,6 +160,24 @@ typedef struct {
  * released with rir_sensor_destroy. */
 rir_status rir_sensor_create(const rir_sensor_desc *desc, rir_sensor **out);
 void rir_sensor_destroy(rir_sensor *sensor);
+
+/* Host copy of the inverse elevation table that rir_sensor_create builds for
+ * pyramid level `level` (Sec. 3.2, Eq. (4)); no device is used (inspection
+ * and tests).  precision (RIR_PREC_*) selects the FP32 or FP64 table.
+ * Entry b is 4 values of that type at entries[4b .. 4b+3] and covers every
+ * sz = sin(phi) that the kernels map to bin b = trunc(clamp((sz - bin_lo) *
+ * bin_scale, 0, nbins - 1)), evaluated in that type with bin_lo, bin_scale
+ * and nbins - 1 rounded to it: the low 32 bits of the first value hold
+ * c | k << 16, then m, uoff(c), uoff(c + k).  The row of sz at the level is
+ * c + k [m > sz] (the nearest row, ties to the smaller index) and uoff(t) =
+ * theta_lut[2^l t] W / (2 pi 2^l) its column offset.  *nbins receives the
+ * entry count and bin_lo / bin_scale (nullable) the FP64 bin parameters;
+ * entries may be NULL to query only, else it holds capacity values (at least
+ * 4 * nbins).  Errors: as rir_sensor_create (no RIR_E_OOM / RIR_E_HIP), and
+ * RIR_E_INVALID for a null desc or nbins, an unknown precision, a level
+ * outside the sensor's pyramid or a capacity below 4 * nbins. */
+rir_status rir_elevation_table(const rir_sensor_desc *desc, int32_t level, int32_t precision, void *entries,
+                               int64_t capacity, int64_t *nbins, double *bin_lo, double *bin_scale);
 
 /* ---------------------------------------------------------------- contexts */
 

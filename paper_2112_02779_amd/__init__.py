@@ -30,6 +30,7 @@ EXPORTS = [
     "rir_ctx_get_tuning", "rir_ctx_enable_timing", "rir_ctx_level_times", "rir_unproject", "rir_project",
     "rir_normals", "rir_icp_batch", "rir_debug_associate", "rir_autotune", "rir_mlp_create", "rir_mlp_destroy",
     "rir_mlp_get_params", "rir_mlp_set_params", "rir_mlp_forward", "rir_mlp_train_step", "rir_last_error",
+    "rir_elevation_table",
 ]
 
 
@@ -115,6 +116,8 @@ def lib():
         "rir_mlp_forward": [vp, vp, i64, vp, vp],
         "rir_mlp_train_step": [vp, vp, vp, i64, f32, vp, vp, vp],
         "rir_last_error": [],
+        "rir_elevation_table": [ctypes.POINTER(SensorDesc), i32, i32, vp, i64, ctypes.POINTER(i64),
+                                ctypes.POINTER(f64), ctypes.POINTER(f64)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -180,6 +183,25 @@ class Sensor:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.rir_sensor_destroy(self.handle)
             self.handle = None
+
+
+def elevation_table(m, level: int, fp64: bool = False, inv_bins: int = 0):
+    """Host copy of the packed inverse elevation table of pyramid level
+    `level` for the sensor model m (H, W, phi, theta, r0): (entries
+    [nbins, 4] of float32 or float64, bin_lo, bin_scale).  No device is used."""
+    phi = np.ascontiguousarray(m.phi, dtype=np.float64)
+    theta = None if m.theta is None else np.ascontiguousarray(m.theta, dtype=np.float64)
+    d = SensorDesc(int(m.H), int(m.W), phi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   None if theta is None else theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   float(m.r0), int(inv_bins))
+    nb, lo, sc = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    prec = PREC_FP64 if fp64 else PREC_FP32
+    _check(lib().rir_elevation_table(ctypes.byref(d), int(level), prec, None, 0, ctypes.byref(nb), ctypes.byref(lo),
+                                     ctypes.byref(sc)))
+    out = np.zeros((nb.value, 4), dtype=np.float64 if fp64 else np.float32)
+    _check(lib().rir_elevation_table(ctypes.byref(d), int(level), prec, out.ctypes.data, out.size, ctypes.byref(nb),
+                                     None, None))
+    return out, lo.value, sc.value
 
 
 class Context:

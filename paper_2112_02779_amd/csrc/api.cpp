@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "elev_table.h"
 #include "rir.h"
 #include "rir_internal.h"
 
@@ -85,17 +86,19 @@ namespace {
 struct HostTables {
     std::vector<double> row, col, nrow, theta;
     std::vector<double> mu[kMaxLevels], uoff[kMaxLevels];
-    std::vector<int32_t> bins[kMaxLevels];
-    double s_lo, s_hi, cos_h, sin_h;
-    double bin_lo[kMaxLevels], bin_scale[kMaxLevels], kW[kMaxLevels];
+    double s_lo, s_hi, cos_h, sin_h, lo, hi;
+    double kW[kMaxLevels];
+    long nbins[kMaxLevels];
+    std::vector<float> ebin_f[kMaxLevels];
+    std::vector<double> ebin_d[kMaxLevels];
 };
 
 // FP64 construction of the tables of Sec. 3: the factors of Eq. (1), the
 // product-form neighbour-difference factors, and per level the sin of the
-// elevation midpoints between strided rows with an inverse table over
-// sin(phi) (Sec. 3.2: 2 H_l bins at least, more when a bin would hold two
-// boundaries).
-void build_tables(const rir_sensor &s, int inv_bins, HostTables &t)
+// elevation midpoints between strided rows with the packed inverse table over
+// sin(phi) (Sec. 3.2): 2 H_l bins at least, and at least two per smallest
+// midpoint gap, doubled until no bin holds two distinct midpoints.
+bool build_tables(const rir_sensor &s, int inv_bins, HostTables &t)
 {
     const int H = s.H, W = s.W;
     t.row.resize(4 * H);
@@ -132,16 +135,16 @@ void build_tables(const rir_sensor &s, int inv_bins, HostTables &t)
     t.s_lo = phi_lo <= -0.5 * M_PI ? -INFINITY : std::sin(phi_lo);
     t.cos_h = std::cos(kTwoPi / W);
     t.sin_h = std::sin(kTwoPi / W);
-    const double lo = std::isfinite(t.s_lo) ? t.s_lo : -1.0;
-    const double hi = std::isfinite(t.s_hi) ? t.s_hi : 1.0;
+    t.lo = std::isfinite(t.s_lo) ? t.s_lo : -1.0;
+    t.hi = std::isfinite(t.s_hi) ? t.s_hi : 1.0;
     for (int l = 0; l < s.nlev; ++l) {
         const int st = 1 << l, Hl = H / st;
         t.kW[l] = (double)W / (kTwoPi * st);
         t.uoff[l].resize(Hl);
         for (int k = 0; k < Hl; ++k)
             t.uoff[l][k] = s.theta[st * k] * (double)W / (kTwoPi * st);
-        t.mu[l].assign(std::max(Hl - 1, 1), 0.0);
-        double gmin = hi - lo;
+        t.mu[l].assign(std::max(Hl - 1, 0), 0.0);
+        double gmin = t.hi - t.lo;
         for (int k = 0; k + 1 < Hl; ++k) {
             t.mu[l][k] = std::sin(0.5 * (s.phi[st * k] + s.phi[st * (k + 1)]));
             if (k > 0)
@@ -149,25 +152,22 @@ void build_tables(const rir_sensor &s, int inv_bins, HostTables &t)
         }
         long nb = std::max<long>(2L * Hl, std::max(inv_bins, 2));
         if (Hl > 2 && gmin > 0)
-            nb = std::max<long>(nb, (long)std::ceil((hi - lo) / gmin) + 1);
-        nb = std::min<long>(nb, 1L << 16);
-        t.bin_lo[l] = lo;
-        t.bin_scale[l] = (double)nb / (hi - lo);
-        t.bins[l].resize(nb);
-        for (long b = 0; b < nb; ++b) {
-            const double top = lo + (double)(b + 1) / t.bin_scale[l];
-            int c = 0;
-            while (c < Hl - 1 && t.mu[l][c] > top)
-                ++c;
-            t.bins[l][b] = c;
+            nb = std::max<long>(nb, (long)std::ceil(2.0 * (t.hi - t.lo) / gmin) + 1);
+        for (;; nb *= 2) {
+            if (nb > (1L << 20))
+                return false;
+            if (build_ebin<float>(t.mu[l], t.uoff[l], nb, t.lo, t.hi, t.ebin_f[l]) &&
+                build_ebin<double>(t.mu[l], t.uoff[l], nb, t.lo, t.hi, t.ebin_d[l]))
+                break;
         }
+        t.nbins[l] = nb;
     }
+    return true;
 }
 
 template <typename T>
 void fill_tab(SensorTab<T> &tab, const rir_sensor &s, const HostTables &t, char *base, const size_t *off_row,
-              const size_t *off_col, const size_t *off_nrow, const size_t *off_theta, const size_t *off_mu,
-              const size_t *off_uoff, const size_t *off_bins)
+              const size_t *off_col, const size_t *off_nrow, const size_t *off_theta, const size_t *off_ebin)
 {
     tab.H = s.H;
     tab.W = s.W;
@@ -183,18 +183,15 @@ void fill_tab(SensorTab<T> &tab, const rir_sensor &s, const HostTables &t, char 
     tab.theta = reinterpret_cast<const T *>(base + *off_theta);
     for (int l = 0; l < kMaxLevels; ++l) {
         if (l < s.nlev) {
-            tab.nbins[l] = (int)t.bins[l].size();
-            tab.bin_lo[l] = (T)t.bin_lo[l];
-            tab.bin_scale[l] = (T)t.bin_scale[l];
+            tab.nbins[l] = (int)t.nbins[l];
+            tab.bin_lo[l] = (T)t.lo;
+            tab.bin_scale[l] = (T)((double)t.nbins[l] / (t.hi - t.lo));
             tab.kW[l] = (T)t.kW[l];
-            tab.mu[l] = reinterpret_cast<const T *>(base + off_mu[l]);
-            tab.uoff[l] = reinterpret_cast<const T *>(base + off_uoff[l]);
-            tab.bins[l] = reinterpret_cast<const int32_t *>(base + off_bins[l]);
+            tab.ebin[l] = reinterpret_cast<const T *>(base + off_ebin[l]);
         } else {
             tab.nbins[l] = 0;
             tab.bin_lo[l] = tab.bin_scale[l] = tab.kW[l] = (T)0;
-            tab.mu[l] = tab.uoff[l] = nullptr;
-            tab.bins[l] = nullptr;
+            tab.ebin[l] = nullptr;
         }
     }
 }
@@ -209,55 +206,101 @@ void put(std::vector<char> &img, size_t off, const std::vector<double> &v)
 
 }  // namespace
 
+namespace {
+
+// Validates a sensor description and copies it into s (no device work).
+rir_status read_desc(const rir_sensor_desc *desc, rir_sensor &s, const char *who)
+{
+    const std::string w(who);
+    const int H = desc->H, W = desc->W;
+    if (H < 2 || W < 4)
+        return fail(RIR_E_LUT, w + ": need H >= 2 and W >= 4");
+    if (!desc->phi_lut)
+        return fail(RIR_E_INVALID, w + ": phi_lut is null");
+    if (!(desc->r0 >= 0.0) || !std::isfinite(desc->r0))
+        return fail(RIR_E_LUT, w + ": r0 must be finite and >= 0");
+    s.H = H;
+    s.W = W;
+    s.r0 = desc->r0;
+    s.phi.assign(desc->phi_lut, desc->phi_lut + H);
+    s.theta.assign(H, 0.0);
+    if (desc->theta_lut)
+        s.theta.assign(desc->theta_lut, desc->theta_lut + H);
+    for (int v = 0; v < H; ++v) {
+        if (!std::isfinite(s.phi[v]) || std::fabs(s.phi[v]) >= 0.5 * M_PI)
+            return fail(RIR_E_LUT, w + ": phi_lut entries must be finite with |phi| < pi/2");
+        if (v > 0 && !(s.phi[v] < s.phi[v - 1]))
+            return fail(RIR_E_LUT, w + ": phi_lut must be strictly decreasing (row 0 = top beam)");
+        if (!std::isfinite(s.theta[v]) || std::fabs(s.theta[v]) >= M_PI)
+            return fail(RIR_E_LUT, w + ": theta_lut entries must be finite with |theta| < pi");
+    }
+    int nlev = 0;
+    while (nlev < kMaxLevels && H % (1 << nlev) == 0 && W % (1 << nlev) == 0 && (W >> nlev) >= 2)
+        ++nlev;
+    s.nlev = nlev;
+    return RIR_OK;
+}
+
+}  // namespace
+
+extern "C" rir_status rir_elevation_table(const rir_sensor_desc *desc, int32_t level, int32_t precision,
+                                          void *entries, int64_t capacity, int64_t *nbins, double *bin_lo,
+                                          double *bin_scale)
+{
+    if (!desc || !nbins)
+        return fail(RIR_E_INVALID, "rir_elevation_table: null argument");
+    if (precision != RIR_PREC_FP32 && precision != RIR_PREC_FP64)
+        return fail(RIR_E_INVALID, "rir_elevation_table: unknown precision");
+    rir_sensor s;
+    rir_status st = read_desc(desc, s, "rir_elevation_table");
+    if (st != RIR_OK)
+        return st;
+    if (level < 0 || level >= s.nlev)
+        return fail(RIR_E_INVALID, "rir_elevation_table: level outside the sensor's pyramid");
+    HostTables t;
+    if (!build_tables(s, std::max(desc->inv_bins, 0), t))
+        return fail(RIR_E_LUT, "rir_elevation_table: elevation midpoints too close for the inverse table");
+    const int64_t nb = t.nbins[level];
+    *nbins = nb;
+    if (bin_lo)
+        *bin_lo = t.lo;
+    if (bin_scale)
+        *bin_scale = (double)nb / (t.hi - t.lo);
+    if (!entries)
+        return RIR_OK;
+    if (capacity < 4 * nb)
+        return fail(RIR_E_INVALID, "rir_elevation_table: capacity below 4 * nbins");
+    if (precision == RIR_PREC_FP32)
+        std::memcpy(entries, t.ebin_f[level].data(), 4 * sizeof(float) * nb);
+    else
+        std::memcpy(entries, t.ebin_d[level].data(), 4 * sizeof(double) * nb);
+    return RIR_OK;
+}
+
 extern "C" rir_status rir_sensor_create(const rir_sensor_desc *desc, rir_sensor **out)
 {
     if (!desc || !out)
         return fail(RIR_E_INVALID, "rir_sensor_create: null argument");
     *out = nullptr;
-    const int H = desc->H, W = desc->W;
-    if (H < 2 || W < 4)
-        return fail(RIR_E_LUT, "rir_sensor_create: need H >= 2 and W >= 4");
-    if (!desc->phi_lut)
-        return fail(RIR_E_INVALID, "rir_sensor_create: phi_lut is null");
-    if (!(desc->r0 >= 0.0) || !std::isfinite(desc->r0))
-        return fail(RIR_E_LUT, "rir_sensor_create: r0 must be finite and >= 0");
     std::unique_ptr<rir_sensor> s(new rir_sensor());
-    s->H = H;
-    s->W = W;
-    s->r0 = desc->r0;
-    s->phi.assign(desc->phi_lut, desc->phi_lut + H);
-    s->theta.assign(H, 0.0);
-    if (desc->theta_lut)
-        s->theta.assign(desc->theta_lut, desc->theta_lut + H);
-    for (int v = 0; v < H; ++v) {
-        if (!std::isfinite(s->phi[v]) || std::fabs(s->phi[v]) >= 0.5 * M_PI)
-            return fail(RIR_E_LUT, "rir_sensor_create: phi_lut entries must be finite with |phi| < pi/2");
-        if (v > 0 && !(s->phi[v] < s->phi[v - 1]))
-            return fail(RIR_E_LUT, "rir_sensor_create: phi_lut must be strictly decreasing (row 0 = top beam)");
-        if (!std::isfinite(s->theta[v]) || std::fabs(s->theta[v]) >= M_PI)
-            return fail(RIR_E_LUT, "rir_sensor_create: theta_lut entries must be finite with |theta| < pi");
-    }
-    int nlev = 0;
-    while (nlev < kMaxLevels && H % (1 << nlev) == 0 && W % (1 << nlev) == 0 && (W >> nlev) >= 2)
-        ++nlev;
-    s->nlev = nlev;
+    rir_status st = read_desc(desc, *s, "rir_sensor_create");
+    if (st != RIR_OK)
+        return st;
+    const int nlev = s->nlev;
     HIP_TRY(hipGetDevice(&s->device));
     HostTables t;
-    build_tables(*s, std::max(desc->inv_bins, 0), t);
+    if (!build_tables(*s, std::max(desc->inv_bins, 0), t))
+        return fail(RIR_E_LUT, "rir_sensor_create: elevation midpoints too close for the inverse table");
 
     Layout lay;
     size_t od_row = lay.add(8 * t.row.size()), od_col = lay.add(8 * t.col.size());
     size_t od_nrow = lay.add(8 * t.nrow.size()), od_theta = lay.add(8 * t.theta.size());
     size_t of_row = lay.add(4 * t.row.size()), of_col = lay.add(4 * t.col.size());
     size_t of_nrow = lay.add(4 * t.nrow.size()), of_theta = lay.add(4 * t.theta.size());
-    size_t od_mu[kMaxLevels] = {}, of_mu[kMaxLevels] = {}, od_uoff[kMaxLevels] = {}, of_uoff[kMaxLevels] = {};
-    size_t o_bins[kMaxLevels] = {};
+    size_t od_ebin[kMaxLevels] = {}, of_ebin[kMaxLevels] = {};
     for (int l = 0; l < nlev; ++l) {
-        od_mu[l] = lay.add(8 * t.mu[l].size());
-        of_mu[l] = lay.add(4 * t.mu[l].size());
-        od_uoff[l] = lay.add(8 * t.uoff[l].size());
-        of_uoff[l] = lay.add(4 * t.uoff[l].size());
-        o_bins[l] = lay.add(4 * t.bins[l].size());
+        od_ebin[l] = lay.add(8 * t.ebin_d[l].size());
+        of_ebin[l] = lay.add(4 * t.ebin_f[l].size());
     }
     size_t o_tf = lay.add(sizeof(SensorTab<float>)), o_td = lay.add(sizeof(SensorTab<double>));
     std::vector<char> img(lay.bytes, 0);
@@ -270,16 +313,13 @@ extern "C" rir_status rir_sensor_create(const rir_sensor_desc *desc, rir_sensor 
     put<float>(img, of_nrow, t.nrow);
     put<float>(img, of_theta, t.theta);
     for (int l = 0; l < nlev; ++l) {
-        put<double>(img, od_mu[l], t.mu[l]);
-        put<float>(img, of_mu[l], t.mu[l]);
-        put<double>(img, od_uoff[l], t.uoff[l]);
-        put<float>(img, of_uoff[l], t.uoff[l]);
-        std::memcpy(img.data() + o_bins[l], t.bins[l].data(), 4 * t.bins[l].size());
+        std::memcpy(img.data() + od_ebin[l], t.ebin_d[l].data(), 8 * t.ebin_d[l].size());
+        std::memcpy(img.data() + of_ebin[l], t.ebin_f[l].data(), 4 * t.ebin_f[l].size());
     }
     HIP_TRY(hipMalloc(&s->dmem, lay.bytes));
     char *base = static_cast<char *>(s->dmem);
-    fill_tab(s->tf, *s, t, base, &of_row, &of_col, &of_nrow, &of_theta, of_mu, of_uoff, o_bins);
-    fill_tab(s->td, *s, t, base, &od_row, &od_col, &od_nrow, &od_theta, od_mu, od_uoff, o_bins);
+    fill_tab(s->tf, *s, t, base, &of_row, &of_col, &of_nrow, &of_theta, of_ebin);
+    fill_tab(s->td, *s, t, base, &od_row, &od_col, &od_nrow, &od_theta, od_ebin);
     std::memcpy(img.data() + o_tf, &s->tf, sizeof(s->tf));
     std::memcpy(img.data() + o_td, &s->td, sizeof(s->td));
     HIP_TRY(hipMemcpy(s->dmem, img.data(), lay.bytes, hipMemcpyHostToDevice));
@@ -344,7 +384,7 @@ struct Plan {
     int device = 0;
     int n_pairs = 0;
     bool fp64 = false;
-    int tile_px[kMaxLevels] = {}, block = 0;
+    int tile_seg[kMaxLevels] = {}, block = 0;
     int n_tiles[kMaxLevels] = {};
     int grid[kMaxLevels] = {};
     void *dmem = nullptr;
@@ -563,21 +603,22 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     const size_t tsz = P->fp64 ? sizeof(double) : sizeof(float);
     const int L = key.k.levels;
     P->block = key.k.tune.block;
+    // a tile is block * px_per_thread pixels (in 64-pixel row segments);
     // coarser levels have 4x fewer pixels each: shrink the pixels per thread
     // with them (down to one) so that they still spread over the whole chip
     for (int l = 0; l < L; ++l)
-        P->tile_px[l] = key.k.tune.block * std::max(1, key.k.tune.px_per_thread >> (2 * l));
+        P->tile_seg[l] = key.k.tune.block / kSegPx * std::max(1, key.k.tune.px_per_thread >> (2 * l));
     std::vector<std::vector<int2>> tiles(L);
     std::vector<int> t0(n * kMaxLevels, 0), nt(n * kMaxLevels, 0);
     for (int l = 0; l < L; ++l) {
         for (int i = 0; i < n; ++i) {
             const rir_sensor *s = pairs[i].sensor;
-            const int Nl = (s->H >> l) * (s->W >> l);
-            const int k = (Nl + P->tile_px[l] - 1) / P->tile_px[l];
+            const int nseg = (s->H >> l) * (((s->W >> l) + kSegPx - 1) / kSegPx);
+            const int k = (nseg + P->tile_seg[l] - 1) / P->tile_seg[l];
             t0[i * kMaxLevels + l] = (int)tiles[l].size();
             nt[i * kMaxLevels + l] = k;
             for (int j = 0; j < k; ++j)
-                tiles[l].push_back(make_int2(i, j * P->tile_px[l]));
+                tiles[l].push_back(make_int2(i, j * P->tile_seg[l]));
         }
         P->n_tiles[l] = (int)tiles[l].size();
         int G = P->n_tiles[l];
@@ -640,7 +681,6 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
                 d->dstr[l] = nullptr;
                 d->dst4[l] = nullptr;
                 d->tile0[l] = d->ntile[l] = 0;
-                d->invW[l] = 0.f;
             }
             for (int l = 0; l < L; ++l) {
                 using TT = typename std::remove_pointer<typename std::remove_reference<decltype(d->dst4[0])>::type>::type;
@@ -651,7 +691,6 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
                 d->dst4[l] = reinterpret_cast<TT *>(base + o_dst4[i * kMaxLevels + l]);
                 d->tile0[l] = t0[i * kMaxLevels + l];
                 d->ntile[l] = nt[i * kMaxLevels + l];
-                d->invW[l] = 1.0f / (float)(s->W >> l);
             }
             set_desc_images(d, pairs[i]);
         };
@@ -760,7 +799,7 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
     a.level = level;
     a.iter = iter;
     a.levels = P->key.k.levels;
-    a.tile_px = P->tile_px[level];
+    a.tile_seg = P->tile_seg[level];
     a.chunk = P->key.k.tune.chunk;
     a.xcd_remap = P->key.k.tune.xcd_remap;
     a.mode = mode;
@@ -787,7 +826,7 @@ rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t s
     a.pairs = P->d_desc;
     a.tiles = P->d_tiles[0];
     a.n_tiles = P->n_tiles[0];
-    a.tile_px = P->tile_px[0];
+    a.tile_seg = P->tile_seg[0];
     a.levels = P->key.k.levels;
     a.init_centroid = p->init_mode == 1;
     a.edge_rel = p->edge_rel;
@@ -1077,7 +1116,7 @@ extern "C" rir_status rir_project(const rir_sensor *sensor, int32_t level, const
     if (n == 0)
         return RIR_OK;
     HIP_TRY(hipSetDevice(sensor->device));
-    HIP_TRY(launch_project(sensor->tf, level, xyz, n, u, v, r, valid, static_cast<hipStream_t>(stream)));
+    HIP_TRY(launch_project(sensor->d_tf, level, xyz, n, u, v, r, valid, static_cast<hipStream_t>(stream)));
     return RIR_OK;
 }
 

@@ -1,16 +1,18 @@
 // Kernels of the range-image ICP hot path on gfx950 (Dong et al., Sec. 3-4.1):
 //  - geometry entry points (unproject, project, normals);
 //  - the prepass: target normal image (cross product of neighbour
-//    differences) written at level 0 and subsampled into the strided pyramid
-//    levels together with the source ranges (Sec. 4.1);
+//    differences) written at level 0 as (n, n . q) records and subsampled
+//    into the strided pyramid levels together with the source and target
+//    ranges (Sec. 4.1);
 //  - the Gauss-Newton step: per source pixel unprojection, rigid transform,
 //    projection, projective association, residual, Jacobian and robust weight
 //    (Eq. (5)-(7)), accumulated in registers, reduced across the wavefront by
 //    recursive halving and across waves through LDS into one partial record
-//    per tile; the last workgroup to finish a pair sums that pair's tile
-//    records in FP64 in a fixed order, solves the 6x6 system by Cholesky and
-//    applies the SE(3) update.  No floating-point atomics: results are
-//    bitwise reproducible for a fixed tuning.
+//    per tile;
+//  - the solve: per pair, the tile records summed in FP64 in a fixed order,
+//    the 6x6 system solved by Cholesky and the SE(3) update applied.
+// No floating-point atomics: results are bitwise reproducible for a fixed
+// tuning.
 #include <float.h>
 
 #include "rir_internal.h"
@@ -44,21 +46,25 @@ __device__ __forceinline__ TileIter tile_iter(int n_tiles, int xcd_remap)
     return it;
 }
 
-// Row/column of pixel i in a W-wide image, from a float reciprocal and one
-// correction step (exact for i < 2^24).
-__device__ __forceinline__ void split_index(int i, int W, float invW, int &u, int &v)
+// Stores through global-address-space pointers (the generic form would
+// also wait on the LDS counter).
+__device__ __forceinline__ void gst4(float *p, V4<float> v)
 {
-    int q = (int)((float)i * invW);
-    int r = i - q * W;
-    if (r < 0) {
-        q -= 1;
-        r += W;
-    } else if (r >= W) {
-        q += 1;
-        r -= W;
-    }
-    u = r;
-    v = q;
+    typedef float vtype __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) vtype gtype;
+    *(gtype *)p = vtype{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ void gst4(double *p, V4<double> v)
+{
+    typedef double vtype __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) vtype gtype;
+    ((gtype *)p)[0] = vtype{v.x, v.y};
+    ((gtype *)p)[1] = vtype{v.z, v.w};
+}
+__device__ __forceinline__ void gst1(float *p, float v)
+{
+    typedef __attribute__((address_space(1))) float gtype;
+    *(gtype *)p = v;
 }
 
 // Sum of 32 per-lane values over the 64-lane wavefront by recursive halving:
@@ -111,10 +117,10 @@ __global__ void k_unproject(SensorTab<float> S, const float *range, float *xyz, 
     }
 }
 
-__global__ void k_project(SensorTab<float> S, int level, const float *xyz, int64_t n, int32_t *uo, int32_t *vo,
-                          float *ro, uint8_t *valid)
+__global__ void k_project(const SensorTab<float> *tab, int level, const float *xyz, int64_t n, int32_t *uo,
+                          int32_t *vo, float *ro, uint8_t *valid)
 {
-    const LevelView<float> V = level_view(S, level);
+    const LevelView<float> V = level_view(tab, level);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
         int u = -1, v = -1;
@@ -122,19 +128,18 @@ __global__ void k_project(SensorTab<float> S, int level, const float *xyz, int64
         const bool ok = project(V, x, y, z, u, v, r);
         uo[i] = ok ? u : -1;
         vo[i] = ok ? v : -1;
-        ro[i] = r;
+        ro[i] = ok ? r : sqrtf(x * x + y * y + z * z);
         valid[i] = ok ? 1 : 0;
     }
 }
 
 __global__ void k_normals(SensorTab<float> S, const float *range, double edge_rel, float *nrm, uint8_t *valid)
 {
-    const NormalView<float> NV = normal_view(S);
     const int N = S.H * S.W;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
         const int v = i / S.W, u = i - v * S.W;
         V3<float> n = {0.f, 0.f, 0.f};
-        const bool ok = normal_at(NV, range, u, v, edge_rel, n);
+        const bool ok = normal_at(S, range, u, v, edge_rel, n);
         nrm[3 * (size_t)i] = ok ? n.x : 0.f;
         nrm[3 * (size_t)i + 1] = ok ? n.y : 0.f;
         nrm[3 * (size_t)i + 2] = ok ? n.z : 0.f;
@@ -155,84 +160,86 @@ __global__ void k_clear(int *flags, int n_flags, rir_level_stats *stats, int n_s
 
 // ----------------------------------------------------------------------------- prepass
 
-// Normal image and pyramid (Sec. 4.1): one thread per level-0 pixel writes the
-// (normal, range) record of the target at level 0 and, for pixels on the grid
-// of level l, the strided copies of the target record, target range and
-// source range.  With init_centroid each tile also records the sums of its
-// valid source and target points (reduced per pair by k_centroid).
-constexpr int kPrepChunk = 4;
-
+// Normal image and pyramid (Sec. 4.1): each wavefront takes one segment of a
+// target row, computes the normals of its 64 pixels (row factors by scalar
+// loads, neighbour ranges by bounds-checked buffer loads) and writes the
+// (n, n . q) record at level 0 and, for pixels on the grid of level l, the
+// strided copies of the record, the target range and the source range.  With
+// init_centroid each tile also records the sums of its valid source and
+// target points (reduced per pair by k_centroid).
 template <typename T>
 __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
 {
     __shared__ T s_red[4][kAccum];
     const PairDesc<T> *pairs = reinterpret_cast<const PairDesc<T> *>(a.pairs);
     T *psum = reinterpret_cast<T *>(a.psum);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwave = blockDim.x >> 6;
     for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step) {
-        const int2 tl = a.tiles[it.cur];
-        const PairDesc<T> &P = pairs[tl.x];
-        const NormalView<T> NV = normal_view(*P.tab);
-        const int W = P.W, N = P.H * P.W;
-        const int end = min(tl.y + a.tile_px, N);
-        const float invW = P.invW[0];
-        const float *dr = P.dstr[0], *sr = P.src[0];
-        T *d40 = P.dst4[0];
+        const int2 tl = cload(a.tiles + it.cur);
+        const PairDesc<T> *P = pairs + tl.x;
+        const SensorTab<T> *S = cload(&P->tab);
+        const int H = cload(&P->H), W = cload(&P->W), spr = (W + kSegPx - 1) / kSegPx;
+        const int seg_end = min(tl.y + a.tile_seg, H * spr);
+        const uint32_t img = (uint32_t)(H * W) * 4u;
+        const rsrc_t drs = make_rsrc(cload(&P->dstr[0]), img), srs = make_rsrc(cload(&P->src[0]), img);
+        const rsrc_t crs = make_rsrc(cload(&S->col), (uint32_t)(W * 2 * sizeof(T)));
+        const T *rowt = cload(&S->row), *nrowt = cload(&S->nrow);
+        const T r0 = cload(&S->r0), cos_h = cload(&S->cos_h), sin_h = cload(&S->sin_h);
+        T *d40 = cload(&P->dst4[0]);
         T acc[kAccum];
 #pragma unroll
         for (int k = 0; k < kAccum; ++k)
             acc[k] = (T)0;
-        const int bd = blockDim.x;
-        for (int i0 = tl.y + tid; i0 - tid < end; i0 += kPrepChunk * bd) {
-            V4<T> rec[kPrepChunk];
-            float rcv[kPrepChunk], rsv[kPrepChunk];
-            int uu[kPrepChunk], vv[kPrepChunk];
-#pragma unroll
-            for (int j = 0; j < kPrepChunk; ++j) {
-                const int i = i0 + j * bd;
-                rec[j] = V4<T>{(T)0, (T)0, (T)0, (T)0};
-                rcv[j] = rsv[j] = 0.f;
-                uu[j] = vv[j] = 0;
-                if (i < end) {
-                    split_index(i, W, invW, uu[j], vv[j]);
-                    V3<T> n;
-                    rcv[j] = dr[i];
-                    rsv[j] = sr[i];
-                    if (normal_at(NV, dr, uu[j], vv[j], a.edge_rel, n))
-                        rec[j] = V4<T>{n.x, n.y, n.z, (T)rcv[j]};
+        for (int seg = tl.y + wave; seg < seg_end; seg += nwave) {
+            const int v = seg / spr, u = (seg - v * spr) * kSegPx + lane;
+            const bool in = u < W;
+            const int i = v * W + u;
+            const float rc = bld1<float>(drs, in ? 4u * (uint32_t)i : kNoLoad);
+            const float rs = bld1<float>(srs, in ? 4u * (uint32_t)i : kNoLoad);
+            T ca, sa;
+            bld2(crs, in ? (uint32_t)u * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca, sa);
+            const V4<T> rw = sld4(rowt, v);
+            V4<T> rec = {(T)0, (T)0, (T)0, (T)0};
+            if (v > 0 && v < H - 1) {
+                const int ul = u == 0 ? W - 1 : u - 1, ur = u == W - 1 ? 0 : u + 1;
+                const float rl = bld1<float>(drs, in ? 4u * (uint32_t)(v * W + ul) : kNoLoad);
+                const float rr = bld1<float>(drs, in ? 4u * (uint32_t)(v * W + ur) : kNoLoad);
+                const float ru = bld1<float>(drs, in ? 4u * (uint32_t)(i - W) : kNoLoad);
+                const float rd = bld1<float>(drs, in ? 4u * (uint32_t)(i + W) : kNoLoad);
+                V3<T> n;
+                if (normal_core(ca, sa, rw, sld4(rowt, v + 1), sld4(rowt, v - 1), sld4(nrowt, 2 * v),
+                                sld4(nrowt, 2 * v + 1), r0, cos_h, sin_h, rc, rl, rr, ru, rd, a.edge_rel, n)) {
+                    const V3<T> d = ray_dir(rw, ca, sa);
+                    const T q0 = (T)rc * d.x + r0 * ca, q1 = (T)rc * d.y + r0 * sa, q2 = (T)rc * d.z;
+                    rec = V4<T>{n.x, n.y, n.z, n.x * q0 + n.y * q1 + n.z * q2};
                 }
             }
-#pragma unroll
-            for (int j = 0; j < kPrepChunk; ++j) {
-                const int i = i0 + j * bd;
-                if (i >= end)
-                    continue;
-                const int u = uu[j], v = vv[j];
-                st4(d40 + 4 * (size_t)i, rec[j]);
-                for (int l = 1; l < a.levels; ++l) {
-                    const int msk = (1 << l) - 1;
-                    if ((u & msk) == 0 && (v & msk) == 0) {
-                        const size_t q = (size_t)(v >> l) * (W >> l) + (u >> l);
-                        st4(P.dst4[l] + 4 * q, rec[j]);
-                        P.dstr[l][q] = rcv[j];
-                        P.src[l][q] = rsv[j];
-                    }
+            if (!in)
+                continue;
+            gst4(d40 + 4 * (size_t)i, rec);
+            for (int l = 1; l < a.levels; ++l) {
+                const int msk = (1 << l) - 1;
+                if ((u & msk) == 0 && (v & msk) == 0) {
+                    const size_t q = (size_t)(v >> l) * (W >> l) + (u >> l);
+                    gst4(cload(&P->dst4[l]) + 4 * q, rec);
+                    gst1(cload(&P->dstr[l]) + q, rc);
+                    gst1(cload(&P->src[l]) + q, rs);
                 }
-                if (a.init_centroid) {
-                    if (range_ok(rsv[j])) {
-                        V3<T> pp = unproject(NV.row, NV.col, NV.r0, u, v, (T)rsv[j]);
-                        acc[0] += pp.x;
-                        acc[1] += pp.y;
-                        acc[2] += pp.z;
-                        acc[3] += (T)1;
-                    }
-                    if (range_ok(rcv[j])) {
-                        V3<T> q = unproject(NV.row, NV.col, NV.r0, u, v, (T)rcv[j]);
-                        acc[4] += q.x;
-                        acc[5] += q.y;
-                        acc[6] += q.z;
-                        acc[7] += (T)1;
-                    }
+            }
+            if (a.init_centroid) {
+                const V3<T> d = ray_dir(rw, ca, sa);
+                if (range_ok(rs)) {
+                    acc[0] += (T)rs * d.x + r0 * ca;
+                    acc[1] += (T)rs * d.y + r0 * sa;
+                    acc[2] += (T)rs * d.z;
+                    acc[3] += (T)1;
+                }
+                if (range_ok(rc)) {
+                    acc[4] += (T)rc * d.x + r0 * ca;
+                    acc[5] += (T)rc * d.y + r0 * sa;
+                    acc[6] += (T)rc * d.z;
+                    acc[7] += (T)1;
                 }
             }
         }
@@ -283,12 +290,16 @@ __global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
 // ----------------------------------------------------------------------------- step
 
 // One Gauss-Newton iteration at level l for every pair of the batch (Eq. (5)-(7),
-// Sec. 4.1).  Each workgroup walks its tiles; a tile is a run of tile_px
-// consecutive source pixels of one pair's level-l image, and each thread takes
-// CHUNK of them at a time (pixels i0 + j * blockDim) so that CHUNK source
-// loads, then CHUNK target gathers, are in flight together.  The tile's sums
-// go to one record (k_solve reduces them).  FINE tags the finest-level
-// instance (same code) so that profiles report it separately.
+// Sec. 4.1).  Each workgroup walks its tiles; a tile is a run of tile_seg
+// segments of one pair's level-l image, and each wavefront takes CHUNK
+// segments at a time (its own 64-pixel pieces of CHUNK rows), so that CHUNK
+// source loads, then CHUNK target gathers, are in flight together.  Per
+// segment the row's ray frame is rotated once: x = r (ca g1 + sa g2 + g3) +
+// r0 R (ca, sa, 0) + t with g1 = R (cphi ctheta, cphi stheta, 0),
+// g2 = R (-cphi stheta, cphi ctheta, 0), g3 = sphi R e_z (Eq. (1) then the
+// pose).  The target record holds (n, n . q), so e = n . x - n . q.  The
+// tile's sums go to one record (k_solve reduces them).  FINE tags the
+// finest-level instance (same code) so that profiles report it separately.
 template <typename T, int WMODE, bool FINE, int CHUNK>
 __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
 {
@@ -296,7 +307,8 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
     __shared__ int s_wcnt[4][4];
     const PairDesc<T> *pairs = reinterpret_cast<const PairDesc<T> *>(a.pairs);
     T *psum = reinterpret_cast<T *>(a.psum);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwave = blockDim.x >> 6;
     const int l = a.level, s = 1 << l;
     const T delta = (T)a.delta, inv_delta = (T)(1.0 / a.delta);
     const T mc2 = a.max_corr > 0.0 ? (T)(a.max_corr * a.max_corr) : (T)-1;
@@ -305,95 +317,113 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
     if constexpr (WMODE == 1)
         mlp_load(a.mlp, F);
     for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step) {
-        const int2 tl = a.tiles[it.cur];
+        const int2 tl = cload(a.tiles + it.cur);
         const int pair = tl.x;
         if (!dbg) {
             const int *fl = a.flags + (size_t)pair * kFlagStride;
-            if (fl[l] & 1)
+            if (cload(fl + l) & 1)
                 continue;
-            if (a.mode == kStepFallback && !(fl[kMaxLevels] & 1))
+            if (a.mode == kStepFallback && !(cload(fl + kMaxLevels) & 1))
                 continue;
         }
-        const PairDesc<T> &P = pairs[pair];
-        const LevelView<T> V = level_view(*P.tab, l);
+        const PairDesc<T> *P = pairs + pair;
+        const LevelView<T> V = level_view(cload(&P->tab), l);
+        const LevelImage LI = {cload(&P->dstr[l]), V.Hl, V.Wl};
         const double *Tp = a.poses + 16 * (size_t)pair;
-        const T r00 = (T)Tp[0], r01 = (T)Tp[1], r02 = (T)Tp[2], t0 = (T)Tp[3];
-        const T r10 = (T)Tp[4], r11 = (T)Tp[5], r12 = (T)Tp[6], t1 = (T)Tp[7];
-        const T r20 = (T)Tp[8], r21 = (T)Tp[9], r22 = (T)Tp[10], t2 = (T)Tp[11];
-        const int Wl = P.W >> l, Nl = (P.H >> l) * Wl;
-        const int end = min(tl.y + a.tile_px, Nl);
-        const float invW = P.invW[l];
-        const float *srcl = P.src[l];
-        const T *d4 = P.dst4[l];
+        const T r00 = (T)cload(Tp + 0), r01 = (T)cload(Tp + 1), r02 = (T)cload(Tp + 2), t0 = (T)cload(Tp + 3);
+        const T r10 = (T)cload(Tp + 4), r11 = (T)cload(Tp + 5), r12 = (T)cload(Tp + 6), t1 = (T)cload(Tp + 7);
+        const T r20 = (T)cload(Tp + 8), r21 = (T)cload(Tp + 9), r22 = (T)cload(Tp + 10), t2 = (T)cload(Tp + 11);
+        const int Wl = V.Wl, Hl = V.Hl, spr = (Wl + kSegPx - 1) / kSegPx;
+        const int seg_end = min(tl.y + a.tile_seg, Hl * spr);
+        const uint32_t npx = (uint32_t)(Hl * Wl);
+        const rsrc_t srs = make_rsrc(cload(&P->src[l]), npx * 4u);
+        const rsrc_t drs = make_rsrc(cload(&P->dst4[l]), npx * (uint32_t)(4 * sizeof(T)));
+        const T r0 = V.r0;
         T acc[kAccum];
 #pragma unroll
         for (int k = 0; k < kAccum; ++k)
             acc[k] = (T)0;
         int c_valid = 0, c_in = 0, c_proj = 0;
-        const int bd = blockDim.x;
-        for (int i0 = tl.y + tid; i0 - tid < end; i0 += CHUNK * bd) {
+        for (int s0 = tl.y + wave; s0 < seg_end; s0 += CHUNK * nwave) {
             float rs[CHUNK];
+            T ca[CHUNK], sa[CHUNK];
+            int vs[CHUNK], us[CHUNK];
+            bool in[CHUNK];
 #pragma unroll
             for (int j = 0; j < CHUNK; ++j) {
-                const int i = i0 + j * bd;
-                rs[j] = i < end ? srcl[i] : 0.f;
+                const int seg = s0 + j * nwave;
+                const bool live = seg < seg_end;
+                const int v = live ? seg / spr : 0;
+                const int u = (seg - v * spr) * kSegPx + lane;
+                in[j] = live && u < Wl;
+                vs[j] = v;
+                us[j] = u;
+                rs[j] = bld1<float>(srs, in[j] ? 4u * (uint32_t)(v * Wl + u) : kNoLoad);
+                bld2(V.col, in[j] ? (uint32_t)(s * u) * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca[j], sa[j]);
             }
             bool proj[CHUNK];
             int ul[CHUNK], vl[CHUNK];
             T xx[CHUNK], xy[CHUNK], xz[CHUNK], xr[CHUNK];
 #pragma unroll
             for (int j = 0; j < CHUNK; ++j) {
-                proj[j] = false;
-                ul[j] = vl[j] = -1;
-                xx[j] = xy[j] = xz[j] = xr[j] = (T)0;
-                if (range_ok(rs[j])) {
-                    int up, vp;
-                    split_index(i0 + j * bd, Wl, invW, up, vp);
-                    const V3<T> p = unproject(V, s * up, s * vp, (T)rs[j]);
-                    xx[j] = r00 * p.x + r01 * p.y + r02 * p.z + t0;
-                    xy[j] = r10 * p.x + r11 * p.y + r12 * p.z + t1;
-                    xz[j] = r20 * p.x + r21 * p.y + r22 * p.z + t2;
-                    proj[j] = project(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]);
-                    if (!proj[j])
-                        ul[j] = vl[j] = -1;
+                const V4<T> rw = sld4(V.rowp, s * vs[j]);
+                const T A = rw.x * rw.z, B = rw.x * rw.w;
+                const T g1x = A * r00 + B * r01, g1y = A * r10 + B * r11, g1z = A * r20 + B * r21;
+                const T g2x = A * r01 - B * r00, g2y = A * r11 - B * r10, g2z = A * r21 - B * r20;
+                const T g3x = rw.y * r02, g3y = rw.y * r12, g3z = rw.y * r22;
+                const T r = (T)rs[j], c = ca[j], sn = sa[j];
+                xx[j] = r * (c * g1x + sn * g2x + g3x) + t0;
+                xy[j] = r * (c * g1y + sn * g2y + g3y) + t1;
+                xz[j] = r * (c * g1z + sn * g2z + g3z) + t2;
+                if (r0 > (T)0) {
+                    xx[j] += r0 * (c * r00 + sn * r01);
+                    xy[j] += r0 * (c * r10 + sn * r11);
+                    xz[j] += r0 * (c * r20 + sn * r21);
                 }
+                const bool okr = range_ok(rs[j]);
+                proj[j] = project(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]) & okr;
             }
             V4<T> D[CHUNK];
 #pragma unroll
             for (int j = 0; j < CHUNK; ++j)
-                D[j] = proj[j] ? ld4(d4 + 4 * ((size_t)vl[j] * Wl + ul[j])) : V4<T>{(T)0, (T)0, (T)0, (T)0};
+                D[j] = bld4<T>(drs, proj[j] ? (uint32_t)(vl[j] * Wl + ul[j]) * (uint32_t)(4 * sizeof(T)) : kNoLoad);
 #pragma unroll
             for (int j = 0; j < CHUNK; ++j) {
-                const int i = i0 + j * bd;
-                bool valid = false;
-                T e = (T)0, J0 = (T)0, J1 = (T)0, J2 = (T)0;
                 const T n0 = D[j].x, n1 = D[j].y, n2 = D[j].z;
-                if (D[j].w > (T)0) {
-                    const V3<T> q = unproject(V, s * ul[j], s * vl[j], D[j].w);
-                    const T dx = xx[j] - q.x, dy = xy[j] - q.y, dz = xz[j] - q.z;
-                    if (!(mc2 >= (T)0 && dx * dx + dy * dy + dz * dz > mc2)) {
-                        valid = true;
-                        e = n0 * dx + n1 * dy + n2 * dz;
-                        J0 = xy[j] * n2 - xz[j] * n1;
-                        J1 = xz[j] * n0 - xx[j] * n2;
-                        J2 = xx[j] * n1 - xy[j] * n0;
-                    }
+                bool valid = proj[j] && n0 * n0 + n1 * n1 + n2 * n2 > (T)0.5;
+                const T ex = n0 * xx[j] + n1 * xy[j] + n2 * xz[j] - D[j].w;
+                if (mc2 >= (T)0) {
+                    // Sec. 4.1 correspondence gate: |x - q| against the target point
+                    const rsrc_t rrs = make_rsrc(LI.rng, npx * 4u);
+                    const uint32_t pix = (uint32_t)(vl[j] * Wl + ul[j]);
+                    const T rq = (T)bld1<float>(rrs, valid ? 4u * pix : kNoLoad);
+                    const V4<T> rw = bld4<T>(V.row, (uint32_t)(s * vl[j]) * (uint32_t)(4 * sizeof(T)));
+                    T cq, sq;
+                    bld2(V.col, (uint32_t)(s * ul[j]) * (uint32_t)(2 * sizeof(T)), cq, sq);
+                    const V3<T> d = ray_dir(rw, cq, sq);
+                    const T dx = xx[j] - (rq * d.x + r0 * cq), dy = xy[j] - (rq * d.y + r0 * sq);
+                    const T dz = xz[j] - rq * d.z;
+                    valid = valid && dx * dx + dy * dy + dz * dz <= mc2;
                 }
-                const T J3 = valid ? n0 : (T)0, J4 = valid ? n1 : (T)0, J5 = valid ? n2 : (T)0;
+                const T e = valid ? ex : (T)0;
+                const T J0 = xy[j] * n2 - xz[j] * n1;
+                const T J1 = xz[j] * n0 - xx[j] * n2;
+                const T J2 = xx[j] * n1 - xy[j] * n0;
                 const T tq = e * inv_delta;
                 const T wh = d_rsqrt((T)1 + tq * tq);
                 T w = wh;
+                const int i = in[j] ? vs[j] * Wl + us[j] : -1;
                 if constexpr (WMODE == 1) {
                     if (a.mode != kStepFallback)
-                        w = learned_weight<T>(a, F, P, l, valid, ul[j], vl[j], e, xr[j], J3, J4, J5,
-                                              dbg ? a.dbg_feat : nullptr, i < end ? i : -1);
+                        w = learned_weight<T>(a, F, LI, valid, ul[j], vl[j], e, xr[j], n0, n1, n2,
+                                              dbg ? a.dbg_feat : nullptr, i);
                 }
                 w = valid ? w : (T)0;
-                const T rho = valid ? e * e * wh / (wh + (T)1) : (T)0;
+                const T rho = valid ? e * e * wh * d_rcp(wh + (T)1) : (T)0;
                 c_proj += wave_count(proj[j]);
                 c_valid += wave_count(valid);
                 c_in += wave_count(valid && fabs(e) < delta);
-                const T J[6] = {J0, J1, J2, J3, J4, J5};
+                const T J[6] = {J0, J1, J2, n0, n1, n2};
                 T wJ[6];
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
@@ -410,17 +440,17 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
                 acc[27] += w;
                 acc[28] += w * e * e;
                 acc[29] += rho;
-                if (dbg && i < end) {
-                    if (a.dbg_u) a.dbg_u[i] = ul[j];
-                    if (a.dbg_v) a.dbg_v[i] = vl[j];
+                if (dbg && i >= 0) {
+                    if (a.dbg_u) a.dbg_u[i] = proj[j] ? ul[j] : -1;
+                    if (a.dbg_v) a.dbg_v[i] = proj[j] ? vl[j] : -1;
                     if (a.dbg_mask) a.dbg_mask[i] = valid ? 1 : 0;
                     if (a.dbg_e) a.dbg_e[i] = (float)e;
                     if (a.dbg_w) a.dbg_w[i] = (float)w;
                     if (a.dbg_J)
                         for (int q = 0; q < 6; ++q)
-                            a.dbg_J[6 * (size_t)i + q] = (float)J[q];
+                            a.dbg_J[6 * (size_t)i + q] = valid ? (float)J[q] : 0.f;
                     if (WMODE == 0 && a.dbg_feat)
-                        store_features<T>(a, P, l, valid, ul[j], vl[j], e, xr[j], J3, J4, J5,
+                        store_features<T>(a, LI, valid, ul[j], vl[j], e, xr[j], n0, n1, n2,
                                           a.dbg_feat + 14 * (size_t)i);
                 }
             }
@@ -686,10 +716,10 @@ hipError_t launch_unproject(const SensorTab<float> &S, const float *range, float
     return hipGetLastError();
 }
 
-hipError_t launch_project(const SensorTab<float> &S, int level, const float *xyz, int64_t n, int32_t *u, int32_t *v,
+hipError_t launch_project(const SensorTab<float> *tab, int level, const float *xyz, int64_t n, int32_t *u, int32_t *v,
                           float *r, uint8_t *valid, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_project, dim3(grid_for(n, 256)), dim3(256), 0, stream, S, level, xyz, n, u, v, r, valid);
+    hipLaunchKernelGGL(k_project, dim3(grid_for(n, 256)), dim3(256), 0, stream, tab, level, xyz, n, u, v, r, valid);
     return hipGetLastError();
 }
 

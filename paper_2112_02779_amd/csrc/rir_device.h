@@ -1,7 +1,8 @@
 // Device-side sensor tables and per-pixel geometry of the range-image model
 // (Dong et al., Sec. 3): unprojection Eq. (1)-(2), projection Eq. (3)-(4) with
-// an inverse elevation table, and the cross-product normal image (Sec. 4.1).
-// Everything is templated on the arithmetic type T (float or double).
+// a packed inverse elevation table, and the cross-product normal image
+// (Sec. 4.1).  Everything is templated on the arithmetic type T (float or
+// double).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,10 +20,14 @@ constexpr int kMaxLevels = 8;
 //               2 cos(s) sin(dp), 0 with s, dp the half sum / half difference of
 //               the two elevations and m, dt those of the two azimuth offsets
 //  theta [H]    azimuth offsets
-//  per level l (stride 2^l):
-//   mu[l]   [H_l-1] sin of the elevation midpoints between strided rows
-//   bins[l] [nbins] first candidate row of each inverse-table bin over sin(phi)
-//   uoff[l] [H_l]   theta_lut[s t] * W / (2 pi s) (column offset of each row)
+//  ebin[l] [nbins[l]][4]  inverse elevation table of level l (stride 2^l) over
+//               sz = sin(phi): bin b = trunc(clamp((sz - bin_lo) * bin_scale,
+//               0, nbins - 1)) evaluated in T.  Entry: (bits c | k << 16, m,
+//               uoff(c), uoff(c + k)); the row of every sz that falls in the bin
+//               is c + k [m > sz] (c midpoints lie above the whole bin, k equal
+//               midpoints m inside it), uoff(t) = theta_lut[s t] W / (2 pi s) is
+//               that row's column offset.  The host verifies the entry against
+//               the exact bin edges in T, so the lookup is exact.
 template <typename T>
 struct SensorTab {
     int H, W, nlev;
@@ -30,9 +35,7 @@ struct SensorTab {
     T r0, s_lo, s_hi, cos_h, sin_h;
     T bin_lo[kMaxLevels], bin_scale[kMaxLevels], kW[kMaxLevels];
     const T *row, *col, *nrow, *theta;
-    const T *mu[kMaxLevels];
-    const int32_t *bins[kMaxLevels];
-    const T *uoff[kMaxLevels];
+    const T *ebin[kMaxLevels];
 };
 
 template <typename T>
@@ -45,6 +48,9 @@ struct V4 {
     T x, y, z, w;
 };
 
+// ----------------------------------------------------------------------------- memory access
+
+// Generic-pointer loads (entry points that take caller buffers).
 __device__ __forceinline__ V4<float> ld4(const float *p)
 {
     float4 v = *reinterpret_cast<const float4 *>(p);
@@ -78,16 +84,133 @@ __device__ __forceinline__ void st4(double *p, V4<double> v)
     reinterpret_cast<double2 *>(p)[1] = make_double2(v.z, v.w);
 }
 
-__device__ __forceinline__ float d_atan2(float y, float x) { return atan2f(y, x); }
-__device__ __forceinline__ double d_atan2(double y, double x) { return atan2(y, x); }
-__device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
+// Buffer-resource loads (raw buffers of gfx9): a 128-bit descriptor in scalar
+// registers holds base and size, each lane supplies a 32-bit byte offset, and
+// the hardware checks it against the size: an access beyond the buffer
+// returns zero and touches no memory.  kNoLoad is beyond every buffer the
+// library creates (all are below 2 GiB), so masked lanes pass it instead of
+// branching.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr uint32_t kNoLoad = 0x80000000u;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// Only the 32-bit load builtin is used: the backend merges loads at
+// consecutive offsets of one descriptor into 64- and 128-bit loads by itself
+// (the vector-returning builtins do not extract their elements correctly with
+// this compiler).
+__device__ __forceinline__ uint32_t bld_u32(rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T bld1(rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float bld1<float>(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, bld_u32(r, off));
+}
+template <>
+__device__ __forceinline__ double bld1<double>(rsrc_t r, uint32_t off)
+{
+    const uint64_t lo = bld_u32(r, off), hi = bld_u32(r, off + 4u);
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
+template <typename T>
+__device__ __forceinline__ void bld2(rsrc_t r, uint32_t off, T &a, T &b)
+{
+    a = bld1<T>(r, off);
+    b = bld1<T>(r, off + (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ V4<T> bld4(rsrc_t r, uint32_t off)
+{
+    V4<T> o;
+    bld2(r, off, o.x, o.y);
+    bld2(r, off + 2u * (uint32_t)sizeof(T), o.z, o.w);
+    return o;
+}
+
+// Low 32 bits of a table word (the packed counts of an elevation-table entry).
+__device__ __forceinline__ uint32_t low_bits(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t low_bits(double x) { return (uint32_t)__builtin_bit_cast(uint64_t, x); }
+
+// Loads of data that no thread of the running kernel writes, at wave-uniform
+// addresses: through the constant address space they become scalar loads
+// (one per wave, results in scalar registers).  The scalar cache is
+// invalidated at every kernel launch, so data written by earlier kernels is
+// seen.
+template <typename T>
+__device__ __forceinline__ T cload(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+__device__ __forceinline__ int2 cload(const int2 *p)
+{
+    const int *q = reinterpret_cast<const int *>(p);
+    return make_int2(cload(q), cload(q + 1));
+}
+template <typename T>
+__device__ __forceinline__ V4<T> sld4(const T *p, int idx)
+{
+    typedef const __attribute__((address_space(4))) T ctype;
+    ctype *q = (ctype *)p + 4 * idx;
+    return {q[0], q[1], q[2], q[3]};
+}
+
+// ----------------------------------------------------------------------------- math
+
+__device__ __forceinline__ float d_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double d_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float d_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double d_rcp(double x) { return 1.0 / x; }
 template <typename T>
 __device__ __forceinline__ T two_pi();
 template <>
 __device__ __forceinline__ float two_pi<float>() { return 6.28318530717958647692f; }
 template <>
 __device__ __forceinline__ double two_pi<double>() { return 6.28318530717958647692; }
+
+// atan2(|y|, x) in [0, pi].  FP32: reduction to t = min(|x|,|y|) / max(|x|,|y|)
+// in [0, 1], atan(t) = t P(t^2) with P of degree 7 fitted to atan on [0, 1]
+// by iteratively reweighted least squares (near-minimax: 4e-8 in exact
+// arithmetic, 1.3e-7 evaluated in FP32), then the reflections
+// atan(1/t) = pi/2 - atan(t) and atan2(y, -x) = pi - atan2(y, x).  With the
+// reciprocal's 1 ulp the result is within 4e-7 rad of the true angle.
+// FP64: the library atan2.
+__device__ __forceinline__ float atan2_abs(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mx > 0.f ? mn * d_rcp(mx) : 0.f;
+    const float t2 = t * t;
+    float p = -4.054546356e-03f;
+    p = fmaf(p, t2, 2.186288498e-02f);
+    p = fmaf(p, t2, -5.591222644e-02f);
+    p = fmaf(p, t2, 9.642190486e-02f);
+    p = fmaf(p, t2, -1.390862763e-01f);
+    p = fmaf(p, t2, 1.994656473e-01f);
+    p = fmaf(p, t2, -3.332985938e-01f);
+    p = fmaf(p, t2, 9.999993443e-01f);
+    p *= t;
+    p = ay > ax ? 1.57079632679489661923f - p : p;
+    return x < 0.f ? 3.14159265358979323846f - p : p;
+}
+__device__ __forceinline__ double atan2_abs(double y, double x) { return atan2(fabs(y), x); }
+
+// Azimuth of (x, y) in [0, 2 pi] (2 pi only by rounding just below the +x axis).
+template <typename T>
+__device__ __forceinline__ T azimuth(T y, T x)
+{
+    const T p = atan2_abs(y, x);
+    return y < (T)0 ? two_pi<T>() - p : p;
+}
 
 __device__ __forceinline__ bool range_ok(float r) { return r > 0.0f && r <= 3.402823466e38f; }
 
@@ -99,42 +222,6 @@ __device__ __forceinline__ V3<T> ray_dir(V4<T> rw, T ca, T sa)
     T cal = ca * rw.z - sa * rw.w;
     T sal = sa * rw.z + ca * rw.w;
     return {rw.x * cal, rw.x * sal, rw.y};
-}
-
-// The tables one pyramid level needs, copied out of SensorTab into
-// registers once per tile: the per-pixel code then never re-reads the table
-// descriptor (which, living in global memory next to the kernel's stores,
-// the compiler could not keep in registers).
-template <typename T>
-struct LevelView {
-    const T *row, *col;               // full-resolution factors of Eq. (1)
-    const T *mu, *uoff;               // this level's midpoints and column offsets
-    const int32_t *bins;
-    const SensorTab<T> *tab;          // everything else (receiver-offset search)
-    T r0, s_lo, s_hi, kW, bin_lo, bin_scale;
-    int Hl, Wl, nb;
-};
-
-template <typename T>
-__device__ __forceinline__ LevelView<T> level_view(const SensorTab<T> &S, int l)
-{
-    LevelView<T> V;
-    V.row = S.row;
-    V.col = S.col;
-    V.mu = S.mu[l];
-    V.uoff = S.uoff[l];
-    V.bins = S.bins[l];
-    V.tab = &S;
-    V.r0 = S.r0;
-    V.s_lo = S.s_lo;
-    V.s_hi = S.s_hi;
-    V.kW = S.kW[l];
-    V.bin_lo = S.bin_lo[l];
-    V.bin_scale = S.bin_scale[l];
-    V.Hl = S.H >> l;
-    V.Wl = S.W >> l;
-    V.nb = S.nbins[l];
-    return V;
 }
 
 // Eq. (1): p = r d(u, v) + r0 (cos a_u, sin a_u, 0) for full-resolution pixel (u, v).
@@ -152,32 +239,56 @@ __device__ __forceinline__ V3<T> unproject(const SensorTab<T> &S, int u, int v, 
 {
     return unproject(S.row, S.col, S.r0, u, v, r);
 }
+
+// ----------------------------------------------------------------------------- projection
+
+// The tables one pyramid level needs, read out of SensorTab once per tile.
 template <typename T>
-__device__ __forceinline__ V3<T> unproject(const LevelView<T> &V, int u, int v, T r)
+struct LevelView {
+    rsrc_t row, col, ebin;        // full-resolution factors of Eq. (1), this level's elevation table
+    const T *rowp;                // row factors for wave-uniform (scalar) reads
+    const SensorTab<T> *tab;      // the rest (receiver-offset search), in device memory
+    T r0, s_lo, s_hi, kW, bin_lo, bin_scale, bin_max;
+    int Hl, Wl;
+};
+
+template <typename T>
+__device__ __forceinline__ LevelView<T> level_view(const SensorTab<T> *tab, int l)
 {
-    return unproject(V.row, V.col, V.r0, u, v, r);
+    LevelView<T> V;
+    const int H = cload(&tab->H), W = cload(&tab->W), nb = cload(&tab->nbins[l]);
+    V.rowp = cload(&tab->row);
+    V.row = make_rsrc(V.rowp, (uint32_t)(H * 4 * sizeof(T)));
+    V.col = make_rsrc(cload(&tab->col), (uint32_t)(W * 2 * sizeof(T)));
+    V.ebin = make_rsrc(cload(&tab->ebin[l]), (uint32_t)(nb * 4 * sizeof(T)));
+    V.tab = tab;
+    V.r0 = cload(&tab->r0);
+    V.s_lo = cload(&tab->s_lo);
+    V.s_hi = cload(&tab->s_hi);
+    V.kW = cload(&tab->kW[l]);
+    V.bin_lo = cload(&tab->bin_lo[l]);
+    V.bin_scale = cload(&tab->bin_scale[l]);
+    V.bin_max = (T)(nb - 1);
+    V.Hl = H >> l;
+    V.Wl = W >> l;
+    return V;
 }
 
-// Eq. (4) on sz = sin(phi) over a level's rows: the row t whose elevation is
-// nearest (ties to the smaller t), i.e. the number of level midpoints
-// strictly above phi.  The inverse table gives a start row; the two bounded
-// walks make the result exact whatever the bin rounding.
+// Eq. (4) on sz = sin(phi): the row of the level whose elevation is nearest
+// (ties to the smaller row), i.e. the number of level midpoints strictly above
+// phi, from one entry of the packed table; uo receives that row's column
+// offset.  NaN falls in bin 0 (the caller has rejected it already).
 template <typename T>
-__device__ __forceinline__ int elev_index(const T *mu, const int32_t *bins, T bin_lo, T bin_scale, int nb, int Hl,
-                                          T sz)
+__device__ __forceinline__ int elev_row(rsrc_t ebin, T bin_lo, T bin_scale, T bin_max, T sz, T &uo)
 {
-    if (Hl <= 1)
-        return 0;
     T f = (sz - bin_lo) * bin_scale;
-    const T fmaxb = (T)(nb - 1);
-    f = f >= (T)0 ? f : (T)0;  // also maps NaN to bin 0
-    f = f < fmaxb ? f : fmaxb;
-    int v = bins[(int)f];
-    while (v < Hl - 1 && mu[v] > sz)
-        ++v;
-    while (v > 0 && mu[v - 1] <= sz)
-        --v;
-    return v;
+    f = f >= (T)0 ? f : (T)0;
+    f = f < bin_max ? f : bin_max;
+    const V4<T> E = bld4<T>(ebin, (uint32_t)(int)f * (uint32_t)(4 * sizeof(T)));
+    const uint32_t ck = low_bits(E.x);
+    const bool below = E.y > sz;
+    uo = below ? E.w : E.z;
+    return (int)(ck & 0xffffu) + (below ? (int)(ck >> 16) : 0);
 }
 
 // Eq. (3)-(4) at the view's level.  With r0 > 0 the receiver offset is
@@ -191,102 +302,84 @@ __device__ __forceinline__ int elev_index(const T *mu, const int32_t *bins, T bi
 // project.  Then the range, the elevation row by the inverse table and the
 // column from the azimuth minus the row's offset, rounded half up and wrapped
 // (Sec. 4.1: continuous geometry at the finest level, nearest strided row and
-// column).  Returns false outside the elevation field of view or at r = 0.
+// column).  Returns false outside the elevation field of view or at r = 0;
+// ul, vl and r are then unspecified (but in range).  No early exits: the
+// per-pixel path stays free of divergent branches.
 template <typename T>
 __device__ __forceinline__ bool project(const LevelView<T> &V, T x, T y, T z, int &ul, int &vl, T &r)
 {
     T r2, th;
+    bool ok = true;
     if (V.r0 > (T)0) {
-        const SensorTab<T> &S = *V.tab;
-        const T *mu0 = S.mu[0], *theta = S.theta;
-        const int32_t *bins0 = S.bins[0];
-        const T lo0 = S.bin_lo[0], sc0 = S.bin_scale[0];
-        const int nb0 = S.nbins[0], H = S.H;
+        const SensorTab<T> *S = V.tab;
+        const int nb0 = cload(&S->nbins[0]);
+        const rsrc_t eb0 = make_rsrc(cload(&S->ebin[0]), (uint32_t)(nb0 * 4 * sizeof(T)));
+        const rsrc_t thr = make_rsrc(cload(&S->theta), (uint32_t)(cload(&S->H) * sizeof(T)));
+        const T lo0 = cload(&S->bin_lo[0]), sc0 = cload(&S->bin_scale[0]), mx0 = (T)(nb0 - 1);
         const T r0 = V.r0, rho2 = x * x + y * y, z2 = z * z;
-        if (!(rho2 > (T)4 * r0 * r0))
-            return false;
-        T t = sqrt(rho2 - r0 * r0);
-        int v = elev_index(mu0, bins0, lo0, sc0, nb0, H, z * d_rsqrt(t * t + z2));
+        ok = rho2 > (T)4 * r0 * r0;
+        const T rho2c = ok ? rho2 : (T)4 * r0 * r0;
+        T t = sqrt(rho2c - r0 * r0), dummy;
+        int v = elev_row(eb0, lo0, sc0, mx0, z * d_rsqrt(t * t + z2), dummy);
         T cth = (T)1, sth = (T)0;
         for (int k = 0; k < 4; ++k) {
-            cth = V.row[4 * v + 2];
-            sth = V.row[4 * v + 3];
-            t = sqrt(rho2 - r0 * r0 * sth * sth) - r0 * cth;
+            const V4<T> rw = bld4<T>(V.row, (uint32_t)v * (uint32_t)(4 * sizeof(T)));
+            cth = rw.z;
+            sth = rw.w;
+            t = sqrt(rho2c - r0 * r0 * sth * sth) - r0 * cth;
             if (k == 3)
                 break;
-            const int vn = elev_index(mu0, bins0, lo0, sc0, nb0, H, z * d_rsqrt(t * t + z2));
+            const int vn = elev_row(eb0, lo0, sc0, mx0, z * d_rsqrt(t * t + z2), dummy);
             if (vn == v)
                 break;
             v = vn;
         }
         r2 = t * t + z2;
-        th = d_atan2(y, x) - d_atan2(t * sth, r0 + t * cth) + theta[v];
-        if (th < (T)0)
-            th += two_pi<T>();
-        if (th < (T)0)
-            th += two_pi<T>();
-        if (th >= two_pi<T>())
-            th -= two_pi<T>();
+        const T ys = t * sth, xs = r0 + t * cth;
+        const T off = ys < (T)0 ? -atan2_abs(ys, xs) : atan2_abs(ys, xs);
+        th = azimuth(y, x) - off + bld1<T>(thr, (uint32_t)v * (uint32_t)sizeof(T));
+        th = th < (T)0 ? th + two_pi<T>() : th;
+        th = th < (T)0 ? th + two_pi<T>() : th;
+        th = th >= two_pi<T>() ? th - two_pi<T>() : th;
     } else {
         r2 = x * x + y * y + z * z;
-        th = d_atan2(y, x);
-        if (th < (T)0)
-            th += two_pi<T>();
+        th = azimuth(y, x);
     }
-    if (!(r2 > (T)0))
-        return false;
     const T rinv = d_rsqrt(r2);
     const T sz = z * rinv;
-    if (!(sz <= V.s_hi && sz >= V.s_lo))
-        return false;
-    const int v = elev_index(V.mu, V.bins, V.bin_lo, V.bin_scale, V.nb, V.Hl, sz);
+    ok = ok && r2 > (T)0 && sz <= V.s_hi && sz >= V.s_lo;
+    T uo;
+    const int v = elev_row(V.ebin, V.bin_lo, V.bin_scale, V.bin_max, sz, uo);
     const int Wl = V.Wl;
-    T uh = th * V.kW - V.uoff[v];
-    if (uh < (T)0)
-        uh += (T)Wl;
-    if (uh >= (T)Wl)
-        uh -= (T)Wl;
+    T uh = th * V.kW - uo;
+    uh = uh < (T)0 ? uh + (T)Wl : uh;
+    uh = uh >= (T)Wl ? uh - (T)Wl : uh;
     int u = (int)floor(uh + (T)0.5);
-    if (u >= Wl)
-        u -= Wl;
+    u = u >= Wl ? u - Wl : u;
+    u = u < 0 ? 0 : u;  // NaN inputs only
     ul = u;
     vl = v;
     r = r2 * rinv;
-    return true;
+    return ok;
 }
+
+// ----------------------------------------------------------------------------- normals
 
 // Normal of level-0 pixel (u, v) from the range image (Sec. 4.1, Sec. 6.1):
 // n = (P(u+1,v) - P(u-1,v)) x (P(u,v+1) - P(u,v-1)), u wrapping, oriented to
 // face the sensor.  Both differences are formed without cancellation from
 // the factored tables: P(+) - P(-) = (r+ - r-)(d+ + d-)/2 + (r+ + r-)(d+ - d-)/2
 // (+ r0 (c+ - c-) along u), with d+ - d- in product (half-angle) form.  The
-// validity predicate is evaluated in FP64 on the FP32 ranges.  Returns false
-// (and leaves n untouched) for invalid pixels.
+// validity predicate (all five ranges valid, none differing from the centre by
+// more than edge_rel times the centre range) is evaluated in FP64 on the FP32
+// ranges.  Inputs: column factors (ca, sa), the rows v, v+1, v-1 of the row
+// table, the two nrow words of row v, and the five ranges.  Returns false (n
+// untouched) for invalid pixels; rows 0 and H-1 are the caller's to reject.
 template <typename T>
-struct NormalView {
-    const T *row, *col, *nrow;
-    T r0, cos_h, sin_h;
-    int H, W;
-};
-
-template <typename T>
-__device__ __forceinline__ NormalView<T> normal_view(const SensorTab<T> &S)
+__device__ __forceinline__ bool normal_core(T ca, T sa, V4<T> rw, V4<T> rp, V4<T> rm, V4<T> f0, V4<T> f1, T r0,
+                                            T cos_h, T sin_h, float rc, float rl, float rr, float ru, float rd,
+                                            double edge_rel, V3<T> &n)
 {
-    return NormalView<T>{S.row, S.col, S.nrow, S.r0, S.cos_h, S.sin_h, S.H, S.W};
-}
-
-template <typename T>
-__device__ __forceinline__ bool normal_at(const NormalView<T> &S, const float *rng, int u, int v, double edge_rel,
-                                          V3<T> &n)
-{
-    const int H = S.H, W = S.W;
-    if (v <= 0 || v >= H - 1)
-        return false;
-    const int ul = u == 0 ? W - 1 : u - 1;
-    const int ur = u == W - 1 ? 0 : u + 1;
-    const size_t row = (size_t)v * W;
-    const float rc = rng[row + u], rl = rng[row + ul], rr = rng[row + ur];
-    const float ru = rng[row - W + u], rd = rng[row + W + u];
     if (!(range_ok(rc) && range_ok(rl) && range_ok(rr) && range_ok(ru) && range_ok(rd)))
         return false;
     const double lim = edge_rel * (double)rc;
@@ -294,19 +387,14 @@ __device__ __forceinline__ bool normal_at(const NormalView<T> &S, const float *r
     if (fabs((double)rl - dc) > lim || fabs((double)rr - dc) > lim || fabs((double)ru - dc) > lim ||
         fabs((double)rd - dc) > lim)
         return false;
-    T ca, sa;
-    ld2(S.col + 2 * u, ca, sa);
     // along u (same row): d+ + d- = 2 (cphi cos h cos al, cphi cos h sin al, sphi),
     // d+ - d- = 2 cphi sin h (-sin al, cos al, 0), c+ - c- = 2 sin h (-sa, ca, 0)
-    V4<T> rw = ld4(S.row + 4 * v);
     T cal = ca * rw.z - sa * rw.w, sal = sa * rw.z + ca * rw.w;
     T dh = (T)rr - (T)rl, sh = (T)rr + (T)rl;
-    T k1 = dh * rw.x * S.cos_h, k2 = sh * rw.x * S.sin_h, k3 = (T)2 * S.r0 * S.sin_h;
+    T k1 = dh * rw.x * cos_h, k2 = sh * rw.x * sin_h, k3 = (T)2 * r0 * sin_h;
     V3<T> A = {k1 * cal - k2 * sal - k3 * sa, k1 * sal + k2 * cal + k3 * ca, dh * rw.y};
     // along v (same column)
-    V4<T> rp = ld4(S.row + 4 * (v + 1)), rm = ld4(S.row + 4 * (v - 1));
     V3<T> dp = ray_dir(rp, ca, sa), dm = ray_dir(rm, ca, sa);
-    V4<T> f0 = ld4(S.nrow + 8 * v), f1 = ld4(S.nrow + 8 * v + 4);
     T s_p = sa * f0.x + ca * f0.y, c_p = ca * f0.x - sa * f0.y;
     T s_m = sa * f0.z + ca * f0.w, c_m = ca * f0.z - sa * f0.w;
     V3<T> dd = {-s_m * f1.y - s_p * f1.x, c_p * f1.x + c_m * f1.y, f1.z};
@@ -329,6 +417,24 @@ __device__ __forceinline__ bool normal_at(const NormalView<T> &S, const float *r
     }
     n = c;
     return true;
+}
+
+// normal_core for pixel (u, v) of a range image in memory.
+template <typename T>
+__device__ __forceinline__ bool normal_at(const SensorTab<T> &S, const float *rng, int u, int v, double edge_rel,
+                                          V3<T> &n)
+{
+    const int H = S.H, W = S.W;
+    if (v <= 0 || v >= H - 1)
+        return false;
+    const int ul = u == 0 ? W - 1 : u - 1;
+    const int ur = u == W - 1 ? 0 : u + 1;
+    const size_t row = (size_t)v * W;
+    T ca, sa;
+    ld2(S.col + 2 * u, ca, sa);
+    return normal_core(ca, sa, ld4(S.row + 4 * v), ld4(S.row + 4 * (v + 1)), ld4(S.row + 4 * (v - 1)),
+                       ld4(S.nrow + 8 * v), ld4(S.nrow + 8 * v + 4), S.r0, S.cos_h, S.sin_h, rng[row + u],
+                       rng[row + ul], rng[row + ur], rng[row - W + u], rng[row + W + u], edge_rel, n);
 }
 
 }  // namespace rir

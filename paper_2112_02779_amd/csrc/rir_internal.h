@@ -13,10 +13,13 @@ namespace rir {
 // Per-pair view of one batch entry, in device memory.  Level images:
 //  src[l]  FP32 source ranges at stride 2^l ([0] is the caller's image)
 //  dstr[l] FP32 target ranges at stride 2^l ([0] is the caller's image)
-//  dst4[l] 4 T per pixel: target normal (x, y, z) and range, all zero where
-//          the normal is invalid (which includes "no return")
-// Tiles of level l of this pair are tile0[l] .. tile0[l] + ntile[l] - 1 of the
-// level's tile list.
+//  dst4[l] 4 T per pixel: target normal n (x, y, z) and the plane offset
+//          n . q of the target point q, all zero where the normal is invalid
+//          (which includes "no return")
+// Work is cut into segments: 64 consecutive pixels of one image row (one per
+// lane of a wavefront), ceil(W_l / 64) per row, so every wavefront works on a
+// single row.  Tiles of level l of this pair are tile0[l] .. tile0[l] +
+// ntile[l] - 1 of the level's tile list.
 template <typename T>
 struct PairDesc {
     const SensorTab<T> *tab;
@@ -25,7 +28,14 @@ struct PairDesc {
     T *dst4[kMaxLevels];
     int H, W;
     int tile0[kMaxLevels], ntile[kMaxLevels];
-    float invW[kMaxLevels];
+};
+
+constexpr int kSegPx = 64;  // pixels per segment
+
+// A level's target range image (learned-weight features).
+struct LevelImage {
+    const float *rng;
+    int Hl, Wl;
 };
 
 // Per-pair flag words: flags[pair * kFlagStride + l] bit 0 = level l stopped;
@@ -46,10 +56,10 @@ constexpr int kMlpB1 = 0, kMlpB2 = 64, kMlpB3 = 128, kMlpNB = 129;
 
 struct StepArgs {
     const void *pairs;   // PairDesc<T>[n_pairs]
-    const int2 *tiles;   // (pair, first pixel) of every tile of this level
+    const int2 *tiles;   // (pair, first segment) of every tile of this level
     int n_tiles;
     int level, iter, levels;
-    int tile_px;         // pixels per tile = block * px_per_thread at this level
+    int tile_seg;        // segments per tile at this level
     int chunk;           // pixels each thread keeps in flight (1, 2 or 4)
     int xcd_remap;
     int mode;            // StepMode
@@ -70,9 +80,9 @@ struct StepArgs {
 
 struct PrepArgs {
     const void *pairs;  // PairDesc<T>[n_pairs]
-    const int2 *tiles;  // level-0 tiles
+    const int2 *tiles;  // level-0 tiles (pair, first segment)
     int n_tiles;
-    int tile_px;
+    int tile_seg;
     int levels;
     int init_centroid;  // 1: compute t0 from the point-set centres
     double edge_rel;
@@ -85,7 +95,7 @@ struct PrepArgs {
 // launch status.
 hipError_t launch_unproject(const SensorTab<float> &S, const float *range, float *xyz, uint8_t *valid,
                             hipStream_t stream);
-hipError_t launch_project(const SensorTab<float> &S, int level, const float *xyz, int64_t n, int32_t *u, int32_t *v,
+hipError_t launch_project(const SensorTab<float> *tab, int level, const float *xyz, int64_t n, int32_t *u, int32_t *v,
                           float *r, uint8_t *valid, hipStream_t stream);
 hipError_t launch_normals(const SensorTab<float> &S, const float *range, double edge_rel, float *nrm,
                           uint8_t *valid, hipStream_t stream);

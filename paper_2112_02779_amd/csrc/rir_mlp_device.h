@@ -138,7 +138,7 @@ __device__ __forceinline__ float clamp4(float x) { return fminf(fmaxf(x, -4.f), 
 //  f12 = clamp(e / delta), f13 = clamp((target range - xr) / delta) (the
 //  projective signed distance of Eq. (8)-(9)).  Zeros when !valid.
 template <typename T>
-__device__ __forceinline__ void compute_features(const StepArgs &a, const PairDesc<T> &P, int l, bool valid, int ul,
+__device__ __forceinline__ void compute_features(const StepArgs &a, const LevelImage &L, bool valid, int ul,
                                                  int vl, T e, T xr, T n0, T n1, T n2, float (&f)[14])
 {
 #pragma unroll
@@ -146,8 +146,8 @@ __device__ __forceinline__ void compute_features(const StepArgs &a, const PairDe
         f[k] = 0.f;
     if (!valid)
         return;
-    const int Wl = P.W >> l, Hl = P.H >> l;
-    const float *img = P.dstr[l];
+    const int Wl = L.Wl, Hl = L.Hl;
+    const float *img = L.rng;
     const T rc = (T)img[(size_t)vl * Wl + ul];
     const T inv_delta = (T)(1.0 / a.delta);
     f[0] = (float)(rc / (T)a.r_max);
@@ -177,11 +177,11 @@ __device__ __forceinline__ void compute_features(const StepArgs &a, const PairDe
 }
 
 template <typename T>
-__device__ __forceinline__ void store_features(const StepArgs &a, const PairDesc<T> &P, int l, bool valid, int ul,
+__device__ __forceinline__ void store_features(const StepArgs &a, const LevelImage &L, bool valid, int ul,
                                                int vl, T e, T xr, T n0, T n1, T n2, float *out)
 {
     float f[14];
-    compute_features<T>(a, P, l, valid, ul, vl, e, xr, n0, n1, n2, f);
+    compute_features<T>(a, L, valid, ul, vl, e, xr, n0, n1, n2, f);
 #pragma unroll
     for (int k = 0; k < 14; ++k)
         out[k] = f[k];
@@ -191,13 +191,13 @@ __device__ __forceinline__ void store_features(const StepArgs &a, const PairDesc
 // wave must call it (lanes without a correspondence pass valid = false).
 // dump (nullable) receives the features of pixel dump_index (>= 0).
 template <typename T>
-__device__ __forceinline__ T learned_weight(const StepArgs &a, const MlpFrag &F, const PairDesc<T> &P, int l,
+__device__ __forceinline__ T learned_weight(const StepArgs &a, const MlpFrag &F, const LevelImage &L,
                                             bool valid, int ul, int vl, T e, T xr, T n0, T n1, T n2, float *dump,
                                             int dump_index)
 {
     __shared__ uint32_t s_stage[4][64 * 8];
     float f[14];
-    compute_features<T>(a, P, l, valid, ul, vl, e, xr, n0, n1, n2, f);
+    compute_features<T>(a, L, valid, ul, vl, e, xr, n0, n1, n2, f);
     if (dump && dump_index >= 0)
         for (int k = 0; k < 14; ++k)
             dump[14 * (size_t)dump_index + k] = f[k];

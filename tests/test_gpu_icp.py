@@ -142,7 +142,9 @@ def test_fp64_mode_matches_oracle_tightly(rir, ctx):
 
 def test_self_registration_is_identity(rir, ctx):
     """At the identity every source pixel projects onto itself (lossless
-    round trip), so every residual is exactly zero and the pose stays I."""
+    round trip), so every residual vanishes up to FP32 rounding of the point
+    and plane offset (|x| <= 100 m: a few ulp of 100 m) and the pose stays
+    at I to the same order."""
     pair = _pair("pair64", 5)
     sen = rir.Sensor.from_model(pair.sensor)
     img = to_dev(pair.dst)
@@ -158,11 +160,13 @@ def test_self_registration_is_identity(rir, ctx):
         src_ok = pair.dst[::s, ::s] > 0
         moved = src_ok & ((u != uu) | (v != vv))
         assert not moved.any(), (lvl, np.argwhere(moved)[:5], u[moved][:5], v[moved][:5])
-        assert np.all(e[m] == 0.0), (lvl, np.argwhere(m & (e != 0))[:5], e[m & (e != 0)][:5])
+        assert m.sum() > 0.3 * src_ok.sum()
+        assert np.max(np.abs(e[m])) < 3e-5, (lvl, np.max(np.abs(e[m])))
     same = synth.Pair(pair.sensor, pair.dst, pair.dst, np.eye(4), 5)
     Tg, st = _run_gpu(rir, ctx, pair.sensor, [same], [3, 3, 3], 3)
-    np.testing.assert_array_equal(Tg[0], np.eye(4))
-    assert np.all(st["sum_w_e2"] == 0.0)
+    er, et = rot_trans_error(Tg[0], np.eye(4))
+    assert er < 1e-6 and et < 1e-5, (er, et)
+    assert np.all(st["sum_w_e2"] < 1e-9 * st["n_valid"])
 
 
 def test_run_twice_is_bitwise_identical_and_graph_equals_eager(rir, ctx):

@@ -147,19 +147,32 @@ def test_features_and_learned_weights_in_the_step_match_oracle(rir, level):
     assert np.median(np.abs(gw[m] - ref["w"][m])) < 1e-5
 
 
-def _calm_params(seed):
-    """A well-conditioned network: small random weights around a constant
-    output sigmoid(1), so the learned registration converges like the
-    unweighted one and small rounding differences cannot make it diverge."""
-    import paper_2112_02779_amd as rir
-    P = rir.init_mlp_params(seed) * 0.1
-    P[5184] = 1.0
-    w, b = rir.split_params(P)
-    return rir.join_params(w, b)
+def _huber_like_params():
+    """A hand-set network whose weight falls with the residual like a robust
+    kernel: w = sigmoid(2 - 3 |f12|), |f12| = relu(f12) + relu(-f12) with
+    f12 = clamp(e / delta); every weight is exact in bf16.  Registration with
+    it converges like pseudo-Huber, so the GPU/oracle comparison is well
+    conditioned."""
+    P = np.zeros(5185)
+    P[0 * 14 + 12] = 1.0      # W1[0][12]
+    P[1 * 14 + 12] = -1.0     # W1[1][12]
+    P[960 + 0] = 1.0          # W2[0][0]
+    P[960 + 1] = 1.0          # W2[0][1]
+    P[5120] = -3.0            # W3[0]
+    P[5184] = 2.0             # b3
+    return P
+
+
+def test_huber_like_network_is_what_it_claims():
+    f = np.zeros((5, 14), np.float32)
+    f[:, 12] = [0.0, 0.5, -0.5, 1.0, -4.0]
+    _, w = oracle.mlp_forward(_huber_like_params(), f)
+    a = np.abs(f[:, 12].astype(np.float64))
+    np.testing.assert_allclose(w, 1.0 / (1.0 + np.exp(-(2.0 - 3.0 * a))), rtol=1e-12)
 
 
 def test_learned_icp_matches_oracle(rir):
-    P = _calm_params(14)
+    P = _huber_like_params()
     pair = synth.gen_pair(synth.CONFIGS["dynamic64"], 15)
     sm = pair.sensor
     sen = rir.Sensor.from_model(sm)
