@@ -140,8 +140,8 @@ typedef struct {
 
 /* Tuning of the association/reduction launch (picked by rir_autotune).
  * block: threads per workgroup (64, 128 or 256); px_per_thread: pixels each
- * thread visits per finest-level tile (1..16; level l uses px_per_thread /
- * 4^l, at least 1); grid_mult: persistent workgroups per compute unit (0 =
+ * thread visits per tile at levels 0 and 1 (1..16; each coarser level uses
+ * 4x fewer, at least 1); grid_mult: persistent workgroups per compute unit (0 =
  * one workgroup per tile); xcd_remap: 1 maps consecutive tiles to the same
  * XCD (L2) of the chip; chunk: 64-pixel row segments whose loads each
  * wavefront keeps in flight together (1, 2 or 4). */

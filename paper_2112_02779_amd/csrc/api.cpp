@@ -385,6 +385,7 @@ struct Plan {
     int n_pairs = 0;
     bool fp64 = false;
     int tile_seg[kMaxLevels] = {}, block = 0;
+    bool lean[kMaxLevels] = {};  // the lean step variant applies (StepArgs::lean)
     int n_tiles[kMaxLevels] = {};
     int grid[kMaxLevels] = {};
     void *dmem = nullptr;
@@ -603,11 +604,21 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     const size_t tsz = P->fp64 ? sizeof(double) : sizeof(float);
     const int L = key.k.levels;
     P->block = key.k.tune.block;
-    // a tile is block * px_per_thread pixels (in 64-pixel row segments);
-    // coarser levels have 4x fewer pixels each: shrink the pixels per thread
-    // with them (down to one) so that they still spread over the whole chip
-    for (int l = 0; l < L; ++l)
-        P->tile_seg[l] = key.k.tune.block / kSegPx * std::max(1, key.k.tune.px_per_thread >> (2 * l));
+    // a tile is block * px_per_thread pixels (in 64-pixel row segments) at
+    // levels 0 and 1, and 4x fewer per level below (down to one pixel per
+    // thread): large tiles amortise the per-tile reduction, small ones keep
+    // the chip full on the coarse levels.  The rule depends on the tuning
+    // only, so a pair's result does not depend on the batch around it.
+    for (int l = 0; l < L; ++l) {
+        const int sh = l > 1 ? 2 * (l - 1) : 0;
+        P->tile_seg[l] = key.k.tune.block / kSegPx * std::max(1, key.k.tune.px_per_thread >> sh);
+    }
+    for (int l = 0; l < L; ++l) {
+        bool lean = !(key.k.max_corr > 0.0);
+        for (int i = 0; i < n; ++i)
+            lean = lean && pairs[i].sensor->r0 == 0.0 && ((pairs[i].sensor->W >> l) % kSegPx) == 0;
+        P->lean[l] = lean;
+    }
     std::vector<std::vector<int2>> tiles(L);
     std::vector<int> t0(n * kMaxLevels, 0), nt(n * kMaxLevels, 0);
     for (int l = 0; l < L; ++l) {
@@ -644,8 +655,10 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     size_t o_stats = lay.add((size_t)n * L * sizeof(rir_level_stats));
     size_t o_flags = lay.add((size_t)n * kFlagStride * sizeof(int));
     std::vector<size_t> o_src(n * kMaxLevels, 0), o_dstr(n * kMaxLevels, 0), o_dst4(n * kMaxLevels, 0);
+    std::vector<size_t> o_frames(n, 0);
     for (int i = 0; i < n; ++i) {
         const rir_sensor *s = pairs[i].sensor;
+        o_frames[i] = lay.add((size_t)s->H * kFrame * tsz);
         for (int l = 0; l < L; ++l) {
             const size_t Nl = (size_t)(s->H >> l) * (s->W >> l);
             if (l > 0) {
@@ -674,6 +687,8 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
         const rir_sensor *s = pairs[i].sensor;
         auto fill = [&](auto *d, auto *tab) {
             d->tab = tab;
+            using TF = typename std::remove_pointer<typename std::remove_reference<decltype(d->frames)>::type>::type;
+            d->frames = reinterpret_cast<TF *>(base + o_frames[i]);
             d->H = s->H;
             d->W = s->W;
             for (int l = 0; l < kMaxLevels; ++l) {
@@ -803,6 +818,8 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
     a.chunk = P->key.k.tune.chunk;
     a.xcd_remap = P->key.k.tune.xcd_remap;
     a.mode = mode;
+    a.stats_pass = (mode == kStepDebug || iter == P->key.k.iters[level] - 1) ? 1 : 0;
+    a.lean = (mode != kStepDebug && P->lean[level]) ? 1 : 0;
     a.learned = p->weight_mode == RIR_WEIGHT_LEARNED;
     a.psum = P->d_psum;
     a.pcnt = P->d_pcnt;
@@ -834,6 +851,8 @@ rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t s
     a.poses = P->d_poses;
     a.xcd_remap = P->key.k.tune.xcd_remap;
     HIP_TRY(launch_prepass(P->fp64, a, P->grid[0], P->block, P->n_pairs, st));
+    StepArgs f = step_args(P, p, 0, 0, kStepNormal);
+    HIP_TRY(launch_frames(P->fp64, f, P->n_pairs, st));
     return RIR_OK;
 }
 
@@ -1010,7 +1029,9 @@ extern "C" rir_status rir_debug_associate(rir_ctx *ctx, const rir_icp_params *pa
     a.dbg_w = w;
     a.dbg_J = J;
     a.dbg_feat = feat;
-    hipError_t e2 = e1 == hipSuccess ? launch_step(P->fp64, q.weight_mode, a, P->grid[level], P->block, st) : e1;
+    hipError_t e2 = e1 == hipSuccess ? launch_frames(P->fp64, a, 1, st) : e1;
+    if (e2 == hipSuccess)
+        e2 = launch_step(P->fp64, q.weight_mode, a, P->grid[level], P->block, st);
     if (e2 == hipSuccess)
         e2 = launch_solve(P->fp64, a, 1, st);
     hipError_t e3 = hipStreamSynchronize(st);

@@ -163,7 +163,7 @@ __global__ void k_clear(int *flags, int n_flags, rir_level_stats *stats, int n_s
 // Normal image and pyramid (Sec. 4.1): each wavefront takes one segment of a
 // target row, computes the normals of its 64 pixels (row factors by scalar
 // loads, neighbour ranges by bounds-checked buffer loads) and writes the
-// (n, n . q) record at level 0 and, for pixels on the grid of level l, the
+// (n, n . q) record (0, 0, 0, NaN where the normal is invalid) at level 0 and, for pixels on the grid of level l, the
 // strided copies of the record, the target range and the source range.  With
 // init_centroid each tile also records the sums of its valid source and
 // target points (reduced per pair by k_centroid).
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
             T ca, sa;
             bld2(crs, in ? (uint32_t)u * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca, sa);
             const V4<T> rw = sld4(rowt, v);
-            V4<T> rec = {(T)0, (T)0, (T)0, (T)0};
+            V4<T> rec = {(T)0, (T)0, (T)0, quiet_nan<T>()};
             if (v > 0 && v < H - 1) {
                 const int ul = u == 0 ? W - 1 : u - 1, ur = u == W - 1 ? 0 : u + 1;
                 const float rl = bld1<float>(drs, in ? 4u * (uint32_t)(v * W + ul) : kNoLoad);
@@ -293,14 +293,17 @@ __global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
 // Sec. 4.1).  Each workgroup walks its tiles; a tile is a run of tile_seg
 // segments of one pair's level-l image, and each wavefront takes CHUNK
 // segments at a time (its own 64-pixel pieces of CHUNK rows), so that CHUNK
-// source loads, then CHUNK target gathers, are in flight together.  Per
-// segment the row's ray frame is rotated once: x = r (ca g1 + sa g2 + g3) +
-// r0 R (ca, sa, 0) + t with g1 = R (cphi ctheta, cphi stheta, 0),
-// g2 = R (-cphi stheta, cphi ctheta, 0), g3 = sphi R e_z (Eq. (1) then the
-// pose).  The target record holds (n, n . q), so e = n . x - n . q.  The
-// tile's sums go to one record (k_solve reduces them).  FINE tags the
-// finest-level instance (same code) so that profiles report it separately.
-template <typename T, int WMODE, bool FINE, int CHUNK>
+// source loads, then CHUNK target gathers, are in flight together.  A
+// segment's row frame (g1, g2, g3: the ray directions of Eq. (1) rotated by
+// the pose) is read with scalar loads, so unprojection plus the rigid
+// transform is x = r (ca g1 + sa g2 + g3) + r0 R (ca, sa, 0) + t.  The
+// target record holds (n, n . q), so e = n . x - n . q (NaN, hence invalid,
+// where the record is).  The tile's sums go to one record (k_solve reduces
+// them).  FINE tags the finest-level instance (same code) so that profiles
+// report it separately.  LEAN instances (StepArgs::lean) leave out the
+// receiver offset, the distance gate, the debug dumps and the per-lane row-end
+// test.
+template <typename T, int WMODE, bool FINE, int CHUNK, bool LEAN>
 __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
 {
     __shared__ T s_wave[4][kAccum];
@@ -311,8 +314,9 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwave = blockDim.x >> 6;
     const int l = a.level, s = 1 << l;
     const T delta = (T)a.delta, inv_delta = (T)(1.0 / a.delta);
-    const T mc2 = a.max_corr > 0.0 ? (T)(a.max_corr * a.max_corr) : (T)-1;
-    const bool dbg = a.mode == kStepDebug;
+    const T mc2 = !LEAN && a.max_corr > 0.0 ? (T)(a.max_corr * a.max_corr) : (T)-1;
+    const bool dbg = !LEAN && a.mode == kStepDebug;
+    const uint32_t lane4 = 4u * (uint32_t)lane, lane_col = (uint32_t)(lane << l) * (uint32_t)(2 * sizeof(T));
     MlpFrag F;
     if constexpr (WMODE == 1)
         mlp_load(a.mlp, F);
@@ -338,7 +342,11 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
         const uint32_t npx = (uint32_t)(Hl * Wl);
         const rsrc_t srs = make_rsrc(cload(&P->src[l]), npx * 4u);
         const rsrc_t drs = make_rsrc(cload(&P->dst4[l]), npx * (uint32_t)(4 * sizeof(T)));
-        const T r0 = V.r0;
+        const T r0 = LEAN ? (T)0 : V.r0;
+        const T *frames = cload(&P->frames);
+        const T h1x = r0 * r00, h1y = r0 * r10, h1z = r0 * r20;  // r0 R e_x
+        const T h2x = r0 * r01, h2y = r0 * r11, h2z = r0 * r21;  // r0 R e_y
+        const bool stats = a.stats_pass != 0;
         T acc[kAccum];
 #pragma unroll
         for (int k = 0; k < kAccum; ++k)
@@ -354,44 +362,52 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
                 const int seg = s0 + j * nwave;
                 const bool live = seg < seg_end;
                 const int v = live ? seg / spr : 0;
-                const int u = (seg - v * spr) * kSegPx + lane;
-                in[j] = live && u < Wl;
+                const int u0 = (seg - v * spr) * kSegPx, u = u0 + lane;
                 vs[j] = v;
                 us[j] = u;
-                rs[j] = bld1<float>(srs, in[j] ? 4u * (uint32_t)(v * Wl + u) : kNoLoad);
-                bld2(V.col, in[j] ? (uint32_t)(s * u) * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca[j], sa[j]);
+                if constexpr (LEAN) {
+                    // whole segments: uniform base plus the lane's offset
+                    in[j] = live;
+                    const uint32_t sb = live ? 4u * (uint32_t)(v * Wl + u0) : kNoLoad;
+                    const uint32_t cb = live ? (uint32_t)(s * u0) * (uint32_t)(2 * sizeof(T)) : kNoLoad;
+                    rs[j] = bld1<float>(srs, sb + lane4);
+                    bld2(V.col, cb + lane_col, ca[j], sa[j]);
+                } else {
+                    in[j] = live && u < Wl;
+                    rs[j] = bld1<float>(srs, in[j] ? 4u * (uint32_t)(v * Wl + u) : kNoLoad);
+                    bld2(V.col, in[j] ? (uint32_t)(s * u) * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca[j], sa[j]);
+                }
             }
             bool proj[CHUNK];
             int ul[CHUNK], vl[CHUNK];
             T xx[CHUNK], xy[CHUNK], xz[CHUNK], xr[CHUNK];
 #pragma unroll
             for (int j = 0; j < CHUNK; ++j) {
-                const V4<T> rw = sld4(V.rowp, s * vs[j]);
-                const T A = rw.x * rw.z, B = rw.x * rw.w;
-                const T g1x = A * r00 + B * r01, g1y = A * r10 + B * r11, g1z = A * r20 + B * r21;
-                const T g2x = A * r01 - B * r00, g2y = A * r11 - B * r10, g2z = A * r21 - B * r20;
-                const T g3x = rw.y * r02, g3y = rw.y * r12, g3z = rw.y * r22;
+                const T *fr = frames + (size_t)(s * vs[j]) * kFrame;
+                const V4<T> f0 = sld4(fr, 0), f1 = sld4(fr, 1), f2 = sld4(fr, 2);
                 const T r = (T)rs[j], c = ca[j], sn = sa[j];
-                xx[j] = r * (c * g1x + sn * g2x + g3x) + t0;
-                xy[j] = r * (c * g1y + sn * g2y + g3y) + t1;
-                xz[j] = r * (c * g1z + sn * g2z + g3z) + t2;
-                if (r0 > (T)0) {
-                    xx[j] += r0 * (c * r00 + sn * r01);
-                    xy[j] += r0 * (c * r10 + sn * r11);
-                    xz[j] += r0 * (c * r20 + sn * r21);
+                xx[j] = r * (c * f0.x + sn * f0.w + f1.z) + t0;
+                xy[j] = r * (c * f0.y + sn * f1.x + f1.w) + t1;
+                xz[j] = r * (c * f0.z + sn * f1.y + f2.x) + t2;
+                if (!LEAN && r0 > (T)0) {
+                    xx[j] += c * h1x + sn * h2x;
+                    xy[j] += c * h1y + sn * h2y;
+                    xz[j] += c * h1z + sn * h2z;
                 }
                 const bool okr = range_ok(rs[j]);
-                proj[j] = project(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]) & okr;
+                proj[j] = project<T, !LEAN>(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]) & okr;
             }
             V4<T> D[CHUNK];
 #pragma unroll
             for (int j = 0; j < CHUNK; ++j)
-                D[j] = bld4<T>(drs, proj[j] ? (uint32_t)(vl[j] * Wl + ul[j]) * (uint32_t)(4 * sizeof(T)) : kNoLoad);
+                D[j] = bld4<T>(drs, proj[j] ? (__umul24((uint32_t)vl[j], (uint32_t)Wl) + (uint32_t)ul[j]) *
+                                                   (uint32_t)(4 * sizeof(T))
+                                             : kNoLoad);
 #pragma unroll
             for (int j = 0; j < CHUNK; ++j) {
                 const T n0 = D[j].x, n1 = D[j].y, n2 = D[j].z;
-                bool valid = proj[j] && n0 * n0 + n1 * n1 + n2 * n2 > (T)0.5;
                 const T ex = n0 * xx[j] + n1 * xy[j] + n2 * xz[j] - D[j].w;
+                bool valid = proj[j] && ex == ex;
                 if (mc2 >= (T)0) {
                     // Sec. 4.1 correspondence gate: |x - q| against the target point
                     const rsrc_t rrs = make_rsrc(LI.rng, npx * 4u);
@@ -419,10 +435,14 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
                                               dbg ? a.dbg_feat : nullptr, i);
                 }
                 w = valid ? w : (T)0;
-                const T rho = valid ? e * e * wh * d_rcp(wh + (T)1) : (T)0;
-                c_proj += wave_count(proj[j]);
                 c_valid += wave_count(valid);
-                c_in += wave_count(valid && fabs(e) < delta);
+                if (stats) {
+                    acc[29] += valid ? e * e * wh * d_rcp(wh + (T)1) : (T)0;
+                    c_proj += wave_count(proj[j]);
+                    c_in += wave_count(valid && fabs(e) < delta);
+                }
+                // an invalid pixel has w = 0, e = 0 and finite J (n = 0 unless the
+                // distance gate rejected it), so it adds exact zeros
                 const T J[6] = {J0, J1, J2, n0, n1, n2};
                 T wJ[6];
 #pragma unroll
@@ -439,7 +459,6 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
                     acc[21 + r] += wJ[r] * e;
                 acc[27] += w;
                 acc[28] += w * e * e;
-                acc[29] += rho;
                 if (dbg && i >= 0) {
                     if (a.dbg_u) a.dbg_u[i] = proj[j] ? ul[j] : -1;
                     if (a.dbg_v) a.dbg_v[i] = proj[j] ? vl[j] : -1;
@@ -592,9 +611,122 @@ __device__ __forceinline__ void se3_left_update(const double (&xi)[6], double *T
         T[i] = Tn[i];
 }
 
+// The solve of one pair (one thread): statistics, Cholesky, the left SE(3)
+// update of the pose (copied to pose_out).  Returns whether the pose moved.
+__device__ __forceinline__ bool solve_pair(const StepArgs &a, int pair, int *fl, const double *tot,
+                                        const long long *cnt, double *pose_out)
+{
+    const int l = a.level;
+    double U[21], g[6];
+#pragma unroll
+    for (int k = 0; k < 21; ++k)
+        U[k] = tot[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        g[k] = tot[21 + k];
+    const double sum_w = tot[27], sum_we2 = tot[28], rho = tot[29];
+    const int n_valid = (int)cnt[0];
+    bool finite = isfinite(sum_w) && isfinite(sum_we2) && isfinite(rho);
+#pragma unroll
+    for (int k = 0; k < 21; ++k)
+        finite = finite && isfinite(U[k]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        finite = finite && isfinite(g[k]);
+    rir_level_stats *out = a.stats + (a.mode == kStepDebug ? 0 : (size_t)pair * a.levels + l);
+#pragma unroll
+    for (int k = 0; k < 21; ++k)
+        out->JtJ[k] = U[k];
+    double xi[6] = {0, 0, 0, 0, 0, 0};
+    const bool ok = n_valid >= 6 && finite && cholesky6(U, g, xi);
+    if (a.learned && a.mode == kStepNormal && (!ok || sum_w < 0.1 * (double)n_valid)) {
+        // learned weights rejected: the pseudo-Huber pass that follows redoes
+        // this iteration and rewrites the statistics
+        fl[kMaxLevels] = 1;
+        return false;
+    }
+    int status = a.mode == kStepFallback ? RIR_LEVEL_FALLBACK_HUBER : RIR_LEVEL_OK;
+    double srot = 0.0, stra = 0.0;
+    bool moved = false;
+    if (a.mode == kStepFallback)
+        fl[kMaxLevels] = 0;
+    if (!ok) {
+        status = finite ? RIR_LEVEL_DEGENERATE : RIR_LEVEL_NONFINITE;
+        if (a.mode != kStepDebug)
+            fl[l] = 1;
+    } else {
+        srot = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+        stra = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+        if (a.mode != kStepDebug) {
+            double *Tp = a.poses + 16 * (size_t)pair;
+            se3_left_update(xi, Tp);
+            for (int k = 0; k < 12; ++k)
+                pose_out[k] = Tp[k];
+            moved = true;
+        }
+    }
+    out->status = status;
+    out->iters_run = a.iter + 1;
+    out->n_valid = n_valid;
+    out->n_inlier = (int)cnt[1];
+    out->n_proj = (int)cnt[2];
+    out->pad = 0;
+    out->sum_w = sum_w;
+    out->sum_w_e2 = sum_we2;
+    out->robust_cost = rho;
+    out->step_rot = srot;
+    out->step_trans = stra;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        out->Jtr[k] = g[k];
+    return moved;
+}
+
+// Ray frames of every full-resolution row of one pair for the pose in
+// s_pose (the PairDesc::frames layout), written by the threads of one
+// workgroup; FP64 arithmetic, stored in T.
+template <typename T>
+__device__ __forceinline__ void write_frames(const PairDesc<T> *P, const double (&R)[12])
+{
+    const SensorTab<T> *tab = cload(&P->tab);
+    const T *row = cload(&tab->row);
+    T *fr = cload(&P->frames);
+    const int H = cload(&P->H);
+    for (int v = threadIdx.x; v < H; v += blockDim.x) {
+        const double cphi = (double)row[4 * v], sphi = (double)row[4 * v + 1];
+        const double A = cphi * (double)row[4 * v + 2], B = cphi * (double)row[4 * v + 3];
+        T *o = fr + (size_t)v * kFrame;
+        o[0] = (T)(A * R[0] + B * R[1]);
+        o[1] = (T)(A * R[4] + B * R[5]);
+        o[2] = (T)(A * R[8] + B * R[9]);
+        o[3] = (T)(A * R[1] - B * R[0]);
+        o[4] = (T)(A * R[5] - B * R[4]);
+        o[5] = (T)(A * R[9] - B * R[8]);
+        o[6] = (T)(sphi * R[2]);
+        o[7] = (T)(sphi * R[6]);
+        o[8] = (T)(sphi * R[10]);
+        o[9] = o[10] = o[11] = (T)0;
+    }
+}
+
+// Frames for the current poses of all pairs (after the poses are set from
+// the host or by the centroid initialisation).  One workgroup per pair.
+template <typename T>
+__global__ __launch_bounds__(256) void k_frames(StepArgs a)
+{
+    const int pair = blockIdx.x;
+    const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + pair;
+    double R[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        R[k] = a.poses[16 * (size_t)pair + k];
+    write_frames(P, R);
+}
+
 // Reduction of one pair's tile records in FP64 (tile order, independent of
 // the batch) and the Gauss-Newton update of Eq. (7): Cholesky solve,
-// T <- Exp(xi) T, per-level statistics.  One wave per pair.
+// T <- Exp(xi) T, per-level statistics, then the ray frames of the new pose.
+// One workgroup per pair.
 template <typename T>
 __global__ __launch_bounds__(256) void k_solve(StepArgs a)
 {
@@ -602,6 +734,8 @@ __global__ __launch_bounds__(256) void k_solve(StepArgs a)
     __shared__ long long s_cpart[8][4];
     __shared__ double s_tot[32];
     __shared__ long long s_cnt[4];
+    __shared__ double s_pose[12];
+    __shared__ int s_moved;
     const int pair = blockIdx.x, lane = threadIdx.x, l = a.level;
     int *fl = a.flags + (size_t)pair * kFlagStride;
     if (a.mode != kStepDebug) {
@@ -640,64 +774,16 @@ __global__ __launch_bounds__(256) void k_solve(StepArgs a)
         s_cnt[lane - 32] = t;
     }
     __syncthreads();
-    if (lane != 0)
-        return;
-    double U[21], g[6];
+    if (lane == 0)
+        s_moved = solve_pair(a, pair, fl, s_tot, s_cnt, s_pose) ? 1 : 0;
+    __syncthreads();
+    if (s_moved) {
+        double R[12];
 #pragma unroll
-    for (int k = 0; k < 21; ++k)
-        U[k] = s_tot[k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        g[k] = s_tot[21 + k];
-    const double sum_w = s_tot[27], sum_we2 = s_tot[28], rho = s_tot[29];
-    const int n_valid = (int)s_cnt[0];
-    bool finite = isfinite(sum_w) && isfinite(sum_we2) && isfinite(rho);
-#pragma unroll
-    for (int k = 0; k < 21; ++k)
-        finite = finite && isfinite(U[k]);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        finite = finite && isfinite(g[k]);
-    rir_level_stats *out = a.stats + (a.mode == kStepDebug ? 0 : (size_t)pair * a.levels + l);
-#pragma unroll
-    for (int k = 0; k < 21; ++k)
-        out->JtJ[k] = U[k];
-    double xi[6] = {0, 0, 0, 0, 0, 0};
-    const bool ok = n_valid >= 6 && finite && cholesky6(U, g, xi);
-    if (a.learned && a.mode == kStepNormal && (!ok || sum_w < 0.1 * (double)n_valid)) {
-        // learned weights rejected: the pseudo-Huber pass that follows redoes
-        // this iteration and rewrites the statistics
-        fl[kMaxLevels] = 1;
-        return;
+        for (int k = 0; k < 12; ++k)
+            R[k] = s_pose[k];
+        write_frames(&P, R);
     }
-    int status = a.mode == kStepFallback ? RIR_LEVEL_FALLBACK_HUBER : RIR_LEVEL_OK;
-    double srot = 0.0, stra = 0.0;
-    if (a.mode == kStepFallback)
-        fl[kMaxLevels] = 0;
-    if (!ok) {
-        status = finite ? RIR_LEVEL_DEGENERATE : RIR_LEVEL_NONFINITE;
-        if (a.mode != kStepDebug)
-            fl[l] = 1;
-    } else {
-        srot = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
-        stra = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
-        if (a.mode != kStepDebug)
-            se3_left_update(xi, a.poses + 16 * (size_t)pair);
-    }
-    out->status = status;
-    out->iters_run = a.iter + 1;
-    out->n_valid = n_valid;
-    out->n_inlier = (int)s_cnt[1];
-    out->n_proj = (int)s_cnt[2];
-    out->pad = 0;
-    out->sum_w = sum_w;
-    out->sum_w_e2 = sum_we2;
-    out->robust_cost = rho;
-    out->step_rot = srot;
-    out->step_trans = stra;
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        out->Jtr[k] = g[k];
 }
 
 // ----------------------------------------------------------------------------- launchers
@@ -763,13 +849,31 @@ hipError_t launch_solve(bool fp64, const StepArgs &a, int n_pairs, hipStream_t s
     return hipGetLastError();
 }
 
+hipError_t launch_frames(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream)
+{
+    if (fp64)
+        hipLaunchKernelGGL(k_frames<double>, dim3(n_pairs), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_frames<float>, dim3(n_pairs), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename T, int WMODE, int CHUNK, bool LEAN>
+static void launch_step_l(const StepArgs &a, int grid, int block, hipStream_t stream)
+{
+    if (a.level == 0)
+        hipLaunchKernelGGL((k_icp_step<T, WMODE, true, CHUNK, LEAN>), dim3(grid), dim3(block), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_icp_step<T, WMODE, false, CHUNK, LEAN>), dim3(grid), dim3(block), 0, stream, a);
+}
+
 template <typename T, int WMODE, int CHUNK>
 static void launch_step_c(const StepArgs &a, int grid, int block, hipStream_t stream)
 {
-    if (a.level == 0)
-        hipLaunchKernelGGL((k_icp_step<T, WMODE, true, CHUNK>), dim3(grid), dim3(block), 0, stream, a);
+    if (a.lean)
+        launch_step_l<T, WMODE, CHUNK, true>(a, grid, block, stream);
     else
-        hipLaunchKernelGGL((k_icp_step<T, WMODE, false, CHUNK>), dim3(grid), dim3(block), 0, stream, a);
+        launch_step_l<T, WMODE, CHUNK, false>(a, grid, block, stream);
 }
 
 template <typename T, int WMODE>

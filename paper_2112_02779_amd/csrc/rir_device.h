@@ -178,11 +178,11 @@ template <>
 __device__ __forceinline__ double two_pi<double>() { return 6.28318530717958647692; }
 
 // atan2(|y|, x) in [0, pi].  FP32: reduction to t = min(|x|,|y|) / max(|x|,|y|)
-// in [0, 1], atan(t) = t P(t^2) with P of degree 7 fitted to atan on [0, 1]
-// by iteratively reweighted least squares (near-minimax: 4e-8 in exact
-// arithmetic, 1.3e-7 evaluated in FP32), then the reflections
+// in [0, 1], atan(t) = t P(t^2) with P of degree 6 fitted to atan on [0, 1]
+// by iteratively reweighted least squares (near-minimax: 2.5e-7 in exact
+// arithmetic, 3.3e-7 evaluated in FP32), then the reflections
 // atan(1/t) = pi/2 - atan(t) and atan2(y, -x) = pi - atan2(y, x).  With the
-// reciprocal's 1 ulp the result is within 4e-7 rad of the true angle.
+// reciprocal's 1 ulp the result is within 7e-7 rad of the true angle.
 // FP64: the library atan2.
 __device__ __forceinline__ float atan2_abs(float y, float x)
 {
@@ -190,14 +190,13 @@ __device__ __forceinline__ float atan2_abs(float y, float x)
     const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
     const float t = mx > 0.f ? mn * d_rcp(mx) : 0.f;
     const float t2 = t * t;
-    float p = -4.054546356e-03f;
-    p = fmaf(p, t2, 2.186288498e-02f);
-    p = fmaf(p, t2, -5.591222644e-02f);
-    p = fmaf(p, t2, 9.642190486e-02f);
-    p = fmaf(p, t2, -1.390862763e-01f);
-    p = fmaf(p, t2, 1.994656473e-01f);
-    p = fmaf(p, t2, -3.332985938e-01f);
-    p = fmaf(p, t2, 9.999993443e-01f);
+    float p = 6.811757572e-03f;
+    p = fmaf(p, t2, -3.360411525e-02f);
+    p = fmaf(p, t2, 7.962355018e-02f);
+    p = fmaf(p, t2, -1.323333532e-01f);
+    p = fmaf(p, t2, 1.980781406e-01f);
+    p = fmaf(p, t2, -3.331736922e-01f);
+    p = fmaf(p, t2, 9.999961257e-01f);
     p *= t;
     p = ay > ax ? 1.57079632679489661923f - p : p;
     return x < 0.f ? 3.14159265358979323846f - p : p;
@@ -213,6 +212,13 @@ __device__ __forceinline__ T azimuth(T y, T x)
 }
 
 __device__ __forceinline__ bool range_ok(float r) { return r > 0.0f && r <= 3.402823466e38f; }
+
+template <typename T>
+__device__ __forceinline__ T quiet_nan();
+template <>
+__device__ __forceinline__ float quiet_nan<float>() { return __builtin_bit_cast(float, 0x7fc00000u); }
+template <>
+__device__ __forceinline__ double quiet_nan<double>() { return __builtin_bit_cast(double, 0x7ff8000000000000ull); }
 
 // Ray direction of row `rw` (cos phi, sin phi, cos theta, sin theta) at encoder
 // angle (ca, sa): d = (cos phi cos(a + theta), cos phi sin(a + theta), sin phi).
@@ -304,13 +310,14 @@ __device__ __forceinline__ int elev_row(rsrc_t ebin, T bin_lo, T bin_scale, T bi
 // (Sec. 4.1: continuous geometry at the finest level, nearest strided row and
 // column).  Returns false outside the elevation field of view or at r = 0;
 // ul, vl and r are then unspecified (but in range).  No early exits: the
-// per-pixel path stays free of divergent branches.
-template <typename T>
+// per-pixel path stays free of divergent branches.  R0 = false compiles the
+// receiver-offset branch out (callers that know r0 = 0).
+template <typename T, bool R0 = true>
 __device__ __forceinline__ bool project(const LevelView<T> &V, T x, T y, T z, int &ul, int &vl, T &r)
 {
     T r2, th;
     bool ok = true;
-    if (V.r0 > (T)0) {
+    if (R0 && V.r0 > (T)0) {
         const SensorTab<T> *S = V.tab;
         const int nb0 = cload(&S->nbins[0]);
         const rsrc_t eb0 = make_rsrc(cload(&S->ebin[0]), (uint32_t)(nb0 * 4 * sizeof(T)));
@@ -350,11 +357,12 @@ __device__ __forceinline__ bool project(const LevelView<T> &V, T x, T y, T z, in
     ok = ok && r2 > (T)0 && sz <= V.s_hi && sz >= V.s_lo;
     T uo;
     const int v = elev_row(V.ebin, V.bin_lo, V.bin_scale, V.bin_max, sz, uo);
+    // th in [0, 2 pi] and |uo| < Wl / 2, so the rounded column lies within
+    // one image width of [0, Wl): wrap the integer (exact) rather than the
+    // coordinate
     const int Wl = V.Wl;
-    T uh = th * V.kW - uo;
-    uh = uh < (T)0 ? uh + (T)Wl : uh;
-    uh = uh >= (T)Wl ? uh - (T)Wl : uh;
-    int u = (int)floor(uh + (T)0.5);
+    int u = (int)floor(th * V.kW - uo + (T)0.5);
+    u = u < 0 ? u + Wl : u;
     u = u >= Wl ? u - Wl : u;
     u = u < 0 ? 0 : u;  // NaN inputs only
     ul = u;

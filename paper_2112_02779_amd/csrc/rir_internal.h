@@ -14,23 +14,30 @@ namespace rir {
 //  src[l]  FP32 source ranges at stride 2^l ([0] is the caller's image)
 //  dstr[l] FP32 target ranges at stride 2^l ([0] is the caller's image)
 //  dst4[l] 4 T per pixel: target normal n (x, y, z) and the plane offset
-//          n . q of the target point q, all zero where the normal is invalid
-//          (which includes "no return")
+//          n . q of the target point q; where the normal is invalid (which
+//          includes "no return") n = 0 and the offset is NaN
 // Work is cut into segments: 64 consecutive pixels of one image row (one per
 // lane of a wavefront), ceil(W_l / 64) per row, so every wavefront works on a
 // single row.  Tiles of level l of this pair are tile0[l] .. tile0[l] +
 // ntile[l] - 1 of the level's tile list.
+// frames: per full-resolution row v the ray frame of Eq. (1) rotated by the
+// pair's current pose R, kFrame T each: g1 = R (A, B, 0), g2 = R (-B, A, 0),
+// g3 = sin(phi_v) R e_z with A = cos(phi_v) cos(theta_v), B = cos(phi_v)
+// sin(theta_v), then 3 zeros; R d(u, v) = cos(a_u) g1 + sin(a_u) g2 + g3.
+// Rewritten whenever the pose changes (k_frames, k_solve).
 template <typename T>
 struct PairDesc {
     const SensorTab<T> *tab;
     float *src[kMaxLevels];
     float *dstr[kMaxLevels];
     T *dst4[kMaxLevels];
+    T *frames;
     int H, W;
     int tile0[kMaxLevels], ntile[kMaxLevels];
 };
 
 constexpr int kSegPx = 64;  // pixels per segment
+constexpr int kFrame = 12;  // T per frame row
 
 // A level's target range image (learned-weight features).
 struct LevelImage {
@@ -63,6 +70,12 @@ struct StepArgs {
     int chunk;           // pixels each thread keeps in flight (1, 2 or 4)
     int xcd_remap;
     int mode;            // StepMode
+    int lean;            // 1: no receiver offset, no distance gate, no debug
+                         // dumps and every row a whole number of segments
+                         // (the kernel variant without those paths runs)
+    int stats_pass;      // 1: also accumulate the statistics-only terms (robust
+                         // cost, inlier and projection counts); set on the last
+                         // scheduled iteration of a level and in debug mode
     int learned;         // the normal pass uses learned weights
     void *psum;          // T[n_tiles][kAccum]
     int4 *pcnt;          // [n_tiles] (n_valid, n_inlier, n_proj, 0)
@@ -102,6 +115,7 @@ hipError_t launch_normals(const SensorTab<float> &S, const float *range, double 
 hipError_t launch_clear(int *flags, int n_flags, rir_level_stats *stats, int n_stats, hipStream_t stream);
 hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, int n_pairs, hipStream_t stream);
 hipError_t launch_solve(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream);
+hipError_t launch_frames(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream);
 hipError_t launch_step(bool fp64, int weight_mode, const StepArgs &a, int grid, int block, hipStream_t stream);
 
 // Learned-weight network (mlp.hip).
