@@ -89,6 +89,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                            "(python -m paper_2112_02779_amd.build); there is no fallback path")
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # loading torch first makes librir bind to that single runtime (loaded the
+    # other way round, torch would find the system runtime and no device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, f32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
     pvp = ctypes.POINTER(ctypes.c_void_p)

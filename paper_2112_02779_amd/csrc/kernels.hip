@@ -317,9 +317,9 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
     const T mc2 = !LEAN && a.max_corr > 0.0 ? (T)(a.max_corr * a.max_corr) : (T)-1;
     const bool dbg = !LEAN && a.mode == kStepDebug;
     const uint32_t lane4 = 4u * (uint32_t)lane, lane_col = (uint32_t)(lane << l) * (uint32_t)(2 * sizeof(T));
-    MlpFrag F;
+    MlpInfer F;
     if constexpr (WMODE == 1)
-        mlp_load(a.mlp, F);
+        mlp_infer_load(a.mlp, F);
     for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step) {
         const int2 tl = cload(a.tiles + it.cur);
         const int pair = tl.x;

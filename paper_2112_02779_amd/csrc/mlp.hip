@@ -19,8 +19,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(MlpDev m, const float *feat
 {
     __shared__ uint32_t stage[4][64 * 8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    MlpFrag F;
-    mlp_load(m, F);
+    MlpInfer F;
+    mlp_infer_load(m, F);
     const int64_t stride = (int64_t)gridDim.x * 4 * 64;
     for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64; base < B; base += stride) {
         const int64_t i = base + lane;

@@ -28,6 +28,34 @@ __device__ __forceinline__ uint32_t f2bf(float f)
 __device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
 __device__ __forceinline__ float round_bf(float f) { return bf2f(f2bf(f)); }
 
+typedef __bf16 bf16x2v_t __attribute__((ext_vector_type(2)));
+typedef float f32x2v_t __attribute__((ext_vector_type(2)));
+typedef short s16x2v_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2v_t __attribute__((ext_vector_type(2)));
+
+// Two floats rounded to bfloat16 (to nearest even, one hardware conversion)
+// and packed, the first in the low half.
+__device__ __forceinline__ uint32_t pack_bf2(float lo, float hi)
+{
+    const f32x2v_t f = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2v_t));
+}
+
+// ReLU of two packed bfloat16 values.  Read as int16, every negative value
+// (and -0) lies below 0 and every positive one above, so the integer maximum
+// with 0 is the ReLU; ReLU after rounding equals rounding after ReLU.
+__device__ __forceinline__ uint32_t relu_bf2(uint32_t x)
+{
+    const s16x2v_t z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2v_t, x), z));
+}
+
+__device__ __forceinline__ bf16x4_t bf4(uint32_t lo, uint32_t hi)
+{
+    const u32x2v_t v = {lo, hi};
+    return __builtin_bit_cast(bf16x4_t, v);
+}
+
 __device__ __forceinline__ f32x4_t mfma16(bf16x4_t a, bf16x4_t b, f32x4_t c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -66,22 +94,56 @@ __device__ __forceinline__ void mlp_load(const MlpDev &m, MlpFrag &F)
     F.b3 = m.b[kMlpB3];
 }
 
+// Inference fragments (lane l: r = l % 16, g = l / 16): a1, a2, b1, b2 as in
+// MlpFrag; a3[kt] holds W3 inputs kt*16 + 4g..+3 in the A rows r = 0, 4, 8,
+// 12 and zeros in the others, so the output layer is an MFMA whose result
+// row 4g (held by the lanes of group g) is z of pixel column r.
+struct MlpInfer {
+    bf16x4_t a1[4];
+    bf16x4_t a2[4][4];
+    bf16x4_t a3[4];
+    float b1[4][4], b2[4][4];
+    float b3;
+};
+
+__device__ __forceinline__ void mlp_infer_load(const MlpDev &m, MlpInfer &F)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * g + j;
+            F.a1[mt][j] = (short)(k < 14 ? m.w[kMlpW1 + (mt * 16 + r) * 14 + k] : 0);
+            F.a3[mt][j] = (short)((r & 3) == 0 ? m.w[kMlpW3 + mt * 16 + k] : 0);
+            F.b1[mt][j] = m.b[kMlpB1 + mt * 16 + k];
+            F.b2[mt][j] = m.b[kMlpB2 + mt * 16 + k];
+        }
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                F.a2[mt][kt][j] = (short)m.w[kMlpW2 + (mt * 16 + r) * 64 + kt * 16 + 4 * g + j];
+    }
+    F.b3 = m.b[kMlpB3];
+}
+
 // Packs 14 features (rounded to bf16) into 8 dwords, two per dword, low half first.
 __device__ __forceinline__ void pack_features(const float (&f)[14], uint32_t (&fp)[8])
 {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const uint32_t lo = 2 * k < 14 ? f2bf(f[2 * k]) : 0u;
-        const uint32_t hi = 2 * k + 1 < 14 ? f2bf(f[2 * k + 1]) : 0u;
-        fp[k] = lo | (hi << 16);
-    }
+    for (int k = 0; k < 7; ++k)
+        fp[k] = pack_bf2(f[2 * k], f[2 * k + 1]);
+    fp[7] = 0u;
 }
 
 // Logit z of the network for the wave's 64 pixels: lane l passes its pixel's
 // packed features and receives z of that pixel.  `lds` is this wave's private
 // 64 x 8-dword staging area (the feature transpose into B-operand layout).
-// Must be called by all 64 lanes.
-__device__ __forceinline__ float mlp_wave(const MlpFrag &F, const uint32_t (&fp)[8], uint32_t *lds)
+// Layers 1 and 2 start from their biases in the accumulators; activations
+// are rounded to bf16 two at a time and ReLU'd in packed form; the output
+// layer is one more MFMA chain.  Must be called by all 64 lanes.
+__device__ __forceinline__ float mlp_wave(const MlpInfer &F, const uint32_t (&fp)[8], uint32_t *lds)
 {
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     uint4 *row = reinterpret_cast<uint4 *>(lds + lane * 8);
@@ -94,35 +156,28 @@ __device__ __forceinline__ float mlp_wave(const MlpFrag &F, const uint32_t (&fp)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const uint2 bb = *reinterpret_cast<const uint2 *>(lds + (nt * 16 + r) * 8 + 2 * g);
-        bf16x4_t B;
-        B[0] = (short)(bb.x & 0xffffu);
-        B[1] = (short)(bb.x >> 16);
-        B[2] = (short)(bb.y & 0xffffu);
-        B[3] = (short)(bb.y >> 16);
-        bf16x4_t hb[4];
+        const bf16x4_t B = bf4(bb.x, bb.y);
+        bf16x4_t h1[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             f32x4_t c = {F.b1[mt][0], F.b1[mt][1], F.b1[mt][2], F.b1[mt][3]};
             c = mfma16(F.a1[mt], B, c);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                hb[mt][j] = (short)f2bf(fmaxf(c[j], 0.f));
+            h1[mt] = bf4(relu_bf2(pack_bf2(c[0], c[1])), relu_bf2(pack_bf2(c[2], c[3])));
         }
-        float part = 0.f;
+        bf16x4_t h2[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             f32x4_t c = {F.b2[mt][0], F.b2[mt][1], F.b2[mt][2], F.b2[mt][3]};
 #pragma unroll
             for (int kt = 0; kt < 4; ++kt)
-                c = mfma16(F.a2[mt][kt], hb[kt], c);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                part += F.w3[mt][j] * round_bf(fmaxf(c[j], 0.f));
+                c = mfma16(F.a2[mt][kt], h1[kt], c);
+            h2[mt] = bf4(relu_bf2(pack_bf2(c[0], c[1])), relu_bf2(pack_bf2(c[2], c[3])));
         }
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        if (nt == g)
-            zsel = part + F.b3;
+        f32x4_t z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+            z = mfma16(F.a3[kt], h2[kt], z);
+        zsel = g == nt ? z[0] + F.b3 : zsel;
     }
     __builtin_amdgcn_wave_barrier();
     return zsel;
@@ -141,14 +196,9 @@ template <typename T>
 __device__ __forceinline__ void compute_features(const StepArgs &a, const LevelImage &L, bool valid, int ul,
                                                  int vl, T e, T xr, T n0, T n1, T n2, float (&f)[14])
 {
-#pragma unroll
-    for (int k = 0; k < 14; ++k)
-        f[k] = 0.f;
-    if (!valid)
-        return;
     const int Wl = L.Wl, Hl = L.Hl;
-    const float *img = L.rng;
-    const T rc = (T)img[(size_t)vl * Wl + ul];
+    const rsrc_t img = make_rsrc(L.rng, (uint32_t)(Hl * Wl) * 4u);
+    const T rc = (T)bld1<float>(img, valid ? 4u * (uint32_t)(vl * Wl + ul) : kNoLoad);
     const T inv_delta = (T)(1.0 / a.delta);
     f[0] = (float)(rc / (T)a.r_max);
     int k = 1;
@@ -161,19 +211,18 @@ __device__ __forceinline__ void compute_features(const StepArgs &a, const LevelI
             const int vv = vl + dv;
             int uu = ul + du;
             uu = uu < 0 ? uu + Wl : (uu >= Wl ? uu - Wl : uu);
-            float val = 4.f;
-            if (vv >= 0 && vv < Hl) {
-                const float rn = img[(size_t)vv * Wl + uu];
-                if (range_ok(rn))
-                    val = clamp4((float)(((T)rn - rc) * inv_delta));
-            }
-            f[k++] = val;
+            const bool in = valid && vv >= 0 && vv < Hl;
+            const float rn = bld1<float>(img, in ? 4u * (uint32_t)(vv * Wl + uu) : kNoLoad);
+            f[k++] = range_ok(rn) ? clamp4((float)(((T)rn - rc) * inv_delta)) : 4.f;
         }
     f[9] = (float)n0;
     f[10] = (float)n1;
     f[11] = (float)n2;
     f[12] = clamp4((float)(e * inv_delta));
     f[13] = clamp4((float)((rc - xr) * inv_delta));
+#pragma unroll
+    for (int q = 0; q < 14; ++q)
+        f[q] = valid ? f[q] : 0.f;
 }
 
 template <typename T>
@@ -191,7 +240,7 @@ __device__ __forceinline__ void store_features(const StepArgs &a, const LevelIma
 // wave must call it (lanes without a correspondence pass valid = false).
 // dump (nullable) receives the features of pixel dump_index (>= 0).
 template <typename T>
-__device__ __forceinline__ T learned_weight(const StepArgs &a, const MlpFrag &F, const LevelImage &L,
+__device__ __forceinline__ T learned_weight(const StepArgs &a, const MlpInfer &F, const LevelImage &L,
                                             bool valid, int ul, int vl, T e, T xr, T n0, T n1, T n2, float *dump,
                                             int dump_index)
 {

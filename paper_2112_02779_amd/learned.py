@@ -3,9 +3,11 @@
 Everything here runs on the GPU through librir (the same kernels as
 registration); nothing calls the test oracle.
 
-Labels (a reading of "labels from the converged residuals"): each pair is
-first registered from its ground-truth pose with pseudo-Huber weights; at
-that converged pose a source pixel whose correspondence has |e*| <= 3 sigma
+Labels (a reading of "labels from the converged residuals"): the residuals
+e* at the ground-truth pose, which for these synthetic scenes is the exact
+solution (pseudo-Huber started there drifts several centimetres under moving
+objects and spurious returns, i.e. towards the very outliers the labels are
+meant to mark).  A source pixel whose correspondence has |e*| <= 3 sigma
 (sigma = the scans' range noise) is labelled 1 (reliable), otherwise 0
 (moving objects, spurious returns, occlusion edges).  Labels therefore do not
 depend on the current pose.  Features are taken where the network will see
@@ -86,7 +88,6 @@ def make_samples(ctx, batch: DeviceBatch, sigma: float, levels=3, iters=(10, 10,
     rng = np.random.default_rng(seed)
     n = len(batch)
     gts = np.stack([p.gt for p in batch.pairs])
-    T_conv, _ = register(ctx, batch, levels, list(iters), init=gts, delta=delta)
     # poses along the plain trajectory from the identity
     views = [np.tile(np.eye(4), (n, 1, 1))]
     for stop in range(levels - 1, 0, -1):
@@ -95,8 +96,11 @@ def make_samples(ctx, batch: DeviceBatch, sigma: float, levels=3, iters=(10, 10,
     views.append(register(ctx, batch, levels, list(iters), delta=delta)[0])
     prm = rir.make_params(levels=levels, iters=list(iters), delta=delta, r_max=r_max)
     feats, labels = [], []
+    t0 = time.perf_counter()
     for i, (sensor, src, dst) in enumerate(batch.items):
-        d0 = rir.debug_associate(ctx, prm, sensor, src, dst, 0, T_conv[i])
+        if i and i % 500 == 0:
+            _log(f"samples from {i}/{n} pairs ({time.perf_counter() - t0:.0f}s)")
+        d0 = rir.debug_associate(ctx, prm, sensor, src, dst, 0, gts[i])
         m0 = d0["mask"].cpu().numpy().astype(bool)
         y0 = (np.abs(d0["e"].cpu().numpy()) <= 3.0 * sigma) & m0
         for V in views:
@@ -120,12 +124,13 @@ def make_samples(ctx, batch: DeviceBatch, sigma: float, levels=3, iters=(10, 10,
 def train(mlp, feats, labels, steps=3000, batch=8192, lr=2e-3, seed=0, log_every=500):
     """Adam on minibatches drawn with replacement; returns the loss history."""
     import torch
-    rng = np.random.default_rng(seed)
     F = torch.from_numpy(np.ascontiguousarray(feats, dtype=np.float32)).to("cuda:0")
     Y = torch.from_numpy(np.ascontiguousarray(labels, dtype=np.float32)).to("cuda:0")
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(seed)
     hist = []
     for k in range(steps):
-        idx = torch.from_numpy(rng.integers(0, F.shape[0], size=batch)).to("cuda:0")
+        idx = torch.randint(0, F.shape[0], (batch,), device="cuda:0", generator=gen)
         cur_lr = lr * (0.1 ** (k / max(steps, 1)))
         loss, _ = mlp.train_step(F[idx].contiguous(), Y[idx].contiguous(), cur_lr)
         if k % log_every == 0 or k == steps - 1:
@@ -188,6 +193,8 @@ def main(argv=None):
     ap.add_argument("--pairs", type=int, default=1000)
     ap.add_argument("--eval-pairs", type=int, default=1000)
     ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--per-view", type=int, default=160)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--weights", default=WEIGHTS)
     args = ap.parse_args(argv)
@@ -196,20 +203,29 @@ def main(argv=None):
     ctx = rir.Context(0)
     if args.cmd == "train":
         t0 = time.perf_counter()
-        pairs = [synth.gen_pair(cfg, 3000 + i) for i in range(args.pairs)]
+        pairs = []
+        for i in range(args.pairs):
+            pairs.append(synth.gen_pair(cfg, 3000 + i))
+            if (i + 1) % 1000 == 0:
+                _log(f"generated {i + 1} training pairs ({time.perf_counter() - t0:.0f}s)")
         _log(f"generated {len(pairs)} training pairs in {time.perf_counter() - t0:.1f}s")
         batch = DeviceBatch(pairs)
         t0 = time.perf_counter()
-        F, Y = make_samples(ctx, batch, sigma=cfg["noise"].sigma)
+        F, Y = make_samples(ctx, batch, sigma=cfg["noise"].sigma, per_view=args.per_view)
+        del batch, pairs
         _log(f"{len(Y)} samples ({Y.mean():.3f} positive) in {time.perf_counter() - t0:.1f}s")
         mlp = rir.Mlp(rir.init_mlp_params(0))
-        hist = train(mlp, F, Y, steps=args.steps)
-        save(mlp, args.out, {"train_pairs": args.pairs, "samples": int(len(Y)), "loss": hist})
+        hist = train(mlp, F, Y, steps=args.steps, lr=args.lr, log_every=max(1, args.steps // 10))
+        save(mlp, args.out, {"train_pairs": args.pairs, "train_seeds": [3000, 3000 + args.pairs - 1],
+                             "samples": int(len(Y)), "positive": float(Y.mean()), "steps": args.steps,
+                             "lr": args.lr, "loss": hist})
         _log(f"saved {args.out}")
     params = load(args.out if args.cmd == "train" else args.weights)
     mlp = rir.Mlp(params)
     pairs = [synth.gen_pair(cfg, 13000 + i) for i in range(args.eval_pairs)]
+    _log(f"evaluating on {len(pairs)} held-out pairs")
     res = evaluate(ctx, mlp, DeviceBatch(pairs))
+    res["eval_seeds"] = [13000, 13000 + args.eval_pairs - 1]
     print(json.dumps(res), flush=True)
 
 
