@@ -103,7 +103,9 @@ typedef struct {
  *  use_graph     1: capture the iteration schedule once per batch shape as
  *                HIP graphs and replay them; 0: launch kernel by kernel.
  *  mlp           learned-weight network (weight_mode LEARNED), else NULL.
- *  r_max         range scale of the first learned feature (metres). */
+ *  r_max         range scale of the first learned feature (metres).
+ *  learned_levels with weight_mode LEARNED: bit l set = learned weights at
+ *                level l, pseudo-Huber at the others; 0 = every level. */
 typedef struct {
     int32_t levels;
     int32_t iters[RIR_MAX_LEVELS];
@@ -116,6 +118,7 @@ typedef struct {
     int32_t use_graph;
     const rir_mlp *mlp;
     double r_max;
+    int32_t learned_levels;
 } rir_icp_params;
 
 /* Statistics of one pyramid level of one pair: those of the level's last

@@ -41,7 +41,8 @@ class OrcParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("iters", ctypes.c_int * 8), ("delta", ctypes.c_double),
                 ("edge_rel", ctypes.c_double), ("max_corr_dist", ctypes.c_double),
                 ("init_mode", ctypes.c_int), ("weight_mode", ctypes.c_int),
-                ("mlp", ctypes.POINTER(ctypes.c_double)), ("r_max", ctypes.c_double)]
+                ("mlp", ctypes.POINTER(ctypes.c_double)), ("r_max", ctypes.c_double),
+                ("learned_levels", ctypes.c_int)]
 
 
 class OrcLevelStats(ctypes.Structure):
@@ -118,13 +119,14 @@ class _SensorHolder:
 
 
 def make_params(levels=3, iters=(10, 10, 10), delta=0.5, edge_rel=0.1, max_corr_dist=0.0, init_mode=0,
-                weight_mode=0, mlp=None, r_max=80.0):
+                weight_mode=0, mlp=None, r_max=80.0, learned_levels=0):
     prm = OrcParams()
     prm.levels = levels
     for i in range(8):
         prm.iters[i] = int(iters[i]) if i < len(iters) else 0
     prm.delta, prm.edge_rel, prm.max_corr_dist = delta, edge_rel, max_corr_dist
     prm.init_mode, prm.weight_mode, prm.r_max = init_mode, weight_mode, r_max
+    prm.learned_levels = int(learned_levels)
     holder = None
     if mlp is not None:
         holder = np.ascontiguousarray(mlp, dtype=np.float64)

@@ -53,6 +53,7 @@ typedef struct {
     int weight_mode;       /* 0: pseudo-Huber, 1: learned */
     const double *mlp;     /* learned-weight parameters (see orc_mlp_*) */
     double r_max;          /* range scale of the first learned feature */
+    int learned_levels;    /* weight_mode 1: bit l = learned at level l, 0 = all levels */
 } orc_params;
 
 typedef struct {
@@ -832,7 +833,7 @@ int orc_icp(const orc_sensor *s, const float *src, const float *dst, const orc_p
         memset(ls, 0, sizeof(*ls));
         for (int it = 0; it < prm->iters[l]; ++it) {
             double Hm[36], g[6], xi[6];
-            int learned = prm->weight_mode == 1;
+            int learned = prm->weight_mode == 1 && (prm->learned_levels == 0 || ((prm->learned_levels >> l) & 1));
             orc_associate(s, l, src, dst, nrm, nv, T, prm, learned, &ab.a);
             accumulate(n, &ab.a, prm->delta, Hm, g, ls);
             ls->iters_run = it + 1;

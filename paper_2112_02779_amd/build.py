@@ -20,8 +20,11 @@ LIB = os.path.join(HERE, "librir.so")
 SOURCES = ["kernels.hip", "mlp.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# -amdgpu-mfma-vgpr-form: matrix-core results go to ordinary vector registers
+# (no accumulation-register round trips in the fused learned-weight step).
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result"]
+          "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form=1", "-I", INCLUDE, "-I", CSRC, "-Wall",
+          "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result"]
 
 
 def _compile(src: str) -> str:

@@ -360,7 +360,7 @@ struct rir_mlp {
 namespace {
 
 struct KeyPod {
-    int levels, iters[kMaxLevels], init_mode, weight_mode, precision, use_graph, debug;
+    int levels, iters[kMaxLevels], init_mode, weight_mode, learned_levels, precision, use_graph, debug;
     double delta, edge_rel, max_corr, r_max;
     uint64_t mlp;
     rir_tuning tune;
@@ -560,6 +560,8 @@ rir_status check_params(const rir_icp_params *p)
         return fail(RIR_E_INVALID, "rir_icp_params.mlp is required with learned weights");
     if (p->weight_mode == RIR_WEIGHT_LEARNED && !(p->r_max > 0.0))
         return fail(RIR_E_INVALID, "rir_icp_params.r_max must be > 0 with learned weights");
+    if (p->learned_levels < 0 || p->learned_levels >= (1 << kMaxLevels))
+        return fail(RIR_E_INVALID, "rir_icp_params.learned_levels must be a bit set over levels 0..7");
     if (p->precision != RIR_PREC_FP32 && p->precision != RIR_PREC_FP64)
         return fail(RIR_E_INVALID, "rir_icp_params.precision must be FP32 or FP64");
     return RIR_OK;
@@ -734,6 +736,7 @@ rir_status get_plan(rir_ctx *ctx, const rir_icp_params *p, const rir_pair *pairs
         k.iters[l] = l < p->levels ? p->iters[l] : 0;
     k.init_mode = p->init_mode;
     k.weight_mode = p->weight_mode;
+    k.learned_levels = p->weight_mode == RIR_WEIGHT_LEARNED ? p->learned_levels : 0;
     k.precision = p->precision;
     k.use_graph = p->use_graph ? 1 : 0;
     k.debug = debug;
@@ -804,6 +807,12 @@ rir_status update_images(Plan *P, const rir_pair *pairs, hipStream_t st)
     return RIR_OK;
 }
 
+// Learned weights at this level (weight_mode LEARNED and the level selected).
+bool learned_at(const rir_icp_params *p, int level)
+{
+    return p->weight_mode == RIR_WEIGHT_LEARNED && (p->learned_levels == 0 || ((p->learned_levels >> level) & 1));
+}
+
 StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, int mode)
 {
     StepArgs a;
@@ -820,7 +829,7 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
     a.mode = mode;
     a.stats_pass = (mode == kStepDebug || iter == P->key.k.iters[level] - 1) ? 1 : 0;
     a.lean = (mode != kStepDebug && P->lean[level]) ? 1 : 0;
-    a.learned = p->weight_mode == RIR_WEIGHT_LEARNED;
+    a.learned = learned_at(p, level) ? 1 : 0;
     a.psum = P->d_psum;
     a.pcnt = P->d_pcnt;
     a.poses = P->d_poses;
@@ -861,9 +870,9 @@ rir_status enqueue_level(const Plan *P, const rir_icp_params *p, int l, hipStrea
 {
     for (int it = 0; it < P->key.k.iters[l]; ++it) {
         StepArgs a = step_args(P, p, l, it, kStepNormal);
-        HIP_TRY(launch_step(P->fp64, p->weight_mode, a, P->grid[l], P->block, st));
+        HIP_TRY(launch_step(P->fp64, a.learned ? RIR_WEIGHT_LEARNED : RIR_WEIGHT_HUBER, a, P->grid[l], P->block, st));
         HIP_TRY(launch_solve(P->fp64, a, P->n_pairs, st));
-        if (p->weight_mode == RIR_WEIGHT_LEARNED) {
+        if (a.learned) {
             StepArgs b = step_args(P, p, l, it, kStepFallback);
             HIP_TRY(launch_step(P->fp64, RIR_WEIGHT_HUBER, b, P->grid[l], P->block, st));
             HIP_TRY(launch_solve(P->fp64, b, P->n_pairs, st));
@@ -1031,7 +1040,7 @@ extern "C" rir_status rir_debug_associate(rir_ctx *ctx, const rir_icp_params *pa
     a.dbg_feat = feat;
     hipError_t e2 = e1 == hipSuccess ? launch_frames(P->fp64, a, 1, st) : e1;
     if (e2 == hipSuccess)
-        e2 = launch_step(P->fp64, q.weight_mode, a, P->grid[level], P->block, st);
+        e2 = launch_step(P->fp64, a.learned ? RIR_WEIGHT_LEARNED : RIR_WEIGHT_HUBER, a, P->grid[level], P->block, st);
     if (e2 == hipSuccess)
         e2 = launch_solve(P->fp64, a, 1, st);
     hipError_t e3 = hipStreamSynchronize(st);

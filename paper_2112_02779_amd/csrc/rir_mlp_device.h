@@ -56,6 +56,24 @@ __device__ __forceinline__ bf16x4_t bf4(uint32_t lo, uint32_t hi)
     return __builtin_bit_cast(bf16x4_t, v);
 }
 
+// The K = 32 matrix-core product (gfx950): lane l holds A[l % 16][8 (l / 16) + j]
+// and B[8 (l / 16) + j][l % 16] for j < 8, and D as in the K = 16 form.
+typedef __bf16 bf16x8v_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4v_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4_t mfma32(bf16x8v_t a, bf16x8v_t b, f32x4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Two K = 16 operands of one lane as one K = 32 operand: j < 4 from lo, j >= 4 from hi.
+__device__ __forceinline__ bf16x8v_t cat8(bf16x4_t lo, bf16x4_t hi)
+{
+    const u32x2v_t a = __builtin_bit_cast(u32x2v_t, lo), b = __builtin_bit_cast(u32x2v_t, hi);
+    const u32x4v_t v = {a.x, a.y, b.x, b.y};
+    return __builtin_bit_cast(bf16x8v_t, v);
+}
+
 __device__ __forceinline__ f32x4_t mfma16(bf16x4_t a, bf16x4_t b, f32x4_t c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -94,17 +112,23 @@ __device__ __forceinline__ void mlp_load(const MlpDev &m, MlpFrag &F)
     F.b3 = m.b[kMlpB3];
 }
 
-// Inference fragments (lane l: r = l % 16, g = l / 16): a1, a2, b1, b2 as in
-// MlpFrag; a3[kt] holds W3 inputs kt*16 + 4g..+3 in the A rows r = 0, 4, 8,
-// 12 and zeros in the others, so the output layer is an MFMA whose result
-// row 4g (held by the lanes of group g) is z of pixel column r.
+// Inference fragments (lane l: r = l % 16, g = l / 16).  Layer 1 uses K = 16
+// products (a1, b1 as in MlpFrag).  Layers 2 and 3 use K = 32 products whose
+// chunk c covers hidden units 32 c .. 32 c + 31 in the order that makes a
+// chunk of B the two K = 16 output tiles 2c and 2c + 1 of the lane itself:
+// operand index 8 g + j is unit (2 c + j / 4) * 16 + 4 g + j % 4.  a2[mt][c]
+// holds W2 row mt * 16 + r over chunk c; a3[c] holds W3 over chunk c in the A
+// rows r = 0, 4, 8, 12 and zeros in the others, so the output layer's result
+// row 4 g (held by the lanes of group g) is z of pixel column r.
 struct MlpInfer {
     bf16x4_t a1[4];
-    bf16x4_t a2[4][4];
-    bf16x4_t a3[4];
+    bf16x8v_t a2[4][2];
+    bf16x8v_t a3[2];
     float b1[4][4], b2[4][4];
     float b3;
 };
+
+__device__ __forceinline__ int chunk_unit(int c, int g, int j) { return (2 * c + (j >> 2)) * 16 + 4 * g + (j & 3); }
 
 __device__ __forceinline__ void mlp_infer_load(const MlpDev &m, MlpInfer &F)
 {
@@ -115,15 +139,28 @@ __device__ __forceinline__ void mlp_infer_load(const MlpDev &m, MlpInfer &F)
         for (int j = 0; j < 4; ++j) {
             const int k = 4 * g + j;
             F.a1[mt][j] = (short)(k < 14 ? m.w[kMlpW1 + (mt * 16 + r) * 14 + k] : 0);
-            F.a3[mt][j] = (short)((r & 3) == 0 ? m.w[kMlpW3 + mt * 16 + k] : 0);
             F.b1[mt][j] = m.b[kMlpB1 + mt * 16 + k];
             F.b2[mt][j] = m.b[kMlpB2 + mt * 16 + k];
         }
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt)
+        for (int c = 0; c < 2; ++c) {
+            u32x4v_t v;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                F.a2[mt][kt][j] = (short)m.w[kMlpW2 + (mt * 16 + r) * 64 + kt * 16 + 4 * g + j];
+            for (int q = 0; q < 4; ++q)
+                v[q] = (uint32_t)m.w[kMlpW2 + (mt * 16 + r) * 64 + chunk_unit(c, g, 2 * q)] |
+                       ((uint32_t)m.w[kMlpW2 + (mt * 16 + r) * 64 + chunk_unit(c, g, 2 * q + 1)] << 16);
+            F.a2[mt][c] = __builtin_bit_cast(bf16x8v_t, v);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        u32x4v_t v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            v[q] = (r & 3) == 0 ? (uint32_t)m.w[kMlpW3 + chunk_unit(c, g, 2 * q)] |
+                                      ((uint32_t)m.w[kMlpW3 + chunk_unit(c, g, 2 * q + 1)] << 16)
+                                : 0u;
+        F.a3[c] = __builtin_bit_cast(bf16x8v_t, v);
     }
     F.b3 = m.b[kMlpB3];
 }
@@ -141,8 +178,8 @@ __device__ __forceinline__ void pack_features(const float (&f)[14], uint32_t (&f
 // packed features and receives z of that pixel.  `lds` is this wave's private
 // 64 x 8-dword staging area (the feature transpose into B-operand layout).
 // Layers 1 and 2 start from their biases in the accumulators; activations
-// are rounded to bf16 two at a time and ReLU'd in packed form; the output
-// layer is one more MFMA chain.  Must be called by all 64 lanes.
+// are rounded to bf16 two at a time and ReLU'd in packed form; layers 2 and 3
+// are K = 32 products.  Must be called by all 64 lanes.
 __device__ __forceinline__ float mlp_wave(const MlpInfer &F, const uint32_t (&fp)[8], uint32_t *lds)
 {
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
@@ -164,19 +201,18 @@ __device__ __forceinline__ float mlp_wave(const MlpInfer &F, const uint32_t (&fp
             c = mfma16(F.a1[mt], B, c);
             h1[mt] = bf4(relu_bf2(pack_bf2(c[0], c[1])), relu_bf2(pack_bf2(c[2], c[3])));
         }
+        const bf16x8v_t h1c[2] = {cat8(h1[0], h1[1]), cat8(h1[2], h1[3])};
         bf16x4_t h2[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             f32x4_t c = {F.b2[mt][0], F.b2[mt][1], F.b2[mt][2], F.b2[mt][3]};
-#pragma unroll
-            for (int kt = 0; kt < 4; ++kt)
-                c = mfma16(F.a2[mt][kt], h1[kt], c);
+            c = mfma32(F.a2[mt][0], h1c[0], c);
+            c = mfma32(F.a2[mt][1], h1c[1], c);
             h2[mt] = bf4(relu_bf2(pack_bf2(c[0], c[1])), relu_bf2(pack_bf2(c[2], c[3])));
         }
         f32x4_t z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kt = 0; kt < 4; ++kt)
-            z = mfma16(F.a3[kt], h2[kt], z);
+        z = mfma32(F.a3[0], cat8(h2[0], h2[1]), z);
+        z = mfma32(F.a3[1], cat8(h2[2], h2[3]), z);
         zsel = g == nt ? z[0] + F.b3 : zsel;
     }
     __builtin_amdgcn_wave_barrier();
@@ -191,7 +227,8 @@ __device__ __forceinline__ float clamp4(float x) { return fminf(fmaxf(x, -4.f), 
 //  for the 8 level-l neighbours in raster order (u wraps; rows outside the
 //  image or neighbours without return give +4), f9..f11 = n,
 //  f12 = clamp(e / delta), f13 = clamp((target range - xr) / delta) (the
-//  projective signed distance of Eq. (8)-(9)).  Zeros when !valid.
+//  projective signed distance of Eq. (8)-(9)).  Unspecified when !valid (the
+//  weight of such a pixel is zero; store_features writes zeros).
 template <typename T>
 __device__ __forceinline__ void compute_features(const StepArgs &a, const LevelImage &L, bool valid, int ul,
                                                  int vl, T e, T xr, T n0, T n1, T n2, float (&f)[14])
@@ -199,8 +236,8 @@ __device__ __forceinline__ void compute_features(const StepArgs &a, const LevelI
     const int Wl = L.Wl, Hl = L.Hl;
     const rsrc_t img = make_rsrc(L.rng, (uint32_t)(Hl * Wl) * 4u);
     const T rc = (T)bld1<float>(img, valid ? 4u * (uint32_t)(vl * Wl + ul) : kNoLoad);
-    const T inv_delta = (T)(1.0 / a.delta);
-    f[0] = (float)(rc / (T)a.r_max);
+    const T inv_delta = (T)(1.0 / a.delta), inv_rmax = (T)(1.0 / (double)a.r_max);
+    f[0] = (float)(rc * inv_rmax);
     int k = 1;
 #pragma unroll
     for (int dv = -1; dv <= 1; ++dv)
@@ -220,9 +257,6 @@ __device__ __forceinline__ void compute_features(const StepArgs &a, const LevelI
     f[11] = (float)n2;
     f[12] = clamp4((float)(e * inv_delta));
     f[13] = clamp4((float)((rc - xr) * inv_delta));
-#pragma unroll
-    for (int q = 0; q < 14; ++q)
-        f[q] = valid ? f[q] : 0.f;
 }
 
 template <typename T>
@@ -233,7 +267,7 @@ __device__ __forceinline__ void store_features(const StepArgs &a, const LevelIma
     compute_features<T>(a, L, valid, ul, vl, e, xr, n0, n1, n2, f);
 #pragma unroll
     for (int k = 0; k < 14; ++k)
-        out[k] = f[k];
+        out[k] = valid ? f[k] : 0.f;
 }
 
 // Learned weight sigmoid(z) of this lane's correspondence; all lanes of the
@@ -249,11 +283,11 @@ __device__ __forceinline__ T learned_weight(const StepArgs &a, const MlpInfer &F
     compute_features<T>(a, L, valid, ul, vl, e, xr, n0, n1, n2, f);
     if (dump && dump_index >= 0)
         for (int k = 0; k < 14; ++k)
-            dump[14 * (size_t)dump_index + k] = f[k];
+            dump[14 * (size_t)dump_index + k] = valid ? f[k] : 0.f;
     uint32_t fp[8];
     pack_features(f, fp);
     const float z = mlp_wave(F, fp, s_stage[threadIdx.x >> 6]);
-    return (T)(1.f / (1.f + __expf(-z)));
+    return (T)d_rcp(1.f + __expf(-z));
 }
 
 }  // namespace rir

@@ -61,12 +61,14 @@ class DeviceBatch:
         return len(self.items)
 
 
-def register(ctx, batch: DeviceBatch, levels, iters, init=None, mlp=None, delta=0.5, r_max=80.0, chunk=256):
+def register(ctx, batch: DeviceBatch, levels, iters, init=None, mlp=None, delta=0.5, r_max=80.0, chunk=256,
+             learned_levels=0):
     """Batched registration; returns host poses [n, 4, 4] and stats [n, levels]."""
     import torch
     rir = _rir()
     prm = rir.make_params(levels=levels, iters=iters, delta=delta, r_max=r_max,
-                          weight_mode=rir.WEIGHT_LEARNED if mlp is not None else rir.WEIGHT_HUBER, mlp=mlp)
+                          weight_mode=rir.WEIGHT_LEARNED if mlp is not None else rir.WEIGHT_HUBER, mlp=mlp,
+                          learned_levels=learned_levels)
     n = len(batch)
     poses = np.zeros((n, 4, 4))
     stats = []
@@ -121,22 +123,48 @@ def make_samples(ctx, batch: DeviceBatch, sigma: float, levels=3, iters=(10, 10,
     return np.concatenate(feats), np.concatenate(labels)
 
 
-def train(mlp, feats, labels, steps=3000, batch=8192, lr=2e-3, seed=0, log_every=500):
-    """Adam on minibatches drawn with replacement; returns the loss history."""
+def train(mlp, feats, labels, steps=3000, batch=8192, lr=2e-3, seed=0, log_every=500, validate=None,
+          val_every=0):
+    """Adam on minibatches drawn with replacement (learning rate decayed 10x
+    over the run); returns the loss history.  With validate (a function of
+    the network returning a score, higher is better) the parameters are
+    scored every val_every steps and at the end, and the best-scoring ones are
+    kept (model selection on held-out pairs by the registration quality the
+    network is for, not by the classification loss)."""
     import torch
     F = torch.from_numpy(np.ascontiguousarray(feats, dtype=np.float32)).to("cuda:0")
     Y = torch.from_numpy(np.ascontiguousarray(labels, dtype=np.float32)).to("cuda:0")
     gen = torch.Generator(device="cuda:0")
     gen.manual_seed(seed)
-    hist = []
+    hist, best = [], None
     for k in range(steps):
         idx = torch.randint(0, F.shape[0], (batch,), device="cuda:0", generator=gen)
         cur_lr = lr * (0.1 ** (k / max(steps, 1)))
         loss, _ = mlp.train_step(F[idx].contiguous(), Y[idx].contiguous(), cur_lr)
-        if k % log_every == 0 or k == steps - 1:
+        last = k == steps - 1
+        if k % log_every == 0 or last:
             hist.append((k, float(loss.cpu())))
             _log(f"step {k} loss {hist[-1][1]:.4f}")
+        if validate is not None and ((val_every and (k + 1) % val_every == 0) or last):
+            score = float(validate(mlp))
+            _log(f"step {k + 1} validation score {score:.4f}")
+            if best is None or score > best[0]:
+                best = (score, k + 1, mlp.get_params())
+    if best is not None:
+        mlp.set_params(best[2])
+        _log(f"kept the parameters of step {best[1]} (validation score {best[0]:.4f})")
+        hist.append(("selected_step", best[1], best[0]))
     return hist
+
+
+def validation_score(ctx, batch, levels=3, iters=(3, 10, 10), learned_levels=0b001):
+    """Success rate (<= 0.25 deg, <= 5 cm) of learned registration on batch."""
+    gts = np.stack([p.gt for p in batch.pairs])
+
+    def score(mlp):
+        T, _ = register(ctx, batch, levels, list(iters), mlp=mlp, learned_levels=learned_levels)
+        return summarize(pose_errors(T, gts))["success_rate"]
+    return score
 
 
 def pose_errors(poses, refs):
@@ -154,21 +182,34 @@ def summarize(err, rot_ok=np.deg2rad(0.25), trans_ok=0.05):
             "success_rate": float(np.mean((err[:, 0] <= rot_ok) & (err[:, 1] <= trans_ok)))}
 
 
-def evaluate(ctx, mlp, batch: DeviceBatch, levels=3, iters=(10, 10, 10), repeats=3):
+# Evaluation modes: (name, iterations per level (finest first), learned?,
+# learned_levels).  "learned" replaces pseudo-Huber at the finest level only
+# (coarse levels start far from the solution, where per-pixel evidence cannot
+# tell inliers from outliers); the "*_3" modes run 3 finest-level iterations.
+MODES = (("huber", (10, 10, 10), False, 0), ("learned", (10, 10, 10), True, 0b001),
+         ("learned_all_levels", (10, 10, 10), True, 0), ("huber_3", (3, 10, 10), False, 0),
+         ("learned_3", (3, 10, 10), True, 0b001))
+
+
+def evaluate(ctx, mlp, batch: DeviceBatch, levels=3, modes=MODES, repeats=3):
     """Learned vs plain pseudo-Huber on the same pairs: pose error against the
-    ground truth and batched throughput (pairs/s) on this GPU."""
+    ground truth, success rate (<= 0.25 deg and <= 5 cm), batched throughput
+    (pairs/s on this GPU) and goodput = pairs/s x success rate."""
     import torch
     gts = np.stack([p.gt for p in batch.pairs])
     res = {}
-    for name, net in (("huber", None), ("learned", mlp)):
-        register(ctx, batch, levels, list(iters), mlp=net)  # warm-up (plans, graphs)
+    for name, iters, use_net, ll in modes:
+        net = mlp if use_net else None
+        register(ctx, batch, levels, list(iters), mlp=net, learned_levels=ll)  # warm-up (plans, graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(repeats):
-            T, st = register(ctx, batch, levels, list(iters), mlp=net)
+            T, st = register(ctx, batch, levels, list(iters), mlp=net, learned_levels=ll)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / repeats
         s = summarize(pose_errors(T, gts))
+        s["iters"] = list(iters)
+        s["learned_levels"] = ll if use_net else None
         s["pairs_per_s"] = len(batch) / dt
         s["goodput_pairs_per_s"] = s["pairs_per_s"] * s["success_rate"]
         s["fallback_levels"] = int(np.sum(st["status"] == 2))
@@ -195,6 +236,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--per-view", type=int, default=160)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--val-pairs", type=int, default=200)
+    ap.add_argument("--val-every", type=int, default=500)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--weights", default=WEIGHTS)
     args = ap.parse_args(argv)
@@ -215,10 +258,15 @@ def main(argv=None):
         del batch, pairs
         _log(f"{len(Y)} samples ({Y.mean():.3f} positive) in {time.perf_counter() - t0:.1f}s")
         mlp = rir.Mlp(rir.init_mlp_params(0))
-        hist = train(mlp, F, Y, steps=args.steps, lr=args.lr, log_every=max(1, args.steps // 10))
+        val = None
+        if args.val_pairs > 0:
+            val = validation_score(ctx, DeviceBatch([synth.gen_pair(cfg, 14000 + i) for i in range(args.val_pairs)]))
+        hist = train(mlp, F, Y, steps=args.steps, lr=args.lr, log_every=max(1, args.steps // 10), validate=val,
+                     val_every=args.val_every)
         save(mlp, args.out, {"train_pairs": args.pairs, "train_seeds": [3000, 3000 + args.pairs - 1],
-                             "samples": int(len(Y)), "positive": float(Y.mean()), "steps": args.steps,
-                             "lr": args.lr, "loss": hist})
+                             "val_seeds": [14000, 14000 + args.val_pairs - 1], "samples": int(len(Y)),
+                             "positive": float(Y.mean()), "steps": args.steps, "lr": args.lr,
+                             "per_view": args.per_view, "loss": hist})
         _log(f"saved {args.out}")
     params = load(args.out if args.cmd == "train" else args.weights)
     mlp = rir.Mlp(params)

@@ -171,17 +171,24 @@ def test_huber_like_network_is_what_it_claims():
     np.testing.assert_allclose(w, 1.0 / (1.0 + np.exp(-(2.0 - 3.0 * a))), rtol=1e-12)
 
 
-def test_learned_icp_matches_oracle(rir):
+# (scene, learned_levels).  With pseudo-Huber at the finest level a dynamic
+# scene need not converge (the re-association cycles at ~1e-4 rad), where no
+# two precisions can agree to 1e-4; the coarse-only case uses a static scene.
+@pytest.mark.parametrize("case", [("dynamic64", 0), ("dynamic64", 0b001), ("pair64", 0b110)])
+def test_learned_icp_matches_oracle(rir, case):
+    cfg, learned_levels = case
     P = _huber_like_params()
-    pair = synth.gen_pair(synth.CONFIGS["dynamic64"], 15)
+    pair = synth.gen_pair(synth.CONFIGS[cfg], 15)
     sm = pair.sensor
     sen = rir.Sensor.from_model(sm)
     ctx = rir.Context(0)
     net = rir.Mlp(P)
-    prm = rir.make_params(levels=3, iters=[10, 10, 10], weight_mode=rir.WEIGHT_LEARNED, mlp=net, r_max=80.0)
+    prm = rir.make_params(levels=3, iters=[10, 10, 10], weight_mode=rir.WEIGHT_LEARNED, mlp=net, r_max=80.0,
+                          learned_levels=learned_levels)
     poses, stats = rir.icp_batch(ctx, prm, [(sen, to_dev(pair.src), to_dev(pair.dst))])
     To, so = oracle.icp(sm, pair.src, pair.dst,
-                        oracle.make_params(levels=3, iters=[10, 10, 10], weight_mode=1, mlp=P, r_max=80.0))
+                        oracle.make_params(levels=3, iters=[10, 10, 10], weight_mode=1, mlp=P, r_max=80.0,
+                                           learned_levels=learned_levels))
     er, et = rot_trans_error(poses.cpu().numpy()[0], To)
     assert er < 1e-4 and et < 1e-3, (er, et)
     st = rir.stats_to_numpy(stats, 1, 3)

@@ -216,3 +216,32 @@ def test_learned_constant_weight_step_is_unweighted_least_squares(orc):
     T3, _ = orc.icp(pair.sensor, pair.src, pair.dst, orc.make_params(levels=1, iters=[1]), T_init=T0)
     assert st2[0]["status"] == orc.ORC_FALLBACK_HUBER
     np.testing.assert_array_equal(T2, T3)
+
+
+def test_learned_levels_select_where_the_network_weighs(orc):
+    """learned_levels = bit set of levels with learned weights: a level
+    outside the set runs exactly the pseudo-Huber iteration, a level inside it
+    the learned one (constant network => unweighted step, which differs)."""
+    import synth
+    pair = synth.gen_pair(synth.CONFIGS["pair64"], 33, shape=(32, 512))
+    P = np.zeros(NP)
+    P[5184] = 0.7
+    T0 = synth.make_pose(synth.rot_axis_angle([0, 0, 1.0], 0.01), [0.05, -0.02, 0.01])
+    huber = orc.make_params(levels=2, iters=[2, 2])
+    Th, sh = orc.icp(pair.sensor, pair.src, pair.dst, huber, T_init=T0)
+    # learned only at level 1: level 1 differs from Huber, so the result does
+    coarse = orc.make_params(levels=2, iters=[2, 2], weight_mode=1, mlp=P, learned_levels=0b10)
+    Tc, sc = orc.icp(pair.sensor, pair.src, pair.dst, coarse, T_init=T0)
+    assert not np.array_equal(Tc, Th)
+    np.testing.assert_allclose(sc[1]["sum_w"], sc[1]["n_valid"] / (1 + np.exp(-0.7)), rtol=1e-12)
+    # learned only at level 1 with no level-0 iterations equals learned everywhere
+    only1 = orc.make_params(levels=2, iters=[0, 2], weight_mode=1, mlp=P, learned_levels=0b10)
+    every = orc.make_params(levels=2, iters=[0, 2], weight_mode=1, mlp=P)
+    np.testing.assert_array_equal(orc.icp(pair.sensor, pair.src, pair.dst, only1, T_init=T0)[0],
+                                  orc.icp(pair.sensor, pair.src, pair.dst, every, T_init=T0)[0])
+    # learned only at level 0 with no level-0 iterations equals pseudo-Huber
+    only0 = orc.make_params(levels=2, iters=[0, 2], weight_mode=1, mlp=P, learned_levels=0b01)
+    plain = orc.make_params(levels=2, iters=[0, 2])
+    T0a, s0a = orc.icp(pair.sensor, pair.src, pair.dst, only0, T_init=T0)
+    np.testing.assert_array_equal(T0a, orc.icp(pair.sensor, pair.src, pair.dst, plain, T_init=T0)[0])
+    assert s0a[1]["status"] == orc.ORC_OK
