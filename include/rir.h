@@ -191,10 +191,13 @@ void rir_ctx_destroy(rir_ctx *ctx);
 rir_status rir_ctx_set_tuning(rir_ctx *ctx, const rir_tuning *tuning);
 rir_status rir_ctx_get_tuning(const rir_ctx *ctx, rir_tuning *tuning);
 
-/* When on, rir_icp_batch records HIP events on its stream around each
- * pyramid level's iterations; rir_ctx_level_times then waits for the last
- * call's events and writes the elapsed milliseconds of level l to ms[l]
- * (ms[levels] receives the normal/pyramid pass).  Host arrays. */
+/* Timing of rir_icp_batch with HIP events recorded in its stream order (as
+ * nodes of the captured graph): on = 0 off, 1 around the normal/pyramid pass
+ * and every pyramid level, 2 around the finest level only (fewer event
+ * nodes, less overhead).  rir_ctx_level_times waits for the last timed call
+ * and writes the elapsed milliseconds of level l to ms[l] (ms[levels]: the
+ * normal/pyramid pass; 0 for parts not timed).  Host arrays.  Errors:
+ * RIR_E_INVALID (null, mode outside 0..2, no timed call yet), RIR_E_HIP. */
 rir_status rir_ctx_enable_timing(rir_ctx *ctx, int32_t on);
 rir_status rir_ctx_level_times(rir_ctx *ctx, float *ms, int32_t n);
 

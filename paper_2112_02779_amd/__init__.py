@@ -229,8 +229,10 @@ class Context:
         _check(lib().rir_ctx_get_tuning(self.handle, ctypes.byref(t)))
         return t.as_dict()
 
-    def enable_timing(self, on=True):
-        _check(lib().rir_ctx_enable_timing(self.handle, int(bool(on))))
+    def enable_timing(self, on=True, finest_only=False):
+        """Event timing of later icp_batch calls: every level and the
+        normal/pyramid pass, or only the finest level (less overhead)."""
+        _check(lib().rir_ctx_enable_timing(self.handle, 0 if not on else (2 if finest_only else 1)))
 
     def level_times(self, levels: int):
         """ms per pyramid level (index l) of the last timed call, plus the

@@ -401,17 +401,20 @@ struct Plan {
     std::vector<const float *> cur_src, cur_dst;
     hipEvent_t desc_evt = nullptr;
     bool desc_pending = false;
-    hipGraphExec_t g_pre = nullptr;
-    hipGraphExec_t g_lev[kMaxLevels] = {};
-    bool graphs = false;
+    // the whole schedule (prepass and every level) as one graph, without and
+    // with the context's timing events as graph nodes
+    hipGraphExec_t g_run[3] = {nullptr, nullptr, nullptr};  // by timing mode
+    hipGraph_t g_src[3] = {nullptr, nullptr, nullptr};      // the graphs they were built from
+    hipGraphNode_t fine_ev[2] = {nullptr, nullptr};         // event nodes of g_src[2]
     ~Plan()
     {
         hipSetDevice(device);
-        if (g_pre)
-            hipGraphExecDestroy(g_pre);
-        for (auto &g : g_lev)
+        for (auto &g : g_run)
             if (g)
                 hipGraphExecDestroy(g);
+        for (auto &g : g_src)
+            if (g)
+                hipGraphDestroy(g);
         if (desc_evt)
             hipEventDestroy(desc_evt);
         if (h_desc)
@@ -430,8 +433,12 @@ struct rir_ctx {
     rir_tuning tune{256, 8, 0, 1, 4};
     std::map<PlanKey, std::unique_ptr<Plan>> plans;
     uint64_t use_clock = 0;
-    bool timing = false;
-    int timing_levels = 0;
+    int timing = 0;  // 0 off, 1 every level and the prepass, 2 the finest level only
+    int timing_levels = 0, timed_mode = 0;  // of the last timed call
+    // mode 2: one event pair per call, round robin over kRing pairs
+    static constexpr int kRing = 64;
+    hipEvent_t ring[kRing][2] = {};
+    int ring_next = 0, ring_n = 0;
     hipEvent_t ev[2 * (kMaxLevels + 1)] = {};
     bool ev_recorded = false;
     ~rir_ctx()
@@ -441,6 +448,10 @@ struct rir_ctx {
         for (auto &e : ev)
             if (e)
                 hipEventDestroy(e);
+        for (auto &pr : ring)
+            for (auto &e : pr)
+                if (e)
+                    hipEventDestroy(e);
         if (cap)
             hipStreamDestroy(cap);
     }
@@ -464,6 +475,9 @@ extern "C" rir_status rir_ctx_create(int device, rir_ctx **out)
     HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     for (auto &e : c->ev)
         HIP_TRY(hipEventCreate(&e));
+    for (auto &pr : c->ring)
+        for (auto &e : pr)
+            HIP_TRY(hipEventCreate(&e));
     *out = c.release();
     return RIR_OK;
 }
@@ -509,12 +523,20 @@ extern "C" rir_status rir_ctx_get_tuning(const rir_ctx *ctx, rir_tuning *tuning)
     return RIR_OK;
 }
 
+namespace {
+// Whether timing mode `timing` brackets part l (l = levels: the prepass).
+bool timed_part(int timing, int l) { return timing == 1 || (timing == 2 && l == 0); }
+}  // namespace
+
 extern "C" rir_status rir_ctx_enable_timing(rir_ctx *ctx, int32_t on)
 {
     if (!ctx)
         return fail(RIR_E_INVALID, "rir_ctx_enable_timing: null context");
-    ctx->timing = on != 0;
+    if (on < 0 || on > 2)
+        return fail(RIR_E_INVALID, "rir_ctx_enable_timing: mode must be 0, 1 or 2");
+    ctx->timing = on;
     ctx->ev_recorded = false;
+    ctx->ring_n = 0;
     return RIR_OK;
 }
 
@@ -528,7 +550,24 @@ extern "C" rir_status rir_ctx_level_times(rir_ctx *ctx, float *ms, int32_t n)
     const int L = ctx->timing_levels;
     for (int i = 0; i < n; ++i)
         ms[i] = 0.f;
+    if (ctx->timed_mode == 2) {
+        // mean over the timed calls since timing was enabled (the last kRing)
+        const int cnt = std::min(ctx->ring_n, rir_ctx::kRing);
+        double sum = 0.0;
+        for (int k = 0; k < cnt; ++k) {
+            const int i = (ctx->ring_next - 1 - k + rir_ctx::kRing) % rir_ctx::kRing;
+            float t = 0.f;
+            HIP_TRY(hipEventSynchronize(ctx->ring[i][1]));
+            HIP_TRY(hipEventElapsedTime(&t, ctx->ring[i][0], ctx->ring[i][1]));
+            sum += t;
+        }
+        if (n > 0 && cnt > 0)
+            ms[0] = (float)(sum / cnt);
+        return RIR_OK;
+    }
     for (int l = 0; l <= L && l < n; ++l) {
+        if (!timed_part(ctx->timed_mode, l))
+            continue;
         HIP_TRY(hipEventSynchronize(ctx->ev[2 * l + 1]));
         HIP_TRY(hipEventElapsedTime(&ms[l], ctx->ev[2 * l], ctx->ev[2 * l + 1]));
     }
@@ -881,74 +920,138 @@ rir_status enqueue_level(const Plan *P, const rir_icp_params *p, int l, hipStrea
     return RIR_OK;
 }
 
-rir_status capture(rir_ctx *ctx, Plan *P, const rir_icp_params *p)
+// Enqueues the whole schedule eagerly: prepass, then the levels coarse to
+// fine, with timing events around the prepass and every level.
+rir_status enqueue_all(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int timing, hipStream_t st,
+                       hipEvent_t *fine = nullptr)
+{
+    const int L = P->key.k.levels;
+    hipEvent_t *evs = ctx->ev;
+    if (timed_part(timing, L))
+        HIP_TRY(hipEventRecord(ctx->ev[2 * L], st));
+    rir_status s = enqueue_prepass(P, p, st);
+    if (s != RIR_OK)
+        return s;
+    if (timed_part(timing, L))
+        HIP_TRY(hipEventRecord(ctx->ev[2 * L + 1], st));
+    for (int l = L - 1; l >= 0; --l) {
+        if (timed_part(timing, l))
+            HIP_TRY(hipEventRecord(l == 0 && fine ? fine[0] : evs[2 * l], st));
+        s = enqueue_level(P, p, l, st);
+        if (s != RIR_OK)
+            return s;
+        if (timed_part(timing, l))
+            HIP_TRY(hipEventRecord(l == 0 && fine ? fine[1] : evs[2 * l + 1], st));
+    }
+    return RIR_OK;
+}
+
+// Captures one part of the schedule (which < 0: prepass, else level which)
+// on the context's private stream.
+rir_status capture_part(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int which, hipGraph_t *out)
 {
     hipStream_t cs = ctx->cap;
-    auto cap_one = [&](int which, hipGraphExec_t *out) -> rir_status {
-        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        rir_status st = which < 0 ? enqueue_prepass(P, p, cs) : enqueue_level(P, p, which, cs);
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    rir_status st = which < 0 ? enqueue_prepass(P, p, cs) : enqueue_level(P, p, which, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st != RIR_OK) {
+        if (g)
+            hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess)
+        return fail(RIR_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    *out = g;
+    return RIR_OK;
+}
+
+// The whole schedule as one graph: the captured prepass and levels as child
+// graphs in a chain, with event-record nodes (the context's timing events)
+// between them when timing.  One launch, no gaps between the parts.
+rir_status capture(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int timing, hipGraphExec_t *out)
+{
+    const int L = P->key.k.levels;
+    std::vector<hipGraph_t> parts;
+    auto cleanup = [&](hipGraph_t parent) {
+        for (hipGraph_t g : parts)
+            hipGraphDestroy(g);
+        if (parent)
+            hipGraphDestroy(parent);
+    };
+    for (int w = -1; w < L; ++w) {
         hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(cs, &g);
+        rir_status st = capture_part(ctx, P, p, w < 0 ? -1 : L - 1 - w, &g);
         if (st != RIR_OK) {
-            if (g)
-                hipGraphDestroy(g);
+            cleanup(nullptr);
             return st;
         }
-        if (e != hipSuccess)
-            return fail(RIR_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-        e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
-        if (e != hipSuccess)
-            return fail(RIR_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        return RIR_OK;
-    };
-    rir_status st = cap_one(-1, &P->g_pre);
-    if (st != RIR_OK)
-        return st;
-    for (int l = 0; l < P->key.k.levels; ++l) {
-        st = cap_one(l, &P->g_lev[l]);
-        if (st != RIR_OK)
-            return st;
+        parts.push_back(g);
     }
-    P->graphs = true;
+    hipGraph_t parent = nullptr;
+    hipError_t e = hipGraphCreate(&parent, 0);
+    hipGraphNode_t prev = nullptr;
+    auto add_event = [&](int k) {
+        hipGraphNode_t n = nullptr;
+        if (e == hipSuccess)
+            e = hipGraphAddEventRecordNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, ctx->ev[k]);
+        prev = n;
+        if (timing == 2 && k < 2)
+            P->fine_ev[k] = n;
+    };
+    for (int w = -1; w < L && e == hipSuccess; ++w) {
+        const int l = w < 0 ? L : L - 1 - w;  // event pair 2l, 2l + 1 (l = L: prepass)
+        if (timed_part(timing, l))
+            add_event(2 * l);
+        hipGraphNode_t n = nullptr;
+        if (e == hipSuccess)
+            e = hipGraphAddChildGraphNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, parts[w + 1]);
+        prev = n;
+        if (timed_part(timing, l))
+            add_event(2 * l + 1);
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(out, parent, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        cleanup(parent);
+        return fail(RIR_E_HIP, std::string("assembling the schedule graph: ") + hipGetErrorString(e));
+    }
+    // the parent stays alive with the plan: its event nodes address the
+    // instantiated graph when the timing events are swapped per call
+    cleanup(nullptr);
+    P->g_src[timing] = parent;
     return RIR_OK;
 }
 
 rir_status run_plan(rir_ctx *ctx, Plan *P, const rir_icp_params *p, hipStream_t st)
 {
-    const int L = P->key.k.levels;
-    const bool tm = ctx->timing;
-    if (p->use_graph && !P->graphs) {
-        rir_status s = capture(ctx, P, p);
-        if (s != RIR_OK)
-            return s;
+    const int tm = ctx->timing;
+    hipEvent_t *fine = nullptr;
+    if (tm == 2) {
+        fine = ctx->ring[ctx->ring_next];
+        ctx->ring_next = (ctx->ring_next + 1) % rir_ctx::kRing;
+        ctx->ring_n = std::min(ctx->ring_n + 1, rir_ctx::kRing);
     }
-    if (tm)
-        HIP_TRY(hipEventRecord(ctx->ev[2 * L], st));
-    if (p->use_graph)
-        HIP_TRY(hipGraphLaunch(P->g_pre, st));
-    else {
-        rir_status s = enqueue_prepass(P, p, st);
-        if (s != RIR_OK)
-            return s;
-    }
-    if (tm)
-        HIP_TRY(hipEventRecord(ctx->ev[2 * L + 1], st));
-    for (int l = L - 1; l >= 0; --l) {
-        if (tm)
-            HIP_TRY(hipEventRecord(ctx->ev[2 * l], st));
-        if (p->use_graph)
-            HIP_TRY(hipGraphLaunch(P->g_lev[l], st));
-        else {
-            rir_status s = enqueue_level(P, p, l, st);
+    if (p->use_graph) {
+        hipGraphExec_t &g = P->g_run[tm];
+        if (!g) {
+            rir_status s = capture(ctx, P, p, tm, &g);
             if (s != RIR_OK)
                 return s;
         }
-        if (tm)
-            HIP_TRY(hipEventRecord(ctx->ev[2 * l + 1], st));
+        if (fine) {
+            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(g, P->fine_ev[0], fine[0]));
+            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(g, P->fine_ev[1], fine[1]));
+        }
+        HIP_TRY(hipGraphLaunch(g, st));
+    } else {
+        rir_status s = enqueue_all(ctx, P, p, tm, st, fine);
+        if (s != RIR_OK)
+            return s;
     }
     if (tm) {
-        ctx->timing_levels = L;
+        ctx->timing_levels = P->key.k.levels;
+        ctx->timed_mode = tm;
         ctx->ev_recorded = true;
     }
     return RIR_OK;
@@ -1067,8 +1170,8 @@ extern "C" rir_status rir_autotune(rir_ctx *ctx, const rir_icp_params *params, i
         return s;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool was_timing = ctx->timing;
-    ctx->timing = false;
+    const int was_timing = ctx->timing;
+    ctx->timing = 0;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));

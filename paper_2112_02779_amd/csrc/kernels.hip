@@ -160,13 +160,17 @@ __global__ void k_clear(int *flags, int n_flags, rir_level_stats *stats, int n_s
 
 // ----------------------------------------------------------------------------- prepass
 
-// Normal image and pyramid (Sec. 4.1): each wavefront takes one segment of a
-// target row, computes the normals of its 64 pixels (row factors by scalar
-// loads, neighbour ranges by bounds-checked buffer loads) and writes the
-// (n, n . q) record (0, 0, 0, NaN where the normal is invalid) at level 0 and, for pixels on the grid of level l, the
+// Normal image and pyramid (Sec. 4.1): each wavefront takes kPrepSeg
+// segments of target rows at a time, issues all their range loads first
+// (centre, row neighbours, rows above and below; bounds-checked buffer
+// loads), then computes the normals of their pixels (row factors by scalar
+// loads) and writes the (n, n . q) records (0, 0, 0, NaN where the normal is
+// invalid) at level 0 and, for rows and columns on the grid of level l, the
 // strided copies of the record, the target range and the source range.  With
 // init_centroid each tile also records the sums of its valid source and
 // target points (reduced per pair by k_centroid).
+constexpr int kPrepSeg = 2;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
 {
@@ -191,55 +195,74 @@ __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
 #pragma unroll
         for (int k = 0; k < kAccum; ++k)
             acc[k] = (T)0;
-        for (int seg = tl.y + wave; seg < seg_end; seg += nwave) {
-            const int v = seg / spr, u = (seg - v * spr) * kSegPx + lane;
-            const bool in = u < W;
-            const int i = v * W + u;
-            const float rc = bld1<float>(drs, in ? 4u * (uint32_t)i : kNoLoad);
-            const float rs = bld1<float>(srs, in ? 4u * (uint32_t)i : kNoLoad);
-            T ca, sa;
-            bld2(crs, in ? (uint32_t)u * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca, sa);
-            const V4<T> rw = sld4(rowt, v);
-            V4<T> rec = {(T)0, (T)0, (T)0, quiet_nan<T>()};
-            if (v > 0 && v < H - 1) {
+        for (int s0 = tl.y + wave; s0 < seg_end; s0 += kPrepSeg * nwave) {
+            int vs[kPrepSeg], us[kPrepSeg];
+            bool in[kPrepSeg];
+            float rc[kPrepSeg], rs[kPrepSeg], rl[kPrepSeg], rr[kPrepSeg], ru[kPrepSeg], rd[kPrepSeg];
+            T ca[kPrepSeg], sa[kPrepSeg];
+#pragma unroll
+            for (int j = 0; j < kPrepSeg; ++j) {
+                const int seg = s0 + j * nwave;
+                const bool live = seg < seg_end;
+                const int v = live ? seg / spr : 0;
+                const int u = (seg - v * spr) * kSegPx + lane;
+                const bool ok = live && u < W;
+                const bool inner = live && v > 0 && v < H - 1;  // normal rows (uniform)
+                const int i = v * W + u;
                 const int ul = u == 0 ? W - 1 : u - 1, ur = u == W - 1 ? 0 : u + 1;
-                const float rl = bld1<float>(drs, in ? 4u * (uint32_t)(v * W + ul) : kNoLoad);
-                const float rr = bld1<float>(drs, in ? 4u * (uint32_t)(v * W + ur) : kNoLoad);
-                const float ru = bld1<float>(drs, in ? 4u * (uint32_t)(i - W) : kNoLoad);
-                const float rd = bld1<float>(drs, in ? 4u * (uint32_t)(i + W) : kNoLoad);
-                V3<T> n;
-                if (normal_core(ca, sa, rw, sld4(rowt, v + 1), sld4(rowt, v - 1), sld4(nrowt, 2 * v),
-                                sld4(nrowt, 2 * v + 1), r0, cos_h, sin_h, rc, rl, rr, ru, rd, a.edge_rel, n)) {
-                    const V3<T> d = ray_dir(rw, ca, sa);
-                    const T q0 = (T)rc * d.x + r0 * ca, q1 = (T)rc * d.y + r0 * sa, q2 = (T)rc * d.z;
-                    rec = V4<T>{n.x, n.y, n.z, n.x * q0 + n.y * q1 + n.z * q2};
-                }
+                vs[j] = v;
+                us[j] = u;
+                in[j] = ok;
+                rc[j] = bld1<float>(drs, ok ? 4u * (uint32_t)i : kNoLoad);
+                rs[j] = bld1<float>(srs, ok ? 4u * (uint32_t)i : kNoLoad);
+                bld2(crs, ok ? (uint32_t)u * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca[j], sa[j]);
+                rl[j] = bld1<float>(drs, ok && inner ? 4u * (uint32_t)(v * W + ul) : kNoLoad);
+                rr[j] = bld1<float>(drs, ok && inner ? 4u * (uint32_t)(v * W + ur) : kNoLoad);
+                ru[j] = bld1<float>(drs, ok && inner ? 4u * (uint32_t)(i - W) : kNoLoad);
+                rd[j] = bld1<float>(drs, ok && inner ? 4u * (uint32_t)(i + W) : kNoLoad);
             }
-            if (!in)
-                continue;
-            gst4(d40 + 4 * (size_t)i, rec);
-            for (int l = 1; l < a.levels; ++l) {
-                const int msk = (1 << l) - 1;
-                if ((u & msk) == 0 && (v & msk) == 0) {
-                    const size_t q = (size_t)(v >> l) * (W >> l) + (u >> l);
-                    gst4(cload(&P->dst4[l]) + 4 * q, rec);
-                    gst1(cload(&P->dstr[l]) + q, rc);
-                    gst1(cload(&P->src[l]) + q, rs);
+#pragma unroll
+            for (int j = 0; j < kPrepSeg; ++j) {
+                const int v = vs[j], u = us[j];
+                const V4<T> rw = sld4(rowt, v);
+                V4<T> rec = {(T)0, (T)0, (T)0, quiet_nan<T>()};
+                if (v > 0 && v < H - 1) {
+                    V3<T> n;
+                    if (normal_core(ca[j], sa[j], rw, sld4(rowt, v + 1), sld4(rowt, v - 1), sld4(nrowt, 2 * v),
+                                    sld4(nrowt, 2 * v + 1), r0, cos_h, sin_h, rc[j], rl[j], rr[j], ru[j], rd[j],
+                                    a.edge_rel, n)) {
+                        const V3<T> d = ray_dir(rw, ca[j], sa[j]);
+                        const T q0 = (T)rc[j] * d.x + r0 * ca[j], q1 = (T)rc[j] * d.y + r0 * sa[j];
+                        const T q2 = (T)rc[j] * d.z;
+                        rec = V4<T>{n.x, n.y, n.z, n.x * q0 + n.y * q1 + n.z * q2};
+                    }
                 }
-            }
-            if (a.init_centroid) {
-                const V3<T> d = ray_dir(rw, ca, sa);
-                if (range_ok(rs)) {
-                    acc[0] += (T)rs * d.x + r0 * ca;
-                    acc[1] += (T)rs * d.y + r0 * sa;
-                    acc[2] += (T)rs * d.z;
-                    acc[3] += (T)1;
+                if (in[j]) {
+                    gst4(d40 + 4 * (size_t)(v * W + u), rec);
+                    if (a.init_centroid) {
+                        const V3<T> d = ray_dir(rw, ca[j], sa[j]);
+                        if (range_ok(rs[j])) {
+                            acc[0] += (T)rs[j] * d.x + r0 * ca[j];
+                            acc[1] += (T)rs[j] * d.y + r0 * sa[j];
+                            acc[2] += (T)rs[j] * d.z;
+                            acc[3] += (T)1;
+                        }
+                        if (range_ok(rc[j])) {
+                            acc[4] += (T)rc[j] * d.x + r0 * ca[j];
+                            acc[5] += (T)rc[j] * d.y + r0 * sa[j];
+                            acc[6] += (T)rc[j] * d.z;
+                            acc[7] += (T)1;
+                        }
+                    }
                 }
-                if (range_ok(rc)) {
-                    acc[4] += (T)rc * d.x + r0 * ca;
-                    acc[5] += (T)rc * d.y + r0 * sa;
-                    acc[6] += (T)rc * d.z;
-                    acc[7] += (T)1;
+                // pyramid copies: rows on the level grid (uniform test), then columns
+                for (int l = 1; l < a.levels && (v & ((1 << l) - 1)) == 0; ++l) {
+                    if (in[j] && (u & ((1 << l) - 1)) == 0) {
+                        const size_t q = (size_t)(v >> l) * (W >> l) + (u >> l);
+                        gst4(cload(&P->dst4[l]) + 4 * q, rec);
+                        gst1(cload(&P->dstr[l]) + q, rc[j]);
+                        gst1(cload(&P->src[l]) + q, rs[j]);
+                    }
                 }
             }
         }
