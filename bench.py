@@ -131,6 +131,164 @@ def learned_vs_plain(rir, ctx, n_pairs=256, repeats=5):
             "modes": res}
 
 
+def _level_sizes(H, W, levels):
+    return [(H >> l) * (W >> l) for l in range(levels)]
+
+
+def algorithmic_bytes(shapes, st, levels, iters):
+    """HBM bytes a batched registration must move at least: the prepass reads
+    both level-0 range images and writes the target records of every level
+    (16 B/px) and the compacted source/target ranges of the coarser levels
+    (8 B/px); each Gauss-Newton iteration reads the source ranges (4 B/px) and
+    gathers one 16 B record per projected pixel (the projection count of the
+    level's last iteration stands in for every iteration of the level)."""
+    total = 0.0
+    for i, (H, W) in enumerate(shapes):
+        N = _level_sizes(H, W, levels)
+        total += 8.0 * N[0] + 16.0 * sum(N) + 8.0 * sum(N[1:])
+        for l in range(levels):
+            total += iters[l] * (4.0 * N[l] + 16.0 * float(st["n_proj"][i, l]))
+    return total
+
+
+def _time_batch(rir, ctx, prm, batch, repeats):
+    import torch
+    rir.icp_batch(ctx, prm, batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        T, st = rir.icp_batch(ctx, prm, batch)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / repeats, T, st
+
+
+def _gt_summary(T, gts):
+    e = np.array([rot_trans_error(A, B) for A, B in zip(T, gts)])
+    ok = float(np.mean((e[:, 0] <= np.deg2rad(0.25)) & (e[:, 1] <= 0.05)))
+    return e, ok
+
+
+def _oracle_check(pairs, idx, prm_kw, T_gpu, threads):
+    """Pose error of the GPU result against the FP64 oracle on pairs idx."""
+    import oracle
+    prm = oracle.make_params(**prm_kw)
+
+    def run(i):
+        return oracle.icp(pairs[i].sensor, pairs[i].src, pairs[i].dst, prm)[0]
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        To = list(ex.map(run, idx))
+    errs = [rot_trans_error(T_gpu[i], T) for i, T in zip(idx, To)]
+    ok = [e[0] <= ROT_TOL and e[1] <= TRANS_TOL for e in errs]
+    return {"checked": len(idx), "within_tol": int(sum(ok)),
+            "max_err_rad_m": [max(e[0] for e in errs), max(e[1] for e in errs)]}
+
+
+def mixed_batch(rir, ctx, oracle_sample, threads, repeats=5):
+    """256 independent pairs of mixed sizes (16x1024 .. 128x2048, room scenes,
+    seeds 2000..2255), 3 levels x 10 iterations: one batched call (one graph
+    for the whole batch) against one call per pair, with the algorithmic HBM
+    bytes of the batch over its time."""
+    import torch
+    import synth
+    cfg = synth.CONFIGS["batch256mixed"]
+    t0 = time.perf_counter()
+    pairs = synth.gen_batch(cfg, 2000)
+    log(f"mixed batch: generated {len(pairs)} pairs in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    sensors = {}
+    batch = []
+    for p in pairs:
+        key = (p.sensor.H, p.sensor.W)
+        if key not in sensors:
+            sensors[key] = rir.Sensor.from_model(p.sensor)
+        batch.append((sensors[key], torch.from_numpy(p.src).to(dev), torch.from_numpy(p.dst).to(dev)))
+    levels, iters = cfg["levels"], cfg["iters"]
+    prm = rir.make_params(levels=levels, iters=iters, delta=cfg["delta"])
+    dt_b, T, st = _time_batch(rir, ctx, prm, batch, repeats)
+    T = T.cpu().numpy()
+    stn = rir.stats_to_numpy(st, len(pairs), levels)
+    for b in batch:  # one plan per shape, built outside the timing
+        rir.icp_batch(ctx, prm, [b])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        for b in batch:
+            rir.icp_batch(ctx, prm, [b])
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / repeats
+    shapes = [(p.sensor.H, p.sensor.W) for p in pairs]
+    nbytes = algorithmic_bytes(shapes, stn, levels, iters)
+    e, ok = _gt_summary(T, [p.gt for p in pairs])
+    res = {"workload": f"{len(pairs)} room-scene pairs, H x W uniform over 16x1024, 32x1024, 64x1024, 128x2048 "
+                       f"(seeds 2000..{2000 + len(pairs) - 1}), {levels} levels x {iters[0]} iterations",
+           "batched_ms": round(dt_b * 1e3, 3), "batched_pairs_per_s": round(len(pairs) / dt_b, 1),
+           "per_pair_calls_ms": round(dt_s * 1e3, 3), "per_pair_calls_pairs_per_s": round(len(pairs) / dt_s, 1),
+           "speedup_batched": round(dt_s / dt_b, 2),
+           "algorithmic_bytes": nbytes, "algorithmic_GBps": round(nbytes / dt_b / 1e9, 1),
+           "hbm_frac": round(nbytes / dt_b / 1e9 / HBM_PEAK_GBS, 4),
+           "success_rate_vs_gt": ok, "median_err_vs_gt_rad_m": [float(np.median(e[:, 0])), float(np.median(e[:, 1]))]}
+    if oracle_sample:
+        idx = list(range(0, len(pairs), max(1, len(pairs) // oracle_sample)))[:oracle_sample]
+        res["oracle"] = _oracle_check(pairs, idx, dict(levels=levels, iters=iters, delta=cfg["delta"],
+                                                       r_max=cfg["noise"].rmax), T, threads)
+    log(f"mixed batch: batched {res['batched_ms']:.3f} ms ({res['hbm_frac']:.3f} of HBM peak), "
+        f"per-pair calls {res['per_pair_calls_ms']:.3f} ms")
+    return res
+
+
+def combined_modes(rir, ctx, oracle_sample, threads, repeats=5):
+    """64 dynamic pairs of mixed sizes (16x1024 .. 128x4096; moved boxes and
+    spurious returns; seeds 4000..4063), 3 levels x 10 iterations, in three
+    modes: FP32 per-pixel pseudo-Huber, learned weights at the finest level,
+    and FP64 everywhere."""
+    import torch
+    import synth
+    from paper_2112_02779_amd import learned
+    cfg = synth.CONFIGS["combined64mixed"]
+    t0 = time.perf_counter()
+    pairs = synth.gen_batch(cfg, 4000)
+    log(f"combined modes: generated {len(pairs)} pairs in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    sensors = {}
+    batch = []
+    for p in pairs:
+        key = (p.sensor.H, p.sensor.W)
+        if key not in sensors:
+            sensors[key] = rir.Sensor.from_model(p.sensor)
+        batch.append((sensors[key], torch.from_numpy(p.src).to(dev), torch.from_numpy(p.dst).to(dev)))
+    levels, iters = cfg["levels"], cfg["iters"]
+    net = rir.Mlp(learned.load())
+    shapes = [(p.sensor.H, p.sensor.W) for p in pairs]
+    gts = [p.gt for p in pairs]
+    modes = {"plain_fp32": dict(),
+             "learned_fp32": dict(weight_mode=rir.WEIGHT_LEARNED, mlp=net, r_max=cfg["noise"].rmax,
+                                  learned_levels=0b001),
+             "plain_fp64": dict(precision=rir.PREC_FP64)}
+    res = {}
+    for name, kw in modes.items():
+        prm = rir.make_params(levels=levels, iters=iters, delta=cfg["delta"], **kw)
+        dt, T, st = _time_batch(rir, ctx, prm, batch, repeats)
+        T = T.cpu().numpy()
+        stn = rir.stats_to_numpy(st, len(pairs), levels)
+        nbytes = algorithmic_bytes(shapes, stn, levels, iters)
+        e, ok = _gt_summary(T, gts)
+        res[name] = {"ms": round(dt * 1e3, 3), "pairs_per_s": round(len(pairs) / dt, 1),
+                     "success_rate_vs_gt": ok, "goodput_pairs_per_s": round(ok * len(pairs) / dt, 1),
+                     "median_err_vs_gt_rad_m": [float(np.median(e[:, 0])), float(np.median(e[:, 1]))],
+                     "algorithmic_GBps": round(nbytes / dt / 1e9, 1)}
+        if oracle_sample and name != "learned_fp32":
+            # the oracle computes in FP64 for both precisions of the library
+            idx = list(range(0, len(pairs), max(1, len(pairs) // oracle_sample)))[:oracle_sample]
+            res[name]["oracle"] = _oracle_check(pairs, idx, dict(levels=levels, iters=iters, delta=cfg["delta"],
+                                                                 r_max=cfg["noise"].rmax), T, threads)
+        log(f"combined modes {name}: {res[name]['ms']:.3f} ms, success {ok:.3f}")
+    return {"workload": f"{len(pairs)} dynamic pairs (20% of the boxes moved, 10% spurious returns), H x W uniform "
+                        f"over 16x1024 .. 128x4096 (seeds 4000..{4000 + len(pairs) - 1}), {levels} levels x "
+                        f"{iters[0]} iterations; success = within 0.25 deg and 5 cm of the ground truth",
+            "modes": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +302,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (value then unchecked)")
     ap.add_argument("--sample-every", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-size batch and the combined-modes measurements")
+    ap.add_argument("--mixed-oracle", type=int, default=8,
+                    help="pairs of each mixed workload checked against the oracle (0: none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -255,6 +417,9 @@ def main():
         log(f"oracle sample {len(idx)} pairs in {dt:.1f}s; within tolerance {sum(ok)}/{len(ok)}; max err {max_err}")
 
     lvp = None if args.no_learned else learned_vs_plain(rir, ctx)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    mixed = None if args.no_mixed else mixed_batch(rir, ctx, 0 if args.no_cpu else args.mixed_oracle, threads)
+    comb = None if args.no_mixed else combined_modes(rir, ctx, 0 if args.no_cpu else args.mixed_oracle, threads)
     pairs_per_s = n / (ms_per_step * 1e-3)
     gt_err = [rot_trans_error(T_gpu[i], p.gt) for i, p in enumerate(pairs)]
     out = {
@@ -283,6 +448,8 @@ def main():
         "level_ms": [round(x, 4) for x in level_ms],
         "degenerate_levels": int(np.sum(st["status"] != 0)),
         "learned_vs_plain": lvp,
+        "mixed_batch": mixed,
+        "combined_modes": comb,
     }
     print(json.dumps(out), flush=True)
 

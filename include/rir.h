@@ -169,9 +169,10 @@ void rir_sensor_destroy(rir_sensor *sensor);
  * and tests).  precision (RIR_PREC_*) selects the FP32 or FP64 table.
  * Entry b is 4 values of that type at entries[4b .. 4b+3] and covers every
  * sz = sin(phi) that the kernels map to bin b = trunc(clamp((sz - bin_lo) *
- * bin_scale, 0, nbins - 1)), evaluated in that type with bin_lo, bin_scale
- * and nbins - 1 rounded to it: the low 32 bits of the first value hold
- * c | k << 16, then m, uoff(c), uoff(c + k).  The row of sz at the level is
+ * bin_scale, 0, nbins - 1)), evaluated in that type (the subtraction and the
+ * product each rounded) with bin_lo, bin_scale and nbins - 1 rounded to it:
+ * the low 32 bits of the first value hold c | (c + k) << 16, then m,
+ * uoff(c), uoff(c + k).  The row of sz at the level is
  * c + k [m > sz] (the nearest row, ties to the smaller index) and uoff(t) =
  * theta_lut[2^l t] W / (2 pi 2^l) its column offset.  *nbins receives the
  * entry count and bin_lo / bin_scale (nullable) the FP64 bin parameters;

@@ -657,7 +657,8 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     for (int l = 0; l < L; ++l) {
         bool lean = !(key.k.max_corr > 0.0);
         for (int i = 0; i < n; ++i)
-            lean = lean && pairs[i].sensor->r0 == 0.0 && ((pairs[i].sensor->W >> l) % kSegPx) == 0;
+            lean = lean && pairs[i].sensor->r0 == 0.0 && ((pairs[i].sensor->W >> l) % kSegPx) == 0 &&
+                   (pairs[i].sensor->W & (pairs[i].sensor->W - 1)) == 0;
         P->lean[l] = lean;
     }
     std::vector<std::vector<int2>> tiles(L);

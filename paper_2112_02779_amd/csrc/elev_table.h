@@ -45,7 +45,9 @@ inline T from_key(typename KeyOf<T>::U k)
 template <typename T>
 inline long bin_of(T sz, T lo, T sc, T bmax)
 {
-    T f = (sz - lo) * sc;
+#pragma clang fp contract(off)
+    const T d = sz - lo;
+    T f = d * sc;
     f = f >= (T)0 ? f : (T)0;
     f = f < bmax ? f : bmax;
     return (long)(int)f;
@@ -99,9 +101,9 @@ inline bool build_ebin(const std::vector<double> &mu, const std::vector<double> 
                 ++k;
             }
         }
-        if (c > 0xffff || k > 0xffff)
+        if (c + k > 0xffff)
             return false;
-        const uint64_t ck = (uint32_t)c | ((uint32_t)k << 16);
+        const uint64_t ck = (uint32_t)c | ((uint32_t)(c + k) << 16);
         std::memcpy(&out[4 * b], &ck, sizeof(T) == 4 ? 4 : 8);
         out[4 * b + 1] = mid;
         out[4 * b + 2] = (T)uoff[c];

@@ -96,7 +96,7 @@ __device__ __forceinline__ int bitrev5(int x)
     return ((x & 1) << 4) | ((x & 2) << 2) | (x & 4) | ((x & 8) >> 2) | ((x & 16) >> 4);
 }
 
-__device__ __forceinline__ int wave_count(bool p) { return __popcll(__ballot(p)); }
+__device__ __forceinline__ int wave_count(bool p) { return __builtin_popcountll(__builtin_amdgcn_ballot_w64(p)); }
 
 // ----------------------------------------------------------------------------- geometry kernels
 
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
 // them).  FINE tags the finest-level instance (same code) so that profiles
 // report it separately.  LEAN instances (StepArgs::lean) leave out the
 // receiver offset, the distance gate, the debug dumps and the per-lane row-end
-// test.
+// test, and wrap columns with a mask (the level width is a power of two).
 template <typename T, int WMODE, bool FINE, int CHUNK, bool LEAN>
 __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
 {
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
 #pragma unroll
         for (int k = 0; k < kAccum; ++k)
             acc[k] = (T)0;
-        int c_valid = 0, c_in = 0, c_proj = 0;
+        int c_valid = 0, c_in = 0, c_proj = 0;  // lane count, wave counts
         for (int s0 = tl.y + wave; s0 < seg_end; s0 += CHUNK * nwave) {
             float rs[CHUNK];
             T ca[CHUNK], sa[CHUNK];
@@ -391,8 +391,9 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
                 if constexpr (LEAN) {
                     // whole segments: uniform base plus the lane's offset
                     in[j] = live;
-                    const uint32_t sb = live ? 4u * (uint32_t)(v * Wl + u0) : kNoLoad;
-                    const uint32_t cb = live ? (uint32_t)(s * u0) * (uint32_t)(2 * sizeof(T)) : kNoLoad;
+                    const uint32_t sb = __builtin_amdgcn_readfirstlane(live ? 4u * (uint32_t)(v * Wl + u0) : kNoLoad);
+                    const uint32_t cb = __builtin_amdgcn_readfirstlane(
+                        live ? (uint32_t)(s * u0) * (uint32_t)(2 * sizeof(T)) : kNoLoad);
                     rs[j] = bld1<float>(srs, sb + lane4);
                     bld2(V.col, cb + lane_col, ca[j], sa[j]);
                 } else {
@@ -408,24 +409,26 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
             for (int j = 0; j < CHUNK; ++j) {
                 const T *fr = frames + (size_t)(s * vs[j]) * kFrame;
                 const V4<T> f0 = sld4(fr, 0), f1 = sld4(fr, 1), f2 = sld4(fr, 2);
-                const T r = (T)rs[j], c = ca[j], sn = sa[j];
-                xx[j] = r * (c * f0.x + sn * f0.w + f1.z) + t0;
-                xy[j] = r * (c * f0.y + sn * f1.x + f1.w) + t1;
-                xz[j] = r * (c * f0.z + sn * f1.y + f2.x) + t2;
+                const T r = (T)rs[j], c = ca[j], sn = sa[j], rc = r * c, rsn = r * sn;
+                xx[j] = fma(rc, f0.x, fma(rsn, f0.w, fma(r, f1.z, t0)));
+                xy[j] = fma(rc, f0.y, fma(rsn, f1.x, fma(r, f1.w, t1)));
+                xz[j] = fma(rc, f0.z, fma(rsn, f1.y, fma(r, f2.x, t2)));
                 if (!LEAN && r0 > (T)0) {
                     xx[j] += c * h1x + sn * h2x;
                     xy[j] += c * h1y + sn * h2y;
                     xz[j] += c * h1z + sn * h2z;
                 }
                 const bool okr = range_ok(rs[j]);
-                proj[j] = project<T, !LEAN>(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]) & okr;
+                proj[j] = project<T, !LEAN, LEAN>(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]) & okr;
             }
+            // the gather needs no mask: project() keeps (ul, vl) inside the
+            // level image for every lane, and a lane that did not project adds
+            // exact zeros below whatever record it reads (w = 0, e = 0, finite J)
             V4<T> D[CHUNK];
 #pragma unroll
             for (int j = 0; j < CHUNK; ++j)
-                D[j] = bld4<T>(drs, proj[j] ? (__umul24((uint32_t)vl[j], (uint32_t)Wl) + (uint32_t)ul[j]) *
-                                                   (uint32_t)(4 * sizeof(T))
-                                             : kNoLoad);
+                D[j] = bld4<T>(drs, (__umul24((uint32_t)vl[j], (uint32_t)Wl) + (uint32_t)ul[j]) *
+                                        (uint32_t)(4 * sizeof(T)));
 #pragma unroll
             for (int j = 0; j < CHUNK; ++j) {
                 const T n0 = D[j].x, n1 = D[j].y, n2 = D[j].z;
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
                                               dbg ? a.dbg_feat : nullptr, i);
                 }
                 w = valid ? w : (T)0;
-                c_valid += wave_count(valid);
+                c_valid += valid ? 1 : 0;
                 if (stats) {
                     acc[29] += valid ? e * e * wh * d_rcp(wh + (T)1) : (T)0;
                     c_proj += wave_count(proj[j]);
@@ -497,11 +500,11 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
                 }
             }
         }
+        acc[30] = (T)c_valid;  // exact: far below 2^24 per tile
         const T tot = wave_sum32(acc, lane);
         if (lane < 32)
             s_wave[wave][bitrev5(lane)] = tot;
         if (lane == 0) {
-            s_wcnt[wave][0] = c_valid;
             s_wcnt[wave][1] = c_in;
             s_wcnt[wave][2] = c_proj;
         }
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
         } else if (tid == kAccum) {
             int4 c = make_int4(0, 0, 0, 0);
             for (int w = 0; w < nwave; ++w) {
-                c.x += s_wcnt[w][0];
+                c.x += (int)s_wave[w][30];
                 c.y += s_wcnt[w][1];
                 c.z += s_wcnt[w][2];
             }

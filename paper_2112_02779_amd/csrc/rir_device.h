@@ -22,12 +22,13 @@ constexpr int kMaxLevels = 8;
 //  theta [H]    azimuth offsets
 //  ebin[l] [nbins[l]][4]  inverse elevation table of level l (stride 2^l) over
 //               sz = sin(phi): bin b = trunc(clamp((sz - bin_lo) * bin_scale,
-//               0, nbins - 1)) evaluated in T.  Entry: (bits c | k << 16, m,
-//               uoff(c), uoff(c + k)); the row of every sz that falls in the bin
-//               is c + k [m > sz] (c midpoints lie above the whole bin, k equal
-//               midpoints m inside it), uoff(t) = theta_lut[s t] W / (2 pi s) is
-//               that row's column offset.  The host verifies the entry against
-//               the exact bin edges in T, so the lookup is exact.
+//               0, nbins - 1)) evaluated in T, each operation rounded.  Entry:
+//               (bits c | (c + k) << 16, m, uoff(c), uoff(c + k)); the row of
+//               every sz that falls in the bin is c + k [m > sz] (c midpoints
+//               lie above the whole bin, k equal midpoints m inside it),
+//               uoff(t) = theta_lut[s t] W / (2 pi s) is that row's column
+//               offset.  The host verifies the entry against the exact bin
+//               edges in T, so the lookup is exact.
 template <typename T>
 struct SensorTab {
     int H, W, nlev;
@@ -188,7 +189,9 @@ __device__ __forceinline__ float atan2_abs(float y, float x)
 {
     const float ax = fabsf(x), ay = fabsf(y);
     const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-    const float t = mx > 0.f ? mn * d_rcp(mx) : 0.f;
+    // x = y = 0 gives NaN; such a point lies on the axis, outside every
+    // elevation field of view, and never projects
+    const float t = mn * d_rcp(mx);
     const float t2 = t * t;
     float p = 6.811757572e-03f;
     p = fmaf(p, t2, -3.360411525e-02f);
@@ -211,7 +214,43 @@ __device__ __forceinline__ T azimuth(T y, T x)
     return y < (T)0 ? two_pi<T>() - p : p;
 }
 
-__device__ __forceinline__ bool range_ok(float r) { return r > 0.0f && r <= 3.402823466e38f; }
+// An angle congruent to the azimuth modulo 2 pi, in [-3 pi / 4, 5 pi / 4]
+// (for callers that wrap the column afterwards).  FP32: with
+// t = y / x where |y| <= |x| (angle atan(t), plus pi for x < 0) and
+// t = -x / y otherwise (angle sign(y) pi / 2 + atan(t)), |t| <= 1 and the
+// odd polynomial of atan2_abs gives atan(t); one fused multiply-add adds the
+// offset.  FP64: from the library atan2.
+__device__ __forceinline__ float azimuth_mod(float y, float x)
+{
+    const bool steep = fabsf(y) > fabsf(x);
+    const float num = steep ? -x : y, den = steep ? y : x;
+    const float t = num * d_rcp(den);  // x = y = 0: NaN (never projects)
+    const float t2 = t * t;
+    float p = 6.811757572e-03f;
+    p = fmaf(p, t2, -3.360411525e-02f);
+    p = fmaf(p, t2, 7.962355018e-02f);
+    p = fmaf(p, t2, -1.323333532e-01f);
+    p = fmaf(p, t2, 1.980781406e-01f);
+    p = fmaf(p, t2, -3.331736922e-01f);
+    p = fmaf(p, t2, 9.999961257e-01f);
+    const float off = steep ? copysignf(1.57079632679489661923f, y) : (x < 0.f ? 3.14159265358979323846f : 0.f);
+    return fmaf(t, p, off);
+}
+__device__ __forceinline__ double azimuth_mod(double y, double x) { return copysign(atan2_abs(y, x), y); }
+
+// Half-up rounding to an integer, floor(x + 1/2).  FP32: one conversion
+// instruction that rounds this way.
+__device__ __forceinline__ int round_half_up(float x)
+{
+    int i;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(i) : "v"(x));
+    return i;
+}
+__device__ __forceinline__ int round_half_up(double x) { return (int)floor(x + 0.5); }
+
+// r > 0 and finite (a return).  FP32: one class test (positive normal or
+// subnormal).
+__device__ __forceinline__ bool range_ok(float r) { return __builtin_amdgcn_classf(r, 0x180); }
 
 template <typename T>
 __device__ __forceinline__ T quiet_nan();
@@ -283,18 +322,27 @@ __device__ __forceinline__ LevelView<T> level_view(const SensorTab<T> *tab, int 
 // Eq. (4) on sz = sin(phi): the row of the level whose elevation is nearest
 // (ties to the smaller row), i.e. the number of level midpoints strictly above
 // phi, from one entry of the packed table; uo receives that row's column
-// offset.  NaN falls in bin 0 (the caller has rejected it already).
+// offset.  The bin is (sz - bin_lo) * bin_scale with both operations rounded
+// (never fused: the host builds the table for exactly this formula), clamped
+// to [0, bin_max].  NaN falls in some bin (the caller has rejected it
+// already).
+__device__ __forceinline__ float clamp_bin(float f, float bmax) { return __builtin_amdgcn_fmed3f(f, 0.f, bmax); }
+__device__ __forceinline__ double clamp_bin(double f, double bmax)
+{
+    f = f >= 0.0 ? f : 0.0;
+    return f < bmax ? f : bmax;
+}
 template <typename T>
 __device__ __forceinline__ int elev_row(rsrc_t ebin, T bin_lo, T bin_scale, T bin_max, T sz, T &uo)
 {
-    T f = (sz - bin_lo) * bin_scale;
-    f = f >= (T)0 ? f : (T)0;
-    f = f < bin_max ? f : bin_max;
+#pragma clang fp contract(off)
+    const T d = sz - bin_lo;
+    const T f = clamp_bin(d * bin_scale, bin_max);
     const V4<T> E = bld4<T>(ebin, (uint32_t)(int)f * (uint32_t)(4 * sizeof(T)));
-    const uint32_t ck = low_bits(E.x);
+    const uint32_t rows = low_bits(E.x);
     const bool below = E.y > sz;
     uo = below ? E.w : E.z;
-    return (int)(ck & 0xffffu) + (below ? (int)(ck >> 16) : 0);
+    return (int)__builtin_amdgcn_ubfe(rows, below ? 16u : 0u, 16u);
 }
 
 // Eq. (3)-(4) at the view's level.  With r0 > 0 the receiver offset is
@@ -311,8 +359,9 @@ __device__ __forceinline__ int elev_row(rsrc_t ebin, T bin_lo, T bin_scale, T bi
 // column).  Returns false outside the elevation field of view or at r = 0;
 // ul, vl and r are then unspecified (but in range).  No early exits: the
 // per-pixel path stays free of divergent branches.  R0 = false compiles the
-// receiver-offset branch out (callers that know r0 = 0).
-template <typename T, bool R0 = true>
+// receiver-offset branch out (callers that know r0 = 0); POW2 = true wraps
+// the column with a mask (callers that know Wl is a power of two).
+template <typename T, bool R0 = true, bool POW2 = false>
 __device__ __forceinline__ bool project(const LevelView<T> &V, T x, T y, T z, int &ul, int &vl, T &r)
 {
     T r2, th;
@@ -350,22 +399,27 @@ __device__ __forceinline__ bool project(const LevelView<T> &V, T x, T y, T z, in
         th = th >= two_pi<T>() ? th - two_pi<T>() : th;
     } else {
         r2 = x * x + y * y + z * z;
-        th = azimuth(y, x);
+        th = azimuth_mod(y, x);
     }
     const T rinv = d_rsqrt(r2);
     const T sz = z * rinv;
-    ok = ok && r2 > (T)0 && sz <= V.s_hi && sz >= V.s_lo;
+    // r2 = 0 or a non-finite point gives a NaN or infinite sz, outside the field
+    ok = ok && sz <= V.s_hi && sz >= V.s_lo;
     T uo;
     const int v = elev_row(V.ebin, V.bin_lo, V.bin_scale, V.bin_max, sz, uo);
-    // th in [0, 2 pi] and |uo| < Wl / 2, so the rounded column lies within
-    // one image width of [0, Wl): wrap the integer (exact) rather than the
+    // th * kW lies in [-3 Wl / 8, Wl] and |uo| < Wl / 2, so the rounded column
+    // is within one image width of [0, Wl): wrap the integer (exact), not the
     // coordinate
     const int Wl = V.Wl;
-    int u = (int)floor(th * V.kW - uo + (T)0.5);
-    u = u < 0 ? u + Wl : u;
-    u = u >= Wl ? u - Wl : u;
-    u = u < 0 ? 0 : u;  // NaN inputs only
-    ul = u;
+    const int u = round_half_up(th * V.kW - uo);
+    if constexpr (POW2) {
+        ul = u & (Wl - 1);
+    } else {
+        uint32_t uu = (uint32_t)u;
+        uu = min(uu, uu + (uint32_t)Wl);
+        uu = min(uu, uu - (uint32_t)Wl);
+        ul = (int)min(uu, (uint32_t)Wl - 1u);  // NaN inputs only
+    }
     vl = v;
     r = r2 * rinv;
     return ok;

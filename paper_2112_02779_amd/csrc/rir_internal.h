@@ -71,8 +71,9 @@ struct StepArgs {
     int xcd_remap;
     int mode;            // StepMode
     int lean;            // 1: no receiver offset, no distance gate, no debug
-                         // dumps and every row a whole number of segments
-                         // (the kernel variant without those paths runs)
+                         // dumps, every row a whole number of segments and
+                         // a power-of-two width (the kernel variant without
+                         // those paths runs)
     int stats_pass;      // 1: also accumulate the statistics-only terms (robust
                          // cost, inlier and projection counts); set on the last
                          // scheduled iteration of a level and in debug mode

@@ -29,10 +29,10 @@ def _lookup(tab, lo, sc, sz, T):
     f = np.where(f < bmax, f, bmax)
     b = f.astype(np.int64)
     E = tab[b]
-    ck = E[:, 0].view(np.uint32 if T is np.float32 else np.uint64).astype(np.uint64) & 0xFFFFFFFF
+    rows = E[:, 0].view(np.uint32 if T is np.float32 else np.uint64).astype(np.uint64) & 0xFFFFFFFF
     below = E[:, 1] > sz
-    c, k = (ck & 0xFFFF).astype(np.int64), (ck >> 16).astype(np.int64)
-    return c + np.where(below, k, 0), np.where(below, E[:, 3], E[:, 2])
+    c, ck = (rows & 0xFFFF).astype(np.int64), (rows >> 16).astype(np.int64)
+    return np.where(below, ck, c), np.where(below, E[:, 3], E[:, 2])
 
 
 def _midpoints(m, level):
