@@ -532,11 +532,12 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
 // Solves H xi = -g in FP64 with H = U^T U (U upper triangular, computed in
 // place over the 21 packed row-major entries of H).  Fails when a pivot is not
 // above 1e-12 times the largest diagonal entry.  Fully unrolled so that every
-// array stays in registers.
+// array stays in registers; the substitutions multiply by the reciprocal
+// pivots (six divisions on the serial path instead of eighteen).
 __device__ __forceinline__ bool cholesky6(double (&U)[21], const double (&g)[6], double (&xi)[6])
 {
     constexpr int off[6] = {0, 6, 11, 15, 18, 20};  // start of row i of the packed triangle
-    double dmax = 0.0;
+    double dmax = 0.0, rdiag[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
         dmax = U[off[i]] > dmax ? U[off[i]] : dmax;
@@ -553,6 +554,7 @@ __device__ __forceinline__ bool cholesky6(double (&U)[21], const double (&g)[6],
         d = sqrt(d > 0.0 ? d : 1.0);
         U[off[j]] = d;
         const double inv = 1.0 / d;
+        rdiag[j] = inv;
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double acc = U[off[j] + i - j];
@@ -571,7 +573,7 @@ __device__ __forceinline__ bool cholesky6(double (&U)[21], const double (&g)[6],
 #pragma unroll
         for (int k = 0; k < i; ++k)
             acc -= U[off[k] + i - k] * y[k];
-        y[i] = acc / U[off[i]];
+        y[i] = acc * rdiag[i];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
@@ -579,7 +581,7 @@ __device__ __forceinline__ bool cholesky6(double (&U)[21], const double (&g)[6],
 #pragma unroll
         for (int k = i + 1; k < 6; ++k)
             acc -= U[off[i] + k - i] * xi[k];
-        xi[i] = acc / U[off[i]];
+        xi[i] = acc * rdiag[i];
     }
     return true;
 }
@@ -773,16 +775,35 @@ __global__ __launch_bounds__(256) void k_solve(StepArgs a)
     const PairDesc<T> &P = reinterpret_cast<const PairDesc<T> *>(a.pairs)[pair];
     const T *psum = reinterpret_cast<const T *>(a.psum);
     const int nt = P.ntile[l], t0 = P.tile0[l];
-    // group g of 32 threads sums tiles g, g + 8, ... (one coalesced record per step)
+    // group g of 32 threads sums tiles g, g + 8, ... in that order (one
+    // coalesced record per step), four records in flight at a time
     const int comp = lane & 31, grp = lane >> 5;
     double sum = 0.0;
     long long c = 0;
-    for (int k = grp; k < nt; k += 8) {
-        sum += (double)psum[(size_t)(t0 + k) * kAccum + comp];
+    auto cnt_of = [&](int k) -> int {
+        const int4 pc = a.pcnt[t0 + k];
+        return comp == 0 ? pc.x : (comp == 1 ? pc.y : pc.z);
+    };
+    int k = grp;
+    for (; k + 24 < nt; k += 32) {
+        const T v0 = psum[(size_t)(t0 + k) * kAccum + comp], v1 = psum[(size_t)(t0 + k + 8) * kAccum + comp];
+        const T v2 = psum[(size_t)(t0 + k + 16) * kAccum + comp], v3 = psum[(size_t)(t0 + k + 24) * kAccum + comp];
         if (comp < 3) {
-            const int4 pc = a.pcnt[t0 + k];
-            c += comp == 0 ? pc.x : (comp == 1 ? pc.y : pc.z);
+            const int c0 = cnt_of(k), c1 = cnt_of(k + 8), c2 = cnt_of(k + 16), c3 = cnt_of(k + 24);
+            c += c0;
+            c += c1;
+            c += c2;
+            c += c3;
         }
+        sum += (double)v0;
+        sum += (double)v1;
+        sum += (double)v2;
+        sum += (double)v3;
+    }
+    for (; k < nt; k += 8) {
+        sum += (double)psum[(size_t)(t0 + k) * kAccum + comp];
+        if (comp < 3)
+            c += cnt_of(k);
     }
     s_part[grp][comp] = sum;
     if (comp < 3)
