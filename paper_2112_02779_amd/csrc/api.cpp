@@ -386,6 +386,7 @@ struct Plan {
     bool fp64 = false;
     int tile_seg[kMaxLevels] = {}, block = 0;
     bool lean[kMaxLevels] = {};  // the lean step variant applies (StepArgs::lean)
+    bool resident[kMaxLevels] = {};  // some pair runs the level in the pair-resident kernel
     int n_tiles[kMaxLevels] = {};
     int grid[kMaxLevels] = {};
     void *dmem = nullptr;
@@ -661,13 +662,32 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
                    (pairs[i].sensor->W & (pairs[i].sensor->W - 1)) == 0;
         P->lean[l] = lean;
     }
+    // Pairs whose level image is small run all iterations of the level in the
+    // pair-resident kernel (a property of the pair and the parameters only, so
+    // that a pair's result never depends on its batch); they get no tiles.
+    // Level 0 always keeps its tiles: the prepass and the centroid
+    // initialisation walk them.
+    auto resident = [&](int i, int l) {
+        if (l == 0)
+            return false;
+        const rir_sensor *s = pairs[i].sensor;
+        const int Hl = s->H >> l, Wl = s->W >> l;
+        const bool learned = key.k.weight_mode == RIR_WEIGHT_LEARNED &&
+                             (key.k.learned_levels == 0 || ((key.k.learned_levels >> l) & 1));
+        return !key.k.debug && !P->fp64 && !learned && !(key.k.max_corr > 0.0) && s->r0 == 0.0 &&
+               (s->W & (s->W - 1)) == 0 &&
+               Wl % kSegPx == 0 && Hl <= kPairRows && Hl * Wl <= kPairMaxPx;
+    };
     std::vector<std::vector<int2>> tiles(L);
     std::vector<int> t0(n * kMaxLevels, 0), nt(n * kMaxLevels, 0);
     for (int l = 0; l < L; ++l) {
+        P->resident[l] = false;
         for (int i = 0; i < n; ++i) {
             const rir_sensor *s = pairs[i].sensor;
             const int nseg = (s->H >> l) * (((s->W >> l) + kSegPx - 1) / kSegPx);
-            const int k = (nseg + P->tile_seg[l] - 1) / P->tile_seg[l];
+            const bool res = resident(i, l);
+            P->resident[l] = P->resident[l] || res;
+            const int k = res ? 0 : (nseg + P->tile_seg[l] - 1) / P->tile_seg[l];
             t0[i * kMaxLevels + l] = (int)tiles[l].size();
             nt[i * kMaxLevels + l] = k;
             for (int j = 0; j < k; ++j)
@@ -867,6 +887,7 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
     a.chunk = P->key.k.tune.chunk;
     a.xcd_remap = P->key.k.tune.xcd_remap;
     a.mode = mode;
+    a.iters = P->key.k.iters[level];
     a.stats_pass = (mode == kStepDebug || iter == P->key.k.iters[level] - 1) ? 1 : 0;
     a.lean = (mode != kStepDebug && P->lean[level]) ? 1 : 0;
     a.learned = learned_at(p, level) ? 1 : 0;
@@ -908,6 +929,10 @@ rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t s
 // Enqueues the Gauss-Newton iterations of one level.
 rir_status enqueue_level(const Plan *P, const rir_icp_params *p, int l, hipStream_t st)
 {
+    if (P->resident[l] && P->key.k.iters[l] > 0)
+        HIP_TRY(launch_level(P->fp64, step_args(P, p, l, 0, kStepNormal), P->n_pairs, st));
+    if (P->n_tiles[l] == 0)
+        return RIR_OK;
     for (int it = 0; it < P->key.k.iters[l]; ++it) {
         StepArgs a = step_args(P, p, l, it, kStepNormal);
         HIP_TRY(launch_step(P->fp64, a.learned ? RIR_WEIGHT_LEARNED : RIR_WEIGHT_HUBER, a, P->grid[l], P->block, st));

@@ -310,223 +310,6 @@ __global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
     }
 }
 
-// ----------------------------------------------------------------------------- step
-
-// One Gauss-Newton iteration at level l for every pair of the batch (Eq. (5)-(7),
-// Sec. 4.1).  Each workgroup walks its tiles; a tile is a run of tile_seg
-// segments of one pair's level-l image, and each wavefront takes CHUNK
-// segments at a time (its own 64-pixel pieces of CHUNK rows), so that CHUNK
-// source loads, then CHUNK target gathers, are in flight together.  A
-// segment's row frame (g1, g2, g3: the ray directions of Eq. (1) rotated by
-// the pose) is read with scalar loads, so unprojection plus the rigid
-// transform is x = r (ca g1 + sa g2 + g3) + r0 R (ca, sa, 0) + t.  The
-// target record holds (n, n . q), so e = n . x - n . q (NaN, hence invalid,
-// where the record is).  The tile's sums go to one record (k_solve reduces
-// them).  FINE tags the finest-level instance (same code) so that profiles
-// report it separately.  LEAN instances (StepArgs::lean) leave out the
-// receiver offset, the distance gate, the debug dumps and the per-lane row-end
-// test, and wrap columns with a mask (the level width is a power of two).
-template <typename T, int WMODE, bool FINE, int CHUNK, bool LEAN>
-__global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
-{
-    __shared__ T s_wave[4][kAccum];
-    __shared__ int s_wcnt[4][4];
-    const PairDesc<T> *pairs = reinterpret_cast<const PairDesc<T> *>(a.pairs);
-    T *psum = reinterpret_cast<T *>(a.psum);
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwave = blockDim.x >> 6;
-    const int l = a.level, s = 1 << l;
-    const T delta = (T)a.delta, inv_delta = (T)(1.0 / a.delta);
-    const T mc2 = !LEAN && a.max_corr > 0.0 ? (T)(a.max_corr * a.max_corr) : (T)-1;
-    const bool dbg = !LEAN && a.mode == kStepDebug;
-    const uint32_t lane4 = 4u * (uint32_t)lane, lane_col = (uint32_t)(lane << l) * (uint32_t)(2 * sizeof(T));
-    MlpInfer F;
-    if constexpr (WMODE == 1)
-        mlp_infer_load(a.mlp, F);
-    for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step) {
-        const int2 tl = cload(a.tiles + it.cur);
-        const int pair = tl.x;
-        if (!dbg) {
-            const int *fl = a.flags + (size_t)pair * kFlagStride;
-            if (cload(fl + l) & 1)
-                continue;
-            if (a.mode == kStepFallback && !(cload(fl + kMaxLevels) & 1))
-                continue;
-        }
-        const PairDesc<T> *P = pairs + pair;
-        const LevelView<T> V = level_view(cload(&P->tab), l);
-        const LevelImage LI = {cload(&P->dstr[l]), V.Hl, V.Wl};
-        const double *Tp = a.poses + 16 * (size_t)pair;
-        const T r00 = (T)cload(Tp + 0), r01 = (T)cload(Tp + 1), r02 = (T)cload(Tp + 2), t0 = (T)cload(Tp + 3);
-        const T r10 = (T)cload(Tp + 4), r11 = (T)cload(Tp + 5), r12 = (T)cload(Tp + 6), t1 = (T)cload(Tp + 7);
-        const T r20 = (T)cload(Tp + 8), r21 = (T)cload(Tp + 9), r22 = (T)cload(Tp + 10), t2 = (T)cload(Tp + 11);
-        const int Wl = V.Wl, Hl = V.Hl, spr = (Wl + kSegPx - 1) / kSegPx;
-        const int seg_end = min(tl.y + a.tile_seg, Hl * spr);
-        const uint32_t npx = (uint32_t)(Hl * Wl);
-        const rsrc_t srs = make_rsrc(cload(&P->src[l]), npx * 4u);
-        const rsrc_t drs = make_rsrc(cload(&P->dst4[l]), npx * (uint32_t)(4 * sizeof(T)));
-        const T r0 = LEAN ? (T)0 : V.r0;
-        const T *frames = cload(&P->frames);
-        const T h1x = r0 * r00, h1y = r0 * r10, h1z = r0 * r20;  // r0 R e_x
-        const T h2x = r0 * r01, h2y = r0 * r11, h2z = r0 * r21;  // r0 R e_y
-        const bool stats = a.stats_pass != 0;
-        T acc[kAccum];
-#pragma unroll
-        for (int k = 0; k < kAccum; ++k)
-            acc[k] = (T)0;
-        int c_valid = 0, c_in = 0, c_proj = 0;  // lane count, wave counts
-        for (int s0 = tl.y + wave; s0 < seg_end; s0 += CHUNK * nwave) {
-            float rs[CHUNK];
-            T ca[CHUNK], sa[CHUNK];
-            int vs[CHUNK], us[CHUNK];
-            bool in[CHUNK];
-#pragma unroll
-            for (int j = 0; j < CHUNK; ++j) {
-                const int seg = s0 + j * nwave;
-                const bool live = seg < seg_end;
-                const int v = live ? seg / spr : 0;
-                const int u0 = (seg - v * spr) * kSegPx, u = u0 + lane;
-                vs[j] = v;
-                us[j] = u;
-                if constexpr (LEAN) {
-                    // whole segments: uniform base plus the lane's offset
-                    in[j] = live;
-                    const uint32_t sb = __builtin_amdgcn_readfirstlane(live ? 4u * (uint32_t)(v * Wl + u0) : kNoLoad);
-                    const uint32_t cb = __builtin_amdgcn_readfirstlane(
-                        live ? (uint32_t)(s * u0) * (uint32_t)(2 * sizeof(T)) : kNoLoad);
-                    rs[j] = bld1<float>(srs, sb + lane4);
-                    bld2(V.col, cb + lane_col, ca[j], sa[j]);
-                } else {
-                    in[j] = live && u < Wl;
-                    rs[j] = bld1<float>(srs, in[j] ? 4u * (uint32_t)(v * Wl + u) : kNoLoad);
-                    bld2(V.col, in[j] ? (uint32_t)(s * u) * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca[j], sa[j]);
-                }
-            }
-            bool proj[CHUNK];
-            int ul[CHUNK], vl[CHUNK];
-            T xx[CHUNK], xy[CHUNK], xz[CHUNK], xr[CHUNK];
-#pragma unroll
-            for (int j = 0; j < CHUNK; ++j) {
-                const T *fr = frames + (size_t)(s * vs[j]) * kFrame;
-                const V4<T> f0 = sld4(fr, 0), f1 = sld4(fr, 1), f2 = sld4(fr, 2);
-                const T r = (T)rs[j], c = ca[j], sn = sa[j], rc = r * c, rsn = r * sn;
-                xx[j] = fma(rc, f0.x, fma(rsn, f0.w, fma(r, f1.z, t0)));
-                xy[j] = fma(rc, f0.y, fma(rsn, f1.x, fma(r, f1.w, t1)));
-                xz[j] = fma(rc, f0.z, fma(rsn, f1.y, fma(r, f2.x, t2)));
-                if (!LEAN && r0 > (T)0) {
-                    xx[j] += c * h1x + sn * h2x;
-                    xy[j] += c * h1y + sn * h2y;
-                    xz[j] += c * h1z + sn * h2z;
-                }
-                const bool okr = range_ok(rs[j]);
-                proj[j] = project<T, !LEAN, LEAN>(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]) & okr;
-            }
-            // the gather needs no mask: project() keeps (ul, vl) inside the
-            // level image for every lane, and a lane that did not project adds
-            // exact zeros below whatever record it reads (w = 0, e = 0, finite J)
-            V4<T> D[CHUNK];
-#pragma unroll
-            for (int j = 0; j < CHUNK; ++j)
-                D[j] = bld4<T>(drs, (__umul24((uint32_t)vl[j], (uint32_t)Wl) + (uint32_t)ul[j]) *
-                                        (uint32_t)(4 * sizeof(T)));
-#pragma unroll
-            for (int j = 0; j < CHUNK; ++j) {
-                const T n0 = D[j].x, n1 = D[j].y, n2 = D[j].z;
-                const T ex = n0 * xx[j] + n1 * xy[j] + n2 * xz[j] - D[j].w;
-                bool valid = proj[j] && ex == ex;
-                if (mc2 >= (T)0) {
-                    // Sec. 4.1 correspondence gate: |x - q| against the target point
-                    const rsrc_t rrs = make_rsrc(LI.rng, npx * 4u);
-                    const uint32_t pix = (uint32_t)(vl[j] * Wl + ul[j]);
-                    const T rq = (T)bld1<float>(rrs, valid ? 4u * pix : kNoLoad);
-                    const V4<T> rw = bld4<T>(V.row, (uint32_t)(s * vl[j]) * (uint32_t)(4 * sizeof(T)));
-                    T cq, sq;
-                    bld2(V.col, (uint32_t)(s * ul[j]) * (uint32_t)(2 * sizeof(T)), cq, sq);
-                    const V3<T> d = ray_dir(rw, cq, sq);
-                    const T dx = xx[j] - (rq * d.x + r0 * cq), dy = xy[j] - (rq * d.y + r0 * sq);
-                    const T dz = xz[j] - rq * d.z;
-                    valid = valid && dx * dx + dy * dy + dz * dz <= mc2;
-                }
-                const T e = valid ? ex : (T)0;
-                const T J0 = xy[j] * n2 - xz[j] * n1;
-                const T J1 = xz[j] * n0 - xx[j] * n2;
-                const T J2 = xx[j] * n1 - xy[j] * n0;
-                const T tq = e * inv_delta;
-                const T wh = d_rsqrt((T)1 + tq * tq);
-                T w = wh;
-                const int i = in[j] ? vs[j] * Wl + us[j] : -1;
-                if constexpr (WMODE == 1) {
-                    if (a.mode != kStepFallback)
-                        w = learned_weight<T>(a, F, LI, valid, ul[j], vl[j], e, xr[j], n0, n1, n2,
-                                              dbg ? a.dbg_feat : nullptr, i);
-                }
-                w = valid ? w : (T)0;
-                c_valid += valid ? 1 : 0;
-                if (stats) {
-                    acc[29] += valid ? e * e * wh * d_rcp(wh + (T)1) : (T)0;
-                    c_proj += wave_count(proj[j]);
-                    c_in += wave_count(valid && fabs(e) < delta);
-                }
-                // an invalid pixel has w = 0, e = 0 and finite J (n = 0 unless the
-                // distance gate rejected it), so it adds exact zeros
-                const T J[6] = {J0, J1, J2, n0, n1, n2};
-                T wJ[6];
-#pragma unroll
-                for (int k = 0; k < 6; ++k)
-                    wJ[k] = w * J[k];
-                int k = 0;
-#pragma unroll
-                for (int r = 0; r < 6; ++r)
-#pragma unroll
-                    for (int c = r; c < 6; ++c)
-                        acc[k++] += wJ[r] * J[c];
-#pragma unroll
-                for (int r = 0; r < 6; ++r)
-                    acc[21 + r] += wJ[r] * e;
-                acc[27] += w;
-                acc[28] += w * e * e;
-                if (dbg && i >= 0) {
-                    if (a.dbg_u) a.dbg_u[i] = proj[j] ? ul[j] : -1;
-                    if (a.dbg_v) a.dbg_v[i] = proj[j] ? vl[j] : -1;
-                    if (a.dbg_mask) a.dbg_mask[i] = valid ? 1 : 0;
-                    if (a.dbg_e) a.dbg_e[i] = (float)e;
-                    if (a.dbg_w) a.dbg_w[i] = (float)w;
-                    if (a.dbg_J)
-                        for (int q = 0; q < 6; ++q)
-                            a.dbg_J[6 * (size_t)i + q] = valid ? (float)J[q] : 0.f;
-                    if (WMODE == 0 && a.dbg_feat)
-                        store_features<T>(a, LI, valid, ul[j], vl[j], e, xr[j], n0, n1, n2,
-                                          a.dbg_feat + 14 * (size_t)i);
-                }
-            }
-        }
-        acc[30] = (T)c_valid;  // exact: far below 2^24 per tile
-        const T tot = wave_sum32(acc, lane);
-        if (lane < 32)
-            s_wave[wave][bitrev5(lane)] = tot;
-        if (lane == 0) {
-            s_wcnt[wave][1] = c_in;
-            s_wcnt[wave][2] = c_proj;
-        }
-        __syncthreads();
-        if (tid < kAccum) {
-            T sum = (T)0;
-            for (int w = 0; w < nwave; ++w)
-                sum += s_wave[w][tid];
-            psum[(size_t)it.cur * kAccum + tid] = sum;
-        } else if (tid == kAccum) {
-            int4 c = make_int4(0, 0, 0, 0);
-            for (int w = 0; w < nwave; ++w) {
-                c.x += (int)s_wave[w][30];
-                c.y += s_wcnt[w][1];
-                c.z += s_wcnt[w][2];
-            }
-            a.pcnt[it.cur] = c;
-        }
-        __syncthreads();
-    }
-}
-
 // ----------------------------------------------------------------------------- solve
 
 // Solves H xi = -g in FP64 with H = U^T U (U upper triangular, computed in
@@ -710,6 +493,27 @@ __device__ __forceinline__ bool solve_pair(const StepArgs &a, int pair, int *fl,
     return moved;
 }
 
+// Frame of ray rows for pose R (FP64, row-major 3x4): for the row with
+// factors rw = (cos phi, sin phi, cos theta, sin theta), g1 = R (A, B, 0),
+// g2 = R (-B, A, 0), g3 = sin(phi) R e_z with A = cos(phi) cos(theta),
+// B = cos(phi) sin(theta); then three zeros (PairDesc::frames layout).
+template <typename T>
+__device__ __forceinline__ void frame_row(const T *rw, const double (&R)[12], T *o)
+{
+    const double cphi = (double)rw[0], sphi = (double)rw[1];
+    const double A = cphi * (double)rw[2], B = cphi * (double)rw[3];
+    o[0] = (T)(A * R[0] + B * R[1]);
+    o[1] = (T)(A * R[4] + B * R[5]);
+    o[2] = (T)(A * R[8] + B * R[9]);
+    o[3] = (T)(A * R[1] - B * R[0]);
+    o[4] = (T)(A * R[5] - B * R[4]);
+    o[5] = (T)(A * R[9] - B * R[8]);
+    o[6] = (T)(sphi * R[2]);
+    o[7] = (T)(sphi * R[6]);
+    o[8] = (T)(sphi * R[10]);
+    o[9] = o[10] = o[11] = (T)0;
+}
+
 // Ray frames of every full-resolution row of one pair for the pose in
 // s_pose (the PairDesc::frames layout), written by the threads of one
 // workgroup; FP64 arithmetic, stored in T.
@@ -720,22 +524,337 @@ __device__ __forceinline__ void write_frames(const PairDesc<T> *P, const double 
     const T *row = cload(&tab->row);
     T *fr = cload(&P->frames);
     const int H = cload(&P->H);
-    for (int v = threadIdx.x; v < H; v += blockDim.x) {
-        const double cphi = (double)row[4 * v], sphi = (double)row[4 * v + 1];
-        const double A = cphi * (double)row[4 * v + 2], B = cphi * (double)row[4 * v + 3];
-        T *o = fr + (size_t)v * kFrame;
-        o[0] = (T)(A * R[0] + B * R[1]);
-        o[1] = (T)(A * R[4] + B * R[5]);
-        o[2] = (T)(A * R[8] + B * R[9]);
-        o[3] = (T)(A * R[1] - B * R[0]);
-        o[4] = (T)(A * R[5] - B * R[4]);
-        o[5] = (T)(A * R[9] - B * R[8]);
-        o[6] = (T)(sphi * R[2]);
-        o[7] = (T)(sphi * R[6]);
-        o[8] = (T)(sphi * R[10]);
-        o[9] = o[10] = o[11] = (T)0;
+    for (int v = threadIdx.x; v < H; v += blockDim.x)
+        frame_row(row + 4 * (size_t)v, R, fr + (size_t)v * kFrame);
+}
+
+// ----------------------------------------------------------------------------- step
+
+// The per-pixel work of one Gauss-Newton iteration (Eq. (5)-(7), Sec. 4.1) over
+// segments [seg_begin, seg_end) of one pair's level image, by all wavefronts of
+// the workgroup: each wavefront takes CHUNK segments at a time (its own
+// 64-pixel pieces of CHUNK rows), so that CHUNK source loads, then CHUNK
+// target gathers, are in flight together.  A segment's row frame (g1, g2, g3:
+// the ray directions of Eq. (1) rotated by the pose) is uniform, so
+// unprojection plus the rigid transform is x = r (ca g1 + sa g2 + g3) +
+// r0 R (ca, sa, 0) + t.  The target record holds (n, n . q), so
+// e = n . x - n . q (NaN, hence invalid, where the record is).  Frames come
+// from the pair's full-resolution table in device memory (scalar loads) or,
+// with LDS_FRAMES, from a table of the level's rows in shared memory.  Each
+// wavefront leaves its sums in s_wave[wave] (kAccum values; [30] the valid
+// count) and its inlier / projection counts in s_wcnt[wave][1..2].  LEAN
+// instances (StepArgs::lean) leave out the receiver offset, the distance gate,
+// the debug dumps and the per-lane row-end test, and wrap columns with a mask
+// (the level width is a power of two).
+template <typename T, int WMODE, int CHUNK, bool LEAN, bool LDS_FRAMES>
+__device__ __forceinline__ void step_segments(const StepArgs &a, const MlpInfer &F, int pair, int seg_begin,
+                                              int seg_end, bool stats, const T (&pose)[12], const T *frames,
+                                              T (*s_wave)[kAccum], int (*s_wcnt)[4])
+{
+    const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + pair;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwave = blockDim.x >> 6;
+    const int l = a.level, s = 1 << l;
+    const T delta = (T)a.delta, inv_delta = (T)(1.0 / a.delta);
+    const T mc2 = !LEAN && a.max_corr > 0.0 ? (T)(a.max_corr * a.max_corr) : (T)-1;
+    const bool dbg = !LEAN && a.mode == kStepDebug;
+    const uint32_t lane4 = 4u * (uint32_t)lane, lane_col = (uint32_t)(lane << l) * (uint32_t)(2 * sizeof(T));
+    const LevelView<T> V = level_view(cload(&P->tab), l);
+    const LevelImage LI = {cload(&P->dstr[l]), V.Hl, V.Wl};
+    const T r00 = pose[0], r01 = pose[1], r10 = pose[4], r11 = pose[5], r20 = pose[8], r21 = pose[9];
+    const T t0 = pose[3], t1 = pose[7], t2 = pose[11];
+    const int Wl = V.Wl, Hl = V.Hl, spr = (Wl + kSegPx - 1) / kSegPx;
+    const uint32_t npx = (uint32_t)(Hl * Wl);
+    const rsrc_t srs = make_rsrc(cload(&P->src[l]), npx * 4u);
+    const rsrc_t drs = make_rsrc(cload(&P->dst4[l]), npx * (uint32_t)(4 * sizeof(T)));
+    const T r0 = LEAN ? (T)0 : V.r0;
+    const T h1x = r0 * r00, h1y = r0 * r10, h1z = r0 * r20;  // r0 R e_x
+    const T h2x = r0 * r01, h2y = r0 * r11, h2z = r0 * r21;  // r0 R e_y
+    T acc[kAccum];
+#pragma unroll
+    for (int k = 0; k < kAccum; ++k)
+        acc[k] = (T)0;
+    int c_valid = 0, c_in = 0, c_proj = 0;  // lane count, wave counts
+    for (int s0 = seg_begin + wave; s0 < seg_end; s0 += CHUNK * nwave) {
+        float rs[CHUNK];
+        T ca[CHUNK], sa[CHUNK];
+        int vs[CHUNK], us[CHUNK];
+        bool in[CHUNK];
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            const int seg = s0 + j * nwave;
+            const bool live = seg < seg_end;
+            const int v = live ? seg / spr : 0;
+            const int u0 = (seg - v * spr) * kSegPx, u = u0 + lane;
+            vs[j] = v;
+            us[j] = u;
+            if constexpr (LEAN) {
+                // whole segments: uniform base plus the lane's offset
+                in[j] = live;
+                const uint32_t sb = __builtin_amdgcn_readfirstlane(live ? 4u * (uint32_t)(v * Wl + u0) : kNoLoad);
+                const uint32_t cb = __builtin_amdgcn_readfirstlane(
+                    live ? (uint32_t)(s * u0) * (uint32_t)(2 * sizeof(T)) : kNoLoad);
+                rs[j] = bld1<float>(srs, sb + lane4);
+                bld2(V.col, cb + lane_col, ca[j], sa[j]);
+            } else {
+                in[j] = live && u < Wl;
+                rs[j] = bld1<float>(srs, in[j] ? 4u * (uint32_t)(v * Wl + u) : kNoLoad);
+                bld2(V.col, in[j] ? (uint32_t)(s * u) * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca[j], sa[j]);
+            }
+        }
+        bool proj[CHUNK];
+        int ul[CHUNK], vl[CHUNK];
+        T xx[CHUNK], xy[CHUNK], xz[CHUNK], xr[CHUNK];
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            V4<T> f0, f1, f2;
+            if constexpr (LDS_FRAMES) {
+                const T *fr = frames + vs[j] * kFrame;
+                f0 = {fr[0], fr[1], fr[2], fr[3]};
+                f1 = {fr[4], fr[5], fr[6], fr[7]};
+                f2 = {fr[8], fr[9], fr[10], fr[11]};
+            } else {
+                const T *fr = frames + (size_t)(s * vs[j]) * kFrame;
+                f0 = sld4(fr, 0);
+                f1 = sld4(fr, 1);
+                f2 = sld4(fr, 2);
+            }
+            const T r = (T)rs[j], c = ca[j], sn = sa[j], rc = r * c, rsn = r * sn;
+            xx[j] = fma(rc, f0.x, fma(rsn, f0.w, fma(r, f1.z, t0)));
+            xy[j] = fma(rc, f0.y, fma(rsn, f1.x, fma(r, f1.w, t1)));
+            xz[j] = fma(rc, f0.z, fma(rsn, f1.y, fma(r, f2.x, t2)));
+            if (!LEAN && r0 > (T)0) {
+                xx[j] += c * h1x + sn * h2x;
+                xy[j] += c * h1y + sn * h2y;
+                xz[j] += c * h1z + sn * h2z;
+            }
+            const bool okr = range_ok(rs[j]);
+            proj[j] = project<T, !LEAN, LEAN>(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]) & okr;
+        }
+        // the gather needs no mask: project() keeps (ul, vl) inside the
+        // level image for every lane, and a lane that did not project adds
+        // exact zeros below whatever record it reads (w = 0, e = 0, finite J)
+        V4<T> D[CHUNK];
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j)
+            D[j] = bld4<T>(drs, (__umul24((uint32_t)vl[j], (uint32_t)Wl) + (uint32_t)ul[j]) *
+                                    (uint32_t)(4 * sizeof(T)));
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            const T n0 = D[j].x, n1 = D[j].y, n2 = D[j].z;
+            const T ex = n0 * xx[j] + n1 * xy[j] + n2 * xz[j] - D[j].w;
+            bool valid = proj[j] && ex == ex;
+            if (mc2 >= (T)0) {
+                // Sec. 4.1 correspondence gate: |x - q| against the target point
+                const rsrc_t rrs = make_rsrc(LI.rng, npx * 4u);
+                const uint32_t pix = (uint32_t)(vl[j] * Wl + ul[j]);
+                const T rq = (T)bld1<float>(rrs, valid ? 4u * pix : kNoLoad);
+                const V4<T> rw = bld4<T>(V.row, (uint32_t)(s * vl[j]) * (uint32_t)(4 * sizeof(T)));
+                T cq, sq;
+                bld2(V.col, (uint32_t)(s * ul[j]) * (uint32_t)(2 * sizeof(T)), cq, sq);
+                const V3<T> d = ray_dir(rw, cq, sq);
+                const T dx = xx[j] - (rq * d.x + r0 * cq), dy = xy[j] - (rq * d.y + r0 * sq);
+                const T dz = xz[j] - rq * d.z;
+                valid = valid && dx * dx + dy * dy + dz * dz <= mc2;
+            }
+            const T e = valid ? ex : (T)0;
+            const T J0 = xy[j] * n2 - xz[j] * n1;
+            const T J1 = xz[j] * n0 - xx[j] * n2;
+            const T J2 = xx[j] * n1 - xy[j] * n0;
+            const T tq = e * inv_delta;
+            const T wh = d_rsqrt((T)1 + tq * tq);
+            T w = wh;
+            const int i = in[j] ? vs[j] * Wl + us[j] : -1;
+            if constexpr (WMODE == 1) {
+                if (a.mode != kStepFallback)
+                    w = learned_weight<T>(a, F, LI, valid, ul[j], vl[j], e, xr[j], n0, n1, n2,
+                                          dbg ? a.dbg_feat : nullptr, i);
+            }
+            w = valid ? w : (T)0;
+            c_valid += valid ? 1 : 0;
+            if (stats) {
+                acc[29] += valid ? e * e * wh * d_rcp(wh + (T)1) : (T)0;
+                c_proj += wave_count(proj[j]);
+                c_in += wave_count(valid && fabs(e) < delta);
+            }
+            // an invalid pixel has w = 0, e = 0 and finite J (n = 0 unless the
+            // distance gate rejected it), so it adds exact zeros
+            const T J[6] = {J0, J1, J2, n0, n1, n2};
+            T wJ[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                wJ[k] = w * J[k];
+            int k = 0;
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = r; c < 6; ++c)
+                    acc[k++] += wJ[r] * J[c];
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+                acc[21 + r] += wJ[r] * e;
+            acc[27] += w;
+            acc[28] += w * e * e;
+            if (dbg && i >= 0) {
+                if (a.dbg_u) a.dbg_u[i] = proj[j] ? ul[j] : -1;
+                if (a.dbg_v) a.dbg_v[i] = proj[j] ? vl[j] : -1;
+                if (a.dbg_mask) a.dbg_mask[i] = valid ? 1 : 0;
+                if (a.dbg_e) a.dbg_e[i] = (float)e;
+                if (a.dbg_w) a.dbg_w[i] = (float)w;
+                if (a.dbg_J)
+                    for (int q = 0; q < 6; ++q)
+                        a.dbg_J[6 * (size_t)i + q] = valid ? (float)J[q] : 0.f;
+                if (WMODE == 0 && a.dbg_feat)
+                    store_features<T>(a, LI, valid, ul[j], vl[j], e, xr[j], n0, n1, n2,
+                                      a.dbg_feat + 14 * (size_t)i);
+            }
+        }
+    }
+    acc[30] = (T)c_valid;  // exact: far below 2^24 per wavefront
+    const T tot = wave_sum32(acc, lane);
+    if (lane < 32)
+        s_wave[wave][bitrev5(lane)] = tot;
+    if (lane == 0) {
+        s_wcnt[wave][1] = c_in;
+        s_wcnt[wave][2] = c_proj;
     }
 }
+
+// One Gauss-Newton iteration at level l for every pair of the batch.  Each
+// workgroup walks its tiles; a tile is a run of tile_seg segments of one
+// pair's level-l image, and its sums go to one record (k_solve reduces them).
+// FINE tags the finest-level instance (same code) so that profiles report it
+// separately.
+template <typename T, int WMODE, bool FINE, int CHUNK, bool LEAN>
+__global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
+{
+    __shared__ T s_wave[4][kAccum];
+    __shared__ int s_wcnt[4][4];
+    T *psum = reinterpret_cast<T *>(a.psum);
+    const int tid = threadIdx.x, nwave = blockDim.x >> 6, l = a.level;
+    const bool dbg = !LEAN && a.mode == kStepDebug;
+    const PairDesc<T> *pairs = reinterpret_cast<const PairDesc<T> *>(a.pairs);
+    MlpInfer F;
+    if constexpr (WMODE == 1)
+        mlp_infer_load(a.mlp, F);
+    for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step) {
+        const int2 tl = cload(a.tiles + it.cur);
+        const int pair = tl.x;
+        if (!dbg) {
+            const int *fl = a.flags + (size_t)pair * kFlagStride;
+            if (cload(fl + l) & 1)
+                continue;
+            if (a.mode == kStepFallback && !(cload(fl + kMaxLevels) & 1))
+                continue;
+        }
+        const PairDesc<T> *P = pairs + pair;
+        const double *Tp = a.poses + 16 * (size_t)pair;
+        T pose[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            pose[k] = (T)cload(Tp + k);
+        const int Hl = cload(&P->H) >> l, spr = ((cload(&P->W) >> l) + kSegPx - 1) / kSegPx;
+        step_segments<T, WMODE, CHUNK, LEAN, false>(a, F, pair, tl.y, min(tl.y + a.tile_seg, Hl * spr),
+                                                    a.stats_pass != 0, pose, cload(&P->frames), s_wave, s_wcnt);
+        __syncthreads();
+        if (tid < kAccum) {
+            T sum = (T)0;
+            for (int w = 0; w < nwave; ++w)
+                sum += s_wave[w][tid];
+            psum[(size_t)it.cur * kAccum + tid] = sum;
+        } else if (tid == kAccum) {
+            int4 c = make_int4(0, 0, 0, 0);
+            for (int w = 0; w < nwave; ++w) {
+                c.x += (int)s_wave[w][30];
+                c.y += s_wcnt[w][1];
+                c.z += s_wcnt[w][2];
+            }
+            a.pcnt[it.cur] = c;
+        }
+        __syncthreads();
+    }
+}
+
+// All Gauss-Newton iterations of level l for one pair per workgroup (pairs
+// with no tiles at this level: small level images, pseudo-Huber weights, lean
+// conditions; the host decides per pair): the workgroup covers the
+// pair's whole level image each iteration, reduces its sums in FP64 (wave
+// order), solves, and keeps the pose and the level rows' frames in shared
+// memory, so that the level needs one launch instead of two per iteration.
+// At the end it writes the frames of all full-resolution rows for the pose
+// reached (the next level's input).
+template <typename T, int CHUNK>
+__global__ __launch_bounds__(kPairBlock) void k_icp_level(StepArgs a)
+{
+    __shared__ T s_wave[kPairBlock / 64][kAccum];
+    __shared__ int s_wcnt[kPairBlock / 64][4];
+    __shared__ T s_fr[kPairRows * kFrame];
+    __shared__ double s_tot[kAccum];
+    __shared__ long long s_cnt[4];
+    __shared__ double s_pose[12];
+    __shared__ int s_go;
+    const int pair = blockIdx.x, tid = threadIdx.x, nwave = blockDim.x >> 6, l = a.level;
+    int *fl = a.flags + (size_t)pair * kFlagStride;
+    const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + pair;
+    if (cload(&P->ntile[l]) != 0 || (cload(fl + l) & 1))
+        return;  // a tiled pair at this level, or the level stopped
+    const SensorTab<T> *tab = cload(&P->tab);
+    const T *rowt = cload(&tab->row);
+    const int Hl = cload(&P->H) >> l, spr = (cload(&P->W) >> l) / kSegPx;
+    if (tid < 12)
+        s_pose[tid] = a.poses[16 * (size_t)pair + tid];
+    __syncthreads();
+    MlpInfer F;
+    for (int it = 0; it < a.iters; ++it) {
+        double R[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            R[k] = s_pose[k];
+        for (int v = tid; v < Hl; v += blockDim.x)
+            frame_row(rowt + 4 * (size_t)(v << l), R, s_fr + v * kFrame);
+        T pose[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            pose[k] = (T)R[k];
+        __syncthreads();
+        const bool last = it == a.iters - 1;
+        step_segments<T, 0, CHUNK, true, true>(a, F, pair, 0, Hl * spr, last, pose, s_fr, s_wave, s_wcnt);
+        __syncthreads();
+        if (tid < kAccum) {
+            double t = 0.0;
+            for (int w = 0; w < nwave; ++w)
+                t += (double)s_wave[w][tid];
+            s_tot[tid] = t;
+        } else if (tid >= 64 && tid < 67) {
+            long long c = 0;
+            for (int w = 0; w < nwave; ++w)
+                c += tid == 64 ? (long long)s_wave[w][30] : (long long)s_wcnt[w][tid - 64];
+            s_cnt[tid - 64] = c;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            StepArgs b = a;
+            b.iter = it;
+            b.stats_pass = last ? 1 : 0;
+            double out[12];
+            const bool moved = solve_pair(b, pair, fl, s_tot, s_cnt, out);
+            if (moved)
+                for (int k = 0; k < 12; ++k)
+                    s_pose[k] = out[k];
+            s_go = moved ? 1 : 0;
+        }
+        __syncthreads();
+        if (!s_go)
+            break;
+    }
+    double R[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        R[k] = s_pose[k];
+    write_frames(P, R);
+}
+
+// ----------------------------------------------------------------------------- solve kernels
 
 // Frames for the current poses of all pairs (after the poses are set from
 // the host or by the centroid initialisation).  One workgroup per pair.
@@ -775,6 +894,8 @@ __global__ __launch_bounds__(256) void k_solve(StepArgs a)
     const PairDesc<T> &P = reinterpret_cast<const PairDesc<T> *>(a.pairs)[pair];
     const T *psum = reinterpret_cast<const T *>(a.psum);
     const int nt = P.ntile[l], t0 = P.tile0[l];
+    if (nt == 0)
+        return;  // the pair-resident kernel runs this pair's level
     // group g of 32 threads sums tiles g, g + 8, ... in that order (one
     // coalesced record per step), four records in flight at a time
     const int comp = lane & 31, grp = lane >> 5;
@@ -932,6 +1053,19 @@ static void launch_step_t(const StepArgs &a, int grid, int block, hipStream_t st
         launch_step_c<T, WMODE, 2>(a, grid, block, stream);
     else
         launch_step_c<T, WMODE, 1>(a, grid, block, stream);
+}
+
+hipError_t launch_level(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream)
+{
+    if (fp64)
+        return hipErrorInvalidValue;  // FP32 per-pixel arithmetic only
+    if (a.chunk >= 4)
+        hipLaunchKernelGGL((k_icp_level<float, 4>), dim3(n_pairs), dim3(kPairBlock), 0, stream, a);
+    else if (a.chunk == 2)
+        hipLaunchKernelGGL((k_icp_level<float, 2>), dim3(n_pairs), dim3(kPairBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_icp_level<float, 1>), dim3(n_pairs), dim3(kPairBlock), 0, stream, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_step(bool fp64, int weight_mode, const StepArgs &a, int grid, int block, hipStream_t stream)

@@ -38,6 +38,11 @@ struct PairDesc {
 
 constexpr int kSegPx = 64;  // pixels per segment
 constexpr int kFrame = 12;  // T per frame row
+// Pair-resident level kernel (k_icp_level): workgroup size, and the largest
+// level image (rows, pixels) it takes.
+constexpr int kPairBlock = 1024;
+constexpr int kPairRows = 64;
+constexpr int kPairMaxPx = 8192;
 
 // A level's target range image (learned-weight features).
 struct LevelImage {
@@ -66,6 +71,7 @@ struct StepArgs {
     const int2 *tiles;   // (pair, first segment) of every tile of this level
     int n_tiles;
     int level, iter, levels;
+    int iters;           // iterations scheduled at this level
     int tile_seg;        // segments per tile at this level
     int chunk;           // pixels each thread keeps in flight (1, 2 or 4)
     int xcd_remap;
@@ -118,6 +124,9 @@ hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, int
 hipError_t launch_solve(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream);
 hipError_t launch_frames(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream);
 hipError_t launch_step(bool fp64, int weight_mode, const StepArgs &a, int grid, int block, hipStream_t stream);
+// All iterations of one level, one workgroup per pair (StepArgs::iters); FP32
+// only (hipErrorInvalidValue for fp64).
+hipError_t launch_level(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream);
 
 // Learned-weight network (mlp.hip).
 hipError_t launch_mlp_forward(const MlpDev &m, const float *feats, int64_t B, float *w_out, hipStream_t stream);

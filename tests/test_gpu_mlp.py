@@ -207,5 +207,7 @@ def test_rejecting_network_falls_back_to_pseudo_huber(rir):
     prm_h = rir.make_params(levels=3, iters=[3, 3, 3])
     Tl, sl = rir.icp_batch(ctx, prm_l, [(sen, src, dst)])
     Th, sh = rir.icp_batch(ctx, prm_h, [(sen, src, dst)])
-    np.testing.assert_array_equal(Tl.cpu().numpy(), Th.cpu().numpy())
+    # the plain run takes the pair-resident kernel on the small coarse levels
+    # (another summation order), so the poses agree to FP32 rounding
+    np.testing.assert_allclose(Tl.cpu().numpy(), Th.cpu().numpy(), rtol=0, atol=1e-7)
     assert np.all(rir.stats_to_numpy(sl, 1, 3)["status"] == rir.LEVEL_FALLBACK_HUBER)
