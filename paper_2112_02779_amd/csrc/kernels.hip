@@ -168,10 +168,10 @@ __global__ void k_clear(int *flags, int n_flags, rir_level_stats *stats, int n_s
 // invalid) at level 0 and, for rows and columns on the grid of level l, the
 // strided copies of the record, the target range and the source range.  With
 // init_centroid each tile also records the sums of its valid source and
-// target points (reduced per pair by k_centroid).
-constexpr int kPrepSeg = 2;
+// target points (reduced per pair by k_centroid); CENTROID instances only.
+constexpr int kPrepSeg = 4;
 
-template <typename T>
+template <typename T, bool CENTROID>
 __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
 {
     __shared__ T s_red[4][kAccum];
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
                 }
                 if (in[j]) {
                     gst4(d40 + 4 * (size_t)(v * W + u), rec);
-                    if (a.init_centroid) {
+                    if constexpr (CENTROID) {
                         const V3<T> d = ray_dir(rw, ca[j], sa[j]);
                         if (range_ok(rs[j])) {
                             acc[0] += (T)rs[j] * d.x + r0 * ca[j];
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
                 }
             }
         }
-        if (!a.init_centroid)
+        if constexpr (!CENTROID)
             continue;
         const T tot = wave_sum32(acc, lane);
         if (lane < 32)
@@ -995,10 +995,17 @@ hipError_t launch_clear(int *flags, int n_flags, rir_level_stats *stats, int n_s
 
 hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, int n_pairs, hipStream_t stream)
 {
-    if (fp64)
-        hipLaunchKernelGGL(k_prepass<double>, dim3(grid), dim3(block), 0, stream, a);
-    else
-        hipLaunchKernelGGL(k_prepass<float>, dim3(grid), dim3(block), 0, stream, a);
+    if (fp64) {
+        if (a.init_centroid)
+            hipLaunchKernelGGL((k_prepass<double, true>), dim3(grid), dim3(block), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_prepass<double, false>), dim3(grid), dim3(block), 0, stream, a);
+    } else {
+        if (a.init_centroid)
+            hipLaunchKernelGGL((k_prepass<float, true>), dim3(grid), dim3(block), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_prepass<float, false>), dim3(grid), dim3(block), 0, stream, a);
+    }
     if (a.init_centroid) {
         if (fp64)
             hipLaunchKernelGGL(k_centroid<double>, dim3(n_pairs), dim3(64), 0, stream, a);
