@@ -86,9 +86,12 @@ def cpu_baseline(pairs, sensor, levels, iters, delta, r_max, sample_every, threa
 
 
 # Learned vs plain pseudo-Huber on held-out dynamic pairs: (name, iterations
-# per level (finest first), learned weights at the finest level?).
+# per level (finest first), learned weights at the finest level?).  Every
+# schedule runs in both modes.
 LEARNED_MODES = (("plain", (10, 10, 10), False), ("learned", (10, 10, 10), True),
-                 ("plain_3", (3, 10, 10), False), ("learned_3", (3, 10, 10), True))
+                 ("plain_3", (3, 10, 10), False), ("learned_3", (3, 10, 10), True),
+                 ("plain_1", (1, 10, 10), False), ("learned_1", (1, 10, 10), True),
+                 ("plain_1_5", (1, 5, 5), False), ("learned_1_5", (1, 5, 5), True))
 
 
 def learned_vs_plain(rir, ctx, n_pairs=256, repeats=5):
@@ -126,9 +129,17 @@ def learned_vs_plain(rir, ctx, n_pairs=256, repeats=5):
                      "median_err_vs_gt_rad_m": [float(np.median(e[:, 0])), float(np.median(e[:, 1]))],
                      "p90_err_vs_gt_rad_m": [float(np.percentile(e[:, 0], 90)), float(np.percentile(e[:, 1], 90))]}
         log(f"learned-vs-plain {name}: {res[name]['pairs_per_s']:.0f} pairs/s, success {ok:.3f}")
+    best = {}
+    for kind in ("plain", "learned"):
+        name = max((k for k in res if k.split("_")[0] == kind), key=lambda k: res[k]["goodput_pairs_per_s"])
+        best[kind] = {"mode": name, "goodput_pairs_per_s": res[name]["goodput_pairs_per_s"]}
+    log(f"learned-vs-plain best goodput: plain {best['plain']}, learned {best['learned']}")
     return {"workload": f"{n_pairs} held-out dynamic 64x1024 pairs (seeds 13000..{13000 + n_pairs - 1}), 3 levels, "
-                        "learned weights at the finest level, success = within 0.25 deg and 5 cm of the ground truth",
-            "modes": res}
+                        "learned weights at the finest level, success = within 0.25 deg and 5 cm of the ground truth, "
+                        "goodput = pairs/s x success; the same schedules run in both modes",
+            "modes": res, "best_goodput": best,
+            "learned_over_plain_best_goodput": round(best["learned"]["goodput_pairs_per_s"] /
+                                                     best["plain"]["goodput_pairs_per_s"], 3)}
 
 
 def _level_sizes(H, W, levels):
