@@ -105,7 +105,12 @@ typedef struct {
  *  mlp           learned-weight network (weight_mode LEARNED), else NULL.
  *  r_max         range scale of the first learned feature (metres).
  *  learned_levels with weight_mode LEARNED: bit l set = learned weights at
- *                level l, pseudo-Huber at the others; 0 = every level. */
+ *                level l, pseudo-Huber at the others; 0 = every level.
+ *  stop_eps      > 0: a level ends after the first applied step whose twist
+ *                has |xi| = sqrt(|omega|^2 + |tau|^2) <= stop_eps (rad and
+ *                metres mixed; the remaining iterations of that level are
+ *                skipped, iters_run tells how many ran); 0: fixed iteration
+ *                counts. */
 typedef struct {
     int32_t levels;
     int32_t iters[RIR_MAX_LEVELS];
@@ -119,6 +124,7 @@ typedef struct {
     const rir_mlp *mlp;
     double r_max;
     int32_t learned_levels;
+    double stop_eps;
 } rir_icp_params;
 
 /* Statistics of one pyramid level of one pair: those of the level's last

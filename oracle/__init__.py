@@ -42,7 +42,7 @@ class OrcParams(ctypes.Structure):
                 ("edge_rel", ctypes.c_double), ("max_corr_dist", ctypes.c_double),
                 ("init_mode", ctypes.c_int), ("weight_mode", ctypes.c_int),
                 ("mlp", ctypes.POINTER(ctypes.c_double)), ("r_max", ctypes.c_double),
-                ("learned_levels", ctypes.c_int)]
+                ("learned_levels", ctypes.c_int), ("stop_eps", ctypes.c_double)]
 
 
 class OrcLevelStats(ctypes.Structure):
@@ -119,7 +119,7 @@ class _SensorHolder:
 
 
 def make_params(levels=3, iters=(10, 10, 10), delta=0.5, edge_rel=0.1, max_corr_dist=0.0, init_mode=0,
-                weight_mode=0, mlp=None, r_max=80.0, learned_levels=0):
+                weight_mode=0, mlp=None, r_max=80.0, learned_levels=0, stop_eps=0.0):
     prm = OrcParams()
     prm.levels = levels
     for i in range(8):
@@ -127,6 +127,7 @@ def make_params(levels=3, iters=(10, 10, 10), delta=0.5, edge_rel=0.1, max_corr_
     prm.delta, prm.edge_rel, prm.max_corr_dist = delta, edge_rel, max_corr_dist
     prm.init_mode, prm.weight_mode, prm.r_max = init_mode, weight_mode, r_max
     prm.learned_levels = int(learned_levels)
+    prm.stop_eps = float(stop_eps)
     holder = None
     if mlp is not None:
         holder = np.ascontiguousarray(mlp, dtype=np.float64)

@@ -54,6 +54,7 @@ typedef struct {
     const double *mlp;     /* learned-weight parameters (see orc_mlp_*) */
     double r_max;          /* range scale of the first learned feature */
     int learned_levels;    /* weight_mode 1: bit l = learned at level l, 0 = all levels */
+    double stop_eps;       /* > 0: a level ends after a step with |xi| <= stop_eps */
 } orc_params;
 
 typedef struct {
@@ -855,6 +856,10 @@ int orc_icp(const orc_sensor *s, const float *src, const float *dst, const orc_p
             mat4_mul(D, T, T);
             ls->step_rot = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
             ls->step_trans = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+            /* optional small-step stop (a fixed iteration count when 0) */
+            if (prm->stop_eps > 0.0 &&
+                ls->step_rot * ls->step_rot + ls->step_trans * ls->step_trans <= prm->stop_eps * prm->stop_eps)
+                break;
         }
     }
     memcpy(T_out, T, sizeof(T));

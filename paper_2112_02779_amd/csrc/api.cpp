@@ -361,7 +361,7 @@ namespace {
 
 struct KeyPod {
     int levels, iters[kMaxLevels], init_mode, weight_mode, learned_levels, precision, use_graph, debug;
-    double delta, edge_rel, max_corr, r_max;
+    double delta, edge_rel, max_corr, r_max, stop_eps;
     uint64_t mlp;
     rir_tuning tune;
 };
@@ -604,6 +604,8 @@ rir_status check_params(const rir_icp_params *p)
         return fail(RIR_E_INVALID, "rir_icp_params.learned_levels must be a bit set over levels 0..7");
     if (p->precision != RIR_PREC_FP32 && p->precision != RIR_PREC_FP64)
         return fail(RIR_E_INVALID, "rir_icp_params.precision must be FP32 or FP64");
+    if (!(p->stop_eps >= 0.0) || !std::isfinite(p->stop_eps))
+        return fail(RIR_E_INVALID, "rir_icp_params.stop_eps must be finite and >= 0");
     return RIR_OK;
 }
 
@@ -803,6 +805,7 @@ rir_status get_plan(rir_ctx *ctx, const rir_icp_params *p, const rir_pair *pairs
     k.delta = p->delta;
     k.edge_rel = p->edge_rel;
     k.max_corr = p->max_corr_dist;
+    k.stop_eps = p->stop_eps;
     k.r_max = p->weight_mode == RIR_WEIGHT_LEARNED ? p->r_max : 0.0;
     k.mlp = p->weight_mode == RIR_WEIGHT_LEARNED ? p->mlp->uid : 0;
     k.tune = ctx->tune;
@@ -898,6 +901,7 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
     a.flags = P->d_flags;
     a.delta = p->delta;
     a.max_corr = p->max_corr_dist;
+    a.stop_eps = p->stop_eps;
     a.r_max = (float)p->r_max;
     if (p->weight_mode == RIR_WEIGHT_LEARNED)
         a.mlp = p->mlp->dev();

@@ -474,6 +474,9 @@ __device__ __forceinline__ bool solve_pair(const StepArgs &a, int pair, int *fl,
             for (int k = 0; k < 12; ++k)
                 pose_out[k] = Tp[k];
             moved = true;
+            // small-step stop: the level's remaining iterations are skipped
+            if (a.stop_eps > 0.0 && srot * srot + stra * stra <= a.stop_eps * a.stop_eps)
+                fl[l] = 1;
         }
     }
     out->status = status;
@@ -841,7 +844,7 @@ __global__ __launch_bounds__(kPairBlock) void k_icp_level(StepArgs a)
             if (moved)
                 for (int k = 0; k < 12; ++k)
                     s_pose[k] = out[k];
-            s_go = moved ? 1 : 0;
+            s_go = moved && !(fl[l] & 1) ? 1 : 0;  // stopped by a small step
         }
         __syncthreads();
         if (!s_go)

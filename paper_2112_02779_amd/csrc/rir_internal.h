@@ -90,6 +90,7 @@ struct StepArgs {
     rir_level_stats *stats;  // [n_pairs][levels] (debug: [1])
     int *flags;          // [n_pairs][kFlagStride]
     double delta, max_corr;
+    double stop_eps;     // > 0: a level stops after a step with |xi| <= stop_eps
     float r_max;
     MlpDev mlp;
     // per-pixel dumps (debug mode; each may be null)

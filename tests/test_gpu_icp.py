@@ -122,6 +122,24 @@ def test_multiscale_pose_matches_oracle_pair64(rir, ctx, seed):
         assert abs(st[0, l]["n_valid"] - so[l]["n_valid"]) <= 0.002 * so[l]["n_valid"] + 5
 
 
+def test_small_step_stop_matches_oracle(rir, ctx):
+    """stop_eps ends a level after a small step, on the tiled and the
+    pair-resident paths alike: the same iteration counts as the oracle
+    (unless a step lies within 5% of the threshold) and the oracle's pose."""
+    eps = 2e-4
+    for seed in (3, 4):
+        pair = _pair("pair64", seed)
+        Tg, st = _run_gpu(rir, ctx, pair.sensor, [pair], [10, 10, 10], 3, stop_eps=eps)
+        To, so = oracle.icp(pair.sensor, pair.src, pair.dst,
+                            oracle.make_params(levels=3, iters=[10, 10, 10], stop_eps=eps))
+        er, et = rot_trans_error(Tg[0], To)
+        assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (seed, er, et)
+        assert any(so[l]["iters_run"] < 10 for l in range(3))
+        for l in range(3):
+            near = abs(np.hypot(so[l]["step_rot"], so[l]["step_trans"]) - eps) < 0.05 * eps
+            assert near or st[0, l]["iters_run"] == so[l]["iters_run"], (seed, l)
+
+
 def test_multiscale_pose_matches_oracle_general_sensor(rir, ctx):
     """Non-uniform elevation table, staggered azimuth offsets and r0 > 0."""
     sm = synth.staggered_sensor(64, 1024, r0=0.015)

@@ -454,6 +454,36 @@ def test_converges_to_ground_truth_on_planar_scene(orc, kind):
         assert er < 4e-4 and et < 2e-3, (er, et)
 
 
+def test_small_step_stop(orc):
+    """stop_eps: a level ends right after the first applied step with
+    |xi| <= stop_eps; earlier steps of that level are larger, and the pose
+    equals that of a run with exactly those iteration counts."""
+    p = _pair(3)
+    eps = 2e-4
+    full = orc.make_params(levels=3, iters=[10, 10, 10])
+    stop = orc.make_params(levels=3, iters=[10, 10, 10], stop_eps=eps)
+    Ts, ss = orc.icp(p.sensor, p.src, p.dst, stop)
+    runs = [int(s["iters_run"]) for s in ss]
+    assert min(runs) < 10
+    for l, s in enumerate(ss):
+        step = np.hypot(s["step_rot"], s["step_trans"])
+        if runs[l] < 10:
+            assert step <= eps
+        # the same schedule, cut by hand, one iteration short: its last step is above eps
+        if runs[l] > 1:
+            it = list(runs)
+            it[l] = runs[l] - 1
+            for k in range(l):  # finer levels do not run before level l ends
+                it[k] = 0
+            _, sc = orc.icp(p.sensor, p.src, p.dst, orc.make_params(levels=3, iters=it))
+            assert np.hypot(sc[l]["step_rot"], sc[l]["step_trans"]) > eps
+    Tc, _ = orc.icp(p.sensor, p.src, p.dst, orc.make_params(levels=3, iters=runs))
+    assert np.array_equal(Ts, Tc)
+    Tf, _ = orc.icp(p.sensor, p.src, p.dst, full)
+    er, et = orc.pose_error(Ts, Tf)
+    assert er < 1e-3 and et < 1e-2
+
+
 def test_degenerate_inputs(orc):
     """Failure handling: an empty source and a ground-only scene (rank-deficient
     normal equations) give status DEGENERATE and leave the pose unchanged."""
