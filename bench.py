@@ -300,6 +300,40 @@ def combined_modes(rir, ctx, oracle_sample, threads, repeats=5):
             "modes": res}
 
 
+def paper_context(rir, ctx, oracle_runs=True, repeats=20):
+    """The shape of the paper's timing (one 128x1024 pair, 3 levels, 20/20/10
+    Gauss-Newton iterations coarse to fine; 10.69-10.90 ms per pair on an RTX
+    3060, normals estimated beforehand): latency of one pair alone, the
+    throughput of 100 such pairs batched, and the FP64 oracle's
+    single-threaded time per pair (median of 5 after one warm-up)."""
+    import torch
+    import synth
+    cfg = synth.CONFIGS["pair64"]
+    iters = [10, 20, 20]
+    pairs = [synth.gen_pair(cfg, 5000 + i, shape=(128, 1024)) for i in range(100)]
+    sen = rir.Sensor.from_model(pairs[0].sensor)
+    dev = torch.device("cuda:0")
+    batch = [(sen, torch.from_numpy(p.src).to(dev), torch.from_numpy(p.dst).to(dev)) for p in pairs]
+    prm = rir.make_params(levels=3, iters=iters, delta=cfg["delta"])
+    dt1, _, _ = _time_batch(rir, ctx, prm, batch[:1], repeats)
+    dtb, T, _ = _time_batch(rir, ctx, prm, batch, 5)
+    res = {"workload": "128x1024 room-scene pairs (seeds 5000..5099), 3 levels, 20/20/10 iterations coarse to fine",
+           "paper_ms_per_pair_rtx3060": [10.69, 10.90],
+           "one_pair_ms": round(dt1 * 1e3, 4), "batched_100_ms": round(dtb * 1e3, 3),
+           "batched_ms_per_pair": round(dtb * 1e3 / len(pairs), 5)}
+    if oracle_runs:
+        import oracle
+        oprm = oracle.make_params(levels=3, iters=iters, delta=cfg["delta"], r_max=cfg["noise"].rmax)
+        ts = []
+        for k in range(6):
+            t0 = time.perf_counter()
+            oracle.icp(pairs[0].sensor, pairs[0].src, pairs[0].dst, oprm)
+            ts.append(time.perf_counter() - t0)
+        res["oracle_single_thread_ms_per_pair"] = round(float(np.median(ts[1:])) * 1e3, 1)
+    log(f"paper context: one pair {res['one_pair_ms']:.3f} ms, batched {res['batched_ms_per_pair']:.4f} ms/pair")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -431,6 +465,7 @@ def main():
     threads = max(1, min(16, os.cpu_count() or 1))
     mixed = None if args.no_mixed else mixed_batch(rir, ctx, 0 if args.no_cpu else args.mixed_oracle, threads)
     comb = None if args.no_mixed else combined_modes(rir, ctx, 0 if args.no_cpu else args.mixed_oracle, threads)
+    context = None if args.no_mixed else paper_context(rir, ctx, oracle_runs=not args.no_cpu)
     pairs_per_s = n / (ms_per_step * 1e-3)
     gt_err = [rot_trans_error(T_gpu[i], p.gt) for i, p in enumerate(pairs)]
     out = {
@@ -461,6 +496,7 @@ def main():
         "learned_vs_plain": lvp,
         "mixed_batch": mixed,
         "combined_modes": comb,
+        "paper_context": context,
     }
     print(json.dumps(out), flush=True)
 
