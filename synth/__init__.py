@@ -346,14 +346,15 @@ def gen_batch(cfg: dict, seed0: int, n_pairs: int | None = None) -> list:
     return [gen_pair(cfg, seed0 + i) for i in range(n)]
 
 
-def gen_sequence(cfg: dict, seed: int, n_scans: int | None = None) -> dict:
+def gen_sequence(cfg: dict, seed: int, n_scans: int | None = None, sensor: Sensor | None = None) -> dict:
     """An odometry sequence: the sensor moves forward U(step_min, step_max) and
     turns by a yaw of U(0, yaw_max) per frame through an outdoor scene.
     Returns the scans and the pairs (k+1 -> k) with their ground truth."""
     rng = np.random.default_rng(seed)
     n = cfg["n_scans"] if n_scans is None else n_scans
     H, W = cfg["shapes"][0]
-    sensor = uniform_sensor(H, W)
+    if sensor is None:
+        sensor = uniform_sensor(H, W)
     poses = []
     T = make_pose(np.eye(3), [0.0, 0.0, cfg["sensor_height"]])
     for k in range(n):
