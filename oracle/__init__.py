@@ -100,6 +100,9 @@ def lib():
         L.orc_system.restype = ctypes.c_int
         L.orc_associate_with_normals.argtypes = [S, ctypes.c_int, _F, _F, _D, _U8, _D, P, _I32, _I32, _U8,
                                                  _U8, _D, _D, _D, _D, _D]
+        L.orc_sdf_points.argtypes = [S, _F, _D, _D, ctypes.c_int64, _D, _D, _U8, _I32, _I32, _D, _D]
+        L.orc_sdf_fuse.argtypes = [S, ctypes.c_int, _F, _D, ctypes.c_int64, _D, ctypes.c_double,
+                                   ctypes.c_double, _D, _D]
         _lib = L
     return _lib
 
@@ -175,6 +178,44 @@ def normals(sensor, rng_img: np.ndarray, edge_rel: float = 0.1):
     valid = np.zeros((h.H, h.W), np.uint8)
     lib().orc_normals(ctypes.byref(h.s), _p(r, _F), float(edge_rel), _p(n, _D), _p(valid, _U8))
     return n, valid.astype(bool)
+
+
+def sdf_points(sensor, rng_img: np.ndarray, pose: np.ndarray, pts: np.ndarray) -> dict:
+    """Eq. (8)-(9) for world points pts [n, 3] against one range image taken at
+    pose (4x4, world -> sensor): d = Omega(u, v) - r where valid."""
+    h = _SensorHolder(sensor)
+    r = np.ascontiguousarray(rng_img, dtype=np.float32)
+    T = np.ascontiguousarray(pose, dtype=np.float64)
+    p = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    n = p.shape[0]
+    out = {k: np.zeros(n) for k in ("d", "omega", "uhat", "phi")}
+    u = np.zeros(n, np.int32)
+    v = np.zeros(n, np.int32)
+    valid = np.zeros(n, np.uint8)
+    lib().orc_sdf_points(ctypes.byref(h.s), _p(r, _F), _p(T, _D), _p(p, _D), n, _p(out["d"], _D),
+                         _p(out["omega"], _D), _p(valid, _U8), _p(u, _I32), _p(v, _I32),
+                         _p(out["uhat"], _D), _p(out["phi"], _D))
+    out.update(u=u, v=v, valid=valid.astype(bool))
+    return out
+
+
+def sdf_fuse(sensor, ranges: np.ndarray, poses: np.ndarray, pts: np.ndarray, trunc: float, r_clip: float,
+             sdf: np.ndarray | None = None, weight: np.ndarray | None = None):
+    """Eq. (10): running mean of the truncated projective SDF of points pts
+    [n, 3] over the scans ranges [F, H, W] with poses [F, 4, 4] (world ->
+    sensor), in order, starting from (sdf, weight) (zeros if None).  Returns
+    new (sdf, weight) arrays."""
+    h = _SensorHolder(sensor)
+    r = np.ascontiguousarray(ranges, dtype=np.float32).reshape(-1, h.H, h.W)
+    T = np.ascontiguousarray(poses, dtype=np.float64).reshape(-1, 4, 4)
+    assert T.shape[0] == r.shape[0]
+    p = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    n = p.shape[0]
+    s = np.zeros(n) if sdf is None else np.array(sdf, dtype=np.float64).reshape(n)
+    w = np.zeros(n) if weight is None else np.array(weight, dtype=np.float64).reshape(n)
+    lib().orc_sdf_fuse(ctypes.byref(h.s), int(r.shape[0]), _p(r, _F), _p(T, _D), n, _p(p, _D),
+                       float(trunc), float(r_clip), _p(s, _D), _p(w, _D))
+    return s, w
 
 
 def bf16(x: float) -> float:

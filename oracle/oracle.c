@@ -1,7 +1,8 @@
 /*
- * FP64 CPU oracle for multi-scale projective point-to-plane ICP on cylindrical
- * range images (Dong, Ryu, Kaess, Park: "Revisiting LiDAR Registration and
- * Reconstruction: A Range Image Perspective", Sec. 3 and Sec. 4.1).
+ * FP64 CPU oracle for multi-scale projective point-to-plane ICP and projective
+ * SDF fusion on cylindrical range images (Dong, Ryu, Kaess, Park: "Revisiting
+ * LiDAR Registration and Reconstruction: A Range Image Perspective", Sec. 3,
+ * Sec. 4.1 and Sec. 4.2).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, single-threaded
  * reference that the GPU library is checked against.  It shares no code,
@@ -16,7 +17,9 @@
  *   Eq. (5)-(6)  projective data association,
  *   Eq. (7)      robust point-to-plane objective solved by Gauss-Newton,
  *   Sec. 4.1     multi-scale registration on strided images with the
- *                original intrinsics.
+ *                original intrinsics,
+ *   Eq. (8)-(10) projective signed distances and their running mean at
+ *                query points (Sec. 4.2).
  * Readings of silent or ambiguous passages are listed next to the code that
  * takes them.  The learned per-pixel weight (a small MLP) is not part of the
  * paper; its forward and backward passes are written out here with the same
@@ -905,4 +908,98 @@ void orc_associate_with_normals(const orc_sensor *s, int level, const float *src
 {
     orc_assoc_out a = {u, v, mask, proj_valid, e, w, J, uhat, phi, NULL};
     orc_associate(s, level, src, dst, nrm, nvalid, T, prm, 0, &a);
+}
+
+/* ------------------------------------------------------------------ Sec. 4.2, Eq. (8)-(10) */
+
+/*
+ * Projective signed distance of a world point x against one range image
+ * (Sec. 4.2).  T is the scan's pose as a row-major 4x4 matrix mapping world
+ * points into its sensor frame (the R_j, t_j of Eq. (8)).
+ *   Eq. (8): [u v r] = Pi(R x + t), at the finest level;
+ *   Eq. (9): d = Omega(u, v) - r, the signed distance along the projection ray
+ *            (positive in front of the observed surface).
+ * Returns 1 with *d and *omega set when the projection lies in the image and
+ * Omega(u, v) is a return (finite and > 0), else 0.  p (nullable) receives
+ * the projection of R x + t.
+ */
+int orc_sdf_point(const orc_sensor *s, const float *range, const double T[16], const double x[3], double *d,
+                  double *omega, orc_proj *p)
+{
+    double xs[3];
+    for (int i = 0; i < 3; ++i)
+        xs[i] = T[4 * i] * x[0] + T[4 * i + 1] * x[1] + T[4 * i + 2] * x[2] + T[4 * i + 3];
+    orc_proj q;
+    orc_project(s, 0, xs, &q);
+    if (p)
+        *p = q;
+    if (!q.valid)
+        return 0;
+    double om = range[(size_t)q.v * s->W + q.u];
+    if (!range_ok(om))
+        return 0;
+    *d = om - q.r;
+    *omega = om;
+    return 1;
+}
+
+/* orc_sdf_point over n points (for the tests): d, Omega, validity and the
+ * continuous projection coordinates (column u_hat, elevation phi). */
+void orc_sdf_points(const orc_sensor *s, const float *range, const double T[16], const double *pts, int64_t n,
+                    double *d, double *omega, uint8_t *valid, int32_t *u, int32_t *v, double *uhat, double *phi)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        orc_proj q;
+        double di = 0.0, oi = 0.0;
+        valid[i] = (uint8_t)orc_sdf_point(s, range, T, pts + 3 * i, &di, &oi, &q);
+        d[i] = di;
+        omega[i] = oi;
+        u[i] = q.u;
+        v[i] = q.v;
+        uhat[i] = q.uhat;
+        phi[i] = q.phi;
+    }
+}
+
+/*
+ * Eq. (10): the SDF at each query point is the mean of its per-scan signed
+ * distances, the least-squares estimate over the scans, kept incrementally
+ * as a running mean (sdf, weight = number of observations) and updated scan
+ * by scan in the given order: sdf <- (sdf * weight + d) / (weight + 1).
+ *
+ * Readings (the section states the untruncated mean and cites classical
+ * volumetric fusion, which truncates):
+ *  - trunc > 0: an observation with d < -trunc is skipped (the point lies
+ *    deeper behind the observed surface than the truncation band) and d is
+ *    limited to at most trunc; trunc <= 0 keeps every observation (plain
+ *    Eq. (10)).
+ *  - r_clip > 0: observations whose range Omega(u, v) exceeds r_clip are
+ *    skipped (far returns are clipped, Sec. 6); r_clip <= 0 keeps them.
+ *  - Scans are those of ranges[f * H * W ...], poses[16 f ...], f = 0..F-1.
+ * sdf and weight (n values each) hold the prior state and are updated in
+ * place.
+ */
+void orc_sdf_fuse(const orc_sensor *s, int n_frames, const float *ranges, const double *poses, int64_t n,
+                  const double *pts, double trunc, double r_clip, double *sdf, double *weight)
+{
+    size_t hw = (size_t)s->H * s->W;
+    for (int f = 0; f < n_frames; ++f) {
+        const float *img = ranges + (size_t)f * hw;
+        const double *T = poses + 16 * (size_t)f;
+        for (int64_t i = 0; i < n; ++i) {
+            double d, om;
+            if (!orc_sdf_point(s, img, T, pts + 3 * i, &d, &om, NULL))
+                continue;
+            if (r_clip > 0.0 && om > r_clip)
+                continue;
+            if (trunc > 0.0) {
+                if (d < -trunc)
+                    continue;
+                if (d > trunc)
+                    d = trunc;
+            }
+            sdf[i] = (sdf[i] * weight[i] + d) / (weight[i] + 1.0);
+            weight[i] += 1.0;
+        }
+    }
 }

@@ -1,0 +1,184 @@
+"""Pins of the oracle's projective SDF (Sec. 4.2, Eq. (8)-(10)) against facts
+other than itself (CPU only): closed forms for a sensor inside a sphere and
+above a ground plane (the synthetic-intrinsics case of Sec. 3.2, where the
+projection is the textbook spherical one), exact distances along pixel rays
+with a receiver offset, and the least-squares (mean) form of Eq. (10).
+"""
+import numpy as np
+
+import synth
+
+
+def _world_to_sensor(R, c):
+    """Pose mapping world points into the frame of a sensor at c with
+    orientation R (sensor axes in world coordinates): x_s = R^T (x - c)."""
+    T = np.eye(4)
+    T[:3, :3] = R.T
+    T[:3, 3] = -R.T @ c
+    return T
+
+
+def _fov_edges(sm):
+    p = sm.phi
+    return p[0] + 0.5 * (p[0] - p[1]), p[-1] - 0.5 * (p[-2] - p[-1])
+
+
+def _sphere_case(sm, seed, trunc, r_clip):
+    """Frames see a constant range image (a sphere of radius rad_f centred on
+    the sensor): d_f(x) = rad_f - |x_s| exactly whenever x_s projects inside the
+    vertical field of view, independent of the pixel it lands on (r0 = 0)."""
+    rng = np.random.default_rng(seed)
+    F = 5
+    rads = np.array([4.0, 6.0, 3.5, 7.5, 5.0])
+    centres = rng.uniform(-0.5, 0.5, size=(F, 3))
+    rots = [synth.rot_axis_angle(synth.unit_vector(rng), rng.uniform(0.0, 0.6)) for _ in range(F)]
+    poses = np.stack([_world_to_sensor(R, c) for R, c in zip(rots, centres)])
+    ranges = np.stack([np.full((sm.H, sm.W), r, np.float32) for r in rads])
+    pts = rng.uniform(-8.0, 8.0, size=(4000, 3))
+    hi, lo = _fov_edges(sm)
+    exp_s, exp_w = np.zeros(len(pts)), np.zeros(len(pts))
+    sums = np.zeros(len(pts))
+    near = np.zeros(len(pts), bool)
+    for f in range(F):
+        xs = pts @ rots[f] - centres[f] @ rots[f]            # R^T (x - c) row-wise
+        rr = np.linalg.norm(xs, axis=1)
+        el = np.arcsin(xs[:, 2] / rr)
+        inside = (el <= hi) & (el >= lo)
+        near |= (np.abs(el - hi) < 1e-9) | (np.abs(el - lo) < 1e-9)
+        d = rads[f] - rr
+        keep = inside
+        if r_clip > 0:
+            keep &= rads[f] <= r_clip
+        if trunc > 0:
+            near |= np.abs(d + trunc) < 1e-9
+            keep &= d >= -trunc
+            d = np.minimum(d, trunc)
+        sums += np.where(keep, d, 0.0)
+        exp_w += keep
+    exp_s = np.where(exp_w > 0, sums / np.maximum(exp_w, 1), 0.0)
+    return ranges, poses, pts, exp_s, exp_w, near
+
+
+def test_sphere_closed_form_untruncated(orc):
+    """Plain Eq. (10): the mean of rad_f - |x_s| over the frames that see x;
+    pins the pose convention (R and t of Eq. (8), via the tilted field of view
+    and the sensor centres), the sign of Eq. (9) and the running mean."""
+    import oracle
+    for sm in (synth.uniform_sensor(32, 256), synth.staggered_sensor(24, 200, r0=0.0)):
+        ranges, poses, pts, es, ew, near = _sphere_case(sm, 3, 0.0, 0.0)
+        s, w = oracle.sdf_fuse(sm, ranges, poses, pts, 0.0, 0.0)
+        ok = ~near
+        np.testing.assert_array_equal(w[ok], ew[ok])
+        np.testing.assert_allclose(s[ok], es[ok], rtol=0, atol=1e-12)
+        assert 0 < np.mean(ew == 0) < 0.9 and np.mean(ew == 5) > 0.05
+
+
+def test_sphere_closed_form_truncated_and_clipped(orc):
+    """Truncation (skip d < -trunc, limit d to trunc) and the range clip
+    (returns beyond r_clip are not integrated) on the same closed form."""
+    import oracle
+    sm = synth.uniform_sensor(32, 256)
+    for trunc, r_clip in ((0.3, 0.0), (0.5, 6.5), (1.0, 3.9)):
+        ranges, poses, pts, es, ew, near = _sphere_case(sm, 4, trunc, r_clip)
+        s, w = oracle.sdf_fuse(sm, ranges, poses, pts, trunc, r_clip)
+        ok = ~near
+        np.testing.assert_array_equal(w[ok], ew[ok])
+        np.testing.assert_allclose(s[ok], es[ok], rtol=0, atol=1e-12)
+        assert np.all(np.abs(s) <= trunc + 1e-15)
+        assert np.any(ew > 0)
+
+
+def test_ground_plane_with_textbook_spherical_projection(orc):
+    """A sensor at height h above the ground z = 0, synthetic intrinsics: beam
+    v below the horizon returns h / (-sin phi_v).  By the textbook projection a
+    point x_s lands on the beam nearest its elevation, so Eq. (9) gives
+    d = h / (-sin phi_v) - |x_s| (rows that see the sky have no return)."""
+    import oracle
+    sm = synth.uniform_sensor(64, 512)
+    h = 1.8
+    img = np.zeros((sm.H, sm.W), np.float32)
+    below = sm.phi < 0
+    img[below, :] = (h / -np.sin(sm.phi[below]))[:, None].astype(np.float32)
+    rng = np.random.default_rng(5)
+    yaw = rng.uniform(0, 2 * np.pi)
+    c = np.array([3.0, -2.0, h])
+    T = _world_to_sensor(synth.yaw_matrix(yaw), c)
+    pts = np.concatenate([c + rng.uniform(-30, 30, size=(6000, 3)) * [1, 1, 0.1]])
+    out = oracle.sdf_points(sm, img, T, pts)
+    xs = (pts - c) @ synth.yaw_matrix(yaw)
+    rr = np.linalg.norm(xs, axis=1)
+    el = np.arcsin(xs[:, 2] / rr)
+    v = np.argmin(np.abs(el[:, None] - sm.phi[None, :]), axis=1)
+    mids = 0.5 * (sm.phi[:-1] + sm.phi[1:])
+    clear = np.min(np.abs(el[:, None] - mids[None, :]), axis=1) > 1e-9
+    hi, lo = _fov_edges(sm)
+    inside = (el <= hi) & (el >= lo)
+    has_ret = inside & below[v]
+    np.testing.assert_array_equal(out["valid"][clear], has_ret[clear])
+    np.testing.assert_array_equal(out["v"][clear & inside], v[clear & inside])
+    m = clear & has_ret
+    exp_d = img[v[m], 0].astype(np.float64) - rr[m]          # h / -sin(phi_v) rounded to FP32
+    np.testing.assert_allclose(out["d"][m], exp_d, rtol=0, atol=1e-9)
+    # points between the sensor and the ground along their ray lie in front of the surface
+    assert np.all((out["d"][m] > 0) == (exp_d > 0))
+    assert m.sum() > 1000
+
+
+def test_distance_along_pixel_rays_with_receiver_offset(orc):
+    """Points placed on the ray of pixel (u, v) at range rho (Eq. (1), receiver
+    offset r0 > 0, staggered azimuth table) project back to that pixel with
+    r = rho, so Eq. (9) gives exactly Omega(u, v) - rho."""
+    import oracle
+    sm = synth.staggered_sensor(32, 512, r0=0.04)
+    rng = np.random.default_rng(6)
+    img = rng.uniform(2.0, 40.0, size=(sm.H, sm.W)).astype(np.float32)
+    R = synth.rot_axis_angle(synth.unit_vector(rng), 0.4)
+    c = np.array([1.0, 2.0, 0.5])
+    T = _world_to_sensor(R, c)
+    n = 3000
+    us = rng.integers(0, sm.W, n)
+    vs = rng.integers(0, sm.H, n)
+    rho = rng.uniform(1.0, 50.0, n)
+    xs = np.stack([oracle.unproject(sm, u, v, r) for u, v, r in zip(us, vs, rho)])
+    pts = xs @ R.T + c                                       # sensor -> world
+    out = oracle.sdf_points(sm, img, T, pts)
+    assert out["valid"].all()
+    np.testing.assert_array_equal(out["u"], us)
+    np.testing.assert_array_equal(out["v"], vs)
+    np.testing.assert_allclose(out["d"], img[vs, us].astype(np.float64) - rho, rtol=0, atol=1e-9)
+
+
+def test_incremental_update_equals_least_squares_mean(orc):
+    """Eq. (10): the running mean after F frames equals argmin_t sum_f (t -
+    d_f)^2, i.e. the plain mean of the per-frame (truncated) distances, in any
+    frame order; and fusing in two calls equals fusing in one."""
+    import oracle
+    seq = synth.gen_sequence(synth.CONFIGS["odometry128x2048"], 11, n_scans=6,
+                             sensor=synth.uniform_sensor(32, 512))
+    poses = np.stack([synth.inv_pose(P) for P in seq["poses"]])
+    ranges = np.stack(seq["scans"])
+    rng = np.random.default_rng(7)
+    c = seq["poses"][0][:3, 3]
+    pts = c + rng.uniform(-15, 15, size=(5000, 3)) * [1, 1, 0.15]
+    trunc, r_clip = 0.5, 30.0
+    D = np.zeros((len(ranges), len(pts)))
+    K = np.zeros_like(D, dtype=bool)
+    for f in range(len(ranges)):
+        o = oracle.sdf_points(seq["sensor"], ranges[f], poses[f], pts)
+        keep = o["valid"] & (o["omega"] <= r_clip) & (o["d"] >= -trunc)
+        D[f] = np.minimum(o["d"], trunc)
+        K[f] = keep
+    w_ls = K.sum(0)
+    t_ls = np.where(w_ls > 0, (D * K).sum(0) / np.maximum(w_ls, 1), 0.0)
+    s, w = oracle.sdf_fuse(seq["sensor"], ranges, poses, pts, trunc, r_clip)
+    np.testing.assert_array_equal(w, w_ls)
+    np.testing.assert_allclose(s, t_ls, rtol=0, atol=1e-12)
+    order = rng.permutation(len(ranges))
+    s2, w2 = oracle.sdf_fuse(seq["sensor"], ranges[order], poses[order], pts, trunc, r_clip)
+    np.testing.assert_array_equal(w2, w)
+    np.testing.assert_allclose(s2, s, rtol=0, atol=1e-12)
+    sa, wa = oracle.sdf_fuse(seq["sensor"], ranges[:2], poses[:2], pts, trunc, r_clip)
+    sb, wb = oracle.sdf_fuse(seq["sensor"], ranges[2:], poses[2:], pts, trunc, r_clip, sa, wa)
+    np.testing.assert_array_equal(wb, w)
+    np.testing.assert_allclose(sb, s, rtol=0, atol=1e-12)
+    assert (w > 0).mean() > 0.3 and (w == len(ranges)).any()
