@@ -103,6 +103,8 @@ def lib():
         L.orc_sdf_points.argtypes = [S, _F, _D, _D, ctypes.c_int64, _D, _D, _U8, _I32, _I32, _D, _D]
         L.orc_sdf_fuse.argtypes = [S, ctypes.c_int, _F, _D, ctypes.c_int64, _D, ctypes.c_double,
                                    ctypes.c_double, _D, _D]
+        L.orc_normals_pca.argtypes = [S, _F, ctypes.c_int, ctypes.c_double, _D, _U8, _D]
+        L.orc_eigen3.argtypes = [_D, _D, _D]
         _lib = L
     return _lib
 
@@ -216,6 +218,29 @@ def sdf_fuse(sensor, ranges: np.ndarray, poses: np.ndarray, pts: np.ndarray, tru
     lib().orc_sdf_fuse(ctypes.byref(h.s), int(r.shape[0]), _p(r, _F), _p(T, _D), n, _p(p, _D),
                        float(trunc), float(r_clip), _p(s, _D), _p(w, _D))
     return s, w
+
+
+def normals_pca(sensor, rng_img: np.ndarray, half: int = 1, edge_rel: float = 0.1):
+    """PCA normals in a (2 half + 1)^2 window: (normals [H, W, 3], valid [H, W],
+    eigenvalues [H, W, 3] ascending)."""
+    assert 1 <= half <= 5
+    h = _SensorHolder(sensor)
+    r = np.ascontiguousarray(rng_img, dtype=np.float32)
+    n = np.zeros((h.H, h.W, 3))
+    lam = np.zeros((h.H, h.W, 3))
+    valid = np.zeros((h.H, h.W), np.uint8)
+    lib().orc_normals_pca(ctypes.byref(h.s), _p(r, _F), int(half), float(edge_rel), _p(n, _D), _p(valid, _U8),
+                          _p(lam, _D))
+    return n, valid.astype(bool), lam
+
+
+def eigen3(A: np.ndarray):
+    """Ascending eigenvalues and eigenvector columns of a symmetric 3x3."""
+    a = np.ascontiguousarray(A, dtype=np.float64).reshape(9)
+    lam = np.zeros(3)
+    V = np.zeros(9)
+    lib().orc_eigen3(_p(a, _D), _p(lam, _D), _p(V, _D))
+    return lam, V.reshape(3, 3)
 
 
 def bf16(x: float) -> float:

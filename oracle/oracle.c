@@ -1003,3 +1003,155 @@ void orc_sdf_fuse(const orc_sensor *s, int n_frames, const float *ranges, const 
         }
     }
 }
+
+/* ------------------------------------------------------------------ PCA normals */
+
+/* Eigenvalues (ascending) and unit eigenvectors (columns of V) of a symmetric
+ * 3x3 matrix A (row-major) by the cyclic Jacobi method: plane rotations that
+ * zero one off-diagonal entry at a time, swept until the off-diagonal part is
+ * negligible. */
+static void jacobi_eigen3(const double A[9], double lam[3], double V[9])
+{
+    double a[9];
+    memcpy(a, A, sizeof(a));
+    for (int i = 0; i < 9; ++i)
+        V[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = a[1] * a[1] + a[2] * a[2] + a[5] * a[5];
+        double dia = a[0] * a[0] + a[4] * a[4] + a[8] * a[8];
+        if (off <= 1e-40 * dia || off == 0.0)
+            break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                double apq = a[3 * p + q];
+                if (apq == 0.0)
+                    continue;
+                /* rotation angle from tan(2 phi) = 2 a_pq / (a_qq - a_pp) */
+                double th = (a[3 * q + q] - a[3 * p + p]) / (2.0 * apq);
+                double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < 3; ++k) { /* A <- A G (columns p, q) */
+                    double akp = a[3 * k + p], akq = a[3 * k + q];
+                    a[3 * k + p] = c * akp - sn * akq;
+                    a[3 * k + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < 3; ++k) { /* A <- G^T A (rows p, q) */
+                    double apk = a[3 * p + k], aqk = a[3 * q + k];
+                    a[3 * p + k] = c * apk - sn * aqk;
+                    a[3 * q + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < 3; ++k) { /* V <- V G */
+                    double vkp = V[3 * k + p], vkq = V[3 * k + q];
+                    V[3 * k + p] = c * vkp - sn * vkq;
+                    V[3 * k + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    /* sort ascending, permuting the columns of V alongside */
+    int idx[3] = {0, 1, 2};
+    double d[3] = {a[0], a[4], a[8]};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2 - i; ++j)
+            if (d[idx[j]] > d[idx[j + 1]]) {
+                int tmp = idx[j];
+                idx[j] = idx[j + 1];
+                idx[j + 1] = tmp;
+            }
+    double W[9];
+    memcpy(W, V, sizeof(W));
+    for (int j = 0; j < 3; ++j) {
+        lam[j] = d[idx[j]];
+        for (int k = 0; k < 3; ++k)
+            V[3 * k + j] = W[3 * k + idx[j]];
+    }
+}
+
+/*
+ * Target normals by principal component analysis of the points in a
+ * (2 half + 1)^2 pixel window (the eigen-decomposition alternative that
+ * Sec. 4.1 names next to the neighbour cross product).
+ *
+ * Readings (the paper gives no details): the window wraps around in u and is
+ * cut at the first and last rows; a pixel of the window takes part iff it is
+ * a return within edge_rel * r_c of the centre range r_c (the gate of the
+ * cross-product normals, so no window mixes surfaces across a depth edge);
+ * the centre must be a return and at least ((2 half + 1)^2 + 1) / 2 pixels
+ * (more than half the window) must take part.  The normal is the eigenvector
+ * of the smallest eigenvalue of the points' covariance (1/n) sum (p - mean)
+ * (p - mean)^T, oriented towards the sensor (n . d <= 0 for the centre's ray
+ * direction d); a window whose middle eigenvalue is at most 1e-6 times the
+ * largest (points on a line) has no normal.  lam (nullable) receives the
+ * three eigenvalues in ascending order per pixel (zeros where invalid).
+ */
+void orc_normals_pca(const orc_sensor *s, const float *range, int half, double edge_rel, double *nrm,
+                     uint8_t *valid, double *lam)
+{
+    int H = s->H, W = s->W, k = 2 * half + 1;
+    int min_pts = (k * k + 1) / 2;
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            size_t i = (size_t)v * W + u;
+            valid[i] = 0;
+            nrm[3 * i] = nrm[3 * i + 1] = nrm[3 * i + 2] = 0.0;
+            if (lam)
+                lam[3 * i] = lam[3 * i + 1] = lam[3 * i + 2] = 0.0;
+            double rc = range[i];
+            if (!range_ok(rc))
+                continue;
+            double lim = edge_rel * rc;
+            double pts[121][3];
+            int n = 0;
+            for (int dv = -half; dv <= half; ++dv) {
+                int vv = v + dv;
+                if (vv < 0 || vv >= H)
+                    continue;
+                for (int du = -half; du <= half; ++du) {
+                    int uu = ((u + du) % W + W) % W;
+                    double r = range[(size_t)vv * W + uu];
+                    if (!range_ok(r) || fabs(r - rc) > lim)
+                        continue;
+                    orc_unproject(s, uu, vv, r, pts[n]);
+                    ++n;
+                }
+            }
+            if (n < min_pts)
+                continue;
+            double m[3] = {0.0, 0.0, 0.0};
+            for (int j = 0; j < n; ++j)
+                for (int c = 0; c < 3; ++c)
+                    m[c] += pts[j][c];
+            for (int c = 0; c < 3; ++c)
+                m[c] /= n;
+            double C[9] = {0.0};
+            for (int j = 0; j < n; ++j)
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        C[3 * a + b] += (pts[j][a] - m[a]) * (pts[j][b] - m[b]);
+            for (int a = 0; a < 9; ++a)
+                C[a] /= n;
+            double ev[3], V[9];
+            jacobi_eigen3(C, ev, V);
+            if (lam) {
+                lam[3 * i] = ev[0];
+                lam[3 * i + 1] = ev[1];
+                lam[3 * i + 2] = ev[2];
+            }
+            if (!(ev[1] > 1e-6 * ev[2]))
+                continue;
+            double nv[3] = {V[0], V[3], V[6]};
+            double d[3];
+            ray_dir(s, u, v, d);
+            if (nv[0] * d[0] + nv[1] * d[1] + nv[2] * d[2] > 0.0) {
+                nv[0] = -nv[0];
+                nv[1] = -nv[1];
+                nv[2] = -nv[2];
+            }
+            nrm[3 * i] = nv[0];
+            nrm[3 * i + 1] = nv[1];
+            nrm[3 * i + 2] = nv[2];
+            valid[i] = 1;
+        }
+}
+
+/* The eigen-decomposition step on its own (for the tests). */
+void orc_eigen3(const double A[9], double lam[3], double V[9]) { jacobi_eigen3(A, lam, V); }
