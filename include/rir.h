@@ -1,6 +1,7 @@
 /*
- * rir.h -- C ABI of librir: multi-scale projective point-to-plane ICP on
- * cylindrical LiDAR range images, on AMD Instinct MI355X (gfx950).
+ * rir.h -- C ABI of librir: multi-scale projective point-to-plane ICP and
+ * projective SDF fusion on cylindrical LiDAR range images, on AMD Instinct
+ * MI355X (gfx950).
  *
  * The method is that of Dong, Ryu, Kaess, Park, "Revisiting LiDAR
  * Registration and Reconstruction: A Range Image Perspective":
@@ -10,7 +11,9 @@
  *                          an inverse elevation table;
  *   Sec. 4.1, Eq. (5)-(7)  projective data association and robust
  *                          point-to-plane Gauss-Newton over a strided
- *                          range/normal pyramid.
+ *                          range/normal pyramid;
+ *   Sec. 4.2, Eq. (8)-(10) projective signed distances fused into a dense
+ *                          voxel-block volume.
  *
  * Conventions shared by every call:
  *  - Images are row-major [v][u], v = 0 the top beam (highest elevation), u the
@@ -231,6 +234,21 @@ rir_status rir_project(const rir_sensor *sensor, int32_t level, const float *xyz
 rir_status rir_normals(const rir_sensor *sensor, const float *range, double edge_rel, float *nrm, uint8_t *valid,
                        void *stream);
 
+/* Normals by principal component analysis of a (2 half + 1)^2 pixel window,
+ * the eigen-decomposition estimator Sec. 4.1 names beside the neighbour cross
+ * product, for n_images contiguous H x W range images (device, FP32):
+ * nrm (device n_images*H*W*3 FP32) and valid (device bytes).  The window
+ * wraps in u and is cut at the first and last rows; a pixel of it takes part
+ * iff it is a return within edge_rel of the centre range.  Valid iff the
+ * centre is a return, more than half the window takes part, and the middle
+ * eigenvalue of the points' covariance exceeds 1e-6 times the largest (not
+ * all on a line); the normal is the eigenvector of the smallest eigenvalue,
+ * facing the sensor.  Covariance and eigen-decomposition in FP64.  half is
+ * 1, 2 or 3.  Errors: RIR_E_INVALID (null, n_images < 0, half outside 1..3,
+ * edge_rel <= 0), RIR_E_HIP. */
+rir_status rir_normals_pca(const rir_sensor *sensor, int32_t n_images, const float *range, int32_t half,
+                           double edge_rel, float *nrm, uint8_t *valid, void *stream);
+
 /* ---------------------------------------------------------------- registration */
 
 /* Registers n_pairs independent scan pairs (Sec. 4.1, Eq. (5)-(7)), all with
@@ -266,6 +284,47 @@ rir_status rir_debug_associate(rir_ctx *ctx, const rir_icp_params *params, const
 rir_status rir_autotune(rir_ctx *ctx, const rir_icp_params *params, int32_t n_pairs, const rir_pair *pairs,
                         const double *init_poses, double *poses_scratch, rir_tuning *best, float *best_ms,
                         void *stream);
+
+/* ---------------------------------------------------------------- reconstruction */
+
+/* Dense SDF volume (Sec. 4.2): nbx x nby x nbz blocks of 16^3 voxels (the
+ * paper's voxel-block shape, here allocated densely).  Voxel (i, j, k),
+ * 0 <= i < 16 nbx etc., sits at origin + voxel * (i, j, k) in world
+ * coordinates (metres).  Storage (device, caller-owned): 2 FP32 values
+ * (sdf, weight) per voxel; blocks in (bz, by, bx) order, bx fastest; inside
+ * a block voxels in (z, y, x) order, x fastest; block (bx, by, bz) holds
+ * voxels 16 bx .. 16 bx + 15 along i, and so on.  A voxel with weight 0 has
+ * not been observed; a zero-filled buffer is an empty volume. */
+typedef struct {
+    int32_t nbx, nby, nbz;
+    double origin[3];
+    double voxel;
+} rir_volume_desc;
+
+/* Fuses n_frames range scans into the volume (Sec. 4.2).  For each voxel x
+ * and each scan f, in the given order: Eq. (8) [u v r] = Pi(R_f x + t_f) at the
+ * finest level, Eq. (9) d = Omega_f(u, v) - r, and the running mean of Eq. (10)
+ * sdf <- sdf + (d - sdf) / (weight + 1), weight <- weight + 1.  An
+ * observation counts only if the projection lies in the image, Omega_f(u, v)
+ * is a return, Omega_f(u, v) <= r_clip (if r_clip > 0; far returns clipped)
+ * and d >= -trunc (if trunc > 0; d is then limited to at most trunc, the
+ * truncated SDF of classical volumetric fusion); trunc <= 0 averages every
+ * observation.
+ *   sensor   the scans' intrinsics (every scan H x W of that sensor).
+ *   vol      host descriptor (see rir_volume_desc).
+ *   voxels   device, 2 * 4096 * nbx * nby * nbz FP32, updated in place.
+ *   ranges   device, n_frames * H * W FP32 scans, contiguous.
+ *   poses    host, n_frames * 16 FP64 row-major 4x4 world -> sensor poses
+ *            (x_s = R x + t); read before the call returns.
+ * FP32 per-voxel arithmetic; the per-block sensor-frame offsets are formed in
+ * FP64.  Work is enqueued on `stream` in launches of up to 16 scans; a block
+ * that no scan of a launch can reach (farther than r_clip + trunc + r0 from
+ * every sensor, with both limits set) is not touched.  n_frames = 0 is a
+ * no-op.  Errors: RIR_E_INVALID (null, n_frames < 0, non-finite pose,
+ * origin, trunc or r_clip, voxel <= 0), RIR_E_SHAPE (block count < 1 or
+ * above 2^31 - 1, 16 scans of H x W at or above 2 GiB), RIR_E_HIP. */
+rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volume_desc *vol, float *voxels, int32_t n_frames,
+                             const float *ranges, const double *poses, double trunc, double r_clip, void *stream);
 
 /* ---------------------------------------------------------------- learned weight */
 

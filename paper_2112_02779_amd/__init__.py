@@ -30,7 +30,7 @@ EXPORTS = [
     "rir_ctx_get_tuning", "rir_ctx_enable_timing", "rir_ctx_level_times", "rir_unproject", "rir_project",
     "rir_normals", "rir_icp_batch", "rir_debug_associate", "rir_autotune", "rir_mlp_create", "rir_mlp_destroy",
     "rir_mlp_get_params", "rir_mlp_set_params", "rir_mlp_forward", "rir_mlp_train_step", "rir_last_error",
-    "rir_elevation_table",
+    "rir_elevation_table", "rir_sdf_integrate", "rir_normals_pca",
 ]
 
 
@@ -82,6 +82,11 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("iters_run", "<i4"), ("n_valid", "<i
 assert STATS_DTYPE.itemsize == ctypes.sizeof(LevelStatsC) == 280
 
 
+class VolumeDesc(ctypes.Structure):
+    _fields_ = [("nbx", ctypes.c_int32), ("nby", ctypes.c_int32), ("nbz", ctypes.c_int32),
+                ("origin", ctypes.c_double * 3), ("voxel", ctypes.c_double)]
+
+
 def lib():
     """The loaded librir.so (raises if it has not been built)."""
     global _lib
@@ -120,6 +125,8 @@ def lib():
         "rir_mlp_set_params": [vp, ctypes.POINTER(ctypes.c_uint16), ctypes.POINTER(f32)],
         "rir_mlp_forward": [vp, vp, i64, vp, vp],
         "rir_mlp_train_step": [vp, vp, vp, i64, f32, vp, vp, vp],
+        "rir_normals_pca": [vp, i32, vp, i32, f64, vp, vp, vp],
+        "rir_sdf_integrate": [vp, ctypes.POINTER(VolumeDesc), vp, i32, vp, ctypes.POINTER(f64), f64, f64, vp],
         "rir_last_error": [],
         "rir_elevation_table": [ctypes.POINTER(SensorDesc), i32, i32, vp, i64, ctypes.POINTER(i64),
                                 ctypes.POINTER(f64), ctypes.POINTER(f64)],
@@ -296,6 +303,70 @@ def normals(sensor: Sensor, rng, edge_rel=0.1, stream=None):
 
 
 # ----------------------------------------------------------------------------- registration
+
+class Volume:
+    """Dense SDF volume of nb = (nbx, nby, nbz) blocks of 16^3 voxels; voxel
+    (i, j, k) sits at origin + voxel * (i, j, k) (world, metres)."""
+
+    EDGE = 16
+
+    def __init__(self, nb, origin, voxel: float):
+        self.nb = tuple(int(n) for n in nb)
+        self.origin = tuple(float(o) for o in origin)
+        self.voxel = float(voxel)
+        self.desc = VolumeDesc(self.nb[0], self.nb[1], self.nb[2], (ctypes.c_double * 3)(*self.origin),
+                               self.voxel)
+
+    @property
+    def shape(self):
+        """Voxel counts (nx, ny, nz)."""
+        return tuple(self.EDGE * n for n in self.nb)
+
+    def alloc(self, device="cuda:0"):
+        """An empty volume: (sdf, weight) = 0 for every voxel, stored as
+        [nbz, nby, nbx, 16 (z), 16 (y), 16 (x), 2] FP32."""
+        import torch
+        nbx, nby, nbz = self.nb
+        E = self.EDGE
+        return torch.zeros((nbz, nby, nbx, E, E, E, 2), dtype=torch.float32, device=device)
+
+    def to_grid(self, voxels):
+        """View of the block layout as [nz, ny, nx, 2] (a permuted copy)."""
+        nbx, nby, nbz = self.nb
+        E = self.EDGE
+        return voxels.permute(0, 3, 1, 4, 2, 5, 6).reshape(nbz * E, nby * E, nbx * E, 2)
+
+
+def sdf_integrate(sensor: Sensor, vol: Volume, voxels, ranges, poses, trunc: float, r_clip: float, stream=None):
+    """Fuses scans ranges [F, H, W] (device FP32) taken at poses [F, 4, 4]
+    (host FP64, world -> sensor) into voxels (Volume.alloc layout) in place."""
+    import torch
+    _require(voxels, torch.float32, "voxels", 2 * 4096 * vol.nb[0] * vol.nb[1] * vol.nb[2])
+    P = np.ascontiguousarray(poses, dtype=np.float64).reshape(-1, 16)
+    F = P.shape[0]
+    if F > 0:
+        _require(ranges, torch.float32, "ranges", F * sensor.H * sensor.W)
+    _check(lib().rir_sdf_integrate(sensor.handle, ctypes.byref(vol.desc), _ptr(voxels), F,
+                                   _ptr(ranges) if F > 0 else None,
+                                   P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(trunc), float(r_clip),
+                                   _stream(stream)))
+    return voxels
+
+
+def normals_pca(sensor: Sensor, rng, half: int = 1, edge_rel=0.1, stream=None):
+    """PCA normals of one [H, W] or a batch [n, H, W] of range images."""
+    import torch
+    _require(rng, torch.float32, "range")
+    if rng.numel() % (sensor.H * sensor.W) != 0:
+        raise ValueError("range must hold whole H x W images")
+    n_img = rng.numel() // (sensor.H * sensor.W)
+    shape = tuple(rng.shape)
+    n = torch.empty(shape + (3,), dtype=torch.float32, device=rng.device)
+    valid = torch.empty(shape, dtype=torch.uint8, device=rng.device)
+    _check(lib().rir_normals_pca(sensor.handle, n_img, _ptr(rng), int(half), float(edge_rel), _ptr(n), _ptr(valid),
+                                 _stream(stream)))
+    return n, valid
+
 
 def _pairs_array(pairs):
     arr = (Pair * len(pairs))()

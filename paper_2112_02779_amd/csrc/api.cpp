@@ -17,6 +17,7 @@
 #include "elev_table.h"
 #include "rir.h"
 #include "rir_internal.h"
+#include "rir_ops.h"
 
 using namespace rir;
 
@@ -1292,6 +1293,106 @@ extern "C" rir_status rir_normals(const rir_sensor *sensor, const float *range, 
         return fail(RIR_E_INVALID, "rir_normals: edge_rel must be > 0");
     HIP_TRY(hipSetDevice(sensor->device));
     HIP_TRY(launch_normals(sensor->tf, range, edge_rel, nrm, valid, static_cast<hipStream_t>(stream)));
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_normals_pca(const rir_sensor *sensor, int32_t n_images, const float *range, int32_t half,
+                                      double edge_rel, float *nrm, uint8_t *valid, void *stream)
+{
+    if (!sensor)
+        return fail(RIR_E_INVALID, "rir_normals_pca: null argument");
+    if (n_images < 0)
+        return fail(RIR_E_INVALID, "rir_normals_pca: n_images < 0");
+    if (n_images > 0 && (!range || !nrm || !valid))
+        return fail(RIR_E_INVALID, "rir_normals_pca: null argument");
+    if (half < 1 || half > 3)
+        return fail(RIR_E_INVALID, "rir_normals_pca: half must be 1, 2 or 3");
+    if (!(edge_rel > 0.0) || !std::isfinite(edge_rel))
+        return fail(RIR_E_INVALID, "rir_normals_pca: edge_rel must be > 0");
+    if (n_images == 0)
+        return RIR_OK;
+    HIP_TRY(hipSetDevice(sensor->device));
+    HIP_TRY(launch_normals_pca(sensor->td, range, n_images, half, edge_rel, nrm, valid,
+                               static_cast<hipStream_t>(stream)));
+    return RIR_OK;
+}
+
+// ============================================================================ projective SDF fusion
+
+extern "C" rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volume_desc *vol, float *voxels,
+                                        int32_t n_frames, const float *ranges, const double *poses, double trunc,
+                                        double r_clip, void *stream)
+{
+    if (!sensor || !vol)
+        return fail(RIR_E_INVALID, "rir_sdf_integrate: null argument");
+    if (n_frames < 0)
+        return fail(RIR_E_INVALID, "rir_sdf_integrate: n_frames < 0");
+    if (n_frames > 0 && (!voxels || !ranges || !poses))
+        return fail(RIR_E_INVALID, "rir_sdf_integrate: null argument");
+    if (vol->nbx < 1 || vol->nby < 1 || vol->nbz < 1)
+        return fail(RIR_E_SHAPE, "rir_sdf_integrate: block counts must be >= 1");
+    const int64_t nblk = (int64_t)vol->nbx * vol->nby * vol->nbz;
+    if (nblk > (int64_t)std::numeric_limits<int32_t>::max())
+        return fail(RIR_E_SHAPE, "rir_sdf_integrate: more than 2^31 - 1 blocks");
+    if (!(vol->voxel > 0.0) || !std::isfinite(vol->voxel))
+        return fail(RIR_E_INVALID, "rir_sdf_integrate: voxel size must be finite and > 0");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(vol->origin[i]))
+            return fail(RIR_E_INVALID, "rir_sdf_integrate: origin must be finite");
+    if (!std::isfinite(trunc) || !std::isfinite(r_clip))
+        return fail(RIR_E_INVALID, "rir_sdf_integrate: trunc and r_clip must be finite");
+    for (int64_t i = 0; i < 16 * (int64_t)n_frames; ++i)
+        if (!std::isfinite(poses[i]))
+            return fail(RIR_E_INVALID, "rir_sdf_integrate: non-finite pose");
+    const int64_t img_bytes = (int64_t)sensor->H * sensor->W * (int64_t)sizeof(float);
+    if (img_bytes * kSdfFrames >= ((int64_t)1 << 31))
+        return fail(RIR_E_SHAPE, "rir_sdf_integrate: range images too large for one launch");
+    if (n_frames == 0)
+        return RIR_OK;
+    HIP_TRY(hipSetDevice(sensor->device));
+
+    SdfArgs a{};
+    a.tab = sensor->d_tf;
+    a.vox = voxels;
+    a.nbx = vol->nbx;
+    a.nby = vol->nby;
+    a.nbz = vol->nbz;
+    a.xcd_remap = 1;
+    a.trunc = trunc > 0.0 ? (float)trunc : std::numeric_limits<float>::infinity();
+    if (r_clip > 0.0) {
+        // the largest float not above r_clip: the FP32 test om <= clip then
+        // decides exactly as om <= r_clip in real arithmetic
+        float c = (float)r_clip;
+        if ((double)c > r_clip)
+            c = std::nextafter(c, 0.0f);
+        a.clip = c;
+    } else {
+        a.clip = std::numeric_limits<float>::infinity();
+    }
+    // A voxel is updated only if Omega <= r_clip and Omega - r >= -trunc, so its
+    // distance to the sensor origin is at most r_clip + trunc + r0; the margin
+    // covers the FP32 rounding of r.
+    a.cull = (trunc > 0.0 && r_clip > 0.0) ? r_clip + trunc + sensor->r0 + 1e-3 + 1e-4 * (r_clip + trunc) : -1.0;
+    for (int i = 0; i < 3; ++i)
+        a.origin[i] = vol->origin[i];
+    a.voxel = vol->voxel;
+    const bool r0 = sensor->r0 > 0.0;
+    const bool pow2 = (sensor->W & (sensor->W - 1)) == 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int32_t f0 = 0; f0 < n_frames; f0 += kSdfFrames) {
+        const int k = std::min<int32_t>(kSdfFrames, n_frames - f0);
+        a.n_frames = k;
+        a.ranges = ranges + (size_t)f0 * (size_t)(img_bytes / (int64_t)sizeof(float));
+        for (int j = 0; j < k; ++j) {
+            const double *T = poses + 16 * (size_t)(f0 + j);
+            for (int r = 0; r < 3; ++r) {
+                for (int c = 0; c < 3; ++c)
+                    a.f[j].R[3 * r + c] = T[4 * r + c];
+                a.f[j].t[r] = T[4 * r + 3];
+            }
+        }
+        HIP_TRY(launch_sdf_fuse(a, r0, pow2, st));
+    }
     return RIR_OK;
 }
 

@@ -1,0 +1,171 @@
+// Target normals by principal component analysis of a pixel window (the
+// eigen-decomposition estimator that Dong et al. name in Sec. 4.1 next to the
+// neighbour cross product), for batches of range images on gfx950.
+//
+// One thread per pixel.  The window's points are unprojected (Eq. (1)) from
+// the FP64 sensor tables and accumulated relative to the centre point in
+// FP64: the covariance of a planar patch has a smallest eigenvalue many
+// orders of magnitude below the largest, which FP32 sums could not resolve.
+// The smallest eigenpair comes from the closed-form (trigonometric)
+// eigenvalues of the symmetric 3x3 matrix and the largest cross product of
+// two rows of A - lambda I.  MI355X runs FP64 vector arithmetic at half the
+// FP32 rate, and the kernel is bound by that arithmetic, not by HBM.
+#include "rir_ops.h"
+
+namespace rir {
+
+namespace {
+
+// Smallest and middle eigenvalue of the symmetric matrix
+// [[a00 a01 a02] [a01 a11 a12] [a02 a12 a22]] (and the largest), with a unit
+// eigenvector of the smallest.  Returns false if no row pair of A - l0 I
+// spans a plane (every eigenvalue equal).
+__device__ __forceinline__ bool smallest_eigenpair(double a00, double a01, double a02, double a11, double a12,
+                                                   double a22, double &l0, double &l1, double &l2, double n[3])
+{
+    const double q = (a00 + a11 + a22) / 3.0;
+    const double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
+    const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+    const double p2 = b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * p1;
+    if (!(p2 > 0.0)) {
+        l0 = l1 = l2 = q;
+        return false;
+    }
+    const double p = sqrt(p2 / 6.0);
+    // det(A - q I) / (2 p^3) = cos(3 phi)
+    const double det = b00 * (b11 * b22 - a12 * a12) - a01 * (a01 * b22 - a12 * a02) + a02 * (a01 * a12 - b11 * a02);
+    double r = det / (2.0 * p * p * p);
+    r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+    const double phi = acos(r) / 3.0;
+    l2 = q + 2.0 * p * cos(phi);
+    l0 = q + 2.0 * p * cos(phi + 2.0943951023931954923);   // + 2 pi / 3
+    l1 = 3.0 * q - l0 - l2;
+    // eigenvector of l0: orthogonal to every row of A - l0 I
+    const double m00 = a00 - l0, m11 = a11 - l0, m22 = a22 - l0;
+    const double c01[3] = {a01 * a12 - a02 * m11, a02 * a01 - m00 * a12, m00 * m11 - a01 * a01};
+    const double c02[3] = {a01 * m22 - a02 * a12, a02 * a02 - m00 * m22, m00 * a12 - a01 * a02};
+    const double c12[3] = {m11 * m22 - a12 * a12, a12 * a02 - a01 * m22, a01 * a12 - m11 * a02};
+    const double s01 = c01[0] * c01[0] + c01[1] * c01[1] + c01[2] * c01[2];
+    const double s02 = c02[0] * c02[0] + c02[1] * c02[1] + c02[2] * c02[2];
+    const double s12 = c12[0] * c12[0] + c12[1] * c12[1] + c12[2] * c12[2];
+    const double *c = c01;
+    double s = s01;
+    if (s02 > s) {
+        c = c02;
+        s = s02;
+    }
+    if (s12 > s) {
+        c = c12;
+        s = s12;
+    }
+    if (!(s > 0.0))
+        return false;
+    const double inv = 1.0 / sqrt(s);
+    n[0] = c[0] * inv;
+    n[1] = c[1] * inv;
+    n[2] = c[2] * inv;
+    return true;
+}
+
+}  // namespace
+
+template <int HALF>
+__global__ __launch_bounds__(256) void k_normals_pca(SensorTab<double> S, const float *range, int64_t n_px,
+                                                     double edge_rel, float *nrm, uint8_t *valid)
+{
+    constexpr int K = 2 * HALF + 1;
+    constexpr int kMinPts = (K * K + 1) / 2;
+    const int H = S.H, W = S.W;
+    const int64_t HW = (int64_t)H * W;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_px;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t img = i / HW;
+        const int pix = (int)(i - img * HW);
+        const int v = pix / W, u = pix - v * W;
+        const float *rg = range + img * HW;
+        const float rcf = rg[pix];
+        bool ok = range_ok(rcf);
+        double n[3] = {0.0, 0.0, 0.0};
+        if (ok) {
+            const double rc = (double)rcf, lim = edge_rel * rc;
+            const V3<double> pc = unproject(S, u, v, rc);
+            double sx = 0, sy = 0, sz = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
+            int cnt = 0;
+#pragma unroll
+            for (int dv = -HALF; dv <= HALF; ++dv) {
+                const int vv = v + dv;
+                if (vv < 0 || vv >= H)
+                    continue;
+#pragma unroll
+                for (int du = -HALF; du <= HALF; ++du) {
+                    int uu = u + du;
+                    uu = uu < 0 ? uu + W : (uu >= W ? uu - W : uu);
+                    const float rf = rg[(int64_t)vv * W + uu];
+                    if (!range_ok(rf) || fabs((double)rf - rc) > lim)
+                        continue;
+                    const V3<double> p = unproject(S, uu, vv, (double)rf);
+                    const double qx = p.x - pc.x, qy = p.y - pc.y, qz = p.z - pc.z;
+                    sx += qx;
+                    sy += qy;
+                    sz += qz;
+                    sxx += qx * qx;
+                    sxy += qx * qy;
+                    sxz += qx * qz;
+                    syy += qy * qy;
+                    syz += qy * qz;
+                    szz += qz * qz;
+                    ++cnt;
+                }
+            }
+            ok = cnt >= kMinPts;
+            if (ok) {
+                const double ic = 1.0 / (double)cnt;
+                const double mx = sx * ic, my = sy * ic, mz = sz * ic;
+                double l0, l1, l2;
+                ok = smallest_eigenpair(sxx * ic - mx * mx, sxy * ic - mx * my, sxz * ic - mx * mz,
+                                        syy * ic - my * my, syz * ic - my * mz, szz * ic - mz * mz, l0, l1, l2, n);
+                // points on a line (middle eigenvalue negligible) have no normal
+                ok = ok && l1 > 1e-6 * l2;
+                if (ok) {
+                    V4<double> rw = ld4(S.row + 4 * v);
+                    double ca, sa;
+                    ld2(S.col + 2 * u, ca, sa);
+                    const V3<double> d = ray_dir(rw, ca, sa);
+                    if (n[0] * d.x + n[1] * d.y + n[2] * d.z > 0.0) {
+                        n[0] = -n[0];
+                        n[1] = -n[1];
+                        n[2] = -n[2];
+                    }
+                }
+            }
+        }
+        nrm[3 * i] = ok ? (float)n[0] : 0.f;
+        nrm[3 * i + 1] = ok ? (float)n[1] : 0.f;
+        nrm[3 * i + 2] = ok ? (float)n[2] : 0.f;
+        valid[i] = ok ? 1 : 0;
+    }
+}
+
+hipError_t launch_normals_pca(const SensorTab<double> &S, const float *range, int n_images, int half, double edge_rel,
+                              float *nrm, uint8_t *valid, hipStream_t stream)
+{
+    const int64_t n = (int64_t)n_images * S.H * S.W;
+    int64_t g = (n + 255) / 256;
+    const int grid = (int)(g > 65536 ? 65536 : (g < 1 ? 1 : g));
+    switch (half) {
+    case 1:
+        hipLaunchKernelGGL(k_normals_pca<1>, dim3(grid), dim3(256), 0, stream, S, range, n, edge_rel, nrm, valid);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_normals_pca<2>, dim3(grid), dim3(256), 0, stream, S, range, n, edge_rel, nrm, valid);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_normals_pca<3>, dim3(grid), dim3(256), 0, stream, S, range, n, edge_rel, nrm, valid);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rir

@@ -44,6 +44,31 @@ def ambiguous(sensor, level, uhat, phi):
     return amb
 
 
+BAND_D = 1e-4     # metres: signed distances this close to -trunc are ambiguous
+
+
+def sdf_ambiguous(sensor, ranges, poses, pts, trunc, r_clip=0.0):
+    """Voxels (world points pts) whose fused value FP32 and FP64 may
+    legitimately disagree on: in some scan the projection falls in the
+    rounding band above, or the signed distance lies within BAND_D of the
+    truncation limit.  With both trunc and r_clip set, scans farther than
+    r_clip + trunc + r0 from the point (plus 1 mm) cannot observe it whatever
+    pixel it lands on and do not count.  Uses the oracle's projections."""
+    import oracle
+    amb = np.zeros(len(pts), bool)
+    pts = np.asarray(pts, dtype=np.float64)
+    for f in range(len(ranges)):
+        o = oracle.sdf_points(sensor, ranges[f], poses[f], pts)
+        a = ambiguous(sensor, 0, o["uhat"], o["phi"])
+        if trunc > 0:
+            a |= o["valid"] & (np.abs(o["d"] + trunc) < BAND_D)
+        if trunc > 0 and r_clip > 0:
+            xs = pts @ poses[f][:3, :3].T + poses[f][:3, 3]
+            a &= np.linalg.norm(xs, axis=1) <= r_clip + trunc + sensor.r0 + 1e-3
+        amb |= a
+    return amb
+
+
 def rot_trans_error(T, Tref):
     """Rotation angle (rad, via the skew part, accurate near zero) and
     translation distance between two 4x4 poses."""
