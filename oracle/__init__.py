@@ -105,6 +105,7 @@ def lib():
                                    ctypes.c_double, _D, _D]
         L.orc_normals_pca.argtypes = [S, _F, ctypes.c_int, ctypes.c_double, _D, _U8, _D]
         L.orc_eigen3.argtypes = [_D, _D, _D]
+        L.orc_deskew.argtypes = [S, _F, _D, _D, _I32, _I32, _D, _D, _D]
         _lib = L
     return _lib
 
@@ -241,6 +242,23 @@ def eigen3(A: np.ndarray):
     V = np.zeros(9)
     lib().orc_eigen3(_p(a, _D), _p(lam, _D), _p(V, _D))
     return lam, V.reshape(3, 3)
+
+
+def deskew(sensor, rng_img: np.ndarray, xi) -> dict:
+    """Re-projection of a scan under per-column poses Exp(s_u xi), s_u =
+    (u + 1/2)/W - 1/2: the output image (nearest range per pixel, 0 = none)
+    and per source pixel the target pixel, new range and continuous
+    projection coordinates."""
+    h = _SensorHolder(sensor)
+    r = np.ascontiguousarray(rng_img, dtype=np.float32)
+    x = np.ascontiguousarray(xi, dtype=np.float64).reshape(6)
+    out = np.zeros((h.H, h.W))
+    tu = np.zeros((h.H, h.W), np.int32)
+    tv = np.zeros((h.H, h.W), np.int32)
+    rr, uh, ph = np.zeros((h.H, h.W)), np.zeros((h.H, h.W)), np.zeros((h.H, h.W))
+    lib().orc_deskew(ctypes.byref(h.s), _p(r, _F), _p(x, _D), _p(out, _D), _p(tu, _I32), _p(tv, _I32), _p(rr, _D),
+                     _p(uh, _D), _p(ph, _D))
+    return {"out": out, "u": tu, "v": tv, "r": rr, "uhat": uh, "phi": ph}
 
 
 def bf16(x: float) -> float:

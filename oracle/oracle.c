@@ -19,7 +19,10 @@
  *   Sec. 4.1     multi-scale registration on strided images with the
  *                original intrinsics,
  *   Eq. (8)-(10) projective signed distances and their running mean at
- *                query points (Sec. 4.2).
+ *                query points (Sec. 4.2),
+ *   Sec. 4.1     PCA normals (the eigen-decomposition alternative),
+ *   Sec. 6       re-projection under per-column poses (the outlook's
+ *                non-rigid model).
  * Readings of silent or ambiguous passages are listed next to the code that
  * takes them.  The learned per-pixel weight (a small MLP) is not part of the
  * paper; its forward and backward passes are written out here with the same
@@ -1155,3 +1158,60 @@ void orc_normals_pca(const orc_sensor *s, const float *range, int half, double e
 
 /* The eigen-decomposition step on its own (for the tests). */
 void orc_eigen3(const double A[9], double lam[3], double V[9]) { jacobi_eigen3(A, lam, V); }
+
+/* ------------------------------------------------------------------ per-column poses */
+
+/*
+ * Re-projection of a scan under per-column poses: the non-rigid model the
+ * paper's outlook (Sec. 6, limitations) proposes, with consecutive poses
+ * assigned to each column as in LOAM, for sensors whose ray centre moves
+ * during the sweep.
+ *
+ * Readings: column u is captured at sweep time s_u = (u + 1/2) / W - 1/2
+ * (in sweeps, 0 at mid-sweep, azimuth order); the motion over one sweep is
+ * the constant twist xi = (omega, tau), so the column's pose relative to the
+ * mid-sweep frame is Exp(s_u xi) (the interpolation between consecutive poses
+ * on SE(3)).  Every return (u, v, r) is unprojected (Eq. (1)), moved into the
+ * mid-sweep frame, and projected again (Eq. (3)-(4), finest level); the output
+ * pixel keeps the smallest range that lands on it (the nearest surface), 0
+ * where nothing lands.  For each source pixel tu, tv receive the target pixel
+ * (-1 if none), rr the new range, uhat / phi the continuous projection.
+ */
+void orc_deskew(const orc_sensor *s, const float *range, const double xi[6], double *out, int32_t *tu, int32_t *tv,
+                double *rr, double *uhat, double *phi)
+{
+    int H = s->H, W = s->W;
+    for (size_t i = 0; i < (size_t)H * W; ++i)
+        out[i] = 0.0;
+    for (int u = 0; u < W; ++u) {
+        double su = ((double)u + 0.5) / (double)W - 0.5;
+        double xs[6], T[16];
+        for (int k = 0; k < 6; ++k)
+            xs[k] = su * xi[k];
+        orc_exp_se3(xs, T);
+        for (int v = 0; v < H; ++v) {
+            size_t i = (size_t)v * W + u;
+            tu[i] = tv[i] = -1;
+            rr[i] = uhat[i] = phi[i] = 0.0;
+            double r = range[i];
+            if (!range_ok(r))
+                continue;
+            double p[3], x[3];
+            orc_unproject(s, u, v, r, p);
+            for (int a = 0; a < 3; ++a)
+                x[a] = T[4 * a] * p[0] + T[4 * a + 1] * p[1] + T[4 * a + 2] * p[2] + T[4 * a + 3];
+            orc_proj q;
+            orc_project(s, 0, x, &q);
+            uhat[i] = q.uhat;
+            phi[i] = q.phi;
+            if (!q.valid)
+                continue;
+            tu[i] = q.u;
+            tv[i] = q.v;
+            rr[i] = q.r;
+            size_t j = (size_t)q.v * W + q.u;
+            if (out[j] == 0.0 || q.r < out[j])
+                out[j] = q.r;
+        }
+    }
+}
