@@ -465,6 +465,32 @@ def normals_pca_timing(rir, seq, repeats=5):
     return res
 
 
+def deskew_timing(rir, seq, repeats=5):
+    """Re-projection under per-column poses (the outlook's non-rigid model) of
+    all the sequence's scans in one call, 1.5 m forward and 3 degrees of yaw
+    per sweep (a fast-moving sensor at 10 Hz); FP64 per pixel."""
+    import torch
+    sm = seq["sensor"]
+    sen = rir.Sensor.from_model(sm)
+    imgs = torch.from_numpy(np.stack(seq["scans"])).to("cuda:0")
+    xis = np.tile([0.0, 0.0, np.deg2rad(3.0), 1.5, 0.0, 0.0], (imgs.shape[0], 1))
+    stream = torch.cuda.current_stream()
+    ts = []
+    for k in range(repeats + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rir.deskew(sen, imgs, xis, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if k > 0:
+            ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    res = {"workload": f"{imgs.shape[0]} scans of {sm.H}x{sm.W} in one call", "ms": round(ms, 4),
+           "ms_per_scan": round(ms / imgs.shape[0], 5), "mpix_per_s": round(imgs.numel() / (ms * 1e-3) / 1e6, 1)}
+    log(f"deskew: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -482,7 +508,7 @@ def main():
                     help="skip the mixed-size batch and the combined-modes measurements")
     ap.add_argument("--mixed-oracle", type=int, default=8,
                     help="pairs of each mixed workload checked against the oracle (0: none)")
-    ap.add_argument("--no-sdf", action="store_true", help="skip the SDF fusion and PCA normal workloads")
+    ap.add_argument("--no-sdf", action="store_true", help="skip the SDF fusion, PCA normal and deskew workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -600,6 +626,7 @@ def main():
     context = None if args.no_mixed else paper_context(rir, ctx, oracle_runs=not args.no_cpu)
     sdf = None if args.no_sdf else sdf_fusion(rir, seq, 0 if args.no_cpu else 4000)
     pca = None if args.no_sdf else normals_pca_timing(rir, seq)
+    desk = None if args.no_sdf else deskew_timing(rir, seq)
     pairs_per_s = n / (ms_per_step * 1e-3)
     gt_err = [rot_trans_error(T_gpu[i], p.gt) for i, p in enumerate(pairs)]
     out = {
@@ -633,6 +660,7 @@ def main():
         "paper_context": context,
         "sdf_fusion": sdf,
         "normals_pca": pca,
+        "deskew": desk,
     }
     print(json.dumps(out), flush=True)
 

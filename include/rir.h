@@ -249,6 +249,26 @@ rir_status rir_normals(const rir_sensor *sensor, const float *range, double edge
 rir_status rir_normals_pca(const rir_sensor *sensor, int32_t n_images, const float *range, int32_t half,
                            double edge_rel, float *nrm, uint8_t *valid, void *stream);
 
+/* Re-projection under per-column poses, the non-rigid model of the paper's
+ * outlook (Sec. 6: consecutive poses assigned to each column, as in LOAM) for
+ * sensors that move during a sweep.  Column u of scan k is captured at sweep
+ * time s_u = (u + 1/2) / W - 1/2 (0 at mid-sweep); with the constant twist
+ * xi_k = (omega, tau) per sweep its pose in the mid-sweep frame is
+ * Exp(s_u xi_k).  Every return (u, v, r) is unprojected (Eq. (1)), moved by its
+ * column's pose and projected again (Eq. (3)-(4), finest level); each output
+ * pixel keeps the smallest range landing on it, 0 where none does.  The result
+ * is a rigid range image again, ready for registration or fusion.
+ *   range_in   device n_images*H*W FP32 scans.
+ *   twists     host n_images*6 FP64 (omega, tau) per sweep; read before the
+ *              call returns.
+ *   range_out  device n_images*H*W FP32, must not overlap range_in (its bits
+ *              serve as the atomic minimum while the call runs).
+ * FP64 pose, point and projection; output ranges rounded to FP32.  Errors:
+ * RIR_E_INVALID (null, n_images < 0, overlapping buffers, non-finite
+ * twist), RIR_E_HIP. */
+rir_status rir_deskew(const rir_sensor *sensor, int32_t n_images, const float *range_in, const double *twists,
+                      float *range_out, void *stream);
+
 /* ---------------------------------------------------------------- registration */
 
 /* Registers n_pairs independent scan pairs (Sec. 4.1, Eq. (5)-(7)), all with

@@ -30,7 +30,7 @@ EXPORTS = [
     "rir_ctx_get_tuning", "rir_ctx_enable_timing", "rir_ctx_level_times", "rir_unproject", "rir_project",
     "rir_normals", "rir_icp_batch", "rir_debug_associate", "rir_autotune", "rir_mlp_create", "rir_mlp_destroy",
     "rir_mlp_get_params", "rir_mlp_set_params", "rir_mlp_forward", "rir_mlp_train_step", "rir_last_error",
-    "rir_elevation_table", "rir_sdf_integrate", "rir_normals_pca",
+    "rir_elevation_table", "rir_sdf_integrate", "rir_normals_pca", "rir_deskew",
 ]
 
 
@@ -125,6 +125,7 @@ def lib():
         "rir_mlp_set_params": [vp, ctypes.POINTER(ctypes.c_uint16), ctypes.POINTER(f32)],
         "rir_mlp_forward": [vp, vp, i64, vp, vp],
         "rir_mlp_train_step": [vp, vp, vp, i64, f32, vp, vp, vp],
+        "rir_deskew": [vp, i32, vp, ctypes.POINTER(f64), vp, vp],
         "rir_normals_pca": [vp, i32, vp, i32, f64, vp, vp, vp],
         "rir_sdf_integrate": [vp, ctypes.POINTER(VolumeDesc), vp, i32, vp, ctypes.POINTER(f64), f64, f64, vp],
         "rir_last_error": [],
@@ -366,6 +367,23 @@ def normals_pca(sensor: Sensor, rng, half: int = 1, edge_rel=0.1, stream=None):
     _check(lib().rir_normals_pca(sensor.handle, n_img, _ptr(rng), int(half), float(edge_rel), _ptr(n), _ptr(valid),
                                  _stream(stream)))
     return n, valid
+
+
+def deskew(sensor: Sensor, rng, twists, stream=None):
+    """Re-projects one [H, W] or a batch [n, H, W] of scans under per-column
+    poses Exp(s_u xi) with one twist xi = (omega, tau) per scan (host [n, 6])."""
+    import torch
+    _require(rng, torch.float32, "range")
+    if rng.numel() % (sensor.H * sensor.W) != 0:
+        raise ValueError("range must hold whole H x W images")
+    n_img = rng.numel() // (sensor.H * sensor.W)
+    tw = np.ascontiguousarray(twists, dtype=np.float64).reshape(-1)
+    if tw.size != 6 * n_img:
+        raise ValueError(f"need {n_img} twists of 6 values")
+    out = torch.empty_like(rng)
+    _check(lib().rir_deskew(sensor.handle, n_img, _ptr(rng), tw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            _ptr(out), _stream(stream)))
+    return out
 
 
 def _pairs_array(pairs):

@@ -1317,6 +1317,30 @@ extern "C" rir_status rir_normals_pca(const rir_sensor *sensor, int32_t n_images
     return RIR_OK;
 }
 
+extern "C" rir_status rir_deskew(const rir_sensor *sensor, int32_t n_images, const float *range_in,
+                                 const double *twists, float *range_out, void *stream)
+{
+    if (!sensor)
+        return fail(RIR_E_INVALID, "rir_deskew: null argument");
+    if (n_images < 0)
+        return fail(RIR_E_INVALID, "rir_deskew: n_images < 0");
+    if (n_images == 0)
+        return RIR_OK;
+    if (!range_in || !twists || !range_out)
+        return fail(RIR_E_INVALID, "rir_deskew: null argument");
+    const size_t bytes = (size_t)n_images * sensor->H * sensor->W * sizeof(float);
+    const char *a = reinterpret_cast<const char *>(range_in), *b = reinterpret_cast<const char *>(range_out);
+    if (a < b + bytes && b < a + bytes)
+        return fail(RIR_E_INVALID, "rir_deskew: range_out overlaps range_in");
+    for (int64_t i = 0; i < 6 * (int64_t)n_images; ++i)
+        if (!std::isfinite(twists[i]))
+            return fail(RIR_E_INVALID, "rir_deskew: non-finite twist");
+    HIP_TRY(hipSetDevice(sensor->device));
+    HIP_TRY(launch_deskew(sensor->d_td, sensor->H, sensor->W, sensor->r0 > 0.0, n_images, range_in, twists,
+                          range_out, static_cast<hipStream_t>(stream)));
+    return RIR_OK;
+}
+
 // ============================================================================ projective SDF fusion
 
 extern "C" rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volume_desc *vol, float *voxels,

@@ -1,6 +1,7 @@
 // Device-side declarations of the entry points beside the registration path:
 // projective SDF fusion into a dense block grid (Sec. 4.2, Eq. (8)-(10),
-// sdf.hip) and PCA normals (normals_pca.hip).
+// sdf.hip), PCA normals (normals_pca.hip) and re-projection under per-column
+// poses (deskew.hip).
 #pragma once
 
 #include "rir_internal.h"
@@ -40,5 +41,10 @@ hipError_t launch_sdf_fuse(const SdfArgs &a, bool r0, bool pow2, hipStream_t str
 // (window 3x3, 5x5, 7x7), hipErrorInvalidValue otherwise.
 hipError_t launch_normals_pca(const SensorTab<double> &S, const float *range, int n_images, int half, double edge_rel,
                               float *nrm, uint8_t *valid, hipStream_t stream);
+
+// Re-projection of n_images contiguous H x W scans under per-column poses
+// Exp(s_u xi_k) (deskew.hip); out must not overlap in.
+hipError_t launch_deskew(const SensorTab<double> *tab, int H, int W, bool r0, int n_images, const float *in,
+                         const double *twists, float *out, hipStream_t stream);
 
 }  // namespace rir

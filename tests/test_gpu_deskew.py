@@ -1,0 +1,105 @@
+"""GPU parity of the re-projection under per-column poses (the non-rigid
+model of the paper's outlook, Sec. 6) against the FP64 oracle, through the C
+ABI.
+
+Both sides work in FP64, so an output pixel can differ only where some
+return's re-projection lies in the rounding band of parity_util (it may then
+land on a neighbouring pixel): every pixel within one pixel of such a
+landing point is left out; all others must hold the same FP32 range (the
+nearest landing return) or both be empty.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import ambiguous, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rir():
+    import torch
+    import paper_2112_02779_amd as rir
+    assert torch.cuda.is_available()
+    return rir
+
+
+def check(sm, img, xi, out_gpu):
+    o = oracle.deskew(sm, img, xi)
+    H, W = img.shape
+    amb = ambiguous(sm, 0, o["uhat"], o["phi"]) & (img > 0)
+    unsure = np.zeros((H, W), bool)
+    vs, us = np.nonzero(amb)
+    # the oracle's landing pixel of an ambiguous return (or the pixel nearest
+    # its continuous coordinates when the oracle found it outside the field)
+    tv = np.where(o["v"][vs, us] >= 0, o["v"][vs, us], np.clip(np.rint(vs), 0, H - 1)).astype(np.int64)
+    tu = np.where(o["u"][vs, us] >= 0, o["u"][vs, us], np.floor(o["uhat"][vs, us] + 0.5)).astype(np.int64) % W
+    for dv in (-1, 0, 1):
+        for du in (-1, 0, 1):
+            unsure[np.clip(tv + dv, 0, H - 1), (tu + du) % W] = True
+    clear = ~unsure
+    ref = o["out"].astype(np.float32)
+    np.testing.assert_array_equal(out_gpu[clear] > 0, ref[clear] > 0)
+    np.testing.assert_allclose(out_gpu[clear], ref[clear], rtol=1.2e-7, atol=0)
+    assert unsure.mean() < 0.1 and (ref > 0).mean() > 0.3
+    print(f"filled {(ref > 0).mean():.3f}, unsure {unsure.mean():.4f}")
+
+
+SENSORS = {
+    "uniform64x1024": lambda: synth.uniform_sensor(64, 1024),
+    "staggered32x500_r0": lambda: synth.staggered_sensor(32, 500, r0=0.02),
+}
+
+
+@pytest.mark.parametrize("name", list(SENSORS))
+def test_deskew_matches_oracle(rir, name):
+    """A batch of three scans with different twists (pure yaw, forward motion
+    with yaw, a general screw) and the zero twist."""
+    sm = SENSORS[name]()
+    sen = rir.Sensor.from_model(sm)
+    imgs = np.stack([synth.gen_pair(synth.CONFIGS["pair64"], 60 + k, sensor=sm).dst for k in range(4)])
+    xis = np.array([[0, 0, np.deg2rad(5.0), 0, 0, 0],
+                    [0, 0, np.deg2rad(2.0), 1.5, 0, 0],
+                    [0.02, -0.03, 0.2, 0.8, -0.6, 0.1],
+                    [0, 0, 0, 0, 0, 0]])
+    out = rir.deskew(sen, to_dev(imgs), xis).cpu().numpy()
+    for k in range(4):
+        check(sm, imgs[k], xis[k], out[k])
+    # zero motion gives the input back (returns inside the field of view)
+    np.testing.assert_allclose(out[3][imgs[3] > 0], imgs[3][imgs[3] > 0], rtol=1.2e-7)
+
+
+def test_deskew_full_size(rir):
+    """One 128 x 2048 outdoor scan, 1.5 m forward and 3 degrees of yaw per sweep."""
+    cfg = synth.CONFIGS["odometry128x2048"]
+    seq = synth.gen_sequence(cfg, 0, n_scans=1)
+    sm = seq["sensor"]
+    sen = rir.Sensor.from_model(sm)
+    img = seq["scans"][0]
+    xi = np.array([0, 0, np.deg2rad(3.0), 1.5, 0, 0])
+    out = rir.deskew(sen, to_dev(img), xi[None]).cpu().numpy()
+    check(sm, img, xi, out)
+
+
+def test_deskew_edge_cases(rir):
+    """No scans is a no-op; a scan without returns gives an empty image; an
+    output overlapping the input and a non-finite twist are errors."""
+    import ctypes
+    import torch
+    sm = synth.uniform_sensor(16, 256)
+    sen = rir.Sensor.from_model(sm)
+    empty = torch.zeros((0, 16, 256), dtype=torch.float32, device="cuda:0")
+    assert rir.deskew(sen, empty, np.zeros((0, 6))).numel() == 0
+    dead = np.zeros((16, 256), np.float32)
+    dead[::3] = np.nan
+    out = rir.deskew(sen, to_dev(dead), np.array([[0, 0, 0.1, 1.0, 0, 0]]))
+    assert float(out.abs().sum()) == 0.0
+    with pytest.raises(rir.RirError):
+        rir.deskew(sen, to_dev(dead), np.array([[0, 0, np.nan, 0, 0, 0]]))
+    buf = to_dev(dead)
+    tw = np.zeros(6)
+    st = rir.lib().rir_deskew(sen.handle, 1, buf.data_ptr(), tw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              buf.data_ptr(), None)
+    assert st == rir.RIR_E_INVALID
