@@ -32,6 +32,11 @@ ROT_TOL, TRANS_TOL = 1e-4, 1e-3
 # kernel sources are the ones the counters were taken with (the bytes do not
 # depend on the launch tuning beyond the 144 B tile records).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_icp_step_fine_odometry128x2048.json")
+SDF_COUNTS_FILE = os.path.join(ROOT, "profiles", "k_sdf_fuse_odometry100x128x2048.json")
+SDF_SOURCES = ["sdf.hip", "rir_ops.h", "rir_device.h", "rir_internal.h"]
+# VALU issue rate: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 FP32 instruction per
+# SIMD every 4 cycles (16 lanes) -> 256 * 4 * 2.4e9 / 4 wave-instructions/s
+VALU_PEAK_WAVE_INSTR = 256 * 4 * 2.4e9 / 4
 KERNEL_SOURCES = ["kernels.hip", "rir_device.h", "rir_internal.h", "rir_mlp_device.h"]
 
 
@@ -42,6 +47,21 @@ def sources_digest():
         with open(os.path.join(ROOT, "paper_2112_02779_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def sdf_counts():
+    """Counter figures of the SDF fusion kernel from the committed summary, or
+    None when they were taken on other kernel sources."""
+    if not os.path.exists(SDF_COUNTS_FILE):
+        return None
+    import hashlib
+    h = hashlib.sha256()
+    for f in SDF_SOURCES:
+        with open(os.path.join(ROOT, "paper_2112_02779_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    with open(SDF_COUNTS_FILE) as fh:
+        d = json.load(fh)
+    return d if d.get("sources_sha256") == h.hexdigest() else None
 
 
 def counted_traffic():
@@ -402,6 +422,16 @@ def sdf_fusion(rir, seq, oracle_sample, repeats=5):
            "algorithmic_bytes": bytes_alg, "hbm_gbps": round(bytes_alg / (ms * 1e-3) / 1e9, 1),
            "hbm_frac": round(bytes_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "paper_context": "40 Hz at 0.2 m voxels, 30 m clip on KITTI (hash grid, RTX 3060)"}
+    cnt = sdf_counts()
+    if cnt is not None:
+        # ALU roofline: counted VALU wave-instructions per evaluation x
+        # evaluations per second, against the issue rate
+        wi = evals * cnt["valu_per_eval"] / 64.0 / (ms * 1e-3)
+        res["roofline"] = {"bound": "alu", "achieved": round(wi / 1e12, 4), "peak": round(VALU_PEAK_WAVE_INSTR / 1e12, 4),
+                           "unit": "T wave-instructions/s", "frac": round(wi / VALU_PEAK_WAVE_INSTR, 4),
+                           "traffic": cnt["hbm_bytes_per_sequence"], "valu_per_eval": cnt["valu_per_eval"]}
+    else:
+        res["roofline"] = None
     flat = vol.to_grid(vox).reshape(-1, 2)
     w_all = flat[:, 1]
     res["observed_voxels"] = int((w_all > 0).sum())

@@ -2,9 +2,9 @@
 // grid of 16^3-voxel blocks on gfx950.
 //
 // One workgroup of 256 threads owns one block: thread (x, y) walks the 16
-// voxels (x, y, 0..15) of its column, reading each voxel's state once and
-// writing it once per launch whatever the number of scans fused into it (up
-// to kSdfFrames).  Per scan and voxel: the sensor-frame position R x + t
+// voxels (x, y, 0..15) of its column a few at a time, reading each voxel's
+// state once and writing it once per launch whatever the number of scans
+// fused into it (up to kSdfFrames).  Per scan and voxel: the sensor-frame position R x + t
 // (three FMAs from per-block constants built in FP64), the projection of
 // Eq. (3)-(4) at the finest level, one gather of the scan's range, the signed
 // distance of Eq. (9) and the running mean of Eq. (10).  A block whose every
@@ -21,6 +21,8 @@ namespace {
 // the sensor-frame position tb of the block's voxel (0, 0, 0), as 12 floats
 // c0x c0y c0z c1x | c1y c1z c2x c2y | c2z tbx tby tbz (three 16-byte reads).
 constexpr int kFrameWords = 16;
+// Voxels of a column each thread processes together.
+constexpr int kVox = 4;
 
 }  // namespace
 
@@ -89,40 +91,53 @@ __global__ __launch_bounds__(256) void k_sdf_fuse(const SdfArgs a)
     const float x = (float)(tid & (kSdfEdge - 1)), y = (float)(tid >> 4);
 
     float2 *vb = reinterpret_cast<float2 *>(a.vox) + (size_t)b * (kSdfEdge * kSdfEdge * kSdfEdge) + tid;
-    // Voxel-outer order: each thread walks its column one voxel at a time and
-    // fuses every scan into it, so only one voxel's state is live (few
-    // registers, many waves in flight to cover the gathers)
-#pragma unroll 2
-    for (int z = 0; z < kSdfEdge; ++z) {
-        const float2 st = vb[z * kSdfEdge * kSdfEdge];
-        float sd = st.x, wt = st.y;
-        bool chg = false;
-        const float zf = (float)z;
+    // Voxel-outer order: each thread walks its column kVox voxels at a time
+    // (z, z + 16 / kVox, ...) and fuses every scan into them, so few voxel
+    // states are live (few registers, many waves in flight) while the kVox
+    // independent projection chains overlap their gathers.
+    constexpr int kStep = kSdfEdge / kVox;
+    for (int z0 = 0; z0 < kStep; ++z0) {
+        float sd[kVox], wt[kVox];
+        bool chg[kVox];
+#pragma unroll
+        for (int k = 0; k < kVox; ++k) {
+            const float2 st = vb[(z0 + k * kStep) * kSdfEdge * kSdfEdge];
+            sd[k] = st.x;
+            wt[k] = st.y;
+            chg[k] = false;
+        }
         for (uint32_t m = mask; m != 0; m &= m - 1) {
             const int f = __builtin_ctz(m);
             const float4 *fr = reinterpret_cast<const float4 *>(s_fr[f]);
             const float4 q0 = fr[0], q1 = fr[1], q2 = fr[2];
-            // tb + x c0 + y c1 + z c2
-            const float xs = fmaf(zf, q1.z, fmaf(y, q0.w, fmaf(x, q0.x, q2.y)));
-            const float ys = fmaf(zf, q1.w, fmaf(y, q1.x, fmaf(x, q0.y, q2.z)));
-            const float zs = fmaf(zf, q2.x, fmaf(y, q1.y, fmaf(x, q0.z, q2.w)));
-            int u, v;
-            float r;
-            const bool ok = project<float, R0, POW2>(V, xs, ys, zs, u, v, r);
-            // u, v are in range even when ok is false: the gather is unconditional
-            const float om =
-                bld1<float>(img, (((uint32_t)f * (uint32_t)H + (uint32_t)v) * (uint32_t)W + (uint32_t)u) * 4u);
-            float d = om - r;
-            const bool use = ok && range_ok(om) && om <= a.clip && d >= -a.trunc;
-            d = fminf(d, a.trunc);
-            const float wn = wt + 1.0f;
-            const float sn = fmaf(d - sd, d_rcp(wn), sd);
-            sd = use ? sn : sd;
-            wt = use ? wn : wt;
-            chg = chg || use;
+            // tb + x c0 + y c1, then + z c2 per voxel
+            const float px = fmaf(y, q0.w, fmaf(x, q0.x, q2.y));
+            const float py = fmaf(y, q1.x, fmaf(x, q0.y, q2.z));
+            const float pz = fmaf(y, q1.y, fmaf(x, q0.z, q2.w));
+            const uint32_t fbase = (uint32_t)f * (uint32_t)H;
+#pragma unroll
+            for (int k = 0; k < kVox; ++k) {
+                const float zf = (float)(z0 + k * kStep);
+                const float xs = fmaf(zf, q1.z, px), ys = fmaf(zf, q1.w, py), zs = fmaf(zf, q2.x, pz);
+                int u, v;
+                float r;
+                const bool ok = project<float, R0, POW2>(V, xs, ys, zs, u, v, r);
+                // u, v are in range even when ok is false: the gather is unconditional
+                const float om = bld1<float>(img, ((fbase + (uint32_t)v) * (uint32_t)W + (uint32_t)u) * 4u);
+                float d = om - r;
+                const bool use = ok && range_ok(om) && om <= a.clip && d >= -a.trunc;
+                d = fminf(d, a.trunc);
+                const float wn = wt[k] + 1.0f;
+                const float sn = fmaf(d - sd[k], d_rcp(wn), sd[k]);
+                sd[k] = use ? sn : sd[k];
+                wt[k] = use ? wn : wt[k];
+                chg[k] = chg[k] || use;
+            }
         }
-        if (chg)
-            vb[z * kSdfEdge * kSdfEdge] = make_float2(sd, wt);
+#pragma unroll
+        for (int k = 0; k < kVox; ++k)
+            if (chg[k])
+                vb[(z0 + k * kStep) * kSdfEdge * kSdfEdge] = make_float2(sd[k], wt[k]);
     }
 }
 
