@@ -50,6 +50,11 @@ def _load():
             ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, dp,
             dp, ctypes.POINTER(ctypes.c_int32)]
         lib.synth_raycast.restype = None
+        lib.synth_raycast_posed.argtypes = [
+            ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double, dp, ctypes.c_int,
+            ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, dp,
+            dp, ctypes.POINTER(ctypes.c_int32)]
+        lib.synth_raycast_posed.restype = None
         _lib = lib
     return _lib
 
@@ -248,6 +253,34 @@ def raycast(sensor: Sensor, scene: Scene, T_world_sensor: np.ndarray):
                       len(scene.boxes), _dptr(bx) if bx.size else None,
                       len(scene.cyls), _dptr(cy) if cy.size else None,
                       _dptr(rng_out), hit.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return rng_out, hit
+
+
+def raycast_moving(sensor: Sensor, scene: Scene, T_mid: np.ndarray, xi):
+    """Exact ranges [H, W] of a sensor that moves during its sweep: column u is
+    taken at sweep time s_u = (u + 1/2)/W - 1/2 from the pose T_mid expm(s_u
+    [xi]) (xi = (omega, tau) per sweep, the matrix exponential by scipy)."""
+    import scipy.linalg
+    lib = _load()
+    H, W = sensor.H, sensor.W
+    w, t = np.asarray(xi[:3], dtype=np.float64), np.asarray(xi[3:], dtype=np.float64)
+    M = np.zeros((4, 4))
+    M[:3, :3] = [[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]]
+    M[:3, 3] = t
+    Ts = np.stack([T_mid @ scipy.linalg.expm(((u + 0.5) / W - 0.5) * M) for u in range(W)])
+    Ts = np.ascontiguousarray(Ts, dtype=np.float64)
+    phi = np.ascontiguousarray(sensor.phi, dtype=np.float64)
+    th = np.ascontiguousarray(sensor.theta, dtype=np.float64)
+    pl = np.ascontiguousarray(scene.planes, dtype=np.float64).reshape(-1)
+    bx = np.ascontiguousarray(scene.boxes, dtype=np.float64).reshape(-1)
+    cy = np.ascontiguousarray(scene.cyls, dtype=np.float64).reshape(-1)
+    rng_out = np.zeros((H, W), dtype=np.float64)
+    hit = np.zeros((H, W), dtype=np.int32)
+    lib.synth_raycast_posed(H, W, _dptr(phi), _dptr(th), float(sensor.r0), _dptr(Ts), 1,
+                            len(scene.planes), _dptr(pl) if pl.size else None,
+                            len(scene.boxes), _dptr(bx) if bx.size else None,
+                            len(scene.cyls), _dptr(cy) if cy.size else None,
+                            _dptr(rng_out), hit.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return rng_out, hit
 
 

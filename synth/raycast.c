@@ -97,13 +97,15 @@ static double hit_cyl(const double o[3], const double d[3], const double *c)
  * boxes:  n_box x 6 (xmin, ymin, zmin, xmax, ymax, zmax)
  * cyls:   n_cyl x 5 (cx, cy, radius, zmin, zmax)
  * range_out[H*W]: distance along the ray to the nearest hit, 0 if none.
+ * synth_raycast_posed with per_column = 1 takes W poses (T[16 u ...]), one per
+ * column: a sensor that moves while it sweeps.
  * hit_out[H*W]: index of the primitive hit (planes first, then boxes, then
  * cylinders), -1 if none.
  */
-void synth_raycast(int H, int W, const double *phi, const double *theta, double r0,
-                   const double *T, int n_pl, const double *planes, int n_box,
-                   const double *boxes, int n_cyl, const double *cyls,
-                   double *range_out, int32_t *hit_out)
+void synth_raycast_posed(int H, int W, const double *phi, const double *theta, double r0,
+                         const double *T, int per_column, int n_pl, const double *planes, int n_box,
+                         const double *boxes, int n_cyl, const double *cyls,
+                         double *range_out, int32_t *hit_out)
 {
     const double two_pi = 6.283185307179586476925286766559;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -111,6 +113,7 @@ void synth_raycast(int H, int W, const double *phi, const double *theta, double 
         double cph = cos(phi[v]), sph = sin(phi[v]);
         double th = theta ? theta[v] : 0.0;
         for (int u = 0; u < W; ++u) {
+            const double *Tu = per_column ? T + 16 * (size_t)u : T;
             double a = two_pi * (double)u / (double)W;
             /* receiver on the head, and the beam direction: head rotation
              * a + theta_v about z applied to the elevation vector */
@@ -119,8 +122,8 @@ void synth_raycast(int H, int W, const double *phi, const double *theta, double 
             double ds[3] = {cph * cos(az), cph * sin(az), sph};
             double o[3], d[3];
             for (int i = 0; i < 3; ++i) {
-                o[i] = T[4 * i + 0] * os[0] + T[4 * i + 1] * os[1] + T[4 * i + 2] * os[2] + T[4 * i + 3];
-                d[i] = T[4 * i + 0] * ds[0] + T[4 * i + 1] * ds[1] + T[4 * i + 2] * ds[2];
+                o[i] = Tu[4 * i + 0] * os[0] + Tu[4 * i + 1] * os[1] + Tu[4 * i + 2] * os[2] + Tu[4 * i + 3];
+                d[i] = Tu[4 * i + 0] * ds[0] + Tu[4 * i + 1] * ds[1] + Tu[4 * i + 2] * ds[2];
             }
             double best = NO_HIT;
             int32_t id = -1;
@@ -141,4 +144,12 @@ void synth_raycast(int H, int W, const double *phi, const double *theta, double 
             hit_out[i] = best < NO_HIT ? id : -1;
         }
     }
+}
+
+void synth_raycast(int H, int W, const double *phi, const double *theta, double r0,
+                   const double *T, int n_pl, const double *planes, int n_box,
+                   const double *boxes, int n_cyl, const double *cyls,
+                   double *range_out, int32_t *hit_out)
+{
+    synth_raycast_posed(H, W, phi, theta, r0, T, 0, n_pl, planes, n_box, boxes, n_cyl, cyls, range_out, hit_out);
 }
