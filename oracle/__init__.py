@@ -106,6 +106,9 @@ def lib():
         L.orc_normals_pca.argtypes = [S, _F, ctypes.c_int, ctypes.c_double, _D, _U8, _D]
         L.orc_eigen3.argtypes = [_D, _D, _D]
         L.orc_deskew.argtypes = [S, _F, _D, _D, _I32, _I32, _D, _D, _D]
+        L.orc_sdf_extract.argtypes = [_D, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D,
+                                      ctypes.c_double, ctypes.c_double, _D, ctypes.c_int64]
+        L.orc_sdf_extract.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -259,6 +262,22 @@ def deskew(sensor, rng_img: np.ndarray, xi) -> dict:
     lib().orc_deskew(ctypes.byref(h.s), _p(r, _F), _p(x, _D), _p(out, _D), _p(tu, _I32), _p(tv, _I32), _p(rr, _D),
                      _p(uh, _D), _p(ph, _D))
     return {"out": out, "u": tu, "v": tv, "r": rr, "uhat": uh, "phi": ph}
+
+
+def sdf_extract(origin, voxel: float, sdf: np.ndarray, weight: np.ndarray, min_weight: float = 1.0,
+                max_jump: float = np.inf) -> np.ndarray:
+    """Zero crossings of an SDF grid sdf/weight [nz, ny, nx] along grid edges:
+    points [n, 3] (see orc_sdf_extract)."""
+    s = np.ascontiguousarray(sdf, dtype=np.float64)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    nz, ny, nx = s.shape
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    n = lib().orc_sdf_extract(_p(o, _D), float(voxel), nx, ny, nz, _p(s, _D), _p(w, _D), float(min_weight),
+                              float(max_jump), None, 0)
+    pts = np.zeros((max(n, 1), 3))
+    lib().orc_sdf_extract(_p(o, _D), float(voxel), nx, ny, nz, _p(s, _D), _p(w, _D), float(min_weight),
+                          float(max_jump), _p(pts, _D), n)
+    return pts[:n]
 
 
 def bf16(x: float) -> float:

@@ -1215,3 +1215,48 @@ void orc_deskew(const orc_sensor *s, const float *range, const double xi[6], dou
         }
     }
 }
+
+/*
+ * Surface points of an SDF volume: the zero crossings of the fused SDF along
+ * the grid edges (the level set that Sec. 4.2 extracts with marching cubes;
+ * this returns its vertices, without the triangles).  Grid of nx * ny * nz
+ * voxels, index (k ny + j) nx + i, voxel (i, j, k) at origin + voxel (i, j, k).
+ * For every pair of voxels a, b adjacent along x, y or z, both with weight >=
+ * min_weight, whose SDF values lie on different sides of zero (s_a > 0 and
+ * s_b <= 0, or the reverse) and differ by at most max_jump (a larger step is
+ * the edge of the truncation band behind an occluder, not a surface), the
+ * point a + t (b - a), t = s_a / (s_a - s_b), is emitted.  Order: voxel a in
+ * index order, then the x, y, z edge.  Writes at most max_pts points (3
+ * doubles each) and returns how many crossings there are.
+ */
+int64_t orc_sdf_extract(const double origin[3], double voxel, int nx, int ny, int nz, const double *sdf,
+                        const double *weight, double min_weight, double max_jump, double *pts, int64_t max_pts)
+{
+    int64_t n = 0;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t a = ((size_t)k * ny + j) * nx + i;
+                if (!(weight[a] >= min_weight))
+                    continue;
+                for (int ax = 0; ax < 3; ++ax) {
+                    int di = ax == 0, dj = ax == 1, dk = ax == 2;
+                    if (i + di >= nx || j + dj >= ny || k + dk >= nz)
+                        continue;
+                    size_t b = ((size_t)(k + dk) * ny + (j + dj)) * nx + (i + di);
+                    if (!(weight[b] >= min_weight))
+                        continue;
+                    double sa = sdf[a], sb = sdf[b];
+                    if ((sa > 0.0) == (sb > 0.0) || fabs(sa - sb) > max_jump)
+                        continue;
+                    double t = sa / (sa - sb);
+                    if (n < max_pts) {
+                        pts[3 * n] = origin[0] + voxel * ((double)i + t * di);
+                        pts[3 * n + 1] = origin[1] + voxel * ((double)j + t * dj);
+                        pts[3 * n + 2] = origin[2] + voxel * ((double)k + t * dk);
+                    }
+                    ++n;
+                }
+            }
+    return n;
+}

@@ -182,3 +182,60 @@ def test_incremental_update_equals_least_squares_mean(orc):
     np.testing.assert_array_equal(wb, w)
     np.testing.assert_allclose(sb, s, rtol=0, atol=1e-12)
     assert (w > 0).mean() > 0.3 and (w == len(ranges)).any()
+
+
+def _grid(shape, origin, voxel):
+    nz, ny, nx = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return np.asarray(origin) + voxel * np.stack([i, j, k], -1).astype(np.float64)
+
+
+def test_extract_plane_is_exact(orc):
+    """A linear SDF (signed distance to the plane z = z0) crosses zero once
+    per grid column, and linear interpolation puts every point on the plane."""
+    import oracle
+    origin, vx, shape = (-1.0, 2.0, -0.55), 0.1, (12, 9, 11)
+    X = _grid(shape, origin, vx)
+    z0 = 0.013
+    sdf = X[..., 2] - z0
+    pts = oracle.sdf_extract(origin, vx, sdf, np.ones(shape))
+    assert len(pts) == shape[1] * shape[2]
+    np.testing.assert_allclose(pts[:, 2], z0, atol=1e-12)
+    # a tilted plane n . x = c: every point on it, crossings along all three axes
+    n = np.array([0.3, -0.5, 0.81])
+    n /= np.linalg.norm(n)
+    cval = float(X.reshape(-1, 3).mean(0) @ n) + 0.01234
+    sdf = X @ n - cval
+    pts = oracle.sdf_extract(origin, vx, sdf, np.ones(shape))
+    np.testing.assert_allclose(pts @ n, cval, atol=1e-12)
+    assert len(pts) > shape[1] * shape[2]
+
+
+def test_extract_sphere_weights_and_jumps(orc):
+    """Sphere |x - c| - R: points within voxel^2 / R of the sphere; voxels of
+    weight below min_weight and steps larger than max_jump give no point."""
+    import oracle
+    origin, vx, shape = (-1.0, -1.0, -1.0), 0.05, (40, 40, 40)
+    X = _grid(shape, origin, vx)
+    c, R = np.array([0.02, -0.03, 0.01]), 0.6
+    sdf = np.linalg.norm(X - c, axis=-1) - R
+    w = np.ones(shape)
+    pts = oracle.sdf_extract(origin, vx, sdf, w)
+    d = np.linalg.norm(pts - c, axis=1) - R
+    assert np.max(np.abs(d)) <= vx * vx / R
+    # edge crossings per unit area average (|n_x| + |n_y| + |n_z|) / voxel^2 = 1.5 / voxel^2
+    area = 4 * np.pi * R * R / (vx * vx)
+    assert 1.4 * area < len(pts) < 1.6 * area
+    # half the volume unobserved: no point where either end has weight 0
+    w2 = w.copy()
+    w2[:, :, : shape[2] // 2] = 0
+    p2 = oracle.sdf_extract(origin, vx, sdf, w2)
+    assert len(p2) < len(pts) and np.all(p2[:, 0] >= origin[0] + vx * (shape[2] // 2) - 1e-12)
+    # clamp to a truncation band of 0.1 with a +-0.1 step planted behind it
+    s3 = np.clip(sdf, -0.1, 0.1)
+    s3[:, :, -1] = np.where(s3[:, :, -2] > 0, -0.1, 0.1)
+    p3 = oracle.sdf_extract(origin, vx, s3, w, max_jump=0.15)
+    d3 = np.linalg.norm(p3 - c, axis=1) - R
+    assert np.max(np.abs(d3)) <= vx * vx / R
+    p4 = oracle.sdf_extract(origin, vx, s3, w)
+    assert len(p4) > len(p3)
