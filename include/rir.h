@@ -346,6 +346,24 @@ typedef struct {
 rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volume_desc *vol, float *voxels, int32_t n_frames,
                              const float *ranges, const double *poses, double trunc, double r_clip, void *stream);
 
+/* Surface points of a fused volume: the zero crossings of the SDF along the
+ * grid edges (the vertices of the level set that Sec. 4.2 meshes with
+ * marching cubes).  For voxels a, b adjacent along x, y or z with both
+ * weights >= min_weight, SDF values on different sides of zero (s_a > 0 >= s_b
+ * or the reverse) and |s_a - s_b| <= max_jump (a larger step is the edge of a
+ * truncation band behind an occluder; INFINITY keeps all), the point
+ * a + t (b - a), t = s_a / (s_a - s_b), in world coordinates (formed in FP64,
+ * stored as FP32).
+ *   voxels      device volume (rir_sdf_integrate layout), read only.
+ *   points      device max_points*3 FP32 (x, y, z), order not defined.
+ *   count       device uint64: number of crossings found (may exceed
+ *               max_points; only the first max_points are stored).
+ * Runs on the current HIP device, asynchronously on `stream`.  Errors:
+ * RIR_E_INVALID (null, max_points < 0, voxel <= 0, non-finite origin or
+ * min_weight, max_jump < 0 or NaN), RIR_E_SHAPE, RIR_E_HIP. */
+rir_status rir_sdf_extract(const rir_volume_desc *vol, const float *voxels, double min_weight, double max_jump,
+                           float *points, int64_t max_points, uint64_t *count, void *stream);
+
 /* ---------------------------------------------------------------- learned weight */
 
 /* Per-pixel robust-weight network 14-64-64-1 (ReLU, ReLU, sigmoid) replacing

@@ -31,6 +31,7 @@ EXPORTS = [
     "rir_normals", "rir_icp_batch", "rir_debug_associate", "rir_autotune", "rir_mlp_create", "rir_mlp_destroy",
     "rir_mlp_get_params", "rir_mlp_set_params", "rir_mlp_forward", "rir_mlp_train_step", "rir_last_error",
     "rir_elevation_table", "rir_sdf_integrate", "rir_normals_pca", "rir_deskew",
+    "rir_sdf_extract",
 ]
 
 
@@ -125,6 +126,7 @@ def lib():
         "rir_mlp_set_params": [vp, ctypes.POINTER(ctypes.c_uint16), ctypes.POINTER(f32)],
         "rir_mlp_forward": [vp, vp, i64, vp, vp],
         "rir_mlp_train_step": [vp, vp, vp, i64, f32, vp, vp, vp],
+        "rir_sdf_extract": [ctypes.POINTER(VolumeDesc), vp, f64, f64, vp, i64, vp, vp],
         "rir_deskew": [vp, i32, vp, ctypes.POINTER(f64), vp, vp],
         "rir_normals_pca": [vp, i32, vp, i32, f64, vp, vp, vp],
         "rir_sdf_integrate": [vp, ctypes.POINTER(VolumeDesc), vp, i32, vp, ctypes.POINTER(f64), f64, f64, vp],
@@ -367,6 +369,23 @@ def normals_pca(sensor: Sensor, rng, half: int = 1, edge_rel=0.1, stream=None):
     _check(lib().rir_normals_pca(sensor.handle, n_img, _ptr(rng), int(half), float(edge_rel), _ptr(n), _ptr(valid),
                                  _stream(stream)))
     return n, valid
+
+
+def sdf_extract(vol: Volume, voxels, min_weight=1.0, max_jump=float("inf"), max_points=None, stream=None):
+    """Zero-crossing surface points of a fused volume: (points [n, 3] FP32
+    device tensor, total crossings).  Synchronises the stream to size the
+    result (max_points defaults to three per voxel, never exceeded)."""
+    import torch
+    _require(voxels, torch.float32, "voxels", 2 * 4096 * vol.nb[0] * vol.nb[1] * vol.nb[2])
+    cap = 3 * 4096 * vol.nb[0] * vol.nb[1] * vol.nb[2] if max_points is None else int(max_points)
+    pts = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=voxels.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=voxels.device)
+    s = torch.cuda.current_stream() if stream is None else stream
+    _check(lib().rir_sdf_extract(ctypes.byref(vol.desc), _ptr(voxels), float(min_weight), float(max_jump), _ptr(pts),
+                                 cap, _ptr(cnt), _stream(s)))
+    s.synchronize()
+    n = int(cnt.item())
+    return pts[:min(n, cap)], n
 
 
 def deskew(sensor: Sensor, rng, twists, stream=None):

@@ -18,6 +18,7 @@
 #include "rir.h"
 #include "rir_internal.h"
 #include "rir_ops.h"
+#include "sdf_extract.h"
 
 using namespace rir;
 
@@ -1417,6 +1418,44 @@ extern "C" rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volu
         }
         HIP_TRY(launch_sdf_fuse(a, r0, pow2, st));
     }
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_sdf_extract(const rir_volume_desc *vol, const float *voxels, double min_weight,
+                                      double max_jump, float *points, int64_t max_points, uint64_t *count,
+                                      void *stream)
+{
+    if (!vol || !voxels || !count || (max_points > 0 && !points))
+        return fail(RIR_E_INVALID, "rir_sdf_extract: null argument");
+    if (max_points < 0)
+        return fail(RIR_E_INVALID, "rir_sdf_extract: max_points < 0");
+    if (vol->nbx < 1 || vol->nby < 1 || vol->nbz < 1)
+        return fail(RIR_E_SHAPE, "rir_sdf_extract: block counts must be >= 1");
+    if ((int64_t)vol->nbx * vol->nby * vol->nbz > (int64_t)std::numeric_limits<int32_t>::max())
+        return fail(RIR_E_SHAPE, "rir_sdf_extract: more than 2^31 - 1 blocks");
+    if (!(vol->voxel > 0.0) || !std::isfinite(vol->voxel))
+        return fail(RIR_E_INVALID, "rir_sdf_extract: voxel size must be finite and > 0");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(vol->origin[i]))
+            return fail(RIR_E_INVALID, "rir_sdf_extract: origin must be finite");
+    if (!std::isfinite(min_weight) || std::isnan(max_jump) || !(max_jump >= 0.0))
+        return fail(RIR_E_INVALID, "rir_sdf_extract: min_weight must be finite and max_jump >= 0");
+    SdfExtractArgs a{};
+    a.vox = voxels;
+    a.nbx = vol->nbx;
+    a.nby = vol->nby;
+    a.nbz = vol->nbz;
+    a.min_weight = (float)min_weight;
+    if ((double)a.min_weight < min_weight)
+        a.min_weight = std::nextafter(a.min_weight, std::numeric_limits<float>::infinity());
+    a.max_jump = max_jump;
+    for (int i = 0; i < 3; ++i)
+        a.origin[i] = vol->origin[i];
+    a.voxel = vol->voxel;
+    a.pts = points;
+    a.max_pts = max_points;
+    a.count = reinterpret_cast<unsigned long long *>(count);
+    HIP_TRY(launch_sdf_extract(a, static_cast<hipStream_t>(stream)));
     return RIR_OK;
 }
 

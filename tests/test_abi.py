@@ -76,6 +76,7 @@ def test_null_handles_are_rejected(L):
     assert L.rir_ctx_level_times(None, None, 0) == rir.RIR_E_INVALID
     assert L.rir_normals_pca(None, 1, None, 1, 0.1, None, None, None) == rir.RIR_E_INVALID
     assert L.rir_deskew(None, 1, None, None, None, None) == rir.RIR_E_INVALID
+    assert L.rir_sdf_extract(None, None, 1.0, 1.0, None, 0, None, None) == rir.RIR_E_INVALID
     vol = rir.Volume((1, 1, 1), (0.0, 0.0, 0.0), 0.1)
     assert L.rir_sdf_integrate(None, ctypes.byref(vol.desc), None, 0, None, None, 0.3, 30.0,
                                None) == rir.RIR_E_INVALID

@@ -186,3 +186,46 @@ def test_full_size_sampled(rir):
     s_ref, w_ref = oracle.sdf_fuse(sm, ranges, poses, pts, trunc, r_clip)
     amb = sdf_ambiguous(sm, ranges, poses, pts, trunc, r_clip)
     compare(got[:, 0], got[:, 1], s_ref, w_ref, amb, 5e-7 * (r_clip + trunc) + 1e-6, len(ranges))
+
+
+def to_blocks(vol, grid):
+    """[nz, ny, nx, 2] grid -> the block layout of Volume.alloc (layout
+    marshalling for test inputs)."""
+    nbx, nby, nbz = vol.nb
+    E = vol.EDGE
+    g = grid.reshape(nbz, E, nby, E, nbx, E, 2)
+    return np.ascontiguousarray(g.transpose(0, 2, 4, 1, 3, 5, 6))
+
+
+def test_extract_matches_oracle(rir):
+    """Zero crossings of a synthetic volume (a sphere and a tilted plane, a
+    truncation band with planted +-0.3 steps, unobserved and light voxels)
+    computed by the GPU and by the oracle from the same FP32 values: same
+    count, every point matched within FP32 rounding of its coordinates."""
+    from scipy.spatial import cKDTree
+    vol = rir.Volume((3, 2, 2), (-1.2, -0.7, -0.9), 0.05)
+    pts = grid_points(vol)
+    c, R = np.array([0.0, 0.1, -0.1]), 0.5
+    n = np.array([0.2, 0.1, 1.0]) / np.linalg.norm([0.2, 0.1, 1.0])
+    s = np.minimum(np.linalg.norm(pts - c, axis=1) - R, pts @ n + 0.4)
+    s = np.clip(s, -0.3, 0.3)
+    rng = np.random.default_rng(12)
+    step = rng.random(len(s)) < 0.01
+    s[step] = -np.sign(s[step]) * 0.3
+    w = np.where(rng.random(len(s)) < 0.05, 0.5, 3.0)
+    w[pts[:, 0] > 0.9] = 0.0
+    nx, ny, nz = vol.shape
+    grid = np.stack([s, w], -1).astype(np.float32).reshape(nz, ny, nx, 2)
+    vox = to_dev(to_blocks(vol, grid))
+    for max_jump in (0.45, np.inf):
+        got, n_gpu = rir.sdf_extract(vol, vox, min_weight=1.0, max_jump=max_jump)
+        got = got.cpu().numpy().astype(np.float64)
+        ref = oracle.sdf_extract(vol.origin, vol.voxel, grid[..., 0].astype(np.float64),
+                                 grid[..., 1].astype(np.float64), 1.0, max_jump)
+        assert n_gpu == len(ref) == len(got) and n_gpu > 1000
+        d1, _ = cKDTree(ref).query(got)
+        d2, _ = cKDTree(got).query(ref)
+        assert d1.max() < 2e-6 and d2.max() < 2e-6, (d1.max(), d2.max())
+    # a cap below the crossing count keeps the count and stores only the cap
+    got, n_all = rir.sdf_extract(vol, vox, min_weight=1.0, max_points=100)
+    assert got.shape[0] == 100 and n_all > 100
