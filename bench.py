@@ -405,13 +405,23 @@ def reconstruction_quality(rir, vol, vox, seq, r_clip, radius, n_sample=200000):
     import torch
     from scipy.spatial import cKDTree
     import synth
+    import ctypes
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
     pts, n = rir.sdf_extract(vol, vox, min_weight=1.0, max_jump=0.45, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    # time the extraction launch alone (the binding's counting pass and host
+    # synchronisation are outside the events)
+    cnt = torch.zeros(1, dtype=torch.int64, device=vox.device)
+    ts = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st = rir.lib().rir_sdf_extract(ctypes.byref(vol.desc), vox.data_ptr(), 1.0, 0.45, pts.data_ptr(), n,
+                                       cnt.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        assert st == 0 and int(cnt.item()) == n
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
     P = pts.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(3)
     sub = P[rng.choice(len(P), min(n_sample, len(P)), replace=False)] if len(P) else P

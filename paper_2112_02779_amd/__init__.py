@@ -373,18 +373,23 @@ def normals_pca(sensor: Sensor, rng, half: int = 1, edge_rel=0.1, stream=None):
 
 def sdf_extract(vol: Volume, voxels, min_weight=1.0, max_jump=float("inf"), max_points=None, stream=None):
     """Zero-crossing surface points of a fused volume: (points [n, 3] FP32
-    device tensor, total crossings).  Synchronises the stream to size the
-    result (max_points defaults to three per voxel, never exceeded)."""
+    device tensor, total crossings).  Synchronises the stream to read the
+    count; with max_points None a counting pass sizes the result exactly,
+    else at most max_points points are stored."""
     import torch
     _require(voxels, torch.float32, "voxels", 2 * 4096 * vol.nb[0] * vol.nb[1] * vol.nb[2])
-    cap = 3 * 4096 * vol.nb[0] * vol.nb[1] * vol.nb[2] if max_points is None else int(max_points)
-    pts = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=voxels.device)
-    cnt = torch.zeros(1, dtype=torch.int64, device=voxels.device)
     s = torch.cuda.current_stream() if stream is None else stream
-    _check(lib().rir_sdf_extract(ctypes.byref(vol.desc), _ptr(voxels), float(min_weight), float(max_jump), _ptr(pts),
-                                 cap, _ptr(cnt), _stream(s)))
-    s.synchronize()
-    n = int(cnt.item())
+    cnt = torch.zeros(1, dtype=torch.int64, device=voxels.device)
+
+    def run(pts, cap):
+        _check(lib().rir_sdf_extract(ctypes.byref(vol.desc), _ptr(voxels), float(min_weight), float(max_jump),
+                                     _ptr(pts), cap, _ptr(cnt), _stream(s)))
+        s.synchronize()
+        return int(cnt.item())
+
+    cap = run(None, 0) if max_points is None else int(max_points)
+    pts = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=voxels.device)
+    n = run(pts, cap)
     return pts[:min(n, cap)], n
 
 
