@@ -466,7 +466,10 @@ def sdf_fusion(rir, seq, oracle_sample, repeats=5):
     lo = P.min(0) - r_clip - 1.0
     hi = P.max(0) + r_clip + 1.0
     nbx, nby = (int(np.ceil((hi[i] - lo[i]) / (16 * vx))) for i in range(2))
-    vol = rir.Volume((nbx, nby, 6), (lo[0], lo[1], -1.6), vx)
+    # z from -1.55 m: voxel centres straddle the ground plane z = 0 instead of
+    # lying on it (a layer exactly on a surface leaves the sign of its SDF to
+    # the range noise)
+    vol = rir.Volume((nbx, nby, 6), (lo[0], lo[1], -1.55), vx)
     sen = rir.Sensor.from_model(sm)
     dev = torch.device("cuda:0")
     ranges = torch.from_numpy(scans).to(dev)

@@ -168,7 +168,7 @@ def test_full_size_sampled(rir):
     lo = P.min(0) - r_clip - 1.0
     hi = P.max(0) + r_clip + 1.0
     nbx, nby = (int(np.ceil((hi[i] - lo[i]) / (16 * vx))) for i in range(2))
-    vol = rir.Volume((nbx, nby, 6), (lo[0], lo[1], -1.6), vx)
+    vol = rir.Volume((nbx, nby, 6), (lo[0], lo[1], -1.55), vx)
     vox = run_gpu(rir, sm, vol, ranges, poses, trunc, r_clip)
     flat = vol.to_grid(vox).reshape(-1, 2)
     w_all = flat[:, 1]
