@@ -51,8 +51,10 @@ __device__ __forceinline__ void exp_twist(const double xi[6], double R[9], doubl
         t[i] = V[3 * i] * xi[3] + V[3 * i + 1] * xi[4] + V[3 * i + 2] * xi[5];
 }
 
-struct Twist {
-    double xi[6];
+// Twists of up to kDeskewBatch scans, passed as kernel arguments.
+constexpr int kDeskewBatch = 32;
+struct Twists {
+    double xi[kDeskewBatch][6];
 };
 
 }  // namespace
@@ -72,22 +74,24 @@ __global__ void k_inf_to_zero(uint32_t *p, int64_t n)
 
 template <bool R0, bool POW2>
 __global__ __launch_bounds__(256) void k_deskew(const SensorTab<double> *tab, const float *in, uint32_t *out,
-                                                Twist tw)
+                                                int n_images, Twists tw)
 {
     const LevelView<double> V = level_view(tab, 0);
     const int H = V.Hl, W = V.Wl;
     const double *row = V.rowp, *col = cload(&tab->col);
     const double r0 = V.r0;
-    const int n = H * W;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float rf = in[i];
+    const int64_t hw = (int64_t)H * W, n = hw * n_images;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        const float rf = in[g];
         if (!range_ok(rf))
             continue;
+        const int img = (int)(g / hw);
+        const int i = (int)(g - (int64_t)img * hw);
         const int v = i / W, u = i - v * W;
         const double su = ((double)u + 0.5) / (double)W - 0.5;
         double xs[6], R[9], t[3];
         for (int k = 0; k < 6; ++k)
-            xs[k] = su * tw.xi[k];
+            xs[k] = su * tw.xi[img][k];
         exp_twist(xs, R, t);
         const V3<double> p = unproject(row, col, r0, u, v, (double)rf);
         const double x = R[0] * p.x + R[1] * p.y + R[2] * p.z + t[0];
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(256) void k_deskew(const SensorTab<double> *tab, co
         double r2;
         if (!project<double, R0, POW2>(V, x, y, z, u2, v2, r2))
             continue;
-        atomicMin(out + (size_t)v2 * W + u2, __float_as_uint((float)r2));
+        atomicMin(out + (size_t)img * hw + (size_t)v2 * W + u2, __float_as_uint((float)r2));
     }
 }
 
@@ -112,19 +116,21 @@ hipError_t launch_deskew(const SensorTab<double> *tab, int H, int W, bool r0, in
     if (e != hipSuccess)
         return e;
     const bool pow2 = (W & (W - 1)) == 0;
-    const int g = (int)std::min<int64_t>((hw + 255) / 256, 65536);
-    for (int k = 0; k < n_images; ++k) {
-        Twist tw;
-        for (int j = 0; j < 6; ++j)
-            tw.xi[j] = twists[6 * k + j];
-        const float *src = in + hw * k;
-        uint32_t *dst = ob + hw * k;
+    for (int k0 = 0; k0 < n_images; k0 += kDeskewBatch) {
+        const int nb = std::min(kDeskewBatch, n_images - k0);
+        Twists tw;
+        for (int k = 0; k < nb; ++k)
+            for (int j = 0; j < 6; ++j)
+                tw.xi[k][j] = twists[6 * (k0 + k) + j];
+        const float *src = in + hw * k0;
+        uint32_t *dst = ob + hw * k0;
+        const int g = (int)std::min<int64_t>((hw * nb + 255) / 256, 65536);
         if (r0)
-            hipLaunchKernelGGL((k_deskew<true, false>), dim3(g), dim3(256), 0, stream, tab, src, dst, tw);
+            hipLaunchKernelGGL((k_deskew<true, false>), dim3(g), dim3(256), 0, stream, tab, src, dst, nb, tw);
         else if (pow2)
-            hipLaunchKernelGGL((k_deskew<false, true>), dim3(g), dim3(256), 0, stream, tab, src, dst, tw);
+            hipLaunchKernelGGL((k_deskew<false, true>), dim3(g), dim3(256), 0, stream, tab, src, dst, nb, tw);
         else
-            hipLaunchKernelGGL((k_deskew<false, false>), dim3(g), dim3(256), 0, stream, tab, src, dst, tw);
+            hipLaunchKernelGGL((k_deskew<false, false>), dim3(g), dim3(256), 0, stream, tab, src, dst, nb, tw);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;

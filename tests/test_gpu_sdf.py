@@ -153,15 +153,20 @@ def test_edge_cases(rir):
     assert torch.equal(vox, before)
 
 
-def test_full_size_sampled(rir):
+@pytest.mark.parametrize("kind", ["uniform", "staggered_r0"])
+def test_full_size_sampled(rir, kind):
     """The benchmark's fusion workload shape: 128 x 2048 scans of an outdoor
     sequence into a 0.1 m volume spanning the path plus the 30 m clip, 32
     scans (two launches); 30000 voxels sampled (half among the observed ones)
     and checked against the oracle one by one; volume-wide properties: weights
-    are whole numbers no larger than the scan count, |sdf| <= trunc (in FP32)."""
+    are whole numbers no larger than the scan count, |sdf| <= trunc (in FP32).
+    Also with the general sensor (staggered azimuths, receiver offset)."""
     import torch
     cfg = synth.CONFIGS["odometry128x2048"]
-    sm = synth.uniform_sensor(*cfg["shapes"][0])
+    if kind == "uniform":
+        sm = synth.uniform_sensor(*cfg["shapes"][0])
+    else:
+        sm = synth.staggered_sensor(*cfg["shapes"][0], r0=0.015)
     ranges, poses, seq = sequence(sm, 32, seed=0)
     trunc, r_clip, vx = 0.3, 30.0, 0.1
     P = np.array([p[:3, 3] for p in seq["poses"]])
