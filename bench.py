@@ -624,7 +624,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the batch of independent pairs would be split across GPUs "
-              "with no communication (see DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "with no communication; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
