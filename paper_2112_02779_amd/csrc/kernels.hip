@@ -622,7 +622,10 @@ __device__ __forceinline__ void step_segments(const StepArgs &a, const MlpInfer 
                 f1 = sld4(fr, 1);
                 f2 = sld4(fr, 2);
             }
-            const T r = (T)rs[j], c = ca[j], sn = sa[j], rc = r * c, rsn = r * sn;
+            // a pixel without a return (0, negative, NaN, infinite) unprojects
+            // at r = 0: its point is finite, so its exact-zero terms stay zero
+            const bool okr = range_ok(rs[j]);
+            const T r = okr ? (T)rs[j] : (T)0, c = ca[j], sn = sa[j], rc = r * c, rsn = r * sn;
             xx[j] = fma(rc, f0.x, fma(rsn, f0.w, fma(r, f1.z, t0)));
             xy[j] = fma(rc, f0.y, fma(rsn, f1.x, fma(r, f1.w, t1)));
             xz[j] = fma(rc, f0.z, fma(rsn, f1.y, fma(r, f2.x, t2)));
@@ -631,7 +634,6 @@ __device__ __forceinline__ void step_segments(const StepArgs &a, const MlpInfer 
                 xy[j] += c * h1y + sn * h2y;
                 xz[j] += c * h1z + sn * h2z;
             }
-            const bool okr = range_ok(rs[j]);
             proj[j] = project<T, !LEAN, LEAN>(V, xx[j], xy[j], xz[j], ul[j], vl[j], xr[j]) & okr;
         }
         // the gather needs no mask: project() keeps (ul, vl) inside the

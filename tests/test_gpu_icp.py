@@ -305,3 +305,43 @@ def test_plans_never_outlive_their_sensors(rir, ctx):
         P2, _ = rir.icp_batch(fresh, prm, [(sen, src, dst)])
         assert torch.equal(P1, P2)
         del sen
+
+
+def test_nonfinite_and_negative_ranges_count_as_no_return(rir, ctx):
+    """Source and target pixels holding NaN, +-Inf or a negative range are
+    'no return' on both sides (the oracle skips them): the pose and the
+    statistics match the oracle and stay finite, on the tiled levels and on
+    the pair-resident coarsest level alike."""
+    pair = _pair("pair64", 11)
+    rng = np.random.default_rng(11)
+    src, dst = pair.src.copy(), pair.dst.copy()
+    bad = np.array([np.nan, np.inf, -np.inf, -1.0, -0.0], np.float32)
+    for img in (src, dst):
+        flat = img.reshape(-1)
+        hit = rng.choice(flat.size, flat.size // 50, replace=False)
+        flat[hit] = bad[rng.integers(0, bad.size, hit.size)]
+        # every value also on the pixels the coarser levels sample
+        flat[np.arange(0, 8 * 1024, 4 * 1024 + 4)] = np.nan
+        img[::4, ::4][5, 7:12] = bad
+    bent = synth.Pair(pair.sensor, src, dst, pair.gt, 11)
+    Tg, st = _run_gpu(rir, ctx, pair.sensor, [bent], [10, 10, 10], 3)
+    To, so = oracle.icp(pair.sensor, src, dst, oracle.make_params(levels=3, iters=[10, 10, 10]))
+    er, et = rot_trans_error(Tg[0], To)
+    assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (er, et)
+    assert np.all(np.isfinite(st["JtJ"])) and np.all(np.isfinite(st["Jtr"]))
+    for l in range(3):
+        assert st[0, l]["status"] == so[l]["status"] == rir.LEVEL_OK, l
+        assert abs(st[0, l]["n_valid"] - so[l]["n_valid"]) <= 0.002 * so[l]["n_valid"] + 5
+    # one iteration at a shared pose: the kernel's normal equations against
+    # the oracle's, and no pixel with a bad source range takes part
+    T = pair.gt @ synth.make_pose(synth.rot_axis_angle([0.3, 1.0, 0.2], 0.01), [0.05, -0.03, 0.02])
+    prm = rir.make_params(levels=3, iters=[1, 1, 1], delta=0.5)
+    out = rir.debug_associate(ctx, prm, rir.Sensor.from_model(pair.sensor), to_dev(src), to_dev(dst), 0, T)
+    ref = oracle.system(pair.sensor, 0, src, dst, oracle.make_params(levels=3, iters=[1, 1, 1], delta=0.5), T)
+    mask = out["mask"].cpu().numpy().astype(bool).reshape(-1)
+    assert not mask[~(src.reshape(-1) > 0) | ~np.isfinite(src.reshape(-1))].any()
+    Hk = _jtj_matrix(out["stats"]["JtJ"])
+    Hr = _jtj_matrix(ref["stats"]["JtJ"])
+    amb = ambiguous(pair.sensor, 0, ref["uhat"], ref["phi"]) & ref["proj_valid"].astype(bool)
+    assert np.all(np.isfinite(Hk))
+    assert _normalised_diff(Hk, Hr) < JTJ_TOL + 4.0 * amb.sum() / max(ref["stats"]["n_valid"], 1)

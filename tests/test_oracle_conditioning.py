@@ -1,0 +1,44 @@
+"""Conditioning of the registration result itself (CPU only).
+
+On dynamic scenes (moved boxes, spurious returns) pseudo-Huber Gauss-Newton
+with a fixed iteration count need not settle: the projective association of
+Sec. 4.1, Eq. (5)-(6), keeps switching pixels between surfaces, and the pose
+after the last iteration depends on where in that cycle it stops.  Such a
+pair's FP64 result moves by more than the parity bar (1e-4 rad / 1 mm) when
+its input ranges are perturbed by one FP32 rounding (relative 1e-7), so no
+FP32 implementation can be held to the bar on it.  A static-scene pair and a
+settled dynamic pair move by orders of magnitude less under the same
+perturbation.  The benchmark's oracle gates report this spread per pair."""
+import numpy as np
+
+import synth
+
+ROT_TOL, TRANS_TOL = 1e-4, 1e-3
+
+
+def _spread(orc, pair, n_draws=3, rel=1e-7, seed=0):
+    prm = orc.make_params(levels=3, iters=[10, 10, 10], delta=0.5, r_max=80.0)
+    T0, _ = orc.icp(pair.sensor, pair.src, pair.dst, prm)
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_draws):
+        s = (pair.src * (1 + rel * rng.standard_normal(pair.src.shape))).astype(np.float32)
+        d = (pair.dst * (1 + rel * rng.standard_normal(pair.dst.shape))).astype(np.float32)
+        T1, _ = orc.icp(pair.sensor, s, d, prm)
+        out.append(orc.pose_error(T1, T0))
+    return np.array(out)
+
+
+def test_cycling_dynamic_pair_is_ill_conditioned(orc):
+    # 32x1024 dynamic pair (mixed-size dynamic batch, seed 4032)
+    pair = synth.gen_pair(synth.CONFIGS["combined64mixed"], 4032)
+    assert pair.src.shape == (32, 1024)
+    sp = _spread(orc, pair, seed=132)
+    assert np.any((sp[:, 0] > ROT_TOL) | (sp[:, 1] > TRANS_TOL)), sp
+
+
+def test_static_and_settled_pairs_are_well_conditioned(orc):
+    for cfg, seed in (("pair64", 0), ("combined64mixed", 4016)):
+        pair = synth.gen_pair(synth.CONFIGS[cfg], seed)
+        sp = _spread(orc, pair, seed=seed)
+        assert np.all(sp[:, 0] < 0.01 * ROT_TOL) and np.all(sp[:, 1] < 0.01 * TRANS_TOL), (cfg, seed, sp)
