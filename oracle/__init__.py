@@ -89,6 +89,7 @@ def lib():
         L.orc_bf16.restype = ctypes.c_double
         L.orc_mlp_nparam.restype = ctypes.c_int
         L.orc_mlp_forward.argtypes = [_D, _F, ctypes.c_int64, _D, _D]
+        L.orc_mlp_preact.argtypes = [_D, _F, ctypes.c_int64, _D, _D, _D, _D]
         L.orc_mlp_loss_grad.argtypes = [_D, _F, _F, ctypes.c_int64, _D]
         L.orc_mlp_loss_grad.restype = ctypes.c_double
         L.orc_exp_se3.argtypes = [_D, _D]
@@ -376,6 +377,18 @@ def mlp_forward(params: np.ndarray, feats: np.ndarray):
     w = np.zeros(B)
     lib().orc_mlp_forward(_p(P, _D), _p(f, _F), B, _p(z, _D), _p(w, _D))
     return z, w
+
+
+def mlp_preact(params: np.ndarray, feats: np.ndarray) -> dict:
+    """Hidden pre-activations a1, a2 [B, 64] of the FP64 forward pass and the
+    magnitude sums s1, s2 [B, 64] that bound FP32 rounding of the same sums."""
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    f = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 14)
+    B = f.shape[0]
+    out = {k: np.zeros((B, 64)) for k in ("a1", "a2", "s1", "s2")}
+    lib().orc_mlp_preact(_p(P, _D), _p(f, _F), B, _p(out["a1"], _D), _p(out["a2"], _D), _p(out["s1"], _D),
+                         _p(out["s2"], _D))
+    return out
 
 
 def mlp_loss_grad(params: np.ndarray, feats: np.ndarray, labels: np.ndarray):

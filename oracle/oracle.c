@@ -394,6 +394,37 @@ void orc_mlp_forward(const double *P, const float *feats, int64_t B, double *z_o
 }
 
 /*
+ * The hidden pre-activations a1 = W1 bf16(f) + b1 and a2 = W2 h1 + b2 of each
+ * feature vector (B x 64 each, exact FP64 sums of the exact bf16 products),
+ * and the magnitude sums s1 = |W1| |bf16(f)| + |b1|, s2 = |W2| h1 + |b2| that
+ * bound the rounding error of any FP32 evaluation of the same sums.  Test
+ * infrastructure for deciding which rows an FP32 implementation can round to
+ * another bf16 activation than the FP64 forward pass (a value within that
+ * rounding of a bf16 tie).
+ */
+void orc_mlp_preact(const double *P, const float *feats, int64_t B, double *a1_out, double *a2_out,
+                    double *s1_out, double *s2_out)
+{
+    double f[MLP_IN], fb[MLP_IN], a1[MLP_H], h1[MLP_H], a2[MLP_H], h2[MLP_H];
+    for (int64_t b = 0; b < B; ++b) {
+        for (int k = 0; k < MLP_IN; ++k)
+            f[k] = feats[b * MLP_IN + k];
+        mlp_forward1(P, f, fb, a1, h1, a2, h2);
+        for (int j = 0; j < MLP_H; ++j) {
+            double s1 = fabs(P[OFF_B1 + j]), s2 = fabs(P[OFF_B2 + j]);
+            for (int k = 0; k < MLP_IN; ++k)
+                s1 += fabs(P[OFF_W1 + j * MLP_IN + k] * fb[k]);
+            for (int k = 0; k < MLP_H; ++k)
+                s2 += fabs(P[OFF_W2 + j * MLP_H + k] * h1[k]);
+            a1_out[b * MLP_H + j] = a1[j];
+            a2_out[b * MLP_H + j] = a2[j];
+            s1_out[b * MLP_H + j] = s1;
+            s2_out[b * MLP_H + j] = s2;
+        }
+    }
+}
+
+/*
  * Mean binary cross-entropy of sigmoid(z) against labels y in {0, 1}, and its
  * gradient with respect to every parameter (layout as above).
  * Backward rounding points shared with the GPU: the output delta

@@ -76,3 +76,39 @@ def rot_trans_error(T, Tref):
     s = np.linalg.norm([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]]) / 2
     c = (np.trace(R) - 1) / 2
     return float(np.arctan2(s, c)), float(np.linalg.norm(T[:3, 3] - Tref[:3, 3]))
+
+
+# Learned weight: the products of bf16 weights and bf16 activations are exact
+# in FP32, so an FP32 evaluation of a hidden pre-activation (K products plus
+# the bias, summed in any order) differs from the exact sum by at most
+# (K - 1) u s, and its own rounding adds u |a| <= u s (u = 2^-24, s the sum of
+# the magnitudes of the terms).  A value farther than (K + 1) u s from a bf16
+# tie therefore rounds to the same bf16 activation on both sides.
+MLP_BAND_FACTOR = 1.0
+
+
+def _bf16_tie_distance(x):
+    """Distance of each value to the nearest rounding boundary of bf16
+    (round-to-nearest-even ties lie halfway between neighbouring bf16
+    values)."""
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    bits = x.astype(np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+    one = np.uint32(0x10000)
+    # largest bf16 value <= x (float32 rounding may have stepped above x)
+    bits = np.where(bits.view(np.float32).astype(np.float64) > x, bits - one, bits)
+    val = lambda b: b.view(np.float32).astype(np.float64)
+    lo, hi, below = val(bits), val(bits + one), val(bits - one)
+    return np.minimum(np.abs(x - 0.5 * (lo + hi)), np.abs(x - 0.5 * (below + lo)))
+
+
+def mlp_band(pre):
+    """Rows (feature vectors) whose bf16 hidden activations an FP32
+    evaluation may round to a neighbouring value: some positive hidden
+    pre-activation lies within the FP32 rounding bound of a bf16 tie.
+    `pre` is the oracle's mlp_preact output."""
+    u = 2.0 ** -24
+    band = np.zeros(pre["a1"].shape[0], bool)
+    for a, s, k in ((pre["a1"], pre["s1"], 16), (pre["a2"], pre["s2"], 66)):
+        tol = MLP_BAND_FACTOR * k * u * s
+        band |= np.any((a > -tol) & (_bf16_tie_distance(a) <= tol), axis=1)
+    return band

@@ -109,6 +109,26 @@ def test_mlp_forward_matches_torch(orc):
     np.testing.assert_allclose(w, 1 / (1 + np.exp(-zt)), rtol=1e-12)
 
 
+def test_mlp_preactivations_match_torch(orc):
+    """The hidden pre-activations the oracle reports (used to find the rows
+    an FP32 evaluation may round differently) are those of torch's float64
+    network with the same rounding points; the magnitude sums bound them."""
+    P = _rand_params(11)
+    f = _rand_feats(12, 300)
+    pre = orc.mlp_preact(P, f)
+    Pt = torch.tensor(P)
+    W1, b1, W2, b2 = Pt[:896].view(64, 14), Pt[896:960], Pt[960:5056].view(64, 64), Pt[5056:5120]
+    fb = _bf(torch.tensor(f, dtype=torch.float64))
+    a1 = fb @ W1.T + b1
+    h1 = _bf(torch.relu(a1))
+    a2 = h1 @ W2.T + b2
+    np.testing.assert_allclose(pre["a1"], a1.numpy(), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(pre["a2"], a2.numpy(), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(pre["s1"], (fb.abs() @ W1.abs().T + b1.abs()).numpy(), rtol=1e-13)
+    np.testing.assert_allclose(pre["s2"], (h1 @ W2.abs().T + b2.abs()).numpy(), rtol=1e-13)
+    assert np.all(pre["s1"] >= np.abs(pre["a1"])) and np.all(pre["s2"] >= np.abs(pre["a2"]))
+
+
 def test_mlp_zero_weights_give_bias_sigmoid(orc):
     P = np.zeros(NP)
     P[5184] = -1.25
