@@ -315,6 +315,26 @@ def icp(sensor, src: np.ndarray, dst: np.ndarray, params: OrcParams, T_init=None
     return To, [stats[i].to_dict() for i in range(params.levels)]
 
 
+def icp_spread(sensor, src: np.ndarray, dst: np.ndarray, params: OrcParams, T_ref=None, n_draws=3, rel=1e-7,
+               seed=0):
+    """Conditioning of the registration result itself: the oracle's pose
+    error (rad, m) against T_ref (default: its own result on the given
+    images) after each of n_draws perturbations of both range images by one
+    relative FP32 rounding (range * (1 + rel * N(0, 1)), rounded to FP32).
+    A result that moves by more than a tolerance under such a perturbation
+    cannot be reproduced to that tolerance by any FP32 implementation."""
+    if T_ref is None:
+        T_ref, _ = icp(sensor, src, dst, params)
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_draws):
+        s = (src * (1 + rel * rng.standard_normal(src.shape))).astype(np.float32)
+        d = (dst * (1 + rel * rng.standard_normal(dst.shape))).astype(np.float32)
+        T1, _ = icp(sensor, s, d, params)
+        out.append(pose_error(T1, T_ref))
+    return np.array(out)
+
+
 def system(sensor, level: int, src, dst, params: OrcParams, T, use_learned=False, with_features=False) -> dict:
     """Per-pixel association terms and the normal equations at a fixed pose."""
     h = _SensorHolder(sensor)

@@ -18,15 +18,7 @@ ROT_TOL, TRANS_TOL = 1e-4, 1e-3
 
 def _spread(orc, pair, n_draws=3, rel=1e-7, seed=0):
     prm = orc.make_params(levels=3, iters=[10, 10, 10], delta=0.5, r_max=80.0)
-    T0, _ = orc.icp(pair.sensor, pair.src, pair.dst, prm)
-    rng = np.random.default_rng(seed)
-    out = []
-    for _ in range(n_draws):
-        s = (pair.src * (1 + rel * rng.standard_normal(pair.src.shape))).astype(np.float32)
-        d = (pair.dst * (1 + rel * rng.standard_normal(pair.dst.shape))).astype(np.float32)
-        T1, _ = orc.icp(pair.sensor, s, d, prm)
-        out.append(orc.pose_error(T1, T0))
-    return np.array(out)
+    return orc.icp_spread(pair.sensor, pair.src, pair.dst, prm, n_draws=n_draws, rel=rel, seed=seed)
 
 
 def test_cycling_dynamic_pair_is_ill_conditioned(orc):
