@@ -114,7 +114,7 @@ LEARNED_MODES = (("plain", (10, 10, 10), False), ("learned", (10, 10, 10), True)
                  ("plain_1_5", (1, 5, 5), False), ("learned_1_5", (1, 5, 5), True))
 
 
-def learned_vs_plain(rir, ctx, n_pairs=256, repeats=5):
+def learned_vs_plain(rir, ctx, n_pairs=256, repeats=5, oracle_sample=0, threads=1):
     """Pose error against the ground truth, success rate (<= 0.25 deg, 5 cm),
     batched pairs/s and goodput of the committed network against plain
     pseudo-Huber on dynamic 64x1024 pairs (20% of the boxes moved, 10%
@@ -130,9 +130,14 @@ def learned_vs_plain(rir, ctx, n_pairs=256, repeats=5):
     net = rir.Mlp(learned.load())
     gts = [p.gt for p in pairs]
     res = {}
-    for name, iters, use_net in LEARNED_MODES:
-        kw = dict(weight_mode=rir.WEIGHT_LEARNED, mlp=net, r_max=cfg["noise"].rmax, learned_levels=0b001) \
-            if use_net else {}
+    onet_params = oracle_trained_network()
+    onet = rir.Mlp(onet_params)
+    # the same schedule with the network the oracle trained by itself: the
+    # learned mode the oracle can check (it never takes the GPU-trained one)
+    modes = LEARNED_MODES + (("oraclenet", (10, 10, 10), "oracle"),)
+    for name, iters, use_net in modes:
+        kw = dict(weight_mode=rir.WEIGHT_LEARNED, mlp=onet if use_net == "oracle" else net,
+                  r_max=cfg["noise"].rmax, learned_levels=0b001) if use_net else {}
         prm = rir.make_params(levels=3, iters=list(iters), delta=cfg["delta"], **kw)
         rir.icp_batch(ctx, prm, batch)
         torch.cuda.synchronize()
@@ -148,6 +153,12 @@ def learned_vs_plain(rir, ctx, n_pairs=256, repeats=5):
                      "goodput_pairs_per_s": round(ok * n_pairs / dt, 1),
                      "median_err_vs_gt_rad_m": [float(np.median(e[:, 0])), float(np.median(e[:, 1]))],
                      "p90_err_vs_gt_rad_m": [float(np.percentile(e[:, 0], 90)), float(np.percentile(e[:, 1], 90))]}
+        if oracle_sample and name in ("plain", "oraclenet"):
+            idx = list(range(0, n_pairs, max(1, n_pairs // oracle_sample)))[:oracle_sample]
+            okw = dict(levels=3, iters=list(iters), delta=cfg["delta"], r_max=cfg["noise"].rmax)
+            if use_net:
+                okw.update(weight_mode=1, mlp=onet_params, learned_levels=0b001)
+            res[name]["oracle"] = _oracle_check(pairs, idx, okw, T.cpu().numpy(), threads)
         log(f"learned-vs-plain {name}: {res[name]['pairs_per_s']:.0f} pairs/s, success {ok:.3f}")
     best = {}
     for kind in ("plain", "learned"):
@@ -199,20 +210,56 @@ def _gt_summary(T, gts):
     return e, ok
 
 
+# ambiguity band of the parity bar: column coordinate within BAND_U px of a
+# half-integer, elevation within BAND_PHI row spacings of a level midpoint
+BAND_U, BAND_PHI = 2e-3, 1e-3
+
+
 def _oracle_check(pairs, idx, prm_kw, T_gpu, threads):
-    """Pose error of the GPU result against the FP64 oracle on pairs idx."""
+    """Pose error of the GPU result against the FP64 oracle on pairs idx.
+    Every pair outside the bar is probed for ill-conditioning on the CPU: the
+    oracle re-run with the rounding decisions inside the parity bar's
+    ambiguity band flipped on seeded coins, and with its input ranges
+    perturbed by one FP32 rounding.  A pair whose oracle result itself moves
+    beyond the bar under either probe is counted as ill-conditioned."""
     import oracle
     prm = oracle.make_params(**prm_kw)
 
     def run(i):
         return oracle.icp(pairs[i].sensor, pairs[i].src, pairs[i].dst, prm)[0]
 
+    t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
         To = list(ex.map(run, idx))
+    dt = time.perf_counter() - t0
     errs = [rot_trans_error(T_gpu[i], T) for i, T in zip(idx, To)]
     ok = [e[0] <= ROT_TOL and e[1] <= TRANS_TOL for e in errs]
-    return {"checked": len(idx), "within_tol": int(sum(ok)),
-            "max_err_rad_m": [max(e[0] for e in errs), max(e[1] for e in errs)]}
+    out_idx = [(i, T) for (i, T), good in zip(zip(idx, To), ok) if not good]
+
+    def probe(arg):
+        i, T = arg
+        p = pairs[i]
+        pr = oracle.make_params(**prm_kw)
+        sp = np.concatenate([oracle.icp_flip_spread(p.sensor, p.src, p.dst, pr, T_ref=T, band_u=BAND_U,
+                                                    band_phi=BAND_PHI, seed=i),
+                             oracle.icp_spread(p.sensor, p.src, p.dst, pr, T_ref=T, seed=i)])
+        return sp
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        spreads = list(ex.map(probe, out_idx))
+    outside = []
+    for (i, _), sp in zip(out_idx, spreads):
+        e = rot_trans_error(T_gpu[i], dict(zip(idx, To))[i])
+        outside.append({"pair": int(i), "seed": int(getattr(pairs[i], "seed", -1)),
+                        "shape": list(pairs[i].src.shape), "err_rad_m": [e[0], e[1]],
+                        "oracle_spread_rad_m": [float(sp[:, 0].max()), float(sp[:, 1].max())],
+                        "ill_conditioned": bool(np.any((sp[:, 0] > ROT_TOL) | (sp[:, 1] > TRANS_TOL)))})
+    ill = sum(o["ill_conditioned"] for o in outside)
+    return {"checked": len(idx), "within_tol": int(sum(ok)), "ill_conditioned": int(ill),
+            "unexplained": len(outside) - int(ill),
+            "max_err_rad_m": [max(e[0] for e in errs), max(e[1] for e in errs)],
+            "outside_tol": outside,
+            "oracle_pairs_per_s_all_threads": round(len(idx) / dt, 3), "oracle_threads": threads}
 
 
 def mixed_batch(rir, ctx, oracle_sample, threads, repeats=5):
@@ -268,6 +315,17 @@ def mixed_batch(rir, ctx, oracle_sample, threads, repeats=5):
     return res
 
 
+ORACLE_NET_FILE = os.path.join(ROOT, "tests", "golden", "oracle_mlp_dynamic64.npz")
+
+
+def oracle_trained_network():
+    """Parameters of the learned-weight network that the oracle trained by
+    itself on the CPU (tests/golden/make_oracle_net.py): the network a
+    learned run can be checked against the oracle with."""
+    with np.load(ORACLE_NET_FILE, allow_pickle=False) as z:
+        return z["params"].astype(np.float64)
+
+
 def combined_modes(rir, ctx, oracle_sample, threads, repeats=5):
     """64 dynamic pairs of mixed sizes (16x1024 .. 128x4096; moved boxes and
     spurious returns; seeds 4000..4063), 3 levels x 10 iterations, in three
@@ -292,9 +350,13 @@ def combined_modes(rir, ctx, oracle_sample, threads, repeats=5):
     net = rir.Mlp(learned.load())
     shapes = [(p.sensor.H, p.sensor.W) for p in pairs]
     gts = [p.gt for p in pairs]
+    onet_params = oracle_trained_network()
+    onet = rir.Mlp(onet_params)
     modes = {"plain_fp32": dict(),
              "learned_fp32": dict(weight_mode=rir.WEIGHT_LEARNED, mlp=net, r_max=cfg["noise"].rmax,
                                   learned_levels=0b001),
+             "learned_fp32_oracle_net": dict(weight_mode=rir.WEIGHT_LEARNED, mlp=onet, r_max=cfg["noise"].rmax,
+                                             learned_levels=0b001),
              "plain_fp64": dict(precision=rir.PREC_FP64)}
     res = {}
     for name, kw in modes.items():
@@ -308,11 +370,19 @@ def combined_modes(rir, ctx, oracle_sample, threads, repeats=5):
                      "success_rate_vs_gt": ok, "goodput_pairs_per_s": round(ok * len(pairs) / dt, 1),
                      "median_err_vs_gt_rad_m": [float(np.median(e[:, 0])), float(np.median(e[:, 1]))],
                      "algorithmic_GBps": round(nbytes / dt / 1e9, 1)}
-        if oracle_sample and name != "learned_fp32":
+        if name == "learned_fp32":
+            # the network the library trained on the GPU: the oracle never takes
+            # a value the GPU produced, so this mode is timed and scored against
+            # the ground truth only; the same kernel with the network the oracle
+            # trained itself is the oracle-checked learned mode below
+            res[name]["oracle"] = None
+        elif oracle_sample:
             # the oracle computes in FP64 for both precisions of the library
             idx = list(range(0, len(pairs), max(1, len(pairs) // oracle_sample)))[:oracle_sample]
-            res[name]["oracle"] = _oracle_check(pairs, idx, dict(levels=levels, iters=iters, delta=cfg["delta"],
-                                                                 r_max=cfg["noise"].rmax), T, threads)
+            okw = dict(levels=levels, iters=iters, delta=cfg["delta"], r_max=cfg["noise"].rmax)
+            if name == "learned_fp32_oracle_net":
+                okw.update(weight_mode=1, mlp=onet_params, learned_levels=0b001)
+            res[name]["oracle"] = _oracle_check(pairs, idx, okw, T, threads)
         log(f"combined modes {name}: {res[name]['ms']:.3f} ms, success {ok:.3f}")
     return {"workload": f"{len(pairs)} dynamic pairs (20% of the boxes moved, 10% spurious returns), H x W uniform "
                         f"over 16x1024 .. 128x4096 (seeds 4000..{4000 + len(pairs) - 1}), {levels} levels x "
@@ -601,6 +671,77 @@ def deskew_timing(rir, seq, repeats=5):
     return res
 
 
+def copy_bandwidth(dev, reps=5):
+    """A plain 1 GiB device-to-device copy (2 GiB of HBM traffic per copy),
+    timed with HIP events on the current stream: the measured streaming
+    bandwidth the kernels' HBM fractions are also quoted against.  Its
+    rocprofv3 FETCH_SIZE / WRITE_SIZE readings scale the byte counters."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * (1 << 30), "ms": round(ms, 4), "GBps": round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1)}
+
+
+def host_cpu():
+    """The host the oracle runs on: logical CPUs, the CPUs this process may
+    run on, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = None
+    return {"logical_cpus": os.cpu_count(), "affinity_cpus": aff, "model": model}
+
+
+def single_pair_latency(rir, ctx, repeats=20):
+    """Config-0 and config-3 shapes on their own: one 64x1024 pair per call
+    (3 levels x 10 iterations, pseudo-Huber), the GPU latency of a call, and
+    the FP64 oracle's single-threaded time per pair (median of 5 after one
+    warm-up) on a static and a dynamic pair."""
+    import torch
+    import synth
+    import oracle
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, seed in (("pair64", 0), ("dynamic64", 13000)):
+        cfg = synth.CONFIGS[name]
+        p = synth.gen_pair(cfg, seed)
+        sen = rir.Sensor.from_model(p.sensor)
+        batch = [(sen, torch.from_numpy(p.src).to(dev), torch.from_numpy(p.dst).to(dev))]
+        prm = rir.make_params(levels=3, iters=[10, 10, 10], delta=cfg["delta"])
+        dt, _, _ = _time_batch(rir, ctx, prm, batch, repeats)
+        oprm = oracle.make_params(levels=3, iters=[10, 10, 10], delta=cfg["delta"], r_max=cfg["noise"].rmax)
+        ts = []
+        for _ in range(6):
+            t0 = time.perf_counter()
+            oracle.icp(p.sensor, p.src, p.dst, oprm)
+            ts.append(time.perf_counter() - t0)
+        res[name] = {"shape": list(p.src.shape), "gpu_ms_per_call": round(dt * 1e3, 4),
+                     "oracle_single_thread_ms": round(float(np.median(ts[1:])) * 1e3, 1)}
+    log(f"single-pair latency: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -612,7 +753,8 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="block,px_per_thread,grid_mult,xcd_remap,chunk to use instead of autotuning")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (value then unchecked)")
-    ap.add_argument("--sample-every", type=int, default=3)
+    ap.add_argument("--sample-every", type=int, default=1,
+                    help="oracle-check every k-th pair of the sequence (1: all)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-size batch and the combined-modes measurements")
@@ -620,7 +762,7 @@ def main():
                     help="pairs of each mixed workload checked against the oracle (0: none)")
     ap.add_argument("--no-sdf", action="store_true", help="skip the SDF fusion, PCA normal and deskew workloads")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
+                    help="accepted for older command lines: the 1 GiB copy probe always runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the batch of independent pairs would be split across GPUs "
@@ -642,14 +784,8 @@ def main():
     log(f"generated {n} pairs of {sm.H}x{sm.W} in {time.perf_counter() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
-    if args.copy_probe:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("copy probe: 3 x 1 GiB device copies done")
-        del a, b
+    copy = copy_bandwidth(dev)
+    log(f"copy probe: {copy}")
     scans = [torch.from_numpy(s).to(dev) for s in seq["scans"]]
     sensor = rir.Sensor.from_model(sm)
     ctx = rir.Context(0)
@@ -715,22 +851,31 @@ def main():
                 "kernel": "rir::k_icp_step<float, 0, true, *> + rir::k_solve<float> (finest-level iteration)",
                 "bytes_per_launch": bytes_l0, "launch_ms": round(l0_launch_ms, 5)}
 
+    roofline["frac_of_measured_copy"] = round(achieved / copy["GBps"], 4)
+    roofline["measured_copy_GBps"] = copy["GBps"]
+
+    # worker threads for the oracle: the host's CPU share of one GPU (16), or
+    # fewer where the process may use fewer CPUs
+    host = host_cpu()
+    threads = max(1, min(16, host["affinity_cpus"] or os.cpu_count() or 1))
     cpu = None
     frac_ok, checked, max_err = 1.0, 0, None
     if not args.no_cpu:
-        threads = max(1, min(16, os.cpu_count() or 1))
         idx, To, dt = cpu_baseline(pairs, sm, levels, iters, delta, r_max, args.sample_every, threads)
         errs = [rot_trans_error(T_gpu[i], T) for i, T in zip(idx, To)]
         ok = [e[0] <= ROT_TOL and e[1] <= TRANS_TOL for e in errs]
         frac_ok, checked = float(np.mean(ok)), len(ok)
         max_err = [max(e[0] for e in errs), max(e[1] for e in errs)]
+        every = "all" if args.sample_every == 1 else f"every {args.sample_every}th"
         cpu = {"value": round(len(idx) / dt, 4), "unit": "scan pairs/s", "cores": threads, "kind": "oracle",
-               "sample": f"{len(idx)} of the {n} pairs (every {args.sample_every}th), FP64 single-threaded "
-                         f"oracle, one pair per thread, {dt:.1f} s wall"}
+               "sample": f"{len(idx)} of the {n} pairs ({every}), FP64 single-threaded oracle, one pair per "
+                         f"thread on {threads} threads, {dt:.1f} s wall",
+               "host": host}
         log(f"oracle sample {len(idx)} pairs in {dt:.1f}s; within tolerance {sum(ok)}/{len(ok)}; max err {max_err}")
 
-    lvp = None if args.no_learned else learned_vs_plain(rir, ctx)
-    threads = max(1, min(16, os.cpu_count() or 1))
+    lvp = None if args.no_learned else learned_vs_plain(rir, ctx, oracle_sample=0 if args.no_cpu else 16,
+                                                        threads=threads)
+    latency = None if args.no_cpu else single_pair_latency(rir, ctx)
     mixed = None if args.no_mixed else mixed_batch(rir, ctx, 0 if args.no_cpu else args.mixed_oracle, threads)
     comb = None if args.no_mixed else combined_modes(rir, ctx, 0 if args.no_cpu else args.mixed_oracle, threads)
     context = None if args.no_mixed else paper_context(rir, ctx, oracle_runs=not args.no_cpu)
@@ -764,6 +909,8 @@ def main():
         "median_err_vs_gt_rad_m": [float(np.median([e[0] for e in gt_err])), float(np.median([e[1] for e in gt_err]))],
         "level_ms": [round(x, 4) for x in level_ms],
         "degenerate_levels": int(np.sum(st["status"] != 0)),
+        "copy_probe": copy,
+        "single_pair_latency": latency,
         "learned_vs_plain": lvp,
         "mixed_batch": mixed,
         "combined_modes": comb,

@@ -274,8 +274,11 @@ rir_status rir_deskew(const rir_sensor *sensor, int32_t n_images, const float *r
 /* Registers n_pairs independent scan pairs (Sec. 4.1, Eq. (5)-(7)), all with
  * the same parameters but any mix of sensors and image sizes, in one batch:
  * one association/reduction launch per Gauss-Newton iteration covers every
- * pair, the tile partial sums of each pair are reduced and its 6x6 system
- * solved by the last workgroup to finish that pair.
+ * pair and writes one partial-sum record per tile; a second launch with one
+ * workgroup per pair sums that pair's records in FP64 in tile order, solves
+ * its 6x6 system and applies the update.  Pairs whose level image is small
+ * run all iterations of that level in one launch, one workgroup per pair.
+ * The whole schedule is replayed as one HIP graph per batch shape.
  *   pairs       host array of n_pairs descriptors (device images).
  *   init_poses  device n_pairs*16 FP64 (ignored with init_mode 1).
  *   poses_out   device n_pairs*16 FP64 (may alias init_poses).

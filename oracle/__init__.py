@@ -42,7 +42,9 @@ class OrcParams(ctypes.Structure):
                 ("edge_rel", ctypes.c_double), ("max_corr_dist", ctypes.c_double),
                 ("init_mode", ctypes.c_int), ("weight_mode", ctypes.c_int),
                 ("mlp", ctypes.POINTER(ctypes.c_double)), ("r_max", ctypes.c_double),
-                ("learned_levels", ctypes.c_int), ("stop_eps", ctypes.c_double)]
+                ("learned_levels", ctypes.c_int), ("stop_eps", ctypes.c_double),
+                ("flip_band_u", ctypes.c_double), ("flip_band_phi", ctypes.c_double),
+                ("flip_seed", ctypes.c_uint64)]
 
 
 class OrcLevelStats(ctypes.Structure):
@@ -332,6 +334,33 @@ def icp_spread(sensor, src: np.ndarray, dst: np.ndarray, params: OrcParams, T_re
         d = (dst * (1 + rel * rng.standard_normal(dst.shape))).astype(np.float32)
         T1, _ = icp(sensor, s, d, params)
         out.append(pose_error(T1, T_ref))
+    return np.array(out)
+
+
+def icp_flip_spread(sensor, src: np.ndarray, dst: np.ndarray, params: OrcParams, T_ref=None, n_draws=3,
+                    band_u=2e-3, band_phi=1e-3, seed=0):
+    """Conditioning of the registration result against the rounding
+    decisions the parity bar leaves open: the oracle's pose error (rad, m)
+    against T_ref (default: its own result) after each of n_draws runs in
+    which every association whose column coordinate lies within band_u
+    pixels of a half-integer, or whose elevation lies within band_phi row
+    spacings of a level midpoint or a field-of-view edge, takes the other
+    admissible candidate on a coin (seeded SplitMix64 draws, per level,
+    iteration and pixel).  A pair whose result moves beyond a tolerance under
+    these flips cannot be held to that tolerance by an implementation whose
+    rounding differs from FP64 inside the band."""
+    if T_ref is None:
+        T_ref, _ = icp(sensor, src, dst, params)
+    saved = (params.flip_band_u, params.flip_band_phi, params.flip_seed)
+    out = []
+    try:
+        for k in range(n_draws):
+            params.flip_band_u, params.flip_band_phi = float(band_u), float(band_phi)
+            params.flip_seed = (int(seed) * 1000003 + k + 1) & 0xFFFFFFFFFFFFFFFF
+            T1, _ = icp(sensor, src, dst, params)
+            out.append(pose_error(T1, T_ref))
+    finally:
+        params.flip_band_u, params.flip_band_phi, params.flip_seed = saved
     return np.array(out)
 
 

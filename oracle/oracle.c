@@ -61,6 +61,14 @@ typedef struct {
     double r_max;          /* range scale of the first learned feature */
     int learned_levels;    /* weight_mode 1: bit l = learned at level l, 0 = all levels */
     double stop_eps;       /* > 0: a level ends after a step with |xi| <= stop_eps */
+    /* Conditioning probe (test infrastructure; all zero for the method itself):
+     * with flip_band_u > 0 every association whose rounding is ambiguous --
+     * column coordinate within flip_band_u pixels of a half-integer, or
+     * elevation within flip_band_phi row spacings of a level midpoint or of
+     * a field-of-view edge -- takes the other admissible candidate when a
+     * coin drawn from (flip_seed, level, iteration, pixel) says so. */
+    double flip_band_u, flip_band_phi;
+    uint64_t flip_seed;
 } orc_params;
 
 typedef struct {
@@ -613,6 +621,57 @@ static void features(const orc_sensor *s, int level, const float *dst, int ul, i
     f[13] = clamp4((rc - rproj) / delta);
 }
 
+/* SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): the output function applied to a counter. */
+static uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Conditioning probe: replaces an ambiguous rounding decision of a
+ * projection by the other admissible one, each decision (column, row,
+ * field-of-view edge) on its own coin.  The band is the one inside which the
+ * parity bar accepts either neighbour, so a result that moves beyond its
+ * tolerance under these flips is not fixed by the decisions the bar
+ * prescribes. */
+static void flip_ambiguous(const orc_sensor *s, int level, const orc_params *prm, uint64_t key, orc_proj *pr)
+{
+    int st = 1 << level, Wl = s->W / st, Hl = s->H / st, H = s->H;
+    double phi = pr->phi;
+    uint64_t c = splitmix64(key);
+    /* elevation: the nearest level midpoint and the field-of-view edges */
+    double gap_top = s->phi[0] - s->phi[1], gap_bot = s->phi[H - 2] - s->phi[H - 1];
+    double edge_gap = gap_top < gap_bot ? gap_top : gap_bot;
+    double phi_hi = s->phi[0] + 0.5 * gap_top, phi_lo = s->phi[H - 1] - 0.5 * gap_bot;
+    if ((fabs(phi - phi_hi) < prm->flip_band_phi * edge_gap || fabs(phi - phi_lo) < prm->flip_band_phi * edge_gap) &&
+        (c & 1))
+        pr->valid = !pr->valid;
+    int v = pr->v;
+    int nb = phi > s->phi[st * v] ? v - 1 : v + 1; /* neighbour across the nearest midpoint */
+    if (nb >= 0 && nb < Hl) {
+        double mid = 0.5 * (s->phi[st * v] + s->phi[st * nb]);
+        double gap = fabs(s->phi[st * v] - s->phi[st * nb]);
+        if (fabs(phi - mid) < prm->flip_band_phi * gap && (c & 2))
+            v = nb;
+    }
+    if (v != pr->v) {
+        double uh = (pr->theta - th_lut(s, v * st)) * (double)s->W / ORC_TWO_PI / (double)st;
+        uh = uh - (double)Wl * floor(uh / (double)Wl);
+        pr->uhat = uh;
+        pr->v = v;
+        pr->u = (int)floor(uh + 0.5) % Wl;
+    }
+    /* column: the other side of the nearest half-integer */
+    double fr = pr->uhat - floor(pr->uhat);
+    if (fabs(fr - 0.5) < prm->flip_band_u && (c & 4)) {
+        int alt = fr < 0.5 ? (int)floor(pr->uhat) + 1 : (int)floor(pr->uhat);
+        pr->u = ((alt % Wl) + Wl) % Wl;
+    }
+}
+
 /*
  * Projective data association at level l (Eq. (5)-(6)) and per-pixel
  * residual, Jacobian and weight for Eq. (7) at pose T (dst <- src).
@@ -652,6 +711,8 @@ void orc_associate(const orc_sensor *s, int level, const float *src, const float
             orc_project(s, level, x, &pr);
             out->uhat[o] = pr.uhat;
             out->phi[o] = pr.phi;
+            if (prm->flip_band_u > 0.0 && pr.r > 0.0 && pr.v >= 0)
+                flip_ambiguous(s, level, prm, prm->flip_seed ^ ((uint64_t)o * 0xD1B54A32D192ED03ull), &pr);
             if (!pr.valid)
                 continue;
             out->proj_valid[o] = 1;
@@ -872,13 +933,15 @@ int orc_icp(const orc_sensor *s, const float *src, const float *dst, const orc_p
         for (int it = 0; it < prm->iters[l]; ++it) {
             double Hm[36], g[6], xi[6];
             int learned = prm->weight_mode == 1 && (prm->learned_levels == 0 || ((prm->learned_levels >> l) & 1));
-            orc_associate(s, l, src, dst, nrm, nv, T, prm, learned, &ab.a);
+            orc_params pit = *prm; /* the probe's coins differ per level and iteration */
+            pit.flip_seed = splitmix64(prm->flip_seed + (uint64_t)(l * 4096 + it));
+            orc_associate(s, l, src, dst, nrm, nv, T, &pit, learned, &ab.a);
             accumulate(n, &ab.a, prm->delta, Hm, g, ls);
             ls->iters_run = it + 1;
             ls->status = ORC_OK;
             int ok = ls->n_valid >= 6 && all_finite(Hm, 36) && all_finite(g, 6) && cholesky_solve(Hm, g, xi);
             if (learned && (!ok || ls->sum_w < 0.1 * ls->n_valid)) {
-                orc_associate(s, l, src, dst, nrm, nv, T, prm, 0, &ab.a);
+                orc_associate(s, l, src, dst, nrm, nv, T, &pit, 0, &ab.a);
                 accumulate(n, &ab.a, prm->delta, Hm, g, ls);
                 ok = ls->n_valid >= 6 && all_finite(Hm, 36) && all_finite(g, 6) && cholesky_solve(Hm, g, xi);
                 ls->status = ORC_FALLBACK_HUBER;
