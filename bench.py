@@ -215,6 +215,34 @@ def _gt_summary(T, gts):
 BAND_U, BAND_PHI = 2e-3, 1e-3
 
 
+def probe_outside(pairs, out, prm_kw, T_gpu, threads):
+    """For each (pair index, oracle pose) outside the bar: the GPU's error,
+    the ground-truth error of the oracle's own result, and the oracle's
+    spread under the band flips and one FP32 rounding of the inputs."""
+    import oracle
+
+    def probe(arg):
+        i, T = arg
+        p = pairs[i]
+        pr = oracle.make_params(**prm_kw)
+        return np.concatenate([oracle.icp_flip_spread(p.sensor, p.src, p.dst, pr, T_ref=T, n_draws=6,
+                                                      band_u=BAND_U, band_phi=BAND_PHI, seed=i),
+                               oracle.icp_spread(p.sensor, p.src, p.dst, pr, T_ref=T, seed=i)])
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        spreads = list(ex.map(probe, out))
+    res = []
+    for (i, T), sp in zip(out, spreads):
+        e = rot_trans_error(T_gpu[i], T)
+        g = rot_trans_error(T, pairs[i].gt)
+        res.append({"pair": int(i), "seed": int(getattr(pairs[i], "seed", -1)),
+                    "shape": list(pairs[i].src.shape), "err_rad_m": [e[0], e[1]],
+                    "oracle_err_vs_gt_rad_m": [g[0], g[1]],
+                    "oracle_spread_rad_m": [float(sp[:, 0].max()), float(sp[:, 1].max())],
+                    "ill_conditioned": bool(np.any((sp[:, 0] > ROT_TOL) | (sp[:, 1] > TRANS_TOL)))})
+    return res
+
+
 def _oracle_check(pairs, idx, prm_kw, T_gpu, threads):
     """Pose error of the GPU result against the FP64 oracle on pairs idx.
     Every pair outside the bar is probed for ill-conditioning on the CPU: the
@@ -234,26 +262,8 @@ def _oracle_check(pairs, idx, prm_kw, T_gpu, threads):
     dt = time.perf_counter() - t0
     errs = [rot_trans_error(T_gpu[i], T) for i, T in zip(idx, To)]
     ok = [e[0] <= ROT_TOL and e[1] <= TRANS_TOL for e in errs]
-    out_idx = [(i, T) for (i, T), good in zip(zip(idx, To), ok) if not good]
-
-    def probe(arg):
-        i, T = arg
-        p = pairs[i]
-        pr = oracle.make_params(**prm_kw)
-        sp = np.concatenate([oracle.icp_flip_spread(p.sensor, p.src, p.dst, pr, T_ref=T, band_u=BAND_U,
-                                                    band_phi=BAND_PHI, seed=i),
-                             oracle.icp_spread(p.sensor, p.src, p.dst, pr, T_ref=T, seed=i)])
-        return sp
-
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        spreads = list(ex.map(probe, out_idx))
-    outside = []
-    for (i, _), sp in zip(out_idx, spreads):
-        e = rot_trans_error(T_gpu[i], dict(zip(idx, To))[i])
-        outside.append({"pair": int(i), "seed": int(getattr(pairs[i], "seed", -1)),
-                        "shape": list(pairs[i].src.shape), "err_rad_m": [e[0], e[1]],
-                        "oracle_spread_rad_m": [float(sp[:, 0].max()), float(sp[:, 1].max())],
-                        "ill_conditioned": bool(np.any((sp[:, 0] > ROT_TOL) | (sp[:, 1] > TRANS_TOL)))})
+    outside = probe_outside(pairs, [(i, T) for (i, T), good in zip(zip(idx, To), ok) if not good], prm_kw, T_gpu,
+                            threads)
     ill = sum(o["ill_conditioned"] for o in outside)
     return {"checked": len(idx), "within_tol": int(sum(ok)), "ill_conditioned": int(ill),
             "unexplained": len(outside) - int(ill),
@@ -860,12 +870,15 @@ def main():
     threads = max(1, min(16, host["affinity_cpus"] or os.cpu_count() or 1))
     cpu = None
     frac_ok, checked, max_err = 1.0, 0, None
+    outside = None
     if not args.no_cpu:
         idx, To, dt = cpu_baseline(pairs, sm, levels, iters, delta, r_max, args.sample_every, threads)
         errs = [rot_trans_error(T_gpu[i], T) for i, T in zip(idx, To)]
         ok = [e[0] <= ROT_TOL and e[1] <= TRANS_TOL for e in errs]
         frac_ok, checked = float(np.mean(ok)), len(ok)
         max_err = [max(e[0] for e in errs), max(e[1] for e in errs)]
+        outside = probe_outside(pairs, [(i, T) for (i, T), good in zip(zip(idx, To), ok) if not good],
+                                dict(levels=levels, iters=iters, delta=delta, r_max=r_max), T_gpu, threads)
         every = "all" if args.sample_every == 1 else f"every {args.sample_every}th"
         cpu = {"value": round(len(idx) / dt, 4), "unit": "scan pairs/s", "cores": threads, "kind": "oracle",
                "sample": f"{len(idx)} of the {n} pairs ({every}), FP64 single-threaded oracle, one pair per "
@@ -906,6 +919,7 @@ def main():
         "oracle_checked": checked,
         "oracle_within_tol": frac_ok,
         "max_err_vs_oracle_rad_m": max_err,
+        "outside_tol": outside,
         "median_err_vs_gt_rad_m": [float(np.median([e[0] for e in gt_err])), float(np.median([e[1] for e in gt_err]))],
         "level_ms": [round(x, 4) for x in level_ms],
         "degenerate_levels": int(np.sum(st["status"] != 0)),

@@ -605,6 +605,16 @@ __device__ __forceinline__ void step_segments(const StepArgs &a, const MlpInfer 
                 bld2(V.col, in[j] ? (uint32_t)(s * u) * (uint32_t)(2 * sizeof(T)) : kNoLoad, ca[j], sa[j]);
             }
         }
+        // A chunk none of whose lanes has a return (sky rows, mostly) adds
+        // exact zeros to every sum (e = 0, w = 0, finite J) and counts
+        // nothing: the wavefront skips it after the range loads (one
+        // wave-uniform branch; debug dumps keep every segment).
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j)
+            any = any || range_ok(rs[j]);
+        if (!dbg && __builtin_amdgcn_ballot_w64(any) == 0)
+            continue;
         bool proj[CHUNK];
         int ul[CHUNK], vl[CHUNK];
         T xx[CHUNK], xy[CHUNK], xz[CHUNK], xr[CHUNK];
