@@ -394,6 +394,23 @@ rir_status rir_mlp_forward(const rir_mlp *mlp, const float *feats, int64_t B, fl
 rir_status rir_mlp_train_step(rir_mlp *mlp, const float *feats, const float *labels, int64_t B, float lr,
                               float *loss_out, float *grads_out, void *stream);
 
+/* rir_mlp_train_step without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * results as rir_mlp_train_step (bit-identical for the same inputs); the
+ * per-wavefront gradient records go to a fixed device array of 512 records
+ * of 5186 FP32 (10.1 MiB) that the library holds on every GPU it runs on
+ * until the process ends, instead of a buffer it allocates.  B is limited to
+ * 1..32768 (the records of larger batches do not fit).  Every record is
+ * rewritten by each call before it is read, so nothing needs clearing
+ * between calls; all calls on one GPU share that GPU's array, so calls that
+ * may overlap on one GPU (different streams, threads or networks) race and
+ * must be serialised by the caller.  Calls no hipMalloc or hipFree.  Errors:
+ * RIR_E_INVALID (null, B outside 1..32768, lr not finite or < 0),
+ * RIR_E_HIP. */
+rir_status rir_mlp_train_step_noalloc(rir_mlp *mlp, const float *feats, const float *labels, int64_t B, float lr,
+                                      float *loss_out, float *grads_out, void *stream);
+
 /* ---------------------------------------------------------------- errors */
 
 /* Message of the calling thread's last failed call ("" if none). */

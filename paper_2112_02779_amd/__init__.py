@@ -31,7 +31,7 @@ EXPORTS = [
     "rir_normals", "rir_icp_batch", "rir_debug_associate", "rir_autotune", "rir_mlp_create", "rir_mlp_destroy",
     "rir_mlp_get_params", "rir_mlp_set_params", "rir_mlp_forward", "rir_mlp_train_step", "rir_last_error",
     "rir_elevation_table", "rir_sdf_integrate", "rir_normals_pca", "rir_deskew",
-    "rir_sdf_extract",
+    "rir_sdf_extract", "rir_mlp_train_step_noalloc",
 ]
 
 
@@ -126,6 +126,7 @@ def lib():
         "rir_mlp_set_params": [vp, ctypes.POINTER(ctypes.c_uint16), ctypes.POINTER(f32)],
         "rir_mlp_forward": [vp, vp, i64, vp, vp],
         "rir_mlp_train_step": [vp, vp, vp, i64, f32, vp, vp, vp],
+        "rir_mlp_train_step_noalloc": [vp, vp, vp, i64, f32, vp, vp, vp],
         "rir_sdf_extract": [ctypes.POINTER(VolumeDesc), vp, f64, f64, vp, i64, vp, vp],
         "rir_deskew": [vp, i32, vp, ctypes.POINTER(f64), vp, vp],
         "rir_normals_pca": [vp, i32, vp, i32, f64, vp, vp, vp],

@@ -1565,4 +1565,27 @@ extern "C" rir_status rir_mlp_train_step(rir_mlp *m, const float *feats, const f
     return RIR_OK;
 }
 
+extern "C" rir_status rir_mlp_train_step_noalloc(rir_mlp *m, const float *feats, const float *labels, int64_t B,
+                                                 float lr, float *loss_out, float *grads_out, void *stream)
+{
+    if (!m || !feats || !labels)
+        return fail(RIR_E_INVALID, "rir_mlp_train_step_noalloc: null argument");
+    if (B < 1 || B > kMlpScratchMaxB)
+        return fail(RIR_E_INVALID, "rir_mlp_train_step_noalloc: B must be in 1..32768 (the gradient records of "
+                                   "larger batches do not fit the library's fixed scratch array)");
+    if (!(lr >= 0.f) || !std::isfinite(lr))
+        return fail(RIR_E_INVALID, "rir_mlp_train_step_noalloc: lr must be finite and >= 0");
+    HIP_TRY(hipSetDevice(m->device));
+    float *recs = nullptr;
+    HIP_TRY(mlp_scratch(m->device, &recs));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // every record is written in full by the gradient kernel before the Adam
+    // kernel reads it: nothing in the array needs clearing
+    const int nb = mlp_grad_blocks(B);
+    HIP_TRY(launch_mlp_grad(m->dev(), feats, labels, B, recs, nb, st));
+    m->step += 1;
+    HIP_TRY(launch_mlp_adam(recs, nb, B, lr, m->step, m->master, m->b, m->m1, m->m2, m->w, loss_out, grads_out, st));
+    return RIR_OK;
+}
+
 extern "C" const char *rir_last_error(void) { return g_err.c_str(); }

@@ -8,6 +8,8 @@
 //            of these rounded deltas.
 // Gradients are reduced without atomics: every wavefront writes one record,
 // and the update kernel sums the records in a fixed order.
+#include <mutex>
+
 #include "rir_internal.h"
 #include "rir_mlp_device.h"
 
@@ -285,6 +287,32 @@ __global__ __launch_bounds__(256) void k_mlp_adam(const float *gpart, int nrec, 
     } else {
         bias[bi] -= upd;
     }
+}
+
+// Gradient records of the allocation-free training step: a fixed device array
+// of kMlpScratchRecords records (10.1 MiB), one copy per GPU for the life of
+// the process.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current.
+static __device__ __align__(256) float scratch[(size_t)kMlpScratchRecords * kMlpGradRecord];
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[kMlpMaxDevices] = {};
+
+hipError_t mlp_scratch(int device, float **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMlpMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch_ptr[device] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 int mlp_grad_blocks(int64_t B)

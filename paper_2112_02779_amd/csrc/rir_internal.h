@@ -138,5 +138,14 @@ hipError_t launch_mlp_adam(const float *gpart, int nblocks, int64_t B, float lr,
                            hipStream_t stream);
 int mlp_grad_blocks(int64_t B);
 constexpr int kMlpGradRecord = 5185 + 1;  // gradient + loss per block
+// Allocation-free training step: its gradient records live in a fixed device
+// array of kMlpScratchRecords records per GPU, which holds the records of
+// batches up to kMlpScratchMaxB samples (mlp_grad_blocks(kMlpScratchMaxB) ==
+// kMlpScratchRecords).  mlp_scratch returns the array's device address on
+// `device` (which must be current), looked up once per device.
+constexpr int kMlpScratchRecords = 512;
+constexpr int64_t kMlpScratchMaxB = 32768;
+constexpr int kMlpMaxDevices = 64;
+hipError_t mlp_scratch(int device, float **out);
 
 }  // namespace rir
