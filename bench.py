@@ -761,7 +761,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=None,
-                    help="block,px_per_thread,grid_mult,xcd_remap,chunk to use instead of autotuning")
+                    help="block,px_per_thread,grid_mult,xcd_remap,chunk[,solve_in_step] to use instead of autotuning")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (value then unchecked)")
     ap.add_argument("--sample-every", type=int, default=1,
                     help="oracle-check every k-th pair of the sequence (1: all)")
@@ -808,8 +808,7 @@ def main():
 
     tuning, tune_ms = None, None
     if args.tuning:
-        b, ppt, gm, xcd, ch = (int(x) for x in args.tuning.split(","))
-        ctx.set_tuning(b, ppt, gm, xcd, ch)
+        ctx.set_tuning(*(int(x) for x in args.tuning.split(",")))
     elif not args.no_autotune:
         t1 = time.perf_counter()
         tuning, tune_ms = rir.autotune(ctx, params, batch, init)

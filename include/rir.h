@@ -156,9 +156,13 @@ typedef struct {
  * 4x fewer, at least 1); grid_mult: persistent workgroups per compute unit (0 =
  * one workgroup per tile); xcd_remap: 1 maps consecutive tiles to the same
  * XCD (L2) of the chip; chunk: 64-pixel row segments whose loads each
- * wavefront keeps in flight together (1, 2 or 4). */
+ * wavefront keeps in flight together (1, 2 or 4); solve_in_step: 1 (with
+ * grid_mult 0) lets the workgroup that finishes a pair's last tile of an
+ * iteration solve that pair (one launch per Gauss-Newton iteration), 0 solves
+ * every pair in a launch of its own after each association/reduction launch;
+ * both sum the tile records in the same order and give the same results. */
 typedef struct {
-    int32_t block, px_per_thread, grid_mult, xcd_remap, chunk;
+    int32_t block, px_per_thread, grid_mult, xcd_remap, chunk, solve_in_step;
 } rir_tuning;
 
 /* ---------------------------------------------------------------- sensors */

@@ -401,6 +401,7 @@ struct Plan {
     double *d_poses = nullptr;
     rir_level_stats *d_stats = nullptr;
     int *d_flags = nullptr;
+    int *d_tickets = nullptr;  // [n_pairs], right after the flags
     std::vector<const float *> cur_src, cur_dst;
     hipEvent_t desc_evt = nullptr;
     bool desc_pending = false;
@@ -433,7 +434,7 @@ struct rir_ctx {
     int device = 0;
     int n_cu = 256;
     hipStream_t cap = nullptr;  // private stream used only for graph capture
-    rir_tuning tune{256, 8, 0, 1, 4};
+    rir_tuning tune{256, 8, 0, 1, 4, 1};
     std::map<PlanKey, std::unique_ptr<Plan>> plans;
     uint64_t use_clock = 0;
     int timing = 0;  // 0 off, 1 every level and the prepass, 2 the finest level only
@@ -499,6 +500,8 @@ static rir_status check_tuning(const rir_tuning *t)
         return fail(RIR_E_INVALID, "rir_tuning.chunk must be 1, 2 or 4");
     if (t->xcd_remap != 0 && t->xcd_remap != 1)
         return fail(RIR_E_INVALID, "rir_tuning.xcd_remap must be 0 or 1");
+    if (t->solve_in_step != 0 && t->solve_in_step != 1)
+        return fail(RIR_E_INVALID, "rir_tuning.solve_in_step must be 0 or 1");
     return RIR_OK;
 }
 
@@ -719,7 +722,7 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     size_t o_pcnt = lay.add((size_t)max_tiles * sizeof(int4));
     size_t o_pose = lay.add((size_t)n * 16 * sizeof(double));
     size_t o_stats = lay.add((size_t)n * L * sizeof(rir_level_stats));
-    size_t o_flags = lay.add((size_t)n * kFlagStride * sizeof(int));
+    size_t o_flags = lay.add((size_t)(n * kFlagStride + n) * sizeof(int));  // flags, then tickets
     std::vector<size_t> o_src(n * kMaxLevels, 0), o_dstr(n * kMaxLevels, 0), o_dst4(n * kMaxLevels, 0);
     std::vector<size_t> o_frames(n, 0);
     for (int i = 0; i < n; ++i) {
@@ -736,7 +739,7 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     }
     HIP_TRY(hipMalloc(&P->dmem, lay.bytes));
     char *base = static_cast<char *>(P->dmem);
-    HIP_TRY(hipMemset(base + o_flags, 0, (size_t)n * kFlagStride * sizeof(int)));
+    HIP_TRY(hipMemset(base + o_flags, 0, (size_t)(n * kFlagStride + n) * sizeof(int)));
     P->d_desc = base + o_desc;
     for (int l = 0; l < L; ++l) {
         P->d_tiles[l] = reinterpret_cast<int2 *>(base + o_tiles[l]);
@@ -747,6 +750,7 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     P->d_poses = reinterpret_cast<double *>(base + o_pose);
     P->d_stats = reinterpret_cast<rir_level_stats *>(base + o_stats);
     P->d_flags = reinterpret_cast<int *>(base + o_flags);
+    P->d_tickets = P->d_flags + (size_t)n * kFlagStride;
     HIP_TRY(hipHostMalloc(&P->h_desc, P->desc_bytes, hipHostMallocDefault));
     std::memset(P->h_desc, 0, P->desc_bytes);
     for (int i = 0; i < n; ++i) {
@@ -901,6 +905,9 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
     a.poses = P->d_poses;
     a.stats = P->d_stats;
     a.flags = P->d_flags;
+    a.tickets = P->d_tickets;
+    // the solving step launch covers one tile per workgroup
+    a.fused = (mode != kStepDebug && P->key.k.tune.solve_in_step && P->key.k.tune.grid_mult == 0) ? 1 : 0;
     a.delta = p->delta;
     a.max_corr = p->max_corr_dist;
     a.stop_eps = p->stop_eps;
@@ -913,7 +920,7 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
 // Enqueues the normal/pyramid pass (and the flag/statistics reset).
 rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t st)
 {
-    HIP_TRY(launch_clear(P->d_flags, P->n_pairs * kFlagStride, P->d_stats, P->n_pairs * P->key.k.levels, st));
+    HIP_TRY(launch_clear(P->d_flags, P->n_pairs * (kFlagStride + 1), P->d_stats, P->n_pairs * P->key.k.levels, st));
     PrepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.pairs = P->d_desc;
@@ -942,11 +949,13 @@ rir_status enqueue_level(const Plan *P, const rir_icp_params *p, int l, hipStrea
     for (int it = 0; it < P->key.k.iters[l]; ++it) {
         StepArgs a = step_args(P, p, l, it, kStepNormal);
         HIP_TRY(launch_step(P->fp64, a.learned ? RIR_WEIGHT_LEARNED : RIR_WEIGHT_HUBER, a, P->grid[l], P->block, st));
-        HIP_TRY(launch_solve(P->fp64, a, P->n_pairs, st));
+        if (!a.fused)
+            HIP_TRY(launch_solve(P->fp64, a, P->n_pairs, st));
         if (a.learned) {
             StepArgs b = step_args(P, p, l, it, kStepFallback);
             HIP_TRY(launch_step(P->fp64, RIR_WEIGHT_HUBER, b, P->grid[l], P->block, st));
-            HIP_TRY(launch_solve(P->fp64, b, P->n_pairs, st));
+            if (!b.fused)
+                HIP_TRY(launch_solve(P->fp64, b, P->n_pairs, st));
         }
     }
     return RIR_OK;
@@ -1217,7 +1226,7 @@ extern "C" rir_status rir_autotune(rir_ctx *ctx, const rir_icp_params *params, i
         for (int ppt : ppts)
             for (int gm : gms)
                 for (int ch : chunks) {
-                    rir_tuning t{b, ppt, gm, 1, ch};
+                    rir_tuning t{b, ppt, gm, 1, ch, 1};
                     s = rir_ctx_set_tuning(ctx, &t);
                     if (s != RIR_OK)
                         break;

@@ -312,187 +312,202 @@ __global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
 
 // ----------------------------------------------------------------------------- solve
 
-// Solves H xi = -g in FP64 with H = U^T U (U upper triangular, computed in
-// place over the 21 packed row-major entries of H).  Fails when a pivot is not
-// above 1e-12 times the largest diagonal entry.  Fully unrolled so that every
-// array stays in registers; the substitutions multiply by the reciprocal
-// pivots (six divisions on the serial path instead of eighteen).
-__device__ __forceinline__ bool cholesky6(double (&U)[21], const double (&g)[6], double (&xi)[6])
+// FP64 lane exchange helpers for the wavefront solve.
+__device__ __forceinline__ double rlane(double v, int src)
 {
-    constexpr int off[6] = {0, 6, 11, 15, 18, 20};  // start of row i of the packed triangle
-    double dmax = 0.0, rdiag[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-        dmax = U[off[i]] > dmax ? U[off[i]] : dmax;
-    if (!(dmax > 0.0))
-        return false;
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        double d = U[off[j]];
-#pragma unroll
-        for (int k = 0; k < j; ++k)
-            d -= U[off[k] + j - k] * U[off[k] + j - k];
-        ok = ok && (d > 1e-12 * dmax);
-        d = sqrt(d > 0.0 ? d : 1.0);
-        U[off[j]] = d;
-        const double inv = 1.0 / d;
-        rdiag[j] = inv;
-#pragma unroll
-        for (int i = j + 1; i < 6; ++i) {
-            double acc = U[off[j] + i - j];
-#pragma unroll
-            for (int k = 0; k < j; ++k)
-                acc -= U[off[k] + j - k] * U[off[k] + i - k];
-            U[off[j] + i - j] = acc * inv;
-        }
-    }
-    if (!ok)
-        return false;
-    double y[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        double acc = -g[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k)
-            acc -= U[off[k] + i - k] * y[k];
-        y[i] = acc * rdiag[i];
-    }
-#pragma unroll
-    for (int i = 5; i >= 0; --i) {
-        double acc = y[i];
-#pragma unroll
-        for (int k = i + 1; k < 6; ++k)
-            acc -= U[off[i] + k - i] * xi[k];
-        xi[i] = acc * rdiag[i];
-    }
-    return true;
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
+__device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
 
-// T <- Exp(xi) T with Exp(xi) = [R, V tau]: R = I + A K + B K^2,
-// V = I + B K + C K^2, K = [omega]x, K^2 = omega omega^T - |omega|^2 I,
-// A = sin a / a, B = (1 - cos a) / a^2, C = (a - sin a) / a^3 (Taylor below
-// a = 1e-6).
-__device__ __forceinline__ void se3_left_update(const double (&xi)[6], double *T)
-{
-    const double w[3] = {xi[0], xi[1], xi[2]};
-    const double a2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2], a = sqrt(a2);
-    double A, B, C;
-    if (a < 1e-6) {
-        A = 1.0 - a2 / 6.0;
-        B = 0.5 - a2 / 24.0;
-        C = 1.0 / 6.0 - a2 / 120.0;
-    } else {
-        double sn, cs;
-        sincos(a, &sn, &cs);
-        A = sn / a;
-        B = (1.0 - cs) / a2;
-        C = (a - sn) / (a2 * a);
-    }
-    const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
-    double E[12];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        double t = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double I = i == j ? 1.0 : 0.0;
-            const double K2 = w[i] * w[j] - I * a2;
-            E[4 * i + j] = I + A * K[3 * i + j] + B * K2;
-            t += (I + B * K[3 * i + j] + C * K2) * xi[3 + j];
-        }
-        E[4 * i + 3] = t;
-    }
-    double To[12], Tn[12];
-#pragma unroll
-    for (int i = 0; i < 12; ++i)
-        To[i] = T[i];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            double acc = j == 3 ? E[4 * i + 3] : 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                acc += E[4 * i + k] * To[4 * k + j];
-            Tn[4 * i + j] = acc;
-        }
-#pragma unroll
-    for (int i = 0; i < 12; ++i)
-        T[i] = Tn[i];
-}
+// Start of row r of the packed upper triangle of a symmetric 6x6 matrix
+// (21 entries, row-major): entry (r, c), c >= r, is tri_off(r) + c - r.
+__device__ __forceinline__ int tri_off(int r) { return r * 6 - (r * (r - 1)) / 2; }
 
-// The solve of one pair (one thread): statistics, Cholesky, the left SE(3)
-// update of the pose (copied to pose_out).  Returns whether the pose moved.
-__device__ __forceinline__ bool solve_pair(const StepArgs &a, int pair, int *fl, const double *tot,
-                                        const long long *cnt, double *pose_out)
+// The Gauss-Newton update of one pair (Eq. (7)) by one wavefront, each lane
+// holding one entry, so that the solve needs few registers and no single
+// lane walks the whole factorisation:
+//  - lane t < 21 holds entry t of the packed J^T W J; the upper Cholesky
+//    factor U (U^T U = J^T W J) is formed in place, right-looking: at step j
+//    row j is finished (pivot sqrt, row scaled by its reciprocal) and every
+//    later entry (r, c) subtracts U(j, r) U(j, c), so each entry sees its
+//    subtractions in ascending j as in the textbook left-looking form.  A
+//    pivot not above 1e-12 times the largest diagonal entry fails;
+//  - lanes 0..5 solve U^T y = -g, then U xi = y;
+//  - lanes 0..11 form T <- Exp(xi) T (left update, Exp(xi) = [R, V tau] with
+//    R = I + A K + B K^2, V = I + B K + C K^2, K = [omega]x, A = sin a / a,
+//    B = (1 - cos a) / a^2, C = (a - sin a) / a^3, Taylor below a = 1e-6),
+//    one pose entry each.
+// Then the per-level statistics.  tot: the 30 FP64 sums (J^T W J, J^T W e,
+// sum w, sum w e^2, robust cost), cnt: valid, inlier and projection counts.
+// Called by all 64 lanes of one wavefront; returns (wave-uniform) whether the
+// pose moved, and then leaves the new pose in pose_out[0..11].
+__device__ __forceinline__ bool solve_pair_wave(const StepArgs &a, int pair, int *fl, const double *tot,
+                                                const long long *cnt, double *pose_out)
 {
+    int lane = threadIdx.x & 63;
+    // opaque to the optimiser, so that the lane-dependent constants below are
+    // formed here and not hoisted into (and kept live through) the caller's
+    // pixel loop
+    asm volatile("" : "+v"(lane));
     const int l = a.level;
-    double U[21], g[6];
+    const bool isU = lane < 21;
+    int ur = 0, uc = 0;  // (row, column) of this lane's entry
+    {
+        int t = lane;
 #pragma unroll
-    for (int k = 0; k < 21; ++k)
-        U[k] = tot[k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        g[k] = tot[21 + k];
+        for (int r = 0; r < 6; ++r) {
+            const int len = 6 - r;
+            if (t >= 0 && t < len) {
+                ur = r;
+                uc = r + t;
+            }
+            t -= len;
+        }
+    }
+    const double tv = lane < 30 ? tot[lane] : 0.0;
     const double sum_w = tot[27], sum_we2 = tot[28], rho = tot[29];
     const int n_valid = (int)cnt[0];
-    bool finite = isfinite(sum_w) && isfinite(sum_we2) && isfinite(rho);
-#pragma unroll
-    for (int k = 0; k < 21; ++k)
-        finite = finite && isfinite(U[k]);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        finite = finite && isfinite(g[k]);
+    const bool finite = __builtin_amdgcn_ballot_w64(lane < 30 && !isfinite(tv)) == 0;
     rir_level_stats *out = a.stats + (a.mode == kStepDebug ? 0 : (size_t)pair * a.levels + l);
+    if (isU)
+        out->JtJ[lane] = tv;
+    double U = isU ? tv : 0.0;
+    double dmax = 0.0;
 #pragma unroll
-    for (int k = 0; k < 21; ++k)
-        out->JtJ[k] = U[k];
-    double xi[6] = {0, 0, 0, 0, 0, 0};
-    const bool ok = n_valid >= 6 && finite && cholesky6(U, g, xi);
+    for (int j = 0; j < 6; ++j) {
+        const double d = rlane(U, tri_off(j));
+        dmax = d > dmax ? d : dmax;
+    }
+    bool ok = n_valid >= 6 && finite && dmax > 0.0;
+    double rinv = 0.0, v = 0.0;  // lane j < 6: 1 / U(j, j); then y_j, then xi_j
+    if (ok) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const double d = rlane(U, tri_off(j));
+            ok = ok && d > 1e-12 * dmax;
+            const double sd = sqrt(d > 0.0 ? d : 1.0), inv = 1.0 / sd;
+            if (lane == j)
+                rinv = inv;
+            if (isU && ur == j)
+                U = uc == j ? sd : U * inv;
+            const bool below = isU && ur > j;
+            const double ar = shfl_d(U, below ? tri_off(j) + ur - j : 0);
+            const double ac = shfl_d(U, below ? tri_off(j) + uc - j : 0);
+            if (below)
+                U -= ar * ac;
+        }
+    }
+    if (ok) {
+        v = -shfl_d(tv, lane < 6 ? 21 + lane : 0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double yk = rlane(v, k) * rlane(rinv, k);
+            const double ukl = shfl_d(U, lane > k && lane < 6 ? tri_off(k) + lane - k : 0);
+            if (lane == k)
+                v = yk;
+            else if (lane > k && lane < 6)
+                v -= ukl * yk;
+        }
+#pragma unroll
+        for (int k = 5; k >= 0; --k) {
+            const double xk = rlane(v, k) * rlane(rinv, k);
+            const double ulk = shfl_d(U, lane < k ? tri_off(lane) + k - lane : 0);
+            if (lane == k)
+                v = xk;
+            else if (lane < k)
+                v -= ulk * xk;
+        }
+    }
     if (a.learned && a.mode == kStepNormal && (!ok || sum_w < 0.1 * (double)n_valid)) {
         // learned weights rejected: the pseudo-Huber pass that follows redoes
         // this iteration and rewrites the statistics
-        fl[kMaxLevels] = 1;
+        if (lane == 0)
+            fl[kMaxLevels] = 1;
         return false;
     }
     int status = a.mode == kStepFallback ? RIR_LEVEL_FALLBACK_HUBER : RIR_LEVEL_OK;
+    if (a.mode == kStepFallback && lane == 0)
+        fl[kMaxLevels] = 0;
     double srot = 0.0, stra = 0.0;
     bool moved = false;
-    if (a.mode == kStepFallback)
-        fl[kMaxLevels] = 0;
     if (!ok) {
         status = finite ? RIR_LEVEL_DEGENERATE : RIR_LEVEL_NONFINITE;
-        if (a.mode != kStepDebug)
+        if (a.mode != kStepDebug && lane == 0)
             fl[l] = 1;
     } else {
-        srot = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
-        stra = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+        const double w0 = rlane(v, 0), w1 = rlane(v, 1), w2 = rlane(v, 2);
+        const double t0 = rlane(v, 3), t1 = rlane(v, 4), t2 = rlane(v, 5);
+        srot = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+        stra = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
         if (a.mode != kStepDebug) {
+            const double a2 = w0 * w0 + w1 * w1 + w2 * w2, an = sqrt(a2);
+            double A, B, C;
+            if (an < 1e-6) {
+                A = 1.0 - a2 / 6.0;
+                B = 0.5 - a2 / 24.0;
+                C = 1.0 / 6.0 - a2 / 120.0;
+            } else {
+                double sn, cs;
+                sincos(an, &sn, &cs);
+                A = sn / an;
+                B = (1.0 - cs) / a2;
+                C = (an - sn) / (a2 * an);
+            }
             double *Tp = a.poses + 16 * (size_t)pair;
-            se3_left_update(xi, Tp);
-            for (int k = 0; k < 12; ++k)
-                pose_out[k] = Tp[k];
+            const int i = (lane >> 2) & 3, j = lane & 3;
+            const double wi = i == 0 ? w0 : (i == 1 ? w1 : w2);
+            const double w[3] = {w0, w1, w2}, tau[3] = {t0, t1, t2};
+            // row i of K = [omega]x
+            const double K[3] = {i == 0 ? 0.0 : (i == 1 ? w2 : -w1), i == 0 ? -w2 : (i == 1 ? 0.0 : w0),
+                                 i == 0 ? w1 : (i == 1 ? -w0 : 0.0)};
+            double Er[3], Et = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double I = i == k ? 1.0 : 0.0;
+                const double K2 = wi * w[k] - I * a2;
+                Er[k] = I + A * K[k] + B * K2;
+                Et += (I + B * K[k] + C * K2) * tau[k];
+            }
+            double Tn = 0.0;
+            if (lane < 12) {
+                double acc = j == 3 ? Et : 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    acc += Er[k] * Tp[4 * k + j];
+                Tn = acc;
+            }
+            // every lane has read the old pose (one load instruction per k)
+            // before any lane stores
+            __builtin_amdgcn_wave_barrier();
+            if (lane < 12) {
+                Tp[lane] = Tn;
+                pose_out[lane] = Tn;
+            }
             moved = true;
             // small-step stop: the level's remaining iterations are skipped
-            if (a.stop_eps > 0.0 && srot * srot + stra * stra <= a.stop_eps * a.stop_eps)
+            if (a.stop_eps > 0.0 && srot * srot + stra * stra <= a.stop_eps * a.stop_eps && lane == 0)
                 fl[l] = 1;
         }
     }
-    out->status = status;
-    out->iters_run = a.iter + 1;
-    out->n_valid = n_valid;
-    out->n_inlier = (int)cnt[1];
-    out->n_proj = (int)cnt[2];
-    out->pad = 0;
-    out->sum_w = sum_w;
-    out->sum_w_e2 = sum_we2;
-    out->robust_cost = rho;
-    out->step_rot = srot;
-    out->step_trans = stra;
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        out->Jtr[k] = g[k];
+    const double gj = shfl_d(tv, lane < 6 ? 21 + lane : 0);  // all lanes exchange
+    if (lane < 6)
+        out->Jtr[lane] = gj;
+    if (lane == 0) {
+        out->status = status;
+        out->iters_run = a.iter + 1;
+        out->n_valid = n_valid;
+        out->n_inlier = (int)cnt[1];
+        out->n_proj = (int)cnt[2];
+        out->pad = 0;
+        out->sum_w = sum_w;
+        out->sum_w_e2 = sum_we2;
+        out->robust_cost = rho;
+        out->step_rot = srot;
+        out->step_trans = stra;
+    }
     return moved;
 }
 
@@ -527,7 +542,9 @@ __device__ __forceinline__ void write_frames(const PairDesc<T> *P, const double 
     const T *row = cload(&tab->row);
     T *fr = cload(&P->frames);
     const int H = cload(&P->H);
-    for (int v = threadIdx.x; v < H; v += blockDim.x)
+    int v0 = threadIdx.x;
+    asm volatile("" : "+v"(v0));  // see solve_pair_wave
+    for (int v = v0; v < H; v += blockDim.x)
         frame_row(row + 4 * (size_t)v, R, fr + (size_t)v * kFrame);
 }
 
@@ -735,15 +752,20 @@ __device__ __forceinline__ void step_segments(const StepArgs &a, const MlpInfer 
     }
 }
 
+template <typename T, bool COHERENT>
+__device__ __forceinline__ void solve_from_tiles(const StepArgs &a, int pair, int *fl);
+
 // One Gauss-Newton iteration at level l for every pair of the batch.  Each
 // workgroup walks its tiles; a tile is a run of tile_seg segments of one
 // pair's level-l image, and its sums go to one record (k_solve reduces them).
 // FINE tags the finest-level instance (same code) so that profiles report it
-// separately.
-template <typename T, int WMODE, bool FINE, int CHUNK, bool LEAN>
+// separately.  FUSED instances (one tile per workgroup) also solve: the
+// workgroup that finishes a pair's last tile applies that pair's update.
+template <typename T, int WMODE, bool FINE, int CHUNK, bool LEAN, bool FUSED>
 __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
 {
     __shared__ T s_wave[4][kAccum];
+    __shared__ int s_last;
     __shared__ int s_wcnt[4][4];
     T *psum = reinterpret_cast<T *>(a.psum);
     const int tid = threadIdx.x, nwave = blockDim.x >> 6, l = a.level;
@@ -752,15 +774,15 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
     MlpInfer F;
     if constexpr (WMODE == 1)
         mlp_infer_load(a.mlp, F);
-    for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step) {
-        const int2 tl = cload(a.tiles + it.cur);
+    auto tile = [&](int cur) {
+        const int2 tl = cload(a.tiles + cur);
         const int pair = tl.x;
         if (!dbg) {
             const int *fl = a.flags + (size_t)pair * kFlagStride;
             if (cload(fl + l) & 1)
-                continue;
+                return;
             if (a.mode == kStepFallback && !(cload(fl + kMaxLevels) & 1))
-                continue;
+                return;
         }
         const PairDesc<T> *P = pairs + pair;
         const double *Tp = a.poses + 16 * (size_t)pair;
@@ -776,7 +798,11 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
             T sum = (T)0;
             for (int w = 0; w < nwave; ++w)
                 sum += s_wave[w][tid];
-            psum[(size_t)it.cur * kAccum + tid] = sum;
+            T *dst = psum + (size_t)cur * kAccum + tid;
+            if constexpr (FUSED)
+                __hip_atomic_store(dst, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                *dst = sum;
         } else if (tid == kAccum) {
             int4 c = make_int4(0, 0, 0, 0);
             for (int w = 0; w < nwave; ++w) {
@@ -784,9 +810,47 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
                 c.y += s_wcnt[w][1];
                 c.z += s_wcnt[w][2];
             }
-            a.pcnt[it.cur] = c;
+            if constexpr (FUSED) {
+                int *dst = reinterpret_cast<int *>(a.pcnt + cur);
+                __hip_atomic_store(dst + 0, c.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(dst + 1, c.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(dst + 2, c.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                a.pcnt[cur] = c;
+            }
+        }
+        if constexpr (FUSED) {
+            // The record is written with agent-scope (device-coherent) stores;
+            // once they have completed, this tile's ticket is taken.  The
+            // workgroup that takes a pair's last ticket has every record of
+            // the pair visible to its agent-scope loads and solves the pair
+            // (the order of the sum does not depend on which workgroup that
+            // is), then resets the pair's ticket count for the next launch.
+            // No workgroup waits for another, and no cache is flushed.
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the record stores are complete
+            __syncthreads();
+            if (tid == 0) {
+                const int t = __hip_atomic_fetch_add(a.tickets + pair, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_last = t == cload(&P->ntile[l]) - 1 ? 1 : 0;
+            }
+            __syncthreads();
+            if (s_last) {
+                solve_from_tiles<T, true>(a, pair, a.flags + (size_t)pair * kFlagStride);
+                if (tid == 0)
+                    __hip_atomic_store(a.tickets + pair, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         __syncthreads();
+    };
+    if constexpr (FUSED) {
+        // one tile per workgroup (no tile loop whose invariants the solve's
+        // constants could be hoisted out of)
+        const TileIter it = tile_iter(a.n_tiles, a.xcd_remap);
+        if (it.cur < it.end)
+            tile(it.cur);
+    } else {
+        for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step)
+            tile(it.cur);
     }
 }
 
@@ -847,16 +911,13 @@ __global__ __launch_bounds__(kPairBlock) void k_icp_level(StepArgs a)
             s_cnt[tid - 64] = c;
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid < 64) {
             StepArgs b = a;
             b.iter = it;
             b.stats_pass = last ? 1 : 0;
-            double out[12];
-            const bool moved = solve_pair(b, pair, fl, s_tot, s_cnt, out);
-            if (moved)
-                for (int k = 0; k < 12; ++k)
-                    s_pose[k] = out[k];
-            s_go = moved && !(fl[l] & 1) ? 1 : 0;  // stopped by a small step
+            const bool moved = solve_pair_wave(b, pair, fl, s_tot, s_cnt, s_pose);
+            if (tid == 0)
+                s_go = moved && !(fl[l] & 1) ? 1 : 0;  // stopped by a small step
         }
         __syncthreads();
         if (!s_go)
@@ -885,12 +946,85 @@ __global__ __launch_bounds__(256) void k_frames(StepArgs a)
     write_frames(P, R);
 }
 
-// Reduction of one pair's tile records in FP64 (tile order, independent of
-// the batch) and the Gauss-Newton update of Eq. (7): Cholesky solve,
-// T <- Exp(xi) T, per-level statistics, then the ray frames of the new pose.
-// One workgroup per pair.
-template <typename T>
-__global__ __launch_bounds__(256) void k_solve(StepArgs a)
+// Sum of one pair's tile records t0 .. t0 + nt - 1 in FP64 in a fixed order
+// that does not depend on the batch or the block size: group g (of 8) of 32
+// threads, one per record entry, adds tiles g, g + 8, ... in that order (four
+// records in flight at a time), then the 8 group sums are added in group
+// order.  Leaves the 30 sums in s_tot and the 3 counts in s_cnt; all threads
+// of the block (64..256) take part.  COHERENT reads the records with
+// agent-scope loads (records written during the same launch by other
+// workgroups, see k_icp_step).
+template <typename T, bool COHERENT>
+__device__ __forceinline__ void reduce_pair_tiles(const StepArgs &a, int t0, int nt, double (*s_part)[kAccum],
+                                                  long long (*s_cpart)[4], double *s_tot, long long *s_cnt)
+{
+    const T *psum = reinterpret_cast<const T *>(a.psum);
+    const int *pcnt = reinterpret_cast<const int *>(a.pcnt);
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));  // see solve_pair_wave
+    const int comp = tid & 31;
+    auto rec = [&](int k) -> T {
+        const T *q = psum + (size_t)(t0 + k) * kAccum + comp;
+        if constexpr (COHERENT)
+            return __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return *q;
+    };
+    auto cnt_of = [&](int k) -> int {
+        const int *q = pcnt + 4 * (size_t)(t0 + k) + comp;
+        if constexpr (COHERENT)
+            return __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return *q;
+    };
+    for (int grp = tid >> 5; grp < 8; grp += (int)(blockDim.x >> 5)) {
+        double sum = 0.0;
+        long long c = 0;
+        int k = grp;
+        for (; k + 24 < nt; k += 32) {
+            const T v0 = rec(k), v1 = rec(k + 8), v2 = rec(k + 16), v3 = rec(k + 24);
+            if (comp < 3) {
+                const int c0 = cnt_of(k), c1 = cnt_of(k + 8), c2 = cnt_of(k + 16), c3 = cnt_of(k + 24);
+                c += c0;
+                c += c1;
+                c += c2;
+                c += c3;
+            }
+            sum += (double)v0;
+            sum += (double)v1;
+            sum += (double)v2;
+            sum += (double)v3;
+        }
+        for (; k < nt; k += 8) {
+            sum += (double)rec(k);
+            if (comp < 3)
+                c += cnt_of(k);
+        }
+        s_part[grp][comp] = sum;
+        if (comp < 3)
+            s_cpart[grp][comp] = c;
+    }
+    __syncthreads();
+    if (tid < 30) {
+        double t = 0.0;
+        for (int g = 0; g < 8; ++g)
+            t += s_part[g][tid];
+        s_tot[tid] = t;
+    } else if (tid >= 32 && tid < 35) {
+        long long t = 0;
+        for (int g = 0; g < 8; ++g)
+            t += s_cpart[g][tid - 32];
+        s_cnt[tid - 32] = t;
+    }
+    __syncthreads();
+}
+
+// The Gauss-Newton update of one pair from its tile records (Eq. (7)):
+// FP64 fixed-order sum, Cholesky solve, T <- Exp(xi) T, per-level
+// statistics, then the ray frames of the new pose.  Run by every thread of
+// one workgroup.
+template <typename T, bool COHERENT>
+__device__ __forceinline__ void solve_from_tiles(const StepArgs &a, int pair, int *fl)
 {
     __shared__ double s_part[8][kAccum];
     __shared__ long long s_cpart[8][4];
@@ -898,7 +1032,31 @@ __global__ __launch_bounds__(256) void k_solve(StepArgs a)
     __shared__ long long s_cnt[4];
     __shared__ double s_pose[12];
     __shared__ int s_moved;
-    const int pair = blockIdx.x, lane = threadIdx.x, l = a.level;
+    const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + pair;
+    const int l = a.level;
+    reduce_pair_tiles<T, COHERENT>(a, cload(&P->tile0[l]), cload(&P->ntile[l]), s_part, s_cpart, s_tot, s_cnt);
+    if (threadIdx.x < 64) {
+        const bool m = solve_pair_wave(a, pair, fl, s_tot, s_cnt, s_pose);
+        if (threadIdx.x == 0)
+            s_moved = m ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_moved) {
+        double R[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            R[k] = s_pose[k];
+        write_frames(P, R);
+    }
+}
+
+// Reduction of one pair's tile records and the Gauss-Newton update, as a
+// launch of its own (one workgroup per pair): the debug pass, whose step
+// launch does not solve.
+template <typename T>
+__global__ __launch_bounds__(256) void k_solve(StepArgs a)
+{
+    const int pair = blockIdx.x, l = a.level;
     int *fl = a.flags + (size_t)pair * kFlagStride;
     if (a.mode != kStepDebug) {
         if (fl[l] & 1)
@@ -906,67 +1064,10 @@ __global__ __launch_bounds__(256) void k_solve(StepArgs a)
         if (a.mode == kStepFallback && !(fl[kMaxLevels] & 1))
             return;
     }
-    const PairDesc<T> &P = reinterpret_cast<const PairDesc<T> *>(a.pairs)[pair];
-    const T *psum = reinterpret_cast<const T *>(a.psum);
-    const int nt = P.ntile[l], t0 = P.tile0[l];
-    if (nt == 0)
+    const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + pair;
+    if (cload(&P->ntile[l]) == 0)
         return;  // the pair-resident kernel runs this pair's level
-    // group g of 32 threads sums tiles g, g + 8, ... in that order (one
-    // coalesced record per step), four records in flight at a time
-    const int comp = lane & 31, grp = lane >> 5;
-    double sum = 0.0;
-    long long c = 0;
-    auto cnt_of = [&](int k) -> int {
-        const int4 pc = a.pcnt[t0 + k];
-        return comp == 0 ? pc.x : (comp == 1 ? pc.y : pc.z);
-    };
-    int k = grp;
-    for (; k + 24 < nt; k += 32) {
-        const T v0 = psum[(size_t)(t0 + k) * kAccum + comp], v1 = psum[(size_t)(t0 + k + 8) * kAccum + comp];
-        const T v2 = psum[(size_t)(t0 + k + 16) * kAccum + comp], v3 = psum[(size_t)(t0 + k + 24) * kAccum + comp];
-        if (comp < 3) {
-            const int c0 = cnt_of(k), c1 = cnt_of(k + 8), c2 = cnt_of(k + 16), c3 = cnt_of(k + 24);
-            c += c0;
-            c += c1;
-            c += c2;
-            c += c3;
-        }
-        sum += (double)v0;
-        sum += (double)v1;
-        sum += (double)v2;
-        sum += (double)v3;
-    }
-    for (; k < nt; k += 8) {
-        sum += (double)psum[(size_t)(t0 + k) * kAccum + comp];
-        if (comp < 3)
-            c += cnt_of(k);
-    }
-    s_part[grp][comp] = sum;
-    if (comp < 3)
-        s_cpart[grp][comp] = c;
-    __syncthreads();
-    if (lane < 30) {
-        double t = 0.0;
-        for (int g = 0; g < 8; ++g)
-            t += s_part[g][lane];
-        s_tot[lane] = t;
-    } else if (lane >= 32 && lane < 35) {
-        long long t = 0;
-        for (int g = 0; g < 8; ++g)
-            t += s_cpart[g][lane - 32];
-        s_cnt[lane - 32] = t;
-    }
-    __syncthreads();
-    if (lane == 0)
-        s_moved = solve_pair(a, pair, fl, s_tot, s_cnt, s_pose) ? 1 : 0;
-    __syncthreads();
-    if (s_moved) {
-        double R[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k)
-            R[k] = s_pose[k];
-        write_frames(&P, R);
-    }
+    solve_from_tiles<T, false>(a, pair, fl);
 }
 
 // ----------------------------------------------------------------------------- launchers
@@ -1048,13 +1149,22 @@ hipError_t launch_frames(bool fp64, const StepArgs &a, int n_pairs, hipStream_t 
     return hipGetLastError();
 }
 
+template <typename T, int WMODE, int CHUNK, bool LEAN, bool FUSED>
+static void launch_step_f(const StepArgs &a, int grid, int block, hipStream_t stream)
+{
+    if (a.level == 0)
+        hipLaunchKernelGGL((k_icp_step<T, WMODE, true, CHUNK, LEAN, FUSED>), dim3(grid), dim3(block), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_icp_step<T, WMODE, false, CHUNK, LEAN, FUSED>), dim3(grid), dim3(block), 0, stream, a);
+}
+
 template <typename T, int WMODE, int CHUNK, bool LEAN>
 static void launch_step_l(const StepArgs &a, int grid, int block, hipStream_t stream)
 {
-    if (a.level == 0)
-        hipLaunchKernelGGL((k_icp_step<T, WMODE, true, CHUNK, LEAN>), dim3(grid), dim3(block), 0, stream, a);
+    if (a.fused)
+        launch_step_f<T, WMODE, CHUNK, LEAN, true>(a, grid, block, stream);
     else
-        hipLaunchKernelGGL((k_icp_step<T, WMODE, false, CHUNK, LEAN>), dim3(grid), dim3(block), 0, stream, a);
+        launch_step_f<T, WMODE, CHUNK, LEAN, false>(a, grid, block, stream);
 }
 
 template <typename T, int WMODE, int CHUNK>

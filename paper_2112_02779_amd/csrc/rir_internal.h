@@ -84,6 +84,9 @@ struct StepArgs {
                          // cost, inlier and projection counts); set on the last
                          // scheduled iteration of a level and in debug mode
     int learned;         // the normal pass uses learned weights
+    int fused;           // 1: the workgroup that finishes a pair's last tile
+                         // solves that pair (no separate solve launch)
+    int *tickets;        // [n_pairs] tiles finished in this launch (fused)
     void *psum;          // T[n_tiles][kAccum]
     int4 *pcnt;          // [n_tiles] (n_valid, n_inlier, n_proj, 0)
     double *poses;       // [n_pairs][16]

@@ -223,3 +223,26 @@ def test_learned_combined_workload_pair_matches_oracle(rir):
     T, _ = rir.icp_batch(_ctx(rir), prm, _batch(rir, pairs))
     _check_poses(pairs, T.cpu().numpy(), dict(levels=3, iters=[10, 10, 10], weight_mode=1, mlp=P, r_max=80.0,
                                              learned_levels=0b001))
+
+
+@pytest.mark.parametrize("mode", ["plain", "learned"])
+def test_solve_in_step_equals_separate_solve_launch(rir, mode):
+    """The update applied by the workgroup that finishes a pair's last tile
+    (solve_in_step = 1) equals the one of a separate solve launch per
+    iteration bit for bit (same tile records, same summation order), on a
+    mixed batch with tiled and pair-resident levels; learned weights at the
+    finest level with a seeded network (pseudo-Huber redo path included)."""
+    import torch
+    pairs = [synth.gen_pair(synth.CONFIGS["dynamic64"], 60), synth.gen_pair(synth.CONFIGS["pair64"], 61),
+             synth.gen_pair(synth.CONFIGS["combined64mixed"], 4002)]
+    kw = {}
+    if mode == "learned":
+        kw = dict(weight_mode=rir.WEIGHT_LEARNED, mlp=rir.Mlp(_seeded_network(62)), r_max=80.0, learned_levels=0b001)
+    prm = rir.make_params(levels=3, iters=[10, 10, 10], delta=0.5, **kw)
+    out = []
+    for fused in (0, 1):
+        T, st = rir.icp_batch(_ctx(rir, (256, 8, 0, 1, 4, fused)), prm, _batch(rir, pairs))
+        torch.cuda.synchronize()
+        out.append((T.cpu().numpy(), rir.stats_to_numpy(st, len(pairs), 3)))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1].tobytes() == out[1][1].tobytes()
