@@ -857,7 +857,8 @@ def main():
     traffic = counted_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "rir::k_icp_step<float, 0, true, *> + rir::k_solve<float> (finest-level iteration)",
+                "kernel": "rir::k_icp_step<float, 0, true, *> (finest-level iteration; with solve_in_step the pair "
+                          "solve runs in the same launch, else one rir::k_solve<float> launch follows)",
                 "bytes_per_launch": bytes_l0, "launch_ms": round(l0_launch_ms, 5)}
 
     roofline["frac_of_measured_copy"] = round(achieved / copy["GBps"], 4)
