@@ -402,6 +402,8 @@ struct Plan {
     rir_level_stats *d_stats = nullptr;
     int *d_flags = nullptr;
     int *d_tickets = nullptr;  // [n_pairs], right after the flags
+    bool nbf[kMaxLevels] = {};       // level keeps the learned weight's neighbour features
+    size_t max_px[kMaxLevels] = {};  // largest level image of the batch
     std::vector<const float *> cur_src, cur_dst;
     hipEvent_t desc_evt = nullptr;
     bool desc_pending = false;
@@ -724,6 +726,13 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
     size_t o_stats = lay.add((size_t)n * L * sizeof(rir_level_stats));
     size_t o_flags = lay.add((size_t)(n * kFlagStride + n) * sizeof(int));  // flags, then tickets
     std::vector<size_t> o_src(n * kMaxLevels, 0), o_dstr(n * kMaxLevels, 0), o_dst4(n * kMaxLevels, 0);
+    std::vector<size_t> o_nbf(n * kMaxLevels, 0);
+    // learned levels of FP32 plans keep the network's neighbour features of
+    // every target pixel (16 B per pixel, computed once per call)
+    auto nbf_level = [&](int l) {
+        return !P->fp64 && !key.k.debug && key.k.weight_mode == RIR_WEIGHT_LEARNED &&
+               (key.k.learned_levels == 0 || ((key.k.learned_levels >> l) & 1));
+    };
     std::vector<size_t> o_frames(n, 0);
     for (int i = 0; i < n; ++i) {
         const rir_sensor *s = pairs[i].sensor;
@@ -735,6 +744,15 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
                 o_dstr[i * kMaxLevels + l] = lay.add(Nl * sizeof(float));
             }
             o_dst4[i * kMaxLevels + l] = lay.add(Nl * 4 * tsz);
+            if (nbf_level(l))
+                o_nbf[i * kMaxLevels + l] = lay.add(Nl * 16);
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        P->nbf[l] = nbf_level(l);
+        for (int i = 0; i < n; ++i) {
+            const size_t Nl = (size_t)(pairs[i].sensor->H >> l) * (pairs[i].sensor->W >> l);
+            P->max_px[l] = std::max<size_t>(P->max_px[l], Nl);
         }
     }
     HIP_TRY(hipMalloc(&P->dmem, lay.bytes));
@@ -765,6 +783,7 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
                 d->src[l] = nullptr;
                 d->dstr[l] = nullptr;
                 d->dst4[l] = nullptr;
+                d->nbf[l] = nullptr;
                 d->tile0[l] = d->ntile[l] = 0;
             }
             for (int l = 0; l < L; ++l) {
@@ -774,6 +793,8 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
                     d->dstr[l] = reinterpret_cast<float *>(base + o_dstr[i * kMaxLevels + l]);
                 }
                 d->dst4[l] = reinterpret_cast<TT *>(base + o_dst4[i * kMaxLevels + l]);
+                if (P->nbf[l])
+                    d->nbf[l] = reinterpret_cast<uint32_t *>(base + o_nbf[i * kMaxLevels + l]);
                 d->tile0[l] = t0[i * kMaxLevels + l];
                 d->ntile[l] = nt[i * kMaxLevels + l];
             }
@@ -934,6 +955,14 @@ rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t s
     a.poses = P->d_poses;
     a.xcd_remap = P->key.k.tune.xcd_remap;
     HIP_TRY(launch_prepass(P->fp64, a, P->grid[0], P->block, P->n_pairs, st));
+    for (int l = 0; l < P->key.k.levels; ++l)
+        if (P->nbf[l]) {
+            NbrArgs b;
+            b.pairs = P->d_desc;
+            b.level = l;
+            b.delta = p->delta;
+            HIP_TRY(launch_nbr_feats(b, P->n_pairs, (int)P->max_px[l], st));
+        }
     StepArgs f = step_args(P, p, 0, 0, kStepNormal);
     HIP_TRY(launch_frames(P->fp64, f, P->n_pairs, st));
     return RIR_OK;

@@ -310,6 +310,26 @@ __global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
     }
 }
 
+// Neighbour features of the learned weight (PairDesc::nbf) for every target
+// pixel of level l of every pair that keeps them: grid (pixel blocks, pair).
+// FP32 plans only (the step's features are then read back bit for bit).
+__global__ __launch_bounds__(256) void k_nbr_feats(NbrArgs a)
+{
+    const PairDesc<float> *P = reinterpret_cast<const PairDesc<float> *>(a.pairs) + blockIdx.y;
+    const int l = a.level;
+    uint32_t *out = cload(&P->nbf[l]);
+    if (!out)
+        return;
+    const int Hl = cload(&P->H) >> l, Wl = cload(&P->W) >> l, n = Hl * Wl;
+    const float *img = cload(&P->dstr[l]);
+    const float inv_delta = (float)(1.0 / a.delta);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int vl = i / Wl, ul = i - vl * Wl;
+        const uint4 f = neighbour_features<float>(img, Hl, Wl, ul, vl, img[i], inv_delta);
+        reinterpret_cast<uint4 *>(out)[i] = f;
+    }
+}
+
 // ----------------------------------------------------------------------------- solve
 
 // FP64 lane exchange helpers for the wavefront solve.
@@ -581,6 +601,7 @@ __device__ __forceinline__ void step_segments(const StepArgs &a, const MlpInfer 
     const uint32_t lane4 = 4u * (uint32_t)lane, lane_col = (uint32_t)(lane << l) * (uint32_t)(2 * sizeof(T));
     const LevelView<T> V = level_view(cload(&P->tab), l);
     const LevelImage LI = {cload(&P->dstr[l]), V.Hl, V.Wl};
+    const uint32_t *nbf = WMODE == 1 && !dbg ? cload(&P->nbf[l]) : nullptr;
     const T r00 = pose[0], r01 = pose[1], r10 = pose[4], r11 = pose[5], r20 = pose[8], r21 = pose[9];
     const T t0 = pose[3], t1 = pose[7], t2 = pose[11];
     const int Wl = V.Wl, Hl = V.Hl, spr = (Wl + kSegPx - 1) / kSegPx;
@@ -700,7 +721,7 @@ __device__ __forceinline__ void step_segments(const StepArgs &a, const MlpInfer 
             if constexpr (WMODE == 1) {
                 if (a.mode != kStepFallback)
                     w = learned_weight<T>(a, F, LI, valid, ul[j], vl[j], e, xr[j], n0, n1, n2,
-                                          dbg ? a.dbg_feat : nullptr, i);
+                                          dbg ? a.dbg_feat : nullptr, i, nbf);
             }
             w = valid ? w : (T)0;
             c_valid += valid ? 1 : 0;
@@ -1128,6 +1149,12 @@ hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, int
         else
             hipLaunchKernelGGL(k_centroid<float>, dim3(n_pairs), dim3(64), 0, stream, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_nbr_feats(const NbrArgs &a, int n_pairs, int max_px, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_nbr_feats, dim3(grid_for(max_px, 256), n_pairs), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

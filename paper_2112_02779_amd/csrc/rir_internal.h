@@ -31,6 +31,11 @@ struct PairDesc {
     float *src[kMaxLevels];
     float *dstr[kMaxLevels];
     T *dst4[kMaxLevels];
+    // levels with learned weights: per target pixel the 8 neighbour features
+    // of the network (clamped range differences to the 8 level-l neighbours
+    // in raster order), rounded to bf16 and packed two per word (4 words);
+    // null elsewhere
+    uint32_t *nbf[kMaxLevels];
     T *frames;
     int H, W;
     int tile0[kMaxLevels], ntile[kMaxLevels];
@@ -102,6 +107,13 @@ struct StepArgs {
     float *dbg_e, *dbg_w, *dbg_J, *dbg_feat;
 };
 
+// Neighbour features of the learned weight for one level (k_nbr_feats).
+struct NbrArgs {
+    const void *pairs;  // PairDesc<T>[n_pairs]
+    int level;
+    double delta;
+};
+
 struct PrepArgs {
     const void *pairs;  // PairDesc<T>[n_pairs]
     const int2 *tiles;  // level-0 tiles (pair, first segment)
@@ -125,6 +137,9 @@ hipError_t launch_normals(const SensorTab<float> &S, const float *range, double 
                           uint8_t *valid, hipStream_t stream);
 hipError_t launch_clear(int *flags, int n_flags, rir_level_stats *stats, int n_stats, hipStream_t stream);
 hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, int n_pairs, hipStream_t stream);
+// Neighbour features of level a.level for every pair with an nbf image there
+// (FP32 instances only); max_px: the largest level image of the batch.
+hipError_t launch_nbr_feats(const NbrArgs &a, int n_pairs, int max_px, hipStream_t stream);
 hipError_t launch_solve(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream);
 hipError_t launch_frames(bool fp64, const StepArgs &a, int n_pairs, hipStream_t stream);
 hipError_t launch_step(bool fp64, int weight_mode, const StepArgs &a, int grid, int block, hipStream_t stream);

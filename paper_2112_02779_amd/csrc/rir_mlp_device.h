@@ -270,22 +270,70 @@ __device__ __forceinline__ void store_features(const StepArgs &a, const LevelIma
         out[k] = valid ? f[k] : 0.f;
 }
 
+// The 8 neighbour features of target pixel i of a level image, as packed
+// bf16 (the layout of PairDesc::nbf): the same FP32 arithmetic as
+// compute_features, rounded once.  rc is the pixel's range.
+template <typename T>
+__device__ __forceinline__ uint4 neighbour_features(const float *img, int Hl, int Wl, int ul, int vl, T rc,
+                                                    T inv_delta)
+{
+    float f[8];
+    int k = 0;
+#pragma unroll
+    for (int dv = -1; dv <= 1; ++dv)
+#pragma unroll
+        for (int du = -1; du <= 1; ++du) {
+            if (du == 0 && dv == 0)
+                continue;
+            const int vv = vl + dv;
+            int uu = ul + du;
+            uu = uu < 0 ? uu + Wl : (uu >= Wl ? uu - Wl : uu);
+            const float rn = vv >= 0 && vv < Hl ? img[(size_t)vv * Wl + uu] : 0.f;
+            f[k++] = range_ok(rn) ? clamp4((float)(((T)rn - rc) * inv_delta)) : 4.f;
+        }
+    return make_uint4(pack_bf2(f[0], f[1]), pack_bf2(f[2], f[3]), pack_bf2(f[4], f[5]), pack_bf2(f[6], f[7]));
+}
+
 // Learned weight sigmoid(z) of this lane's correspondence; all lanes of the
 // wave must call it (lanes without a correspondence pass valid = false).
-// dump (nullable) receives the features of pixel dump_index (>= 0).
+// dump (nullable) receives the features of pixel dump_index (>= 0).  With
+// nbf (the level's precomputed neighbour features, FP32 only) the features
+// are assembled from one 16-byte record instead of nine range gathers; the
+// packed words are the same bits.
 template <typename T>
 __device__ __forceinline__ T learned_weight(const StepArgs &a, const MlpInfer &F, const LevelImage &L,
                                             bool valid, int ul, int vl, T e, T xr, T n0, T n1, T n2, float *dump,
-                                            int dump_index)
+                                            int dump_index, const uint32_t *nbf)
 {
     __shared__ uint32_t s_stage[4][64 * 8];
-    float f[14];
-    compute_features<T>(a, L, valid, ul, vl, e, xr, n0, n1, n2, f);
-    if (dump && dump_index >= 0)
-        for (int k = 0; k < 14; ++k)
-            dump[14 * (size_t)dump_index + k] = valid ? f[k] : 0.f;
     uint32_t fp[8];
-    pack_features(f, fp);
+    if (sizeof(T) == 4 && nbf) {
+        const uint32_t npx = (uint32_t)(L.Hl * L.Wl);
+        const uint32_t pix = (uint32_t)(vl * L.Wl + ul);
+        const rsrc_t img = make_rsrc(L.rng, npx * 4u);
+        const rsrc_t nb = make_rsrc(nbf, npx * 16u);
+        const T rc = (T)bld1<float>(img, valid ? 4u * pix : kNoLoad);
+        const uint32_t o = valid ? 16u * pix : kNoLoad;
+        const uint32_t d0 = bld_u32(nb, o), d1 = bld_u32(nb, o + 4u), d2 = bld_u32(nb, o + 8u),
+                       d3 = bld_u32(nb, o + 12u);
+        const T inv_delta = (T)(1.0 / a.delta), inv_rmax = (T)(1.0 / (double)a.r_max);
+        // f0 | f1, f2 | f3, ..., f8 | f9 (f1..f8 from the record), then n, e, sdf
+        fp[0] = (pack_bf2((float)(rc * inv_rmax), 0.f) & 0xffffu) | (d0 << 16);
+        fp[1] = __builtin_amdgcn_alignbit(d1, d0, 16);
+        fp[2] = __builtin_amdgcn_alignbit(d2, d1, 16);
+        fp[3] = __builtin_amdgcn_alignbit(d3, d2, 16);
+        fp[4] = (d3 >> 16) | (pack_bf2((float)n0, 0.f) << 16);
+        fp[5] = pack_bf2((float)n1, (float)n2);
+        fp[6] = pack_bf2(clamp4((float)(e * inv_delta)), clamp4((float)((rc - xr) * inv_delta)));
+        fp[7] = 0u;
+    } else {
+        float f[14];
+        compute_features<T>(a, L, valid, ul, vl, e, xr, n0, n1, n2, f);
+        if (dump && dump_index >= 0)
+            for (int k = 0; k < 14; ++k)
+                dump[14 * (size_t)dump_index + k] = valid ? f[k] : 0.f;
+        pack_features(f, fp);
+    }
     const float z = mlp_wave(F, fp, s_stage[threadIdx.x >> 6]);
     return (T)d_rcp(1.f + __expf(-z));
 }
