@@ -5,6 +5,7 @@ rows, no azimuth offsets, no receiver offset) of the same sensor, the error
 grows with frame distance, and the 3-level pyramid matches one level with
 three times its iterations where registration succeeds.  The paper's own numbers need its
 dataset; these are the qualitative claims only (parity unpinned)."""
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -43,3 +44,66 @@ def test_pyramid_matches_single_level_at_short_distances(sweep):
             m, s1 = sweep[name][d]["lut/multi_scale"], sweep[name][d]["lut/single_scale"]
             assert abs(m["success"] - s1["success"]) <= 0.1, (name, d)
             assert m["median_rot_rad"] < 1.3 * s1["median_rot_rad"] + 1e-4, (name, d)
+
+
+def _bar_or_ill(sensor, p_src, p_dst, T_gpu, prm):
+    import oracle
+    from parity_util import BAND_PHI, BAND_U, rot_trans_error
+    To, _ = oracle.icp(sensor, p_src, p_dst, prm)
+    er, et = rot_trans_error(T_gpu, To)
+    if er < 1e-4 and et < 1e-3:
+        return True
+    sp = oracle.icp_flip_spread(sensor, p_src, p_dst, prm, T_ref=To, band_u=BAND_U, band_phi=BAND_PHI)
+    assert np.any((sp[:, 0] > 1e-4) | (sp[:, 1] > 1e-3)), (er, et, sp)
+    return False
+
+
+def test_sweep_schedules_match_oracle():
+    """The sweep's single-level schedule (one level x 30 iterations, uniform
+    sensor) and its "synthetic intrinsics" model registering the staggered
+    sensor's scans (3 levels x 10) against the oracle with the same model:
+    every pair within 1e-4 rad / 1 mm, or ill-conditioned on the CPU."""
+    import torch
+    import oracle
+    import synth
+    import paper_2112_02779_amd as rir
+    from paper_2112_02779_amd import frame_distance as fd
+    cfg = dict(synth.CONFIGS["odometry128x2048"])
+    cfg.update(shapes=[(64, 1024)], step_max=0.5, yaw_max_deg=1.0)
+    ctx = rir.Context(0)
+    within = 0
+    cases = [(synth.uniform_sensor(64, 1024), None, 1, [30]),
+             (synth.staggered_sensor(64, 1024, r0=0.015), fd.synthetic_intrinsics, 3, [10, 10, 10])]
+    for sm, model_of, L, iters in cases:
+        model = model_of(sm) if model_of else sm
+        seq = synth.gen_sequence(cfg, 1000, n_scans=6, sensor=sm)
+        sen = rir.Sensor.from_model(model)
+        dev = torch.device("cuda:0")
+        batch = [(sen, torch.from_numpy(seq["scans"][k + 2]).to(dev), torch.from_numpy(seq["scans"][k]).to(dev))
+                 for k in range(3)]
+        T, _ = rir.icp_batch(ctx, rir.make_params(levels=L, iters=iters, delta=0.5), batch)
+        T = T.cpu().numpy()
+        prm = oracle.make_params(levels=L, iters=iters, delta=0.5)
+        for k in range(3):
+            within += _bar_or_ill(model, seq["scans"][k + 2], seq["scans"][k], T[k], prm)
+    assert within >= 4
+
+
+@pytest.fixture(scope="module")
+def misalignment():
+    from paper_2112_02779_amd import frame_distance
+    return {sc: frame_distance.misalignment_sweep(rots_deg=(0, 5, 15), trans_m=(1, 3), n_pairs=50, scene=sc,
+                                                  seed=1000 if sc == "outdoor" else 0)
+            for sc in ("outdoor", "room")}
+
+
+def test_misalignment_basin(misalignment):
+    """Every schedule (1, 3 or 4 levels, 30 iterations in all) recovers
+    (nearly) every pair from up to 5 deg or 1 m of initial misalignment;
+    success does not rise with the misalignment."""
+    for sc, res in misalignment.items():
+        for name in ("levels_1", "levels_3", "levels_4"):
+            s = [res["rotation"][r][name]["success"] for r in ("0", "5", "15")]
+            assert s[0] == 1.0 and s[1] >= 0.9 and s[2] <= s[1], (sc, name, s)
+            assert res["translation"]["1"][name]["success"] >= 0.9, (sc, name)
+            assert res["translation"]["3"][name]["success"] <= res["translation"]["1"][name]["success"]
