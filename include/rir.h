@@ -113,7 +113,12 @@ typedef struct {
  *                has |xi| = sqrt(|omega|^2 + |tau|^2) <= stop_eps (rad and
  *                metres mixed; the remaining iterations of that level are
  *                skipped, iters_run tells how many ran); 0: fixed iteration
- *                counts. */
+ *                counts.
+ *  normal_window 0: target normals by the cross product of neighbour
+ *                differences (Sec. 4.1); h = 1, 2 or 3: by principal
+ *                component analysis of the (2h+1)^2 window (the
+ *                eigen-decomposition estimator Sec. 4.1 names; the same
+ *                normals as rir_normals_pca, rounded to FP32 in FP32 plans). */
 typedef struct {
     int32_t levels;
     int32_t iters[RIR_MAX_LEVELS];
@@ -128,6 +133,7 @@ typedef struct {
     double r_max;
     int32_t learned_levels;
     double stop_eps;
+    int32_t normal_window;
 } rir_icp_params;
 
 /* Statistics of one pyramid level of one pair: those of the level's last

@@ -44,7 +44,7 @@ class OrcParams(ctypes.Structure):
                 ("mlp", ctypes.POINTER(ctypes.c_double)), ("r_max", ctypes.c_double),
                 ("learned_levels", ctypes.c_int), ("stop_eps", ctypes.c_double),
                 ("flip_band_u", ctypes.c_double), ("flip_band_phi", ctypes.c_double),
-                ("flip_seed", ctypes.c_uint64)]
+                ("flip_seed", ctypes.c_uint64), ("normal_window", ctypes.c_int)]
 
 
 class OrcLevelStats(ctypes.Structure):
@@ -131,7 +131,7 @@ class _SensorHolder:
 
 
 def make_params(levels=3, iters=(10, 10, 10), delta=0.5, edge_rel=0.1, max_corr_dist=0.0, init_mode=0,
-                weight_mode=0, mlp=None, r_max=80.0, learned_levels=0, stop_eps=0.0):
+                weight_mode=0, mlp=None, r_max=80.0, learned_levels=0, stop_eps=0.0, normal_window=0):
     prm = OrcParams()
     prm.levels = levels
     for i in range(8):
@@ -140,6 +140,7 @@ def make_params(levels=3, iters=(10, 10, 10), delta=0.5, edge_rel=0.1, max_corr_
     prm.init_mode, prm.weight_mode, prm.r_max = init_mode, weight_mode, r_max
     prm.learned_levels = int(learned_levels)
     prm.stop_eps = float(stop_eps)
+    prm.normal_window = int(normal_window)
     holder = None
     if mlp is not None:
         holder = np.ascontiguousarray(mlp, dtype=np.float64)

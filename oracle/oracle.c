@@ -69,6 +69,8 @@ typedef struct {
      * coin drawn from (flip_seed, level, iteration, pixel) says so. */
     double flip_band_u, flip_band_phi;
     uint64_t flip_seed;
+    int normal_window;     /* 0: neighbour cross product; h = 1..3: PCA normals of the
+                            * (2h+1)^2 window (Sec. 4.1's eigen-decomposition estimator) */
 } orc_params;
 
 typedef struct {
@@ -105,6 +107,14 @@ static void ray_dir(const orc_sensor *s, int u, int v, double d[3])
     d[1] = sin(th) * cos(ph);
     d[2] = sin(ph);
 }
+
+void orc_normals_pca(const orc_sensor *s, const float *range, int half, double edge_rel, double *nrm,
+                     uint8_t *valid, double *lam);
+
+/* Target normal image of the registration: the neighbour cross product, or
+ * with normal_window = h > 0 the PCA normals of the (2h+1)^2 window, the
+ * alternative estimator Sec. 4.1 names. */
+static void target_normals(const orc_sensor *s, const float *dst, const orc_params *prm, double *nrm, uint8_t *nv);
 
 /* ------------------------------------------------------------------ Eq. (3)-(4) */
 
@@ -899,7 +909,7 @@ int orc_icp(const orc_sensor *s, const float *src, const float *dst, const orc_p
         free(nv);
         return -1;
     }
-    orc_normals(s, dst, prm->edge_rel, nrm, nv);
+    target_normals(s, dst, prm, nrm, nv);
     double T[16];
     memcpy(T, T_init, sizeof(T));
     if (prm->init_mode == 1) {
@@ -985,7 +995,7 @@ int orc_system(const orc_sensor *s, int level, const float *src, const float *ds
         free(nv);
         return -1;
     }
-    orc_normals(s, dst, prm->edge_rel, nrm, nv);
+    target_normals(s, dst, prm, nrm, nv);
     orc_assoc_out a = {u, v, mask, proj_valid, e, w, J, uhat, phi, feat};
     orc_associate(s, level, src, dst, nrm, nv, T, prm, use_learned, &a);
     double Hm[36], g[6];
@@ -1353,4 +1363,12 @@ int64_t orc_sdf_extract(const double origin[3], double voxel, int nx, int ny, in
                 }
             }
     return n;
+}
+
+static void target_normals(const orc_sensor *s, const float *dst, const orc_params *prm, double *nrm, uint8_t *nv)
+{
+    if (prm->normal_window > 0)
+        orc_normals_pca(s, dst, prm->normal_window, prm->edge_rel, nrm, nv, NULL);
+    else
+        orc_normals(s, dst, prm->edge_rel, nrm, nv);
 }

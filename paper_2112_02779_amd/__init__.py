@@ -52,7 +52,7 @@ class IcpParams(ctypes.Structure):
                 ("edge_rel", ctypes.c_double), ("max_corr_dist", ctypes.c_double), ("init_mode", ctypes.c_int32),
                 ("weight_mode", ctypes.c_int32), ("precision", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("mlp", ctypes.c_void_p), ("r_max", ctypes.c_double), ("learned_levels", ctypes.c_int32),
-                ("stop_eps", ctypes.c_double)]
+                ("stop_eps", ctypes.c_double), ("normal_window", ctypes.c_int32)]
 
 
 class Pair(ctypes.Structure):
@@ -256,7 +256,7 @@ class Context:
 
 def make_params(levels=3, iters=(10, 10, 10), delta=0.5, edge_rel=0.1, max_corr_dist=0.0, init_mode=0,
                 weight_mode=WEIGHT_HUBER, precision=PREC_FP32, use_graph=True, mlp=None, r_max=80.0,
-                learned_levels=0, stop_eps=0.0) -> IcpParams:
+                learned_levels=0, stop_eps=0.0, normal_window=0) -> IcpParams:
     p = IcpParams()
     p.levels = int(levels)
     for i in range(MAX_LEVELS):
@@ -268,6 +268,7 @@ def make_params(levels=3, iters=(10, 10, 10), delta=0.5, edge_rel=0.1, max_corr_
     p.r_max = float(r_max)
     p.learned_levels = int(learned_levels)
     p.stop_eps = float(stop_eps)
+    p.normal_window = int(normal_window)
     p._mlp_ref = mlp
     return p
 

@@ -362,7 +362,7 @@ struct rir_mlp {
 namespace {
 
 struct KeyPod {
-    int levels, iters[kMaxLevels], init_mode, weight_mode, learned_levels, precision, use_graph, debug;
+    int levels, iters[kMaxLevels], init_mode, weight_mode, learned_levels, precision, use_graph, debug, normal_window;
     double delta, edge_rel, max_corr, r_max, stop_eps;
     uint64_t mlp;
     rir_tuning tune;
@@ -613,6 +613,8 @@ rir_status check_params(const rir_icp_params *p)
         return fail(RIR_E_INVALID, "rir_icp_params.precision must be FP32 or FP64");
     if (!(p->stop_eps >= 0.0) || !std::isfinite(p->stop_eps))
         return fail(RIR_E_INVALID, "rir_icp_params.stop_eps must be finite and >= 0");
+    if (p->normal_window < 0 || p->normal_window > 3)
+        return fail(RIR_E_INVALID, "rir_icp_params.normal_window must be 0 (cross product) or 1..3 (PCA)");
     return RIR_OK;
 }
 
@@ -775,6 +777,7 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
         const rir_sensor *s = pairs[i].sensor;
         auto fill = [&](auto *d, auto *tab) {
             d->tab = tab;
+            d->tabd = s->d_td;
             using TF = typename std::remove_pointer<typename std::remove_reference<decltype(d->frames)>::type>::type;
             d->frames = reinterpret_cast<TF *>(base + o_frames[i]);
             d->H = s->H;
@@ -833,6 +836,7 @@ rir_status get_plan(rir_ctx *ctx, const rir_icp_params *p, const rir_pair *pairs
     k.edge_rel = p->edge_rel;
     k.max_corr = p->max_corr_dist;
     k.stop_eps = p->stop_eps;
+    k.normal_window = p->normal_window;
     k.r_max = p->weight_mode == RIR_WEIGHT_LEARNED ? p->r_max : 0.0;
     k.mlp = p->weight_mode == RIR_WEIGHT_LEARNED ? p->mlp->uid : 0;
     k.tune = ctx->tune;
@@ -954,6 +958,9 @@ rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t s
     a.psum = P->d_psum;
     a.poses = P->d_poses;
     a.xcd_remap = P->key.k.tune.xcd_remap;
+    a.given_normals = P->key.k.normal_window > 0 ? 1 : 0;
+    if (a.given_normals)
+        HIP_TRY(launch_pca_records(P->fp64, a, P->key.k.normal_window, P->n_pairs, (int)P->max_px[0], st));
     HIP_TRY(launch_prepass(P->fp64, a, P->grid[0], P->block, P->n_pairs, st));
     for (int l = 0; l < P->key.k.levels; ++l)
         if (P->nbf[l]) {

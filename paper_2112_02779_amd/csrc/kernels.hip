@@ -226,7 +226,10 @@ __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
                 const int v = vs[j], u = us[j];
                 const V4<T> rw = sld4(rowt, v);
                 V4<T> rec = {(T)0, (T)0, (T)0, quiet_nan<T>()};
-                if (v > 0 && v < H - 1) {
+                if (a.given_normals) {
+                    if (in[j])
+                        rec = ld4(d40 + 4 * (size_t)(v * W + u));
+                } else if (v > 0 && v < H - 1) {
                     V3<T> n;
                     if (normal_core(ca[j], sa[j], rw, sld4(rowt, v + 1), sld4(rowt, v - 1), sld4(nrowt, 2 * v),
                                     sld4(nrowt, 2 * v + 1), r0, cos_h, sin_h, rc[j], rl[j], rr[j], ru[j], rd[j],
@@ -238,7 +241,8 @@ __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
                     }
                 }
                 if (in[j]) {
-                    gst4(d40 + 4 * (size_t)(v * W + u), rec);
+                    if (!a.given_normals)
+                        gst4(d40 + 4 * (size_t)(v * W + u), rec);
                     if constexpr (CENTROID) {
                         const V3<T> d = ray_dir(rw, ca[j], sa[j]);
                         if (range_ok(rs[j])) {

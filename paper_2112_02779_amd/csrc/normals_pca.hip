@@ -69,12 +69,77 @@ __device__ __forceinline__ bool smallest_eigenpair(double a00, double a01, doubl
 
 }  // namespace
 
+// PCA normal of pixel (u, v) of one H x W range image: the covariance of the
+// window points (2 HALF + 1 square, u wrapping, rows clipped) that have a
+// return within edge_rel of the centre range, about their mean, in FP64;
+// at least half the window must take part, the middle eigenvalue must
+// exceed 1e-6 times the largest (a line has no normal); the normal faces the
+// sensor.  Returns false (n untouched) otherwise.
+template <int HALF>
+__device__ __forceinline__ bool pca_normal(const SensorTab<double> &S, const float *rg, int H, int W, int u, int v,
+                                           double edge_rel, double n[3])
+{
+    constexpr int K = 2 * HALF + 1;
+    constexpr int kMinPts = (K * K + 1) / 2;
+    const float rcf = rg[(int64_t)v * W + u];
+    if (!range_ok(rcf))
+        return false;
+    const double rc = (double)rcf, lim = edge_rel * rc;
+    const V3<double> pc = unproject(S, u, v, rc);
+    double sx = 0, sy = 0, sz = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
+    int cnt = 0;
+#pragma unroll
+    for (int dv = -HALF; dv <= HALF; ++dv) {
+        const int vv = v + dv;
+        if (vv < 0 || vv >= H)
+            continue;
+#pragma unroll
+        for (int du = -HALF; du <= HALF; ++du) {
+            int uu = u + du;
+            uu = uu < 0 ? uu + W : (uu >= W ? uu - W : uu);
+            const float rf = rg[(int64_t)vv * W + uu];
+            if (!range_ok(rf) || fabs((double)rf - rc) > lim)
+                continue;
+            const V3<double> p = unproject(S, uu, vv, (double)rf);
+            const double qx = p.x - pc.x, qy = p.y - pc.y, qz = p.z - pc.z;
+            sx += qx;
+            sy += qy;
+            sz += qz;
+            sxx += qx * qx;
+            sxy += qx * qy;
+            sxz += qx * qz;
+            syy += qy * qy;
+            syz += qy * qz;
+            szz += qz * qz;
+            ++cnt;
+        }
+    }
+    if (cnt < kMinPts)
+        return false;
+    const double ic = 1.0 / (double)cnt;
+    const double mx = sx * ic, my = sy * ic, mz = sz * ic;
+    double l0, l1, l2, m[3];
+    bool ok = smallest_eigenpair(sxx * ic - mx * mx, sxy * ic - mx * my, sxz * ic - mx * mz, syy * ic - my * my,
+                                 syz * ic - my * mz, szz * ic - mz * mz, l0, l1, l2, m);
+    // points on a line (middle eigenvalue negligible) have no normal
+    ok = ok && l1 > 1e-6 * l2;
+    if (!ok)
+        return false;
+    V4<double> rw = ld4(S.row + 4 * v);
+    double ca, sa;
+    ld2(S.col + 2 * u, ca, sa);
+    const V3<double> d = ray_dir(rw, ca, sa);
+    const double sgn = m[0] * d.x + m[1] * d.y + m[2] * d.z > 0.0 ? -1.0 : 1.0;
+    n[0] = sgn * m[0];
+    n[1] = sgn * m[1];
+    n[2] = sgn * m[2];
+    return true;
+}
+
 template <int HALF>
 __global__ __launch_bounds__(256) void k_normals_pca(SensorTab<double> S, const float *range, int64_t n_px,
                                                      double edge_rel, float *nrm, uint8_t *valid)
 {
-    constexpr int K = 2 * HALF + 1;
-    constexpr int kMinPts = (K * K + 1) / 2;
     const int H = S.H, W = S.W;
     const int64_t HW = (int64_t)H * W;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_px;
@@ -82,68 +147,74 @@ __global__ __launch_bounds__(256) void k_normals_pca(SensorTab<double> S, const 
         const int64_t img = i / HW;
         const int pix = (int)(i - img * HW);
         const int v = pix / W, u = pix - v * W;
-        const float *rg = range + img * HW;
-        const float rcf = rg[pix];
-        bool ok = range_ok(rcf);
         double n[3] = {0.0, 0.0, 0.0};
-        if (ok) {
-            const double rc = (double)rcf, lim = edge_rel * rc;
-            const V3<double> pc = unproject(S, u, v, rc);
-            double sx = 0, sy = 0, sz = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
-            int cnt = 0;
-#pragma unroll
-            for (int dv = -HALF; dv <= HALF; ++dv) {
-                const int vv = v + dv;
-                if (vv < 0 || vv >= H)
-                    continue;
-#pragma unroll
-                for (int du = -HALF; du <= HALF; ++du) {
-                    int uu = u + du;
-                    uu = uu < 0 ? uu + W : (uu >= W ? uu - W : uu);
-                    const float rf = rg[(int64_t)vv * W + uu];
-                    if (!range_ok(rf) || fabs((double)rf - rc) > lim)
-                        continue;
-                    const V3<double> p = unproject(S, uu, vv, (double)rf);
-                    const double qx = p.x - pc.x, qy = p.y - pc.y, qz = p.z - pc.z;
-                    sx += qx;
-                    sy += qy;
-                    sz += qz;
-                    sxx += qx * qx;
-                    sxy += qx * qy;
-                    sxz += qx * qz;
-                    syy += qy * qy;
-                    syz += qy * qz;
-                    szz += qz * qz;
-                    ++cnt;
-                }
-            }
-            ok = cnt >= kMinPts;
-            if (ok) {
-                const double ic = 1.0 / (double)cnt;
-                const double mx = sx * ic, my = sy * ic, mz = sz * ic;
-                double l0, l1, l2;
-                ok = smallest_eigenpair(sxx * ic - mx * mx, sxy * ic - mx * my, sxz * ic - mx * mz,
-                                        syy * ic - my * my, syz * ic - my * mz, szz * ic - mz * mz, l0, l1, l2, n);
-                // points on a line (middle eigenvalue negligible) have no normal
-                ok = ok && l1 > 1e-6 * l2;
-                if (ok) {
-                    V4<double> rw = ld4(S.row + 4 * v);
-                    double ca, sa;
-                    ld2(S.col + 2 * u, ca, sa);
-                    const V3<double> d = ray_dir(rw, ca, sa);
-                    if (n[0] * d.x + n[1] * d.y + n[2] * d.z > 0.0) {
-                        n[0] = -n[0];
-                        n[1] = -n[1];
-                        n[2] = -n[2];
-                    }
-                }
-            }
-        }
+        const bool ok = pca_normal<HALF>(S, range + img * HW, H, W, u, v, edge_rel, n);
         nrm[3 * i] = ok ? (float)n[0] : 0.f;
         nrm[3 * i + 1] = ok ? (float)n[1] : 0.f;
         nrm[3 * i + 2] = ok ? (float)n[2] : 0.f;
         valid[i] = ok ? 1 : 0;
     }
+}
+
+// Level-0 target records of the registration from PCA normals (the
+// alternative estimator of Sec. 4.1): record (n, n . q) with n the FP64 PCA
+// normal rounded to T and q the target point from the T tables (as the
+// cross-product prepass forms it); (0, 0, 0, NaN) where there is no normal.
+// Grid: (pixel blocks, pair).
+template <typename T, int HALF>
+__global__ __launch_bounds__(256) void k_pca_records(PrepArgs a)
+{
+    const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + blockIdx.y;
+    const int H = cload(&P->H), W = cload(&P->W), npx = H * W;
+    const SensorTab<double> *Sd = cload(&P->tabd);
+    const SensorTab<T> *S = cload(&P->tab);
+    const float *rg = cload(&P->dstr[0]);
+    T *d40 = cload(&P->dst4[0]);
+    const T *rowt = cload(&S->row), *colt = cload(&S->col);
+    const T r0 = cload(&S->r0);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
+        const int v = i / W, u = i - v * W;
+        double n[3];
+        V4<T> rec = {(T)0, (T)0, (T)0, quiet_nan<T>()};
+        if (pca_normal<HALF>(*Sd, rg, H, W, u, v, a.edge_rel, n)) {
+            const V4<T> rw = ld4(rowt + 4 * v);
+            T ca, sa;
+            ld2(colt + 2 * u, ca, sa);
+            const V3<T> d = ray_dir(rw, ca, sa);
+            const T rc = (T)rg[i];
+            const T q0 = rc * d.x + r0 * ca, q1 = rc * d.y + r0 * sa, q2 = rc * d.z;
+            const T n0 = (T)n[0], n1 = (T)n[1], n2 = (T)n[2];
+            rec = V4<T>{n0, n1, n2, n0 * q0 + n1 * q1 + n2 * q2};
+        }
+        st4(d40 + 4 * (size_t)i, rec);
+    }
+}
+
+template <typename T>
+static hipError_t launch_pca_records_t(const PrepArgs &a, int half, int n_pairs, int max_px, hipStream_t stream)
+{
+    int64_t g = ((int64_t)max_px + 255) / 256;
+    const dim3 grid((unsigned)(g > 65535 ? 65535 : (g < 1 ? 1 : g)), (unsigned)n_pairs);
+    switch (half) {
+    case 1:
+        hipLaunchKernelGGL((k_pca_records<T, 1>), grid, dim3(256), 0, stream, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_pca_records<T, 2>), grid, dim3(256), 0, stream, a);
+        break;
+    case 3:
+        hipLaunchKernelGGL((k_pca_records<T, 3>), grid, dim3(256), 0, stream, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pca_records(bool fp64, const PrepArgs &a, int half, int n_pairs, int max_px, hipStream_t stream)
+{
+    return fp64 ? launch_pca_records_t<double>(a, half, n_pairs, max_px, stream)
+                : launch_pca_records_t<float>(a, half, n_pairs, max_px, stream);
 }
 
 hipError_t launch_normals_pca(const SensorTab<double> &S, const float *range, int n_images, int half, double edge_rel,

@@ -28,6 +28,7 @@ namespace rir {
 template <typename T>
 struct PairDesc {
     const SensorTab<T> *tab;
+    const SensorTab<double> *tabd;  // FP64 tables (PCA target normals)
     float *src[kMaxLevels];
     float *dstr[kMaxLevels];
     T *dst4[kMaxLevels];
@@ -121,6 +122,8 @@ struct PrepArgs {
     int tile_seg;
     int levels;
     int init_centroid;  // 1: compute t0 from the point-set centres
+    int given_normals;  // 1: the level-0 records are already written (PCA
+                        // target normals), the pass only copies them down
     double edge_rel;
     void *psum;         // T[n_tiles][kAccum] (centroid sums)
     double *poses;
@@ -137,6 +140,9 @@ hipError_t launch_normals(const SensorTab<float> &S, const float *range, double 
                           uint8_t *valid, hipStream_t stream);
 hipError_t launch_clear(int *flags, int n_flags, rir_level_stats *stats, int n_stats, hipStream_t stream);
 hipError_t launch_prepass(bool fp64, const PrepArgs &a, int grid, int block, int n_pairs, hipStream_t stream);
+// Level-0 target records (n, n . q) from PCA normals of the (2 half + 1)^2
+// window (normals_pca.hip) for every pair; max_px: the largest level-0 image.
+hipError_t launch_pca_records(bool fp64, const PrepArgs &a, int half, int n_pairs, int max_px, hipStream_t stream);
 // Neighbour features of level a.level for every pair with an nbf image there
 // (FP32 instances only); max_px: the largest level image of the batch.
 hipError_t launch_nbr_feats(const NbrArgs &a, int n_pairs, int max_px, hipStream_t stream);

@@ -92,3 +92,35 @@ def test_pca_normals_edge_cases(rir):
     assert int(valid.sum()) == 0 and float(n.abs().sum()) == 0.0
     with pytest.raises(rir.RirError):
         rir.normals_pca(sen, to_dev(dead), half=4)
+
+
+@pytest.mark.parametrize("case", [("uniform", 1, 0), ("uniform", 2, 0), ("staggered_r0", 1, 0), ("uniform", 1, 1)])
+def test_icp_with_pca_normals_matches_oracle(case):
+    """Registration with PCA target normals (normal_window = h, Sec. 4.1's
+    eigen-decomposition estimator) against the oracle with the same
+    estimator: pose within 1e-4 rad / 1 mm (or ill-conditioned under the
+    band flips), correspondence counts within the ambiguity band's share;
+    FP32 and FP64 plans."""
+    import torch
+    import oracle
+    import synth
+    import paper_2112_02779_amd as rir
+    from parity_util import BAND_PHI, BAND_U, rot_trans_error
+    kind, h, prec = case
+    sm = synth.uniform_sensor(64, 1024) if kind == "uniform" else synth.staggered_sensor(64, 1024, r0=0.015)
+    pair = synth.gen_pair(synth.CONFIGS["pair64"], 80 + h, sensor=sm)
+    sen = rir.Sensor.from_model(sm)
+    dev = torch.device("cuda:0")
+    prm = rir.make_params(levels=3, iters=[10, 10, 10], delta=0.5, normal_window=h, precision=prec)
+    T, st = rir.icp_batch(rir.Context(0), prm,
+                          [(sen, torch.from_numpy(pair.src).to(dev), torch.from_numpy(pair.dst).to(dev))])
+    oprm = oracle.make_params(levels=3, iters=[10, 10, 10], delta=0.5, normal_window=h)
+    To, so = oracle.icp(sm, pair.src, pair.dst, oprm)
+    er, et = rot_trans_error(T.cpu().numpy()[0], To)
+    if not (er < 1e-4 and et < 1e-3):
+        sp = oracle.icp_flip_spread(sm, pair.src, pair.dst, oprm, T_ref=To, band_u=BAND_U, band_phi=BAND_PHI)
+        assert np.any((sp[:, 0] > 1e-4) | (sp[:, 1] > 1e-3)), (er, et, sp)
+    stn = rir.stats_to_numpy(st, 1, 3)
+    for l in range(3):
+        assert stn[0, l]["status"] == so[l]["status"] == 0
+        assert abs(int(stn[0, l]["n_valid"]) - so[l]["n_valid"]) <= 0.002 * so[l]["n_valid"] + 5
