@@ -166,9 +166,15 @@ typedef struct {
  * grid_mult 0) lets the workgroup that finishes a pair's last tile of an
  * iteration solve that pair (one launch per Gauss-Newton iteration), 0 solves
  * every pair in a launch of its own after each association/reduction launch;
- * both sum the tile records in the same order and give the same results. */
+ * both sum the tile records in the same order and give the same results.
+ * lanes (1..4): the coarse levels (all but the finest) of a batch run as up to
+ * `lanes` sub-batches of consecutive pairs (about equal pixel counts) on as
+ * many streams of the context, forked from and joined back into the call's
+ * stream, so that the launches of different sub-batches overlap; lane_fine: 1
+ * runs the finest level in the sub-batches too, 0 as one launch per iteration
+ * over the whole batch.  Neither changes any result. */
 typedef struct {
-    int32_t block, px_per_thread, grid_mult, xcd_remap, chunk, solve_in_step;
+    int32_t block, px_per_thread, grid_mult, xcd_remap, chunk, solve_in_step, lanes, lane_fine;
 } rir_tuning;
 
 /* ---------------------------------------------------------------- sensors */

@@ -61,7 +61,8 @@ class Pair(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("px_per_thread", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("chunk", ctypes.c_int32), ("solve_in_step", ctypes.c_int32)]
+                ("xcd_remap", ctypes.c_int32), ("chunk", ctypes.c_int32), ("solve_in_step", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("lane_fine", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -232,8 +233,9 @@ class Context:
             _lib.rir_ctx_destroy(self.handle)
             self.handle = None
 
-    def set_tuning(self, block=256, px_per_thread=8, grid_mult=0, xcd_remap=1, chunk=4, solve_in_step=1):
-        t = Tuning(block, px_per_thread, grid_mult, xcd_remap, chunk, solve_in_step)
+    def set_tuning(self, block=256, px_per_thread=8, grid_mult=0, xcd_remap=1, chunk=4, solve_in_step=1, lanes=3,
+                   lane_fine=1):
+        t = Tuning(block, px_per_thread, grid_mult, xcd_remap, chunk, solve_in_step, lanes, lane_fine)
         _check(lib().rir_ctx_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:

@@ -391,13 +391,24 @@ struct Plan {
     bool resident[kMaxLevels] = {};  // some pair runs the level in the pair-resident kernel
     int n_tiles[kMaxLevels] = {};
     int grid[kMaxLevels] = {};
+    // the coarse levels (and with lane_fine the finest) run as n_lanes
+    // sub-batches of consecutive pairs
+    // (lane k: pairs lane_p0[k] .. lane_p0[k + 1] - 1, tiles lane_t0[l][k] ..
+    // lane_t0[l][k + 1] - 1 of level l), each on a stream of its own
+    int n_lanes = 1;
+    int lane_p0[kMaxLanes + 1] = {};
+    int lane_t0[kMaxLevels][kMaxLanes + 1] = {};
+    int lane_grid[kMaxLevels][kMaxLanes] = {};
     void *dmem = nullptr;
     void *h_desc = nullptr;   // pinned host copy of the pair descriptors
     size_t desc_bytes = 0;
     void *d_desc = nullptr;
     int2 *d_tiles[kMaxLevels] = {};
+    // tile records; level l's start at record rec0[l] (levels never share
+    // records: sub-batches may be at different levels at the same time)
     void *d_psum = nullptr;
     int4 *d_pcnt = nullptr;
+    int rec0[kMaxLevels] = {};
     double *d_poses = nullptr;
     rir_level_stats *d_stats = nullptr;
     int *d_flags = nullptr;
@@ -436,7 +447,11 @@ struct rir_ctx {
     int device = 0;
     int n_cu = 256;
     hipStream_t cap = nullptr;  // private stream used only for graph capture
-    rir_tuning tune{256, 8, 0, 1, 4, 1};
+    // streams of the coarse-level sub-batches (default priority), forked from
+    // and joined back into the caller's stream with the events below
+    hipStream_t lane_st[kMaxLanes] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kMaxLanes] = {};
+    rir_tuning tune{256, 8, 0, 1, 4, 1, 3, 1};
     std::map<PlanKey, std::unique_ptr<Plan>> plans;
     uint64_t use_clock = 0;
     int timing = 0;  // 0 off, 1 every level and the prepass, 2 the finest level only
@@ -460,6 +475,14 @@ struct rir_ctx {
                     hipEventDestroy(e);
         if (cap)
             hipStreamDestroy(cap);
+        for (auto &q : lane_st)
+            if (q)
+                hipStreamDestroy(q);
+        for (auto &e : join_ev)
+            if (e)
+                hipEventDestroy(e);
+        if (fork_ev)
+            hipEventDestroy(fork_ev);
     }
 };
 
@@ -479,6 +502,11 @@ extern "C" rir_status rir_ctx_create(int device, rir_ctx **out)
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    for (auto &q : c->lane_st)
+        HIP_TRY(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    for (auto &e : c->join_ev)
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (auto &e : c->ev)
         HIP_TRY(hipEventCreate(&e));
     for (auto &pr : c->ring)
@@ -504,6 +532,10 @@ static rir_status check_tuning(const rir_tuning *t)
         return fail(RIR_E_INVALID, "rir_tuning.xcd_remap must be 0 or 1");
     if (t->solve_in_step != 0 && t->solve_in_step != 1)
         return fail(RIR_E_INVALID, "rir_tuning.solve_in_step must be 0 or 1");
+    if (t->lanes < 1 || t->lanes > kMaxLanes)
+        return fail(RIR_E_INVALID, "rir_tuning.lanes must be in 1..4");
+    if (t->lane_fine != 0 && t->lane_fine != 1)
+        return fail(RIR_E_INVALID, "rir_tuning.lane_fine must be 0 or 1");
     return RIR_OK;
 }
 
@@ -712,9 +744,46 @@ rir_status make_plan(rir_ctx *ctx, const PlanKey &key, const rir_pair *pairs, in
             G = (G + 7) / 8 * 8;
         P->grid[l] = std::max(G, 1);
     }
-    int max_tiles = 0;
-    for (int l = 0; l < L; ++l)
-        max_tiles = std::max(max_tiles, P->n_tiles[l]);
+    // Sub-batches of the coarse levels: consecutive pairs, cut where the
+    // running pixel count passes k / n_lanes of the batch's (so that the
+    // lanes carry about equal work).  One lane when no level runs in lanes.
+    {
+        const bool any = L > 1 || key.k.tune.lane_fine;
+        const int S = (any && !key.k.debug) ? std::max(1, std::min(key.k.tune.lanes, n)) : 1;
+        std::vector<double> cum(n + 1, 0.0);
+        for (int i = 0; i < n; ++i)
+            cum[i + 1] = cum[i] + (double)pairs[i].sensor->H * (double)pairs[i].sensor->W;
+        P->n_lanes = S;
+        P->lane_p0[0] = 0;
+        for (int k = 1; k < S; ++k) {
+            int i = P->lane_p0[k - 1] + 1;  // every lane keeps at least one pair
+            while (i < n - (S - k) && cum[i] < cum[n] * k / S)
+                ++i;
+            P->lane_p0[k] = i;
+        }
+        P->lane_p0[S] = n;
+        for (int l = 0; l < L; ++l) {
+            for (int k = 0; k < S; ++k) {
+                const int p0 = P->lane_p0[k];
+                P->lane_t0[l][k] = t0[p0 * kMaxLevels + l];
+            }
+            P->lane_t0[l][S] = P->n_tiles[l];
+            for (int k = 0; k < S; ++k) {
+                int G = P->lane_t0[l][k + 1] - P->lane_t0[l][k];
+                if (key.k.tune.grid_mult > 0)
+                    G = std::min(G, key.k.tune.grid_mult * ctx->n_cu);
+                if (key.k.tune.xcd_remap)
+                    G = (G + 7) / 8 * 8;
+                P->lane_grid[l][k] = std::max(G, 1);
+            }
+        }
+    }
+    int max_tiles = 0;  // records of all levels
+    for (int l = 0; l < L; ++l) {
+        P->rec0[l] = max_tiles;
+        max_tiles += P->n_tiles[l];
+    }
+    max_tiles = std::max(max_tiles, 1);
     // device layout
     Layout lay;
     P->desc_bytes = n * (P->fp64 ? sizeof(PairDesc<double>) : sizeof(PairDesc<float>));
@@ -907,13 +976,20 @@ bool learned_at(const rir_icp_params *p, int level)
     return p->weight_mode == RIR_WEIGHT_LEARNED && (p->learned_levels == 0 || ((p->learned_levels >> level) & 1));
 }
 
-StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, int mode)
+// Arguments of the launches of one iteration; lane >= 0 restricts them to
+// that sub-batch's pairs and tiles.
+StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, int mode, int lane = -1)
 {
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.pairs = P->d_desc;
     a.tiles = P->d_tiles[level];
     a.n_tiles = P->n_tiles[level];
+    if (lane >= 0) {
+        a.tile_base = P->lane_t0[level][lane];
+        a.n_tiles = P->lane_t0[level][lane + 1] - a.tile_base;
+        a.pair_base = P->lane_p0[lane];
+    }
     a.level = level;
     a.iter = iter;
     a.levels = P->key.k.levels;
@@ -925,8 +1001,8 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
     a.stats_pass = (mode == kStepDebug || iter == P->key.k.iters[level] - 1) ? 1 : 0;
     a.lean = (mode != kStepDebug && P->lean[level]) ? 1 : 0;
     a.learned = learned_at(p, level) ? 1 : 0;
-    a.psum = P->d_psum;
-    a.pcnt = P->d_pcnt;
+    a.psum = static_cast<char *>(P->d_psum) + (size_t)P->rec0[level] * kAccum * (P->fp64 ? sizeof(double) : sizeof(float));
+    a.pcnt = P->d_pcnt + P->rec0[level];
     a.poses = P->d_poses;
     a.stats = P->d_stats;
     a.flags = P->d_flags;
@@ -975,61 +1051,130 @@ rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t s
     return RIR_OK;
 }
 
-// Enqueues the Gauss-Newton iterations of one level.
-rir_status enqueue_level(const Plan *P, const rir_icp_params *p, int l, hipStream_t st)
+// Enqueues the Gauss-Newton iterations of one level, for the whole batch
+// (lane < 0) or for one sub-batch.
+rir_status enqueue_level(const Plan *P, const rir_icp_params *p, int l, hipStream_t st, int lane = -1)
 {
+    const int np = lane < 0 ? P->n_pairs : P->lane_p0[lane + 1] - P->lane_p0[lane];
+    const int grid = lane < 0 ? P->grid[l] : P->lane_grid[l][lane];
     if (P->resident[l] && P->key.k.iters[l] > 0)
-        HIP_TRY(launch_level(P->fp64, step_args(P, p, l, 0, kStepNormal), P->n_pairs, st));
-    if (P->n_tiles[l] == 0)
+        HIP_TRY(launch_level(P->fp64, step_args(P, p, l, 0, kStepNormal, lane), np, st));
+    if (step_args(P, p, l, 0, kStepNormal, lane).n_tiles == 0)
         return RIR_OK;
     for (int it = 0; it < P->key.k.iters[l]; ++it) {
-        StepArgs a = step_args(P, p, l, it, kStepNormal);
-        HIP_TRY(launch_step(P->fp64, a.learned ? RIR_WEIGHT_LEARNED : RIR_WEIGHT_HUBER, a, P->grid[l], P->block, st));
+        StepArgs a = step_args(P, p, l, it, kStepNormal, lane);
+        HIP_TRY(launch_step(P->fp64, a.learned ? RIR_WEIGHT_LEARNED : RIR_WEIGHT_HUBER, a, grid, P->block, st));
         if (!a.fused)
-            HIP_TRY(launch_solve(P->fp64, a, P->n_pairs, st));
+            HIP_TRY(launch_solve(P->fp64, a, np, st));
         if (a.learned) {
-            StepArgs b = step_args(P, p, l, it, kStepFallback);
-            HIP_TRY(launch_step(P->fp64, RIR_WEIGHT_HUBER, b, P->grid[l], P->block, st));
+            StepArgs b = step_args(P, p, l, it, kStepFallback, lane);
+            HIP_TRY(launch_step(P->fp64, RIR_WEIGHT_HUBER, b, grid, P->block, st));
             if (!b.fused)
-                HIP_TRY(launch_solve(P->fp64, b, P->n_pairs, st));
+                HIP_TRY(launch_solve(P->fp64, b, np, st));
         }
     }
     return RIR_OK;
 }
 
-// Enqueues the whole schedule eagerly: prepass, then the levels coarse to
-// fine, with timing events around the prepass and every level.
-rir_status enqueue_all(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int timing, hipStream_t st,
-                       hipEvent_t *fine = nullptr)
+// Levels hi .. lo (coarse to fine) of every sub-batch, each on its lane
+// stream: forked from st after the work enqueued so far, joined back into st.
+rir_status enqueue_lanes(rir_ctx *ctx, const Plan *P, const rir_icp_params *p, int hi, int lo, hipStream_t st)
 {
-    const int L = P->key.k.levels;
-    hipEvent_t *evs = ctx->ev;
-    if (timed_part(timing, L))
-        HIP_TRY(hipEventRecord(ctx->ev[2 * L], st));
-    rir_status s = enqueue_prepass(P, p, st);
-    if (s != RIR_OK)
-        return s;
-    if (timed_part(timing, L))
-        HIP_TRY(hipEventRecord(ctx->ev[2 * L + 1], st));
-    for (int l = L - 1; l >= 0; --l) {
-        if (timed_part(timing, l))
-            HIP_TRY(hipEventRecord(l == 0 && fine ? fine[0] : evs[2 * l], st));
-        s = enqueue_level(P, p, l, st);
-        if (s != RIR_OK)
-            return s;
-        if (timed_part(timing, l))
-            HIP_TRY(hipEventRecord(l == 0 && fine ? fine[1] : evs[2 * l + 1], st));
+    HIP_TRY(hipEventRecord(ctx->fork_ev, st));
+    for (int k = 0; k < P->n_lanes; ++k) {
+        hipStream_t q = ctx->lane_st[k];
+        HIP_TRY(hipStreamWaitEvent(q, ctx->fork_ev, 0));
+        for (int l = hi; l >= lo; --l) {
+            rir_status s = enqueue_level(P, p, l, q, k);
+            if (s != RIR_OK)
+                return s;
+        }
+        HIP_TRY(hipEventRecord(ctx->join_ev[k], q));
+        HIP_TRY(hipStreamWaitEvent(st, ctx->join_ev[k], 0));
     }
     return RIR_OK;
 }
 
-// Captures one part of the schedule (which < 0: prepass, else level which)
-// on the context's private stream.
-rir_status capture_part(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int which, hipGraph_t *out)
+// Records timing event e on st.  While st is being captured, the event
+// becomes an event-record node of the graph: added after the nodes the next
+// captured work would depend on, and made the only dependency of that work.
+rir_status record_timing(hipEvent_t e, hipStream_t st, bool capturing)
+{
+    if (!capturing) {
+        HIP_TRY(hipEventRecord(e, st));
+        return RIR_OK;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t nd = 0;
+    HIP_TRY(hipStreamGetCaptureInfo_v2(st, &cs, &id, &g, &deps, &nd));
+    if (cs != hipStreamCaptureStatusActive || !g)
+        return fail(RIR_E_HIP, "timing event outside an active capture");
+    hipGraphNode_t node = nullptr;
+    HIP_TRY(hipGraphAddEventRecordNode(&node, g, deps, nd, e));
+    HIP_TRY(hipStreamUpdateCaptureDependencies(st, &node, 1, hipStreamSetCaptureDependencies));
+    return RIR_OK;
+}
+
+// Enqueues the whole schedule: prepass, then the levels coarse to fine, with
+// timing events around the prepass and every level (timing 1) or around the
+// finest level (timing 2; `fine` the event pair, else the context's).  With
+// more than one lane the coarse levels (with lane_fine all levels) run as
+// concurrent sub-batches, forked once after the prepass and joined at the
+// end; timing joins and forks again at each timed boundary (every level
+// under timing 1, before the finest level under timing 2), so that each
+// timed part has its own time.
+rir_status enqueue_all(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int timing, hipStream_t st, hipEvent_t *fine,
+                       bool capturing)
+{
+    const int L = P->key.k.levels;
+    hipEvent_t *evs = ctx->ev;
+    rir_status s = RIR_OK;
+    if (timed_part(timing, L) && (s = record_timing(evs[2 * L], st, capturing)) != RIR_OK)
+        return s;
+    if ((s = enqueue_prepass(P, p, st)) != RIR_OK)
+        return s;
+    if (timed_part(timing, L) && (s = record_timing(evs[2 * L + 1], st, capturing)) != RIR_OK)
+        return s;
+    const bool lanes = P->n_lanes > 1, fine_lanes = lanes && P->key.k.tune.lane_fine;
+    if (fine_lanes && timing == 0)
+        return enqueue_lanes(ctx, P, p, L - 1, 0, st);
+    if (lanes && timing != 1) {
+        if (L > 1 && (s = enqueue_lanes(ctx, P, p, L - 1, 1, st)) != RIR_OK)
+            return s;
+    } else {
+        for (int l = L - 1; l >= 1; --l) {
+            if (timed_part(timing, l) && (s = record_timing(evs[2 * l], st, capturing)) != RIR_OK)
+                return s;
+            s = lanes ? enqueue_lanes(ctx, P, p, l, l, st) : enqueue_level(P, p, l, st);
+            if (s != RIR_OK)
+                return s;
+            if (timed_part(timing, l) && (s = record_timing(evs[2 * l + 1], st, capturing)) != RIR_OK)
+                return s;
+        }
+    }
+    if (timed_part(timing, 0) && (s = record_timing(fine ? fine[0] : evs[0], st, capturing)) != RIR_OK)
+        return s;
+    if ((s = fine_lanes ? enqueue_lanes(ctx, P, p, 0, 0, st) : enqueue_level(P, p, 0, st)) != RIR_OK)
+        return s;
+    if (timed_part(timing, 0) && (s = record_timing(fine ? fine[1] : evs[1], st, capturing)) != RIR_OK)
+        return s;
+    return RIR_OK;
+}
+
+// The whole schedule as one graph, captured on the context's private stream
+// (the lane streams join the capture): one launch per call, kernels back to
+// back, parallel branches for the sub-batches of the coarse levels, and the
+// timing events as event-record nodes.
+rir_status capture(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int timing, hipGraphExec_t *out)
 {
     hipStream_t cs = ctx->cap;
+    // timing 2: captured with ring pair 0, re-pointed at each call's pair
+    hipEvent_t fine[2] = {ctx->ring[0][0], ctx->ring[0][1]};
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    rir_status st = which < 0 ? enqueue_prepass(P, p, cs) : enqueue_level(P, p, which, cs);
+    rir_status st = enqueue_all(ctx, P, p, timing, cs, timing == 2 ? fine : nullptr, true);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     if (st != RIR_OK) {
@@ -1039,64 +1184,40 @@ rir_status capture_part(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int whic
     }
     if (e != hipSuccess)
         return fail(RIR_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    *out = g;
-    return RIR_OK;
-}
-
-// The whole schedule as one graph: the captured prepass and levels as child
-// graphs in a chain, with event-record nodes (the context's timing events)
-// between them when timing.  One launch, no gaps between the parts.
-rir_status capture(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int timing, hipGraphExec_t *out)
-{
-    const int L = P->key.k.levels;
-    std::vector<hipGraph_t> parts;
-    auto cleanup = [&](hipGraph_t parent) {
-        for (hipGraph_t g : parts)
-            hipGraphDestroy(g);
-        if (parent)
-            hipGraphDestroy(parent);
-    };
-    for (int w = -1; w < L; ++w) {
-        hipGraph_t g = nullptr;
-        rir_status st = capture_part(ctx, P, p, w < 0 ? -1 : L - 1 - w, &g);
-        if (st != RIR_OK) {
-            cleanup(nullptr);
-            return st;
+    if (timing == 2) {
+        P->fine_ev[0] = P->fine_ev[1] = nullptr;
+        size_t nn = 0;
+        e = hipGraphGetNodes(g, nullptr, &nn);
+        std::vector<hipGraphNode_t> nodes(nn);
+        if (e == hipSuccess)
+            e = hipGraphGetNodes(g, nodes.data(), &nn);
+        for (size_t i = 0; i < nn && e == hipSuccess; ++i) {
+            hipGraphNodeType t;
+            e = hipGraphNodeGetType(nodes[i], &t);
+            if (e != hipSuccess || t != hipGraphNodeTypeEventRecord)
+                continue;
+            hipEvent_t ev = nullptr;
+            e = hipGraphEventRecordNodeGetEvent(nodes[i], &ev);
+            for (int k = 0; k < 2; ++k)
+                if (e == hipSuccess && ev == fine[k])
+                    P->fine_ev[k] = nodes[i];
         }
-        parts.push_back(g);
-    }
-    hipGraph_t parent = nullptr;
-    hipError_t e = hipGraphCreate(&parent, 0);
-    hipGraphNode_t prev = nullptr;
-    auto add_event = [&](int k) {
-        hipGraphNode_t n = nullptr;
-        if (e == hipSuccess)
-            e = hipGraphAddEventRecordNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, ctx->ev[k]);
-        prev = n;
-        if (timing == 2 && k < 2)
-            P->fine_ev[k] = n;
-    };
-    for (int w = -1; w < L && e == hipSuccess; ++w) {
-        const int l = w < 0 ? L : L - 1 - w;  // event pair 2l, 2l + 1 (l = L: prepass)
-        if (timed_part(timing, l))
-            add_event(2 * l);
-        hipGraphNode_t n = nullptr;
-        if (e == hipSuccess)
-            e = hipGraphAddChildGraphNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, parts[w + 1]);
-        prev = n;
-        if (timed_part(timing, l))
-            add_event(2 * l + 1);
+        if (e == hipSuccess && (!P->fine_ev[0] || !P->fine_ev[1])) {
+            hipGraphDestroy(g);
+            return fail(RIR_E_HIP, "captured schedule lacks the timing event nodes");
+        }
     }
     if (e == hipSuccess)
-        e = hipGraphInstantiate(out, parent, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        cleanup(parent);
-        return fail(RIR_E_HIP, std::string("assembling the schedule graph: ") + hipGetErrorString(e));
+        hipGraphDestroy(g);
+        return fail(RIR_E_HIP, std::string("instantiating the schedule graph: ") + hipGetErrorString(e));
     }
-    // the parent stays alive with the plan: its event nodes address the
+    // the source graph stays alive with the plan: its event nodes address the
     // instantiated graph when the timing events are swapped per call
-    cleanup(nullptr);
-    P->g_src[timing] = parent;
+    if (P->g_src[timing])
+        hipGraphDestroy(P->g_src[timing]);
+    P->g_src[timing] = g;
     return RIR_OK;
 }
 
@@ -1122,7 +1243,7 @@ rir_status run_plan(rir_ctx *ctx, Plan *P, const rir_icp_params *p, hipStream_t 
         }
         HIP_TRY(hipGraphLaunch(g, st));
     } else {
-        rir_status s = enqueue_all(ctx, P, p, tm, st, fine);
+        rir_status s = enqueue_all(ctx, P, p, tm, st, fine, false);
         if (s != RIR_OK)
             return s;
     }
@@ -1258,35 +1379,48 @@ extern "C" rir_status rir_autotune(rir_ctx *ctx, const rir_icp_params *params, i
     const int chunks[] = {1, 2, 4};
     rir_tuning bt = ctx->tune;
     float bms = INFINITY;
+    // the launch shape with the context's lanes, then the lanes at the best
+    // shape (1..4 sub-batches, finest level in them or not)
+    std::vector<rir_tuning> cands;
     for (int b : blocks)
         for (int ppt : ppts)
             for (int gm : gms)
-                for (int ch : chunks) {
-                    rir_tuning t{b, ppt, gm, 1, ch, 1};
-                    s = rir_ctx_set_tuning(ctx, &t);
-                    if (s != RIR_OK)
-                        break;
-                    // warm-up (builds the plan and captures the graphs)
-                    s = rir_icp_batch(ctx, params, n_pairs, pairs, init_poses, poses_scratch, nullptr, stream);
-                    if (s != RIR_OK)
-                        break;
-                    const int reps = 3;
-                    if (hipEventRecord(e0, st) != hipSuccess)
-                        break;
-                    for (int r = 0; r < reps && s == RIR_OK; ++r)
-                        s = rir_icp_batch(ctx, params, n_pairs, pairs, init_poses, poses_scratch, nullptr, stream);
-                    if (s != RIR_OK)
-                        break;
-                    hipEventRecord(e1, st);
-                    hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    hipEventElapsedTime(&ms, e0, e1);
-                    ms /= reps;
-                    if (ms < bms) {
-                        bms = ms;
-                        bt = t;
-                    }
-                }
+                for (int ch : chunks)
+                    cands.push_back(rir_tuning{b, ppt, gm, 1, ch, 1, ctx->tune.lanes, ctx->tune.lane_fine});
+    const size_t n_shape = cands.size();
+    for (size_t ci = 0; ci < n_shape + 2 * kMaxLanes && s == RIR_OK; ++ci) {
+        rir_tuning t;
+        if (ci < n_shape) {
+            t = cands[ci];
+        } else {
+            t = bt;
+            t.lanes = (int)((ci - n_shape) >> 1) + 1;
+            t.lane_fine = (int)((ci - n_shape) & 1);
+        }
+        s = rir_ctx_set_tuning(ctx, &t);
+        if (s != RIR_OK)
+            break;
+        // warm-up (builds the plan and captures the graphs)
+        s = rir_icp_batch(ctx, params, n_pairs, pairs, init_poses, poses_scratch, nullptr, stream);
+        if (s != RIR_OK)
+            break;
+        const int reps = 3;
+        if (hipEventRecord(e0, st) != hipSuccess)
+            break;
+        for (int r = 0; r < reps && s == RIR_OK; ++r)
+            s = rir_icp_batch(ctx, params, n_pairs, pairs, init_poses, poses_scratch, nullptr, stream);
+        if (s != RIR_OK)
+            break;
+        hipEventRecord(e1, st);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < bms) {
+            bms = ms;
+            bt = t;
+        }
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     ctx->timing = was_timing;

@@ -872,10 +872,10 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
         // constants could be hoisted out of)
         const TileIter it = tile_iter(a.n_tiles, a.xcd_remap);
         if (it.cur < it.end)
-            tile(it.cur);
+            tile(a.tile_base + it.cur);
     } else {
         for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step)
-            tile(it.cur);
+            tile(a.tile_base + it.cur);
     }
 }
 
@@ -897,7 +897,7 @@ __global__ __launch_bounds__(kPairBlock) void k_icp_level(StepArgs a)
     __shared__ long long s_cnt[4];
     __shared__ double s_pose[12];
     __shared__ int s_go;
-    const int pair = blockIdx.x, tid = threadIdx.x, nwave = blockDim.x >> 6, l = a.level;
+    const int pair = a.pair_base + blockIdx.x, tid = threadIdx.x, nwave = blockDim.x >> 6, l = a.level;
     int *fl = a.flags + (size_t)pair * kFlagStride;
     const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + pair;
     if (cload(&P->ntile[l]) != 0 || (cload(fl + l) & 1))
@@ -1081,7 +1081,7 @@ __device__ __forceinline__ void solve_from_tiles(const StepArgs &a, int pair, in
 template <typename T>
 __global__ __launch_bounds__(256) void k_solve(StepArgs a)
 {
-    const int pair = blockIdx.x, l = a.level;
+    const int pair = a.pair_base + blockIdx.x, l = a.level;
     int *fl = a.flags + (size_t)pair * kFlagStride;
     if (a.mode != kStepDebug) {
         if (fl[l] & 1)

@@ -60,6 +60,8 @@ struct LevelImage {
 // flags[pair * kFlagStride + kMaxLevels] bit 0 = learned weights rejected in
 // the last iteration (a pseudo-Huber redo is pending).
 constexpr int kFlagStride = kMaxLevels + 1;
+// Concurrent sub-batches (streams) of the coarse levels of one batch.
+constexpr int kMaxLanes = 4;
 constexpr int kAccum = 32;  // float accumulators per tile (30 used)
 
 enum StepMode { kStepNormal = 0, kStepFallback = 1, kStepDebug = 2 };
@@ -75,7 +77,9 @@ constexpr int kMlpB1 = 0, kMlpB2 = 64, kMlpB3 = 128, kMlpNB = 129;
 struct StepArgs {
     const void *pairs;   // PairDesc<T>[n_pairs]
     const int2 *tiles;   // (pair, first segment) of every tile of this level
-    int n_tiles;
+    int n_tiles;         // tiles of this launch: tiles[tile_base .. tile_base + n_tiles)
+    int tile_base;
+    int pair_base;       // one-workgroup-per-pair launches cover pairs pair_base + blockIdx.x
     int level, iter, levels;
     int iters;           // iterations scheduled at this level
     int tile_seg;        // segments per tile at this level

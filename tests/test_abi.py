@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_struct_sizes_match_header(L):
     assert ctypes.sizeof(rir.LevelStatsC) == 280
     assert rir.STATS_DTYPE.itemsize == 280
-    assert ctypes.sizeof(rir.Tuning) == 24
+    assert ctypes.sizeof(rir.Tuning) == 32
     assert ctypes.sizeof(rir.VolumeDesc) == 48
 
 

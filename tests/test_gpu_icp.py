@@ -221,6 +221,42 @@ def test_pair_alone_equals_pair_in_mixed_batch(rir, ctx):
         assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (i, er, et)
 
 
+def test_lane_count_changes_no_result(rir):
+    """The coarse levels of a batch (or all of them) run as 1-4 concurrent
+    sub-batches (lanes): poses and statistics are bitwise those of one lane,
+    eager and captured, with
+    every timing mode (the captured schedule then carries event nodes), on a
+    mixed batch whose coarse levels use the tiled and the pair-resident paths."""
+    c = rir.Context(0)
+    shapes = [(16, 1024), (32, 1024), (64, 1024), (128, 2048), (64, 1024)]
+    pairs = [_pair("batch256mixed", 2100 + i, shape=shapes[i % 5]) for i in range(7)]
+    sensors = {}
+    batch = []
+    for p in pairs:
+        key = (p.sensor.H, p.sensor.W)
+        if key not in sensors:
+            sensors[key] = rir.Sensor.from_model(p.sensor)
+        batch.append((sensors[key], to_dev(p.src), to_dev(p.dst)))
+    ref = None
+    for lanes, fine in ((1, 0), (2, 0), (3, 1), (4, 1)):
+        c.set_tuning(256, 8, 0, 1, 4, 1, lanes, fine)
+        for graph in (True, False):
+            for timing in (0, 1, 2):
+                c.enable_timing(timing > 0, finest_only=timing == 2)
+                prm = rir.make_params(levels=3, iters=[4, 4, 3], delta=0.5, use_graph=graph)
+                T, st = rir.icp_batch(c, prm, batch)
+                got = (T.cpu().numpy(), st.cpu().numpy().tobytes())
+                if timing:
+                    ms = c.level_times(3)
+                    assert ms[0] > 0.0, (lanes, graph, timing, ms)
+                    if timing == 1:
+                        assert all(x > 0.0 for x in ms), (lanes, graph, ms)
+                if ref is None:
+                    ref = got
+                assert np.array_equal(got[0], ref[0]) and got[1] == ref[1], (lanes, fine, graph, timing)
+    c.enable_timing(False)
+
+
 def test_degenerate_and_empty_inputs(rir, ctx):
     """An empty source and a ground-only scene give status DEGENERATE with the
     pose unchanged, as in the oracle; a tiny ragged image still runs."""
