@@ -1018,36 +1018,52 @@ StepArgs step_args(const Plan *P, const rir_icp_params *p, int level, int iter, 
     return a;
 }
 
-// Enqueues the normal/pyramid pass (and the flag/statistics reset).
-rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t st)
+// Enqueues the flag/ticket/statistics reset of the whole batch.
+rir_status enqueue_clear(const Plan *P, hipStream_t st)
 {
     HIP_TRY(launch_clear(P->d_flags, P->n_pairs * (kFlagStride + 1), P->d_stats, P->n_pairs * P->key.k.levels, st));
+    return RIR_OK;
+}
+
+// Enqueues the normal/pyramid pass (target records, level images, learned
+// neighbour features, initial pose and ray frames) of the whole batch
+// (lane < 0) or of one sub-batch.
+rir_status enqueue_prepass(const Plan *P, const rir_icp_params *p, hipStream_t st, int lane = -1)
+{
+    const int np = lane < 0 ? P->n_pairs : P->lane_p0[lane + 1] - P->lane_p0[lane];
+    const int pb = lane < 0 ? 0 : P->lane_p0[lane];
     PrepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.pairs = P->d_desc;
     a.tiles = P->d_tiles[0];
     a.n_tiles = P->n_tiles[0];
+    if (lane >= 0) {
+        a.tile_base = P->lane_t0[0][lane];
+        a.n_tiles = P->lane_t0[0][lane + 1] - a.tile_base;
+    }
+    a.pair_base = pb;
     a.tile_seg = P->tile_seg[0];
     a.levels = P->key.k.levels;
     a.init_centroid = p->init_mode == 1;
     a.edge_rel = p->edge_rel;
-    a.psum = P->d_psum;
+    a.psum = P->d_psum;  // level-0 records
     a.poses = P->d_poses;
     a.xcd_remap = P->key.k.tune.xcd_remap;
     a.given_normals = P->key.k.normal_window > 0 ? 1 : 0;
     if (a.given_normals)
-        HIP_TRY(launch_pca_records(P->fp64, a, P->key.k.normal_window, P->n_pairs, (int)P->max_px[0], st));
-    HIP_TRY(launch_prepass(P->fp64, a, P->grid[0], P->block, P->n_pairs, st));
+        HIP_TRY(launch_pca_records(P->fp64, a, P->key.k.normal_window, np, (int)P->max_px[0], st));
+    HIP_TRY(launch_prepass(P->fp64, a, lane < 0 ? P->grid[0] : P->lane_grid[0][lane], P->block, np, st));
     for (int l = 0; l < P->key.k.levels; ++l)
         if (P->nbf[l]) {
             NbrArgs b;
             b.pairs = P->d_desc;
+            b.pair_base = pb;
             b.level = l;
             b.delta = p->delta;
-            HIP_TRY(launch_nbr_feats(b, P->n_pairs, (int)P->max_px[l], st));
+            HIP_TRY(launch_nbr_feats(b, np, (int)P->max_px[l], st));
         }
-    StepArgs f = step_args(P, p, 0, 0, kStepNormal);
-    HIP_TRY(launch_frames(P->fp64, f, P->n_pairs, st));
+    StepArgs f = step_args(P, p, 0, 0, kStepNormal, lane);
+    HIP_TRY(launch_frames(P->fp64, f, np, st));
     return RIR_OK;
 }
 
@@ -1076,14 +1092,21 @@ rir_status enqueue_level(const Plan *P, const rir_icp_params *p, int l, hipStrea
     return RIR_OK;
 }
 
-// Levels hi .. lo (coarse to fine) of every sub-batch, each on its lane
-// stream: forked from st after the work enqueued so far, joined back into st.
-rir_status enqueue_lanes(rir_ctx *ctx, const Plan *P, const rir_icp_params *p, int hi, int lo, hipStream_t st)
+// The prepass (with `prepass`) and levels hi .. lo (coarse to fine; none if
+// hi < lo) of every sub-batch, each on its lane stream: forked from st after
+// the work enqueued so far, joined back into st.
+rir_status enqueue_lanes(rir_ctx *ctx, const Plan *P, const rir_icp_params *p, bool prepass, int hi, int lo,
+                         hipStream_t st)
 {
     HIP_TRY(hipEventRecord(ctx->fork_ev, st));
     for (int k = 0; k < P->n_lanes; ++k) {
         hipStream_t q = ctx->lane_st[k];
         HIP_TRY(hipStreamWaitEvent(q, ctx->fork_ev, 0));
+        if (prepass) {
+            rir_status s = enqueue_prepass(P, p, q, k);
+            if (s != RIR_OK)
+                return s;
+        }
         for (int l = hi; l >= lo; --l) {
             rir_status s = enqueue_level(P, p, l, q, k);
             if (s != RIR_OK)
@@ -1118,46 +1141,54 @@ rir_status record_timing(hipEvent_t e, hipStream_t st, bool capturing)
     return RIR_OK;
 }
 
-// Enqueues the whole schedule: prepass, then the levels coarse to fine, with
-// timing events around the prepass and every level (timing 1) or around the
-// finest level (timing 2; `fine` the event pair, else the context's).  With
-// more than one lane the coarse levels (with lane_fine all levels) run as
-// concurrent sub-batches, forked once after the prepass and joined at the
-// end; timing joins and forks again at each timed boundary (every level
-// under timing 1, before the finest level under timing 2), so that each
-// timed part has its own time.
+// Enqueues the whole schedule: reset, prepass, then the levels coarse to
+// fine, with timing events around the prepass and every level (timing 1) or
+// around the finest level (timing 2; `fine` the event pair, else the
+// context's).  With more than one lane the prepass and the coarse levels
+// (with lane_fine all levels) run as concurrent sub-batches, forked once
+// after the reset and joined at the end; timing joins and forks again at
+// each timed boundary (after the prepass and every level under timing 1,
+// before the finest level under timing 2), so that each timed part has its
+// own time.
 rir_status enqueue_all(rir_ctx *ctx, Plan *P, const rir_icp_params *p, int timing, hipStream_t st, hipEvent_t *fine,
                        bool capturing)
 {
     const int L = P->key.k.levels;
     hipEvent_t *evs = ctx->ev;
     rir_status s = RIR_OK;
+    const bool lanes = P->n_lanes > 1, fine_lanes = lanes && P->key.k.tune.lane_fine;
     if (timed_part(timing, L) && (s = record_timing(evs[2 * L], st, capturing)) != RIR_OK)
         return s;
-    if ((s = enqueue_prepass(P, p, st)) != RIR_OK)
+    if ((s = enqueue_clear(P, st)) != RIR_OK)
+        return s;
+    if (lanes && timing == 0)
+        s = enqueue_lanes(ctx, P, p, true, L - 1, fine_lanes ? 0 : 1, st);
+    else if (lanes && timing == 2)
+        s = enqueue_lanes(ctx, P, p, true, L - 1, 1, st);
+    else if (lanes)
+        s = enqueue_lanes(ctx, P, p, true, -1, 0, st);
+    else
+        s = enqueue_prepass(P, p, st);
+    if (s != RIR_OK)
         return s;
     if (timed_part(timing, L) && (s = record_timing(evs[2 * L + 1], st, capturing)) != RIR_OK)
         return s;
-    const bool lanes = P->n_lanes > 1, fine_lanes = lanes && P->key.k.tune.lane_fine;
-    if (fine_lanes && timing == 0)
-        return enqueue_lanes(ctx, P, p, L - 1, 0, st);
-    if (lanes && timing != 1) {
-        if (L > 1 && (s = enqueue_lanes(ctx, P, p, L - 1, 1, st)) != RIR_OK)
-            return s;
-    } else {
+    if (!lanes || timing == 1) {
         for (int l = L - 1; l >= 1; --l) {
             if (timed_part(timing, l) && (s = record_timing(evs[2 * l], st, capturing)) != RIR_OK)
                 return s;
-            s = lanes ? enqueue_lanes(ctx, P, p, l, l, st) : enqueue_level(P, p, l, st);
+            s = lanes ? enqueue_lanes(ctx, P, p, false, l, l, st) : enqueue_level(P, p, l, st);
             if (s != RIR_OK)
                 return s;
             if (timed_part(timing, l) && (s = record_timing(evs[2 * l + 1], st, capturing)) != RIR_OK)
                 return s;
         }
     }
+    if (lanes && timing == 0 && fine_lanes)
+        return RIR_OK;  // the finest level ran in the lanes
     if (timed_part(timing, 0) && (s = record_timing(fine ? fine[0] : evs[0], st, capturing)) != RIR_OK)
         return s;
-    if ((s = fine_lanes ? enqueue_lanes(ctx, P, p, 0, 0, st) : enqueue_level(P, p, 0, st)) != RIR_OK)
+    if ((s = fine_lanes ? enqueue_lanes(ctx, P, p, false, 0, 0, st) : enqueue_level(P, p, 0, st)) != RIR_OK)
         return s;
     if (timed_part(timing, 0) && (s = record_timing(fine ? fine[1] : evs[1], st, capturing)) != RIR_OK)
         return s;
@@ -1322,7 +1353,9 @@ extern "C" rir_status rir_debug_associate(rir_ctx *ctx, const rir_icp_params *pa
     s = update_images(P, pair, st);
     if (s != RIR_OK)
         return s;
-    s = enqueue_prepass(P, &q, st);
+    s = enqueue_clear(P, st);
+    if (s == RIR_OK)
+        s = enqueue_prepass(P, &q, st);
     if (s != RIR_OK)
         return s;
     // the pose goes through the (pinned) descriptor staging event discipline

@@ -180,7 +180,8 @@ __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwave = blockDim.x >> 6;
     for (TileIter it = tile_iter(a.n_tiles, a.xcd_remap); it.cur < it.end; it.cur += it.step) {
-        const int2 tl = cload(a.tiles + it.cur);
+        const int cur = a.tile_base + it.cur;
+        const int2 tl = cload(a.tiles + cur);
         const PairDesc<T> *P = pairs + tl.x;
         const SensorTab<T> *S = cload(&P->tab);
         const int H = cload(&P->H), W = cload(&P->W), spr = (W + kSegPx - 1) / kSegPx;
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(256) void k_prepass(PrepArgs a)
             T sum = (T)0;
             for (int w = 0; w < nwave; ++w)
                 sum += s_red[w][tid];
-            psum[(size_t)it.cur * kAccum + tid] = sum;
+            psum[(size_t)cur * kAccum + tid] = sum;
         }
         __syncthreads();
     }
@@ -293,7 +294,8 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
 {
     __shared__ double s_c[8];
-    const PairDesc<T> &P = reinterpret_cast<const PairDesc<T> *>(a.pairs)[blockIdx.x];
+    const int pair = a.pair_base + blockIdx.x;
+    const PairDesc<T> &P = reinterpret_cast<const PairDesc<T> *>(a.pairs)[pair];
     const T *psum = reinterpret_cast<const T *>(a.psum);
     const int lane = threadIdx.x;
     if (lane < 8) {
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
     }
     __syncthreads();
     if (lane < 16) {
-        double *T0 = a.poses + 16 * (size_t)blockIdx.x;
+        double *T0 = a.poses + 16 * (size_t)pair;
         double val = (lane % 5 == 0) ? 1.0 : 0.0;
         if ((lane == 3 || lane == 7 || lane == 11) && s_c[3] > 0.0 && s_c[7] > 0.0) {
             const int c = lane / 4;
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(64) void k_centroid(PrepArgs a)
 // FP32 plans only (the step's features are then read back bit for bit).
 __global__ __launch_bounds__(256) void k_nbr_feats(NbrArgs a)
 {
-    const PairDesc<float> *P = reinterpret_cast<const PairDesc<float> *>(a.pairs) + blockIdx.y;
+    const PairDesc<float> *P = reinterpret_cast<const PairDesc<float> *>(a.pairs) + a.pair_base + blockIdx.y;
     const int l = a.level;
     uint32_t *out = cload(&P->nbf[l]);
     if (!out)
@@ -962,7 +964,7 @@ __global__ __launch_bounds__(kPairBlock) void k_icp_level(StepArgs a)
 template <typename T>
 __global__ __launch_bounds__(256) void k_frames(StepArgs a)
 {
-    const int pair = blockIdx.x;
+    const int pair = a.pair_base + blockIdx.x;
     const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + pair;
     double R[12];
 #pragma unroll

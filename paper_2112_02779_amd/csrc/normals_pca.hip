@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_normals_pca(SensorTab<double> S, const 
 template <typename T, int HALF>
 __global__ __launch_bounds__(256) void k_pca_records(PrepArgs a)
 {
-    const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + blockIdx.y;
+    const PairDesc<T> *P = reinterpret_cast<const PairDesc<T> *>(a.pairs) + a.pair_base + blockIdx.y;
     const int H = cload(&P->H), W = cload(&P->W), npx = H * W;
     const SensorTab<double> *Sd = cload(&P->tabd);
     const SensorTab<T> *S = cload(&P->tab);

@@ -115,6 +115,7 @@ struct StepArgs {
 // Neighbour features of the learned weight for one level (k_nbr_feats).
 struct NbrArgs {
     const void *pairs;  // PairDesc<T>[n_pairs]
+    int pair_base;      // the launch covers pairs pair_base + blockIdx.y
     int level;
     double delta;
 };
@@ -122,7 +123,9 @@ struct NbrArgs {
 struct PrepArgs {
     const void *pairs;  // PairDesc<T>[n_pairs]
     const int2 *tiles;  // level-0 tiles (pair, first segment)
-    int n_tiles;
+    int n_tiles;        // tiles of this launch: tiles[tile_base .. tile_base + n_tiles)
+    int tile_base;
+    int pair_base;      // per-pair launches cover pairs pair_base + block index
     int tile_seg;
     int levels;
     int init_centroid;  // 1: compute t0 from the point-set centres
