@@ -773,7 +773,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=None,
-                    help="block,px_per_thread,grid_mult,xcd_remap,chunk[,solve_in_step] to use instead of autotuning")
+                    help="block,px_per_thread,grid_mult,xcd_remap,chunk[,solve_in_step[,lanes[,lane_fine]]] to use "
+                         "instead of autotuning")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (value then unchecked)")
     ap.add_argument("--sample-every", type=int, default=1,
                     help="oracle-check every k-th pair of the sequence (1: all)")
@@ -857,21 +858,27 @@ def main():
     T_gpu = poses.cpu().numpy()
     st = rir.stats_to_numpy(stats, n, levels)
 
-    # dominant kernel: the finest-level Gauss-Newton iteration (the k_icp_step
-    # launch and its k_solve launch; the level's graph is timed with HIP events
-    # on the launch stream, 10 iterations per graph)
+    # dominant kernel: the finest-level Gauss-Newton iteration over all pairs
+    # (k_icp_step, the pair solve in the same launch; with lane_fine one
+    # launch per sub-batch of pairs, the launches of an iteration running
+    # concurrently on their streams).  HIP event nodes of the captured
+    # schedule bracket the finest level (fork to join of its lanes), on the
+    # stream the schedule is launched on; 10 iterations per step.
     n0 = sm.H * sm.W
     tile_px = tuning["block"] * tuning["px_per_thread"]  # finest level
     tiles0 = n * ((n0 + tile_px - 1) // tile_px)
     bytes_l0 = 4.0 * n0 * n + 16.0 * float(st["n_proj"][:, 0].sum()) + 144.0 * tiles0
-    l0_launch_ms = fine_ms / iters[0]
-    achieved = bytes_l0 / (l0_launch_ms * 1e-3) / 1e9
+    fine_lanes = min(tuning["lanes"], n) if tuning["lane_fine"] else 1
+    l0_iter_ms = fine_ms / iters[0]
+    achieved = bytes_l0 / (l0_iter_ms * 1e-3) / 1e9
     traffic = counted_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "rir::k_icp_step<float, 0, true, *> (finest-level iteration; with solve_in_step the pair "
-                          "solve runs in the same launch, else one rir::k_solve<float> launch follows)",
-                "bytes_per_launch": bytes_l0, "launch_ms": round(l0_launch_ms, 5)}
+                "kernel": "rir::k_icp_step<float, 0, true, *> (finest-level Gauss-Newton iteration over all pairs, "
+                          "pair solve in the launch" + (f"; {fine_lanes} concurrent launches per iteration, one per "
+                                                        f"sub-batch of pairs" if fine_lanes > 1 else "") + ")",
+                "bytes_per_iteration": bytes_l0, "iteration_ms": round(l0_iter_ms, 5),
+                "launches_per_iteration": fine_lanes}
 
     roofline["frac_of_measured_copy"] = round(achieved / copy["GBps"], 4)
     roofline["measured_copy_GBps"] = copy["GBps"]
