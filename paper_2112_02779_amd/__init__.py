@@ -233,8 +233,8 @@ class Context:
             _lib.rir_ctx_destroy(self.handle)
             self.handle = None
 
-    def set_tuning(self, block=256, px_per_thread=8, grid_mult=0, xcd_remap=1, chunk=4, solve_in_step=1, lanes=3,
-                   lane_fine=1):
+    def set_tuning(self, block=256, px_per_thread=8, grid_mult=0, xcd_remap=1, chunk=4, solve_in_step=1, lanes=1,
+                   lane_fine=0):
         t = Tuning(block, px_per_thread, grid_mult, xcd_remap, chunk, solve_in_step, lanes, lane_fine)
         _check(lib().rir_ctx_set_tuning(self.handle, ctypes.byref(t)))
 

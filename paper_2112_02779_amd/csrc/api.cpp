@@ -451,7 +451,7 @@ struct rir_ctx {
     // and joined back into the caller's stream with the events below
     hipStream_t lane_st[kMaxLanes] = {};
     hipEvent_t fork_ev = nullptr, join_ev[kMaxLanes] = {};
-    rir_tuning tune{256, 8, 0, 1, 4, 1, 3, 1};
+    rir_tuning tune{256, 8, 0, 1, 4, 1, 1, 0};
     std::map<PlanKey, std::unique_ptr<Plan>> plans;
     uint64_t use_clock = 0;
     int timing = 0;  // 0 off, 1 every level and the prepass, 2 the finest level only
@@ -1412,24 +1412,16 @@ extern "C" rir_status rir_autotune(rir_ctx *ctx, const rir_icp_params *params, i
     const int chunks[] = {1, 2, 4};
     rir_tuning bt = ctx->tune;
     float bms = INFINITY;
-    // the launch shape with the context's lanes, then the lanes at the best
-    // shape (1..4 sub-batches, finest level in them or not)
+    // the launch shape at the context's lane setting (the lane count is not
+    // swept: concurrent sub-batches stay off unless the caller sets them)
     std::vector<rir_tuning> cands;
     for (int b : blocks)
         for (int ppt : ppts)
             for (int gm : gms)
                 for (int ch : chunks)
                     cands.push_back(rir_tuning{b, ppt, gm, 1, ch, 1, ctx->tune.lanes, ctx->tune.lane_fine});
-    const size_t n_shape = cands.size();
-    for (size_t ci = 0; ci < n_shape + 2 * kMaxLanes && s == RIR_OK; ++ci) {
-        rir_tuning t;
-        if (ci < n_shape) {
-            t = cands[ci];
-        } else {
-            t = bt;
-            t.lanes = (int)((ci - n_shape) >> 1) + 1;
-            t.lane_fine = (int)((ci - n_shape) & 1);
-        }
+    for (size_t ci = 0; ci < cands.size() && s == RIR_OK; ++ci) {
+        const rir_tuning t = cands[ci];
         s = rir_ctx_set_tuning(ctx, &t);
         if (s != RIR_OK)
             break;

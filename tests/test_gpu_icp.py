@@ -221,6 +221,8 @@ def test_pair_alone_equals_pair_in_mixed_batch(rir, ctx):
         assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (i, er, et)
 
 
+@pytest.mark.skip(reason="concurrent sub-batches are switched off: the full benchmark with them on ended once in "
+                         "a host segmentation fault whose cause is not found yet")
 def test_lane_count_changes_no_result(rir):
     """The coarse levels of a batch (or all of them) run as 1-4 concurrent
     sub-batches (lanes): poses and statistics are bitwise those of one lane,
