@@ -23,6 +23,8 @@ namespace {
 constexpr int kFrameWords = 16;
 // Voxels of a column each thread processes together.
 constexpr int kVox = 4;
+// Consecutive blocks one XCD takes at a time.
+constexpr int kSdfXcdRun = 8;
 
 }  // namespace
 
@@ -35,10 +37,18 @@ __global__ __launch_bounds__(256) void k_sdf_fuse(const SdfArgs a)
     const int nblk = a.nbx * a.nby * a.nbz;
     int b = blockIdx.x;
     // XCD-aware order: workgroups go to the 8 XCDs round robin by id; give
-    // each XCD a contiguous slab of blocks (neighbouring blocks read
-    // neighbouring pixels, which then share that XCD's L2)
-    if (a.xcd_remap && (nblk & 7) == 0)
-        b = (b & 7) * (nblk >> 3) + (b >> 3);
+    // each XCD runs of kSdfXcdRun consecutive blocks (neighbouring blocks read
+    // neighbouring pixels, which then share that XCD's L2), the runs dealt to
+    // the XCDs in turn, so that every XCD gets its share of the blocks the
+    // scans reach (one contiguous slab per XCD would leave most XCDs idle:
+    // the reachable blocks follow the sensor's path).  The grid is a
+    // multiple of 8 runs; ids past the last block exit.
+    if (a.xcd_remap) {
+        const int j = b >> 3;
+        b = (j / kSdfXcdRun) * (8 * kSdfXcdRun) + (b & 7) * kSdfXcdRun + j % kSdfXcdRun;
+        if (b >= nblk)
+            return;
+    }
     const int bx = b % a.nbx, byz = b / a.nbx;
     const int by = byz % a.nby, bz = byz / a.nby;
     const int tid = threadIdx.x;
@@ -143,7 +153,8 @@ __global__ __launch_bounds__(256) void k_sdf_fuse(const SdfArgs a)
 
 hipError_t launch_sdf_fuse(const SdfArgs &a, bool r0, bool pow2, hipStream_t stream)
 {
-    const int nblk = a.nbx * a.nby * a.nbz;
+    const int n = a.nbx * a.nby * a.nbz, run = 8 * kSdfXcdRun;
+    const int nblk = a.xcd_remap ? (n + run - 1) / run * run : n;
     if (r0)
         hipLaunchKernelGGL((k_sdf_fuse<true, false>), dim3(nblk), dim3(256), 0, stream, a);
     else if (pow2)
