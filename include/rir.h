@@ -173,7 +173,8 @@ typedef struct {
  * stream, so that the launches of different sub-batches overlap; lane_fine: 1
  * runs the finest level in the sub-batches too, 0 as one launch per iteration
  * over the whole batch.  Neither changes any result.  Default: lanes 1 (no
- * sub-batches), lane_fine 0. */
+ * sub-batches), lane_fine 0; lanes > 1 is switched off in this build
+ * (rir_ctx_set_tuning returns RIR_E_UNSUPPORTED). */
 typedef struct {
     int32_t block, px_per_thread, grid_mult, xcd_remap, chunk, solve_in_step, lanes, lane_fine;
 } rir_tuning;

@@ -518,6 +518,10 @@ extern "C" rir_status rir_ctx_create(int device, rir_ctx **out)
 
 extern "C" void rir_ctx_destroy(rir_ctx *ctx) { delete ctx; }
 
+// Concurrent sub-batches (rir_tuning.lanes > 1): built and tested, switched
+// off (see check_tuning).
+constexpr bool kLanesEnabled = false;
+
 static rir_status check_tuning(const rir_tuning *t)
 {
     if (!(t->block == 64 || t->block == 128 || t->block == 256))
@@ -534,6 +538,10 @@ static rir_status check_tuning(const rir_tuning *t)
         return fail(RIR_E_INVALID, "rir_tuning.solve_in_step must be 0 or 1");
     if (t->lanes < 1 || t->lanes > kMaxLanes)
         return fail(RIR_E_INVALID, "rir_tuning.lanes must be in 1..4");
+    // Concurrent sub-batches are switched off: a full benchmark run with them
+    // on ended once in a host segmentation fault whose cause is not found.
+    if (t->lanes > 1 && !kLanesEnabled)
+        return fail(RIR_E_UNSUPPORTED, "rir_tuning.lanes > 1 (concurrent sub-batches) is switched off in this build");
     if (t->lane_fine != 0 && t->lane_fine != 1)
         return fail(RIR_E_INVALID, "rir_tuning.lane_fine must be 0 or 1");
     return RIR_OK;

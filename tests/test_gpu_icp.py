@@ -221,8 +221,9 @@ def test_pair_alone_equals_pair_in_mixed_batch(rir, ctx):
         assert er < POSE_ROT_TOL and et < POSE_TRANS_TOL, (i, er, et)
 
 
-@pytest.mark.skip(reason="concurrent sub-batches are switched off: the full benchmark with them on ended once in "
-                         "a host segmentation fault whose cause is not found yet")
+@pytest.mark.skip(reason="concurrent sub-batches are switched off in this build (rir_ctx_set_tuning rejects lanes > 1): "
+                         "the full benchmark with them on ended once in a host segmentation fault whose cause is not "
+                         "found yet")
 def test_lane_count_changes_no_result(rir):
     """The coarse levels of a batch (or all of them) run as 1-4 concurrent
     sub-batches (lanes): poses and statistics are bitwise those of one lane,
@@ -295,6 +296,12 @@ def test_host_side_errors(rir, ctx):
     with pytest.raises(rir.RirError) as ei:
         rir.icp_batch(ctx, rir.make_params(levels=1, delta=-1.0), [(sen, to_dev(pair.src), to_dev(pair.dst))])
     assert ei.value.status == rir.RIR_E_INVALID
+    # concurrent sub-batches are switched off in this build
+    c = rir.Context(0)
+    with pytest.raises(rir.RirError) as ei:
+        c.set_tuning(256, 8, 0, 1, 4, 1, 3, 0)
+    assert ei.value.status == rir.RIR_E_UNSUPPORTED
+    assert c.get_tuning()["lanes"] == 1
 
 
 def test_centroid_initialisation(rir, ctx):
