@@ -7,9 +7,9 @@
 // pixel keeps the nearest range (an atomic minimum on the FP32 bit pattern,
 // which orders like the value for positive floats).
 //
-// One thread per pixel, all in FP64 (the pose, the point and the projection
-// with the FP64 sensor tables), so the output differs from an FP64 reference
-// only where a projection lies on a rounding boundary.
+// All in FP64 (the pose, the point and the projection with the FP64 sensor
+// tables), so the output differs from an FP64 reference only where a
+// projection lies on a rounding boundary.
 #include "rir_ops.h"
 
 namespace rir {
@@ -72,27 +72,38 @@ __global__ void k_inf_to_zero(uint32_t *p, int64_t n)
             p[i] = 0u;
 }
 
+// Columns per workgroup and row groups (threads per column) of k_deskew.
+constexpr int kDeskewCols = 64, kDeskewRowGroups = 4;
+
+// One workgroup per 64 columns of one scan (grid: column blocks x scans of
+// the batch); each thread takes one column and every 4th row of it, so a
+// column's pose Exp(s_u xi) is formed once per thread instead of once per
+// pixel, and the loads of a row are coalesced across the 64 columns.
 template <bool R0, bool POW2>
 __global__ __launch_bounds__(256) void k_deskew(const SensorTab<double> *tab, const float *in, uint32_t *out,
-                                                int n_images, Twists tw)
+                                                Twists tw)
 {
     const LevelView<double> V = level_view(tab, 0);
     const int H = V.Hl, W = V.Wl;
     const double *row = V.rowp, *col = cload(&tab->col);
     const double r0 = V.r0;
-    const int64_t hw = (int64_t)H * W, n = hw * n_images;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
-        const float rf = in[g];
+    const int img = blockIdx.y;
+    const int u = blockIdx.x * kDeskewCols + (int)(threadIdx.x % kDeskewCols);
+    const int v0 = (int)(threadIdx.x / kDeskewCols);
+    if (u >= W)
+        return;
+    const int64_t hw = (int64_t)H * W;
+    const float *src = in + (size_t)img * hw;
+    uint32_t *dst = out + (size_t)img * hw;
+    const double su = ((double)u + 0.5) / (double)W - 0.5;
+    double xs[6], R[9], t[3];
+    for (int k = 0; k < 6; ++k)
+        xs[k] = su * tw.xi[img][k];
+    exp_twist(xs, R, t);
+    for (int v = v0; v < H; v += kDeskewRowGroups) {
+        const float rf = src[(size_t)v * W + u];
         if (!range_ok(rf))
             continue;
-        const int img = (int)(g / hw);
-        const int i = (int)(g - (int64_t)img * hw);
-        const int v = i / W, u = i - v * W;
-        const double su = ((double)u + 0.5) / (double)W - 0.5;
-        double xs[6], R[9], t[3];
-        for (int k = 0; k < 6; ++k)
-            xs[k] = su * tw.xi[img][k];
-        exp_twist(xs, R, t);
         const V3<double> p = unproject(row, col, r0, u, v, (double)rf);
         const double x = R[0] * p.x + R[1] * p.y + R[2] * p.z + t[0];
         const double y = R[3] * p.x + R[4] * p.y + R[5] * p.z + t[1];
@@ -101,7 +112,7 @@ __global__ __launch_bounds__(256) void k_deskew(const SensorTab<double> *tab, co
         double r2;
         if (!project<double, R0, POW2>(V, x, y, z, u2, v2, r2))
             continue;
-        atomicMin(out + (size_t)img * hw + (size_t)v2 * W + u2, __float_as_uint((float)r2));
+        atomicMin(dst + (size_t)v2 * W + u2, __float_as_uint((float)r2));
     }
 }
 
@@ -124,13 +135,14 @@ hipError_t launch_deskew(const SensorTab<double> *tab, int H, int W, bool r0, in
                 tw.xi[k][j] = twists[6 * (k0 + k) + j];
         const float *src = in + hw * k0;
         uint32_t *dst = ob + hw * k0;
-        const int g = (int)std::min<int64_t>((hw * nb + 255) / 256, 65536);
+        const dim3 g((unsigned)((W + kDeskewCols - 1) / kDeskewCols), (unsigned)nb);
+        const dim3 b(kDeskewCols * kDeskewRowGroups);
         if (r0)
-            hipLaunchKernelGGL((k_deskew<true, false>), dim3(g), dim3(256), 0, stream, tab, src, dst, nb, tw);
+            hipLaunchKernelGGL((k_deskew<true, false>), g, b, 0, stream, tab, src, dst, tw);
         else if (pow2)
-            hipLaunchKernelGGL((k_deskew<false, true>), dim3(g), dim3(256), 0, stream, tab, src, dst, nb, tw);
+            hipLaunchKernelGGL((k_deskew<false, true>), g, b, 0, stream, tab, src, dst, tw);
         else
-            hipLaunchKernelGGL((k_deskew<false, false>), dim3(g), dim3(256), 0, stream, tab, src, dst, nb, tw);
+            hipLaunchKernelGGL((k_deskew<false, false>), g, b, 0, stream, tab, src, dst, tw);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
