@@ -2,9 +2,9 @@
 // eigen-decomposition estimator that Dong et al. name in Sec. 4.1 next to the
 // neighbour cross product), for batches of range images on gfx950.
 //
-// One thread per pixel.  The window's points are unprojected (Eq. (1)) from
-// the FP64 sensor tables and accumulated relative to the centre point in
-// FP64: the covariance of a planar patch has a smallest eigenvalue many
+// The window's points are unprojected (Eq. (1)) from the FP64 sensor tables
+// (once per point and tile, into shared memory) and accumulated relative to
+// the centre point in FP64: the covariance of a planar patch has a smallest eigenvalue many
 // orders of magnitude below the largest, which FP32 sums could not resolve.
 // The smallest eigenpair comes from the closed-form (trigonometric)
 // eigenvalues of the symmetric 3x3 matrix and the largest cross product of
@@ -69,6 +69,39 @@ __device__ __forceinline__ bool smallest_eigenpair(double a00, double a01, doubl
 
 }  // namespace
 
+// The normal from the window sums about the centre point (sx.. = sums of
+// q = p - pc, sxx.. of its products, cnt points): covariance about the mean,
+// smallest eigenpair, the middle-eigenvalue test (a line has no normal), the
+// normal turned to face the sensor.  Returns false (n untouched) if none.
+template <int HALF>
+__device__ __forceinline__ bool pca_from_sums(const SensorTab<double> &S, int u, int v, int cnt, double sx, double sy,
+                                              double sz, double sxx, double sxy, double sxz, double syy, double syz,
+                                              double szz, double n[3])
+{
+    constexpr int K = 2 * HALF + 1;
+    constexpr int kMinPts = (K * K + 1) / 2;
+    if (cnt < kMinPts)
+        return false;
+    const double ic = 1.0 / (double)cnt;
+    const double mx = sx * ic, my = sy * ic, mz = sz * ic;
+    double l0, l1, l2, m[3];
+    bool ok = smallest_eigenpair(sxx * ic - mx * mx, sxy * ic - mx * my, sxz * ic - mx * mz, syy * ic - my * my,
+                                 syz * ic - my * mz, szz * ic - mz * mz, l0, l1, l2, m);
+    // points on a line (middle eigenvalue negligible) have no normal
+    ok = ok && l1 > 1e-6 * l2;
+    if (!ok)
+        return false;
+    V4<double> rw = ld4(S.row + 4 * v);
+    double ca, sa;
+    ld2(S.col + 2 * u, ca, sa);
+    const V3<double> d = ray_dir(rw, ca, sa);
+    const double sgn = m[0] * d.x + m[1] * d.y + m[2] * d.z > 0.0 ? -1.0 : 1.0;
+    n[0] = sgn * m[0];
+    n[1] = sgn * m[1];
+    n[2] = sgn * m[2];
+    return true;
+}
+
 // PCA normal of pixel (u, v) of one H x W range image: the covariance of the
 // window points (2 HALF + 1 square, u wrapping, rows clipped) that have a
 // return within edge_rel of the centre range, about their mean, in FP64;
@@ -79,8 +112,6 @@ template <int HALF>
 __device__ __forceinline__ bool pca_normal(const SensorTab<double> &S, const float *rg, int H, int W, int u, int v,
                                            double edge_rel, double n[3])
 {
-    constexpr int K = 2 * HALF + 1;
-    constexpr int kMinPts = (K * K + 1) / 2;
     const float rcf = rg[(int64_t)v * W + u];
     if (!range_ok(rcf))
         return false;
@@ -114,46 +145,93 @@ __device__ __forceinline__ bool pca_normal(const SensorTab<double> &S, const flo
             ++cnt;
         }
     }
-    if (cnt < kMinPts)
-        return false;
-    const double ic = 1.0 / (double)cnt;
-    const double mx = sx * ic, my = sy * ic, mz = sz * ic;
-    double l0, l1, l2, m[3];
-    bool ok = smallest_eigenpair(sxx * ic - mx * mx, sxy * ic - mx * my, sxz * ic - mx * mz, syy * ic - my * my,
-                                 syz * ic - my * mz, szz * ic - mz * mz, l0, l1, l2, m);
-    // points on a line (middle eigenvalue negligible) have no normal
-    ok = ok && l1 > 1e-6 * l2;
-    if (!ok)
-        return false;
-    V4<double> rw = ld4(S.row + 4 * v);
-    double ca, sa;
-    ld2(S.col + 2 * u, ca, sa);
-    const V3<double> d = ray_dir(rw, ca, sa);
-    const double sgn = m[0] * d.x + m[1] * d.y + m[2] * d.z > 0.0 ? -1.0 : 1.0;
-    n[0] = sgn * m[0];
-    n[1] = sgn * m[1];
-    n[2] = sgn * m[2];
-    return true;
+    return pca_from_sums<HALF>(S, u, v, cnt, sx, sy, sz, sxx, sxy, sxz, syy, syz, szz, n);
 }
 
+// Tile of the PCA-normal kernel: 32 columns x 8 rows of one image per
+// workgroup.  The tile's points and a HALF-pixel halo (u wrapping) are
+// unprojected once into shared memory, so each point is formed once instead
+// of once per window it falls in; the sums, the eigenpair and the tests are
+// those of pca_normal, on the same FP64 points, in the same order.
+constexpr int kPcaTileW = 32, kPcaTileH = 8;
+
 template <int HALF>
-__global__ __launch_bounds__(256) void k_normals_pca(SensorTab<double> S, const float *range, int64_t n_px,
-                                                     double edge_rel, float *nrm, uint8_t *valid)
+__global__ __launch_bounds__(256) void k_normals_pca(SensorTab<double> S, const float *range, double edge_rel,
+                                                     float *nrm, uint8_t *valid)
 {
+    constexpr int PW = kPcaTileW + 2 * HALF, PH = kPcaTileH + 2 * HALF;
+    __shared__ double s_x[PH * PW], s_y[PH * PW], s_z[PH * PW];
+    __shared__ float s_r[PH * PW];
     const int H = S.H, W = S.W;
     const int64_t HW = (int64_t)H * W;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_px;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t img = i / HW;
-        const int pix = (int)(i - img * HW);
-        const int v = pix / W, u = pix - v * W;
-        double n[3] = {0.0, 0.0, 0.0};
-        const bool ok = pca_normal<HALF>(S, range + img * HW, H, W, u, v, edge_rel, n);
-        nrm[3 * i] = ok ? (float)n[0] : 0.f;
-        nrm[3 * i + 1] = ok ? (float)n[1] : 0.f;
-        nrm[3 * i + 2] = ok ? (float)n[2] : 0.f;
-        valid[i] = ok ? 1 : 0;
+    const int64_t img = blockIdx.z;
+    const float *rg = range + img * HW;
+    const int u0 = blockIdx.x * kPcaTileW, v0 = blockIdx.y * kPcaTileH;
+    for (int k = threadIdx.x; k < PH * PW; k += blockDim.x) {
+        const int r = k / PW, c = k - r * PW;
+        const int vv = v0 - HALF + r;
+        const int uu = ((u0 - HALF + c) % W + W) % W;
+        float rf = 0.f;
+        double x = 0.0, y = 0.0, z = 0.0;
+        if (vv >= 0 && vv < H) {
+            rf = rg[(int64_t)vv * W + uu];
+            if (range_ok(rf)) {
+                const V3<double> p = unproject(S, uu, vv, (double)rf);
+                x = p.x;
+                y = p.y;
+                z = p.z;
+            }
+        }
+        s_r[k] = rf;
+        s_x[k] = x;
+        s_y[k] = y;
+        s_z[k] = z;
     }
+    __syncthreads();
+    const int tx = (int)threadIdx.x % kPcaTileW, ty = (int)threadIdx.x / kPcaTileW;
+    const int u = u0 + tx, v = v0 + ty;
+    if (u >= W || v >= H)
+        return;
+    const int64_t i = img * HW + (int64_t)v * W + u;
+    const int ci = (ty + HALF) * PW + tx + HALF;
+    const float rcf = s_r[ci];
+    double n[3] = {0.0, 0.0, 0.0};
+    bool ok = false;
+    if (range_ok(rcf)) {
+        const double rc = (double)rcf, lim = edge_rel * rc;
+        const double pcx = s_x[ci], pcy = s_y[ci], pcz = s_z[ci];
+        double sx = 0, sy = 0, sz = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
+        int cnt = 0;
+#pragma unroll
+        for (int dv = -HALF; dv <= HALF; ++dv) {
+            const int vv = v + dv;
+            if (vv < 0 || vv >= H)
+                continue;
+#pragma unroll
+            for (int du = -HALF; du <= HALF; ++du) {
+                const int k = ci + dv * PW + du;
+                const float rf = s_r[k];
+                if (!range_ok(rf) || fabs((double)rf - rc) > lim)
+                    continue;
+                const double qx = s_x[k] - pcx, qy = s_y[k] - pcy, qz = s_z[k] - pcz;
+                sx += qx;
+                sy += qy;
+                sz += qz;
+                sxx += qx * qx;
+                sxy += qx * qy;
+                sxz += qx * qz;
+                syy += qy * qy;
+                syz += qy * qz;
+                szz += qz * qz;
+                ++cnt;
+            }
+        }
+        ok = pca_from_sums<HALF>(S, u, v, cnt, sx, sy, sz, sxx, sxy, sxz, syy, syz, szz, n);
+    }
+    nrm[3 * i] = ok ? (float)n[0] : 0.f;
+    nrm[3 * i + 1] = ok ? (float)n[1] : 0.f;
+    nrm[3 * i + 2] = ok ? (float)n[2] : 0.f;
+    valid[i] = ok ? 1 : 0;
 }
 
 // Level-0 target records of the registration from PCA normals (the
@@ -220,23 +298,29 @@ hipError_t launch_pca_records(bool fp64, const PrepArgs &a, int half, int n_pair
 hipError_t launch_normals_pca(const SensorTab<double> &S, const float *range, int n_images, int half, double edge_rel,
                               float *nrm, uint8_t *valid, hipStream_t stream)
 {
-    const int64_t n = (int64_t)n_images * S.H * S.W;
-    int64_t g = (n + 255) / 256;
-    const int grid = (int)(g > 65536 ? 65536 : (g < 1 ? 1 : g));
-    switch (half) {
-    case 1:
-        hipLaunchKernelGGL(k_normals_pca<1>, dim3(grid), dim3(256), 0, stream, S, range, n, edge_rel, nrm, valid);
-        break;
-    case 2:
-        hipLaunchKernelGGL(k_normals_pca<2>, dim3(grid), dim3(256), 0, stream, S, range, n, edge_rel, nrm, valid);
-        break;
-    case 3:
-        hipLaunchKernelGGL(k_normals_pca<3>, dim3(grid), dim3(256), 0, stream, S, range, n, edge_rel, nrm, valid);
-        break;
-    default:
+    if (half < 1 || half > 3)
         return hipErrorInvalidValue;
+    const int64_t hw = (int64_t)S.H * S.W;
+    const dim3 block(kPcaTileW * kPcaTileH);
+    // images in launches of at most 65535 (the grid's third dimension)
+    for (int k0 = 0; k0 < n_images; k0 += 65535) {
+        const int nb = n_images - k0 < 65535 ? n_images - k0 : 65535;
+        const dim3 grid((unsigned)((S.W + kPcaTileW - 1) / kPcaTileW),
+                        (unsigned)((S.H + kPcaTileH - 1) / kPcaTileH), (unsigned)nb);
+        const float *r = range + hw * k0;
+        float *nm = nrm + 3 * hw * k0;
+        uint8_t *vd = valid + hw * k0;
+        if (half == 1)
+            hipLaunchKernelGGL(k_normals_pca<1>, grid, block, 0, stream, S, r, edge_rel, nm, vd);
+        else if (half == 2)
+            hipLaunchKernelGGL(k_normals_pca<2>, grid, block, 0, stream, S, r, edge_rel, nm, vd);
+        else
+            hipLaunchKernelGGL(k_normals_pca<3>, grid, block, 0, stream, S, r, edge_rel, nm, vd);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace rir
