@@ -698,6 +698,18 @@ __device__ __forceinline__ void step_segments(const StepArgs &a, const MlpInfer 
         for (int j = 0; j < CHUNK; ++j)
             D[j] = bld4<T>(drs, (__umul24((uint32_t)vl[j], (uint32_t)Wl) + (uint32_t)ul[j]) *
                                     (uint32_t)(4 * sizeof(T)));
+        // learned weights (FP32): the features' target-side loads go out with
+        // the record gather (same pixel), not after it
+        constexpr bool kRec = WMODE == 1 && sizeof(T) == 4;
+        const bool use_rec = kRec && nbf && a.mode != kStepFallback;
+        NbrRec NR[kRec ? CHUNK : 1];
+        if constexpr (kRec) {
+            if (use_rec) {
+#pragma unroll
+                for (int j = 0; j < CHUNK; ++j)
+                    NR[j] = load_nbr(LI, nbf, proj[j], ul[j], vl[j]);
+            }
+        }
 #pragma unroll
         for (int j = 0; j < CHUNK; ++j) {
             const T n0 = D[j].x, n1 = D[j].y, n2 = D[j].z;
@@ -724,10 +736,16 @@ __device__ __forceinline__ void step_segments(const StepArgs &a, const MlpInfer 
             const T wh = d_rsqrt((T)1 + tq * tq);
             T w = wh;
             const int i = in[j] ? vs[j] * Wl + us[j] : -1;
-            if constexpr (WMODE == 1) {
+            if constexpr (kRec) {
+                if (use_rec)
+                    w = (T)learned_weight_rec(a, F, NR[j], (float)e, (float)xr[j], (float)n0, (float)n1, (float)n2);
+                else if (a.mode != kStepFallback)
+                    w = learned_weight<T>(a, F, LI, valid, ul[j], vl[j], e, xr[j], n0, n1, n2,
+                                          dbg ? a.dbg_feat : nullptr, i);
+            } else if constexpr (WMODE == 1) {
                 if (a.mode != kStepFallback)
                     w = learned_weight<T>(a, F, LI, valid, ul[j], vl[j], e, xr[j], n0, n1, n2,
-                                          dbg ? a.dbg_feat : nullptr, i, nbf);
+                                          dbg ? a.dbg_feat : nullptr, i);
             }
             w = valid ? w : (T)0;
             c_valid += valid ? 1 : 0;

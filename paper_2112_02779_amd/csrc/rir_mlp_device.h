@@ -294,48 +294,82 @@ __device__ __forceinline__ uint4 neighbour_features(const float *img, int Hl, in
     return make_uint4(pack_bf2(f[0], f[1]), pack_bf2(f[2], f[3]), pack_bf2(f[4], f[5]), pack_bf2(f[6], f[7]));
 }
 
-// Learned weight sigmoid(z) of this lane's correspondence; all lanes of the
-// wave must call it (lanes without a correspondence pass valid = false).
-// dump (nullable) receives the features of pixel dump_index (>= 0).  With
-// nbf (the level's precomputed neighbour features, FP32 only) the features
-// are assembled from one 16-byte record instead of nine range gathers; the
-// packed words are the same bits.
+// Target-side inputs of one correspondence's features (FP32 path): the
+// target range at the associated pixel and its precomputed neighbour record
+// (PairDesc::nbf, 8 packed bf16 features).  Loaded as soon as the pixel is
+// known (right after the projection, beside the target record gather), so
+// that the features cost no extra dependent memory step; lanes with on =
+// false load nothing and get zeros.
+struct NbrRec {
+    float rc;
+    uint32_t d0, d1, d2, d3;
+};
+
+__device__ __forceinline__ NbrRec load_nbr(const LevelImage &L, const uint32_t *nbf, bool on, int ul, int vl)
+{
+    const uint32_t npx = (uint32_t)(L.Hl * L.Wl);
+    const uint32_t pix = (uint32_t)(vl * L.Wl + ul);
+    const rsrc_t img = make_rsrc(L.rng, npx * 4u);
+    const rsrc_t nb = make_rsrc(nbf, npx * 16u);
+    NbrRec r;
+    r.rc = bld1<float>(img, on ? 4u * pix : kNoLoad);
+    const uint32_t o = on ? 16u * pix : kNoLoad;
+    r.d0 = bld_u32(nb, o);
+    r.d1 = bld_u32(nb, o + 4u);
+    r.d2 = bld_u32(nb, o + 8u);
+    r.d3 = bld_u32(nb, o + 12u);
+    return r;
+}
+
+// This wavefront's 64 x 8-dword feature staging area (one per wave of a
+// 256-thread workgroup).
+__device__ __forceinline__ uint32_t *mlp_stage()
+{
+    __shared__ uint32_t s_stage[4][64 * 8];
+    return s_stage[threadIdx.x >> 6];
+}
+
+// Logistic of the network's logit.
+__device__ __forceinline__ float logistic(float z) { return d_rcp(1.f + __expf(-z)); }
+
+// Learned weight sigmoid(z) of this lane's correspondence from its loaded
+// target-side record (FP32): f0 | f1, f2 | f3, ..., f8 | f9 with f1..f8 from
+// the record, then n, e and the projective signed distance.  All lanes of the
+// wave must call it; the result of a lane without a correspondence is
+// unspecified (its weight is masked by the caller).
+__device__ __forceinline__ float learned_weight_rec(const StepArgs &a, const MlpInfer &F, const NbrRec &R, float e,
+                                                    float xr, float n0, float n1, float n2)
+{
+    const float inv_delta = (float)(1.0 / a.delta), inv_rmax = (float)(1.0 / (double)a.r_max);
+    uint32_t fp[8];
+    fp[0] = (pack_bf2(R.rc * inv_rmax, 0.f) & 0xffffu) | (R.d0 << 16);
+    fp[1] = __builtin_amdgcn_alignbit(R.d1, R.d0, 16);
+    fp[2] = __builtin_amdgcn_alignbit(R.d2, R.d1, 16);
+    fp[3] = __builtin_amdgcn_alignbit(R.d3, R.d2, 16);
+    fp[4] = (R.d3 >> 16) | (pack_bf2(n0, 0.f) << 16);
+    fp[5] = pack_bf2(n1, n2);
+    fp[6] = pack_bf2(clamp4(e * inv_delta), clamp4((R.rc - xr) * inv_delta));
+    fp[7] = 0u;
+    return logistic(mlp_wave(F, fp, mlp_stage()));
+}
+
+// Learned weight sigmoid(z) of this lane's correspondence, features gathered
+// here from the level's range image (FP64 path and debug dumps); all lanes of
+// the wave must call it (lanes without a correspondence pass valid = false).
+// dump (nullable) receives the features of pixel dump_index (>= 0).
 template <typename T>
 __device__ __forceinline__ T learned_weight(const StepArgs &a, const MlpInfer &F, const LevelImage &L,
                                             bool valid, int ul, int vl, T e, T xr, T n0, T n1, T n2, float *dump,
-                                            int dump_index, const uint32_t *nbf)
+                                            int dump_index)
 {
-    __shared__ uint32_t s_stage[4][64 * 8];
     uint32_t fp[8];
-    if (sizeof(T) == 4 && nbf) {
-        const uint32_t npx = (uint32_t)(L.Hl * L.Wl);
-        const uint32_t pix = (uint32_t)(vl * L.Wl + ul);
-        const rsrc_t img = make_rsrc(L.rng, npx * 4u);
-        const rsrc_t nb = make_rsrc(nbf, npx * 16u);
-        const T rc = (T)bld1<float>(img, valid ? 4u * pix : kNoLoad);
-        const uint32_t o = valid ? 16u * pix : kNoLoad;
-        const uint32_t d0 = bld_u32(nb, o), d1 = bld_u32(nb, o + 4u), d2 = bld_u32(nb, o + 8u),
-                       d3 = bld_u32(nb, o + 12u);
-        const T inv_delta = (T)(1.0 / a.delta), inv_rmax = (T)(1.0 / (double)a.r_max);
-        // f0 | f1, f2 | f3, ..., f8 | f9 (f1..f8 from the record), then n, e, sdf
-        fp[0] = (pack_bf2((float)(rc * inv_rmax), 0.f) & 0xffffu) | (d0 << 16);
-        fp[1] = __builtin_amdgcn_alignbit(d1, d0, 16);
-        fp[2] = __builtin_amdgcn_alignbit(d2, d1, 16);
-        fp[3] = __builtin_amdgcn_alignbit(d3, d2, 16);
-        fp[4] = (d3 >> 16) | (pack_bf2((float)n0, 0.f) << 16);
-        fp[5] = pack_bf2((float)n1, (float)n2);
-        fp[6] = pack_bf2(clamp4((float)(e * inv_delta)), clamp4((float)((rc - xr) * inv_delta)));
-        fp[7] = 0u;
-    } else {
-        float f[14];
-        compute_features<T>(a, L, valid, ul, vl, e, xr, n0, n1, n2, f);
-        if (dump && dump_index >= 0)
-            for (int k = 0; k < 14; ++k)
-                dump[14 * (size_t)dump_index + k] = valid ? f[k] : 0.f;
-        pack_features(f, fp);
-    }
-    const float z = mlp_wave(F, fp, s_stage[threadIdx.x >> 6]);
-    return (T)d_rcp(1.f + __expf(-z));
+    float f[14];
+    compute_features<T>(a, L, valid, ul, vl, e, xr, n0, n1, n2, f);
+    if (dump && dump_index >= 0)
+        for (int k = 0; k < 14; ++k)
+            dump[14 * (size_t)dump_index + k] = valid ? f[k] : 0.f;
+    pack_features(f, fp);
+    return (T)logistic(mlp_wave(F, fp, mlp_stage()));
 }
 
 }  // namespace rir
