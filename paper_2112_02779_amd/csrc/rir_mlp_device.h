@@ -190,30 +190,43 @@ __device__ __forceinline__ float mlp_wave(const MlpInfer &F, const uint32_t (&fp
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float zsel = 0.f;
+    // column tiles two at a time, layer by layer: two independent chains of
+    // matrix-core products, so that one tile's products run while the
+    // other's results are converted
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const uint2 bb = *reinterpret_cast<const uint2 *>(lds + (nt * 16 + r) * 8 + 2 * g);
-        const bf16x4_t B = bf4(bb.x, bb.y);
-        bf16x4_t h1[4];
+    for (int np = 0; np < 4; np += 2) {
+        bf16x4_t B[2];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            f32x4_t c = {F.b1[mt][0], F.b1[mt][1], F.b1[mt][2], F.b1[mt][3]};
-            c = mfma16(F.a1[mt], B, c);
-            h1[mt] = bf4(relu_bf2(pack_bf2(c[0], c[1])), relu_bf2(pack_bf2(c[2], c[3])));
+        for (int q = 0; q < 2; ++q) {
+            const uint2 bb = *reinterpret_cast<const uint2 *>(lds + ((np + q) * 16 + r) * 8 + 2 * g);
+            B[q] = bf4(bb.x, bb.y);
         }
-        const bf16x8v_t h1c[2] = {cat8(h1[0], h1[1]), cat8(h1[2], h1[3])};
-        bf16x4_t h2[4];
+        bf16x4_t h1[2][4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            f32x4_t c = {F.b2[mt][0], F.b2[mt][1], F.b2[mt][2], F.b2[mt][3]};
-            c = mfma32(F.a2[mt][0], h1c[0], c);
-            c = mfma32(F.a2[mt][1], h1c[1], c);
-            h2[mt] = bf4(relu_bf2(pack_bf2(c[0], c[1])), relu_bf2(pack_bf2(c[2], c[3])));
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                f32x4_t c = {F.b1[mt][0], F.b1[mt][1], F.b1[mt][2], F.b1[mt][3]};
+                c = mfma16(F.a1[mt], B[q], c);
+                h1[q][mt] = bf4(relu_bf2(pack_bf2(c[0], c[1])), relu_bf2(pack_bf2(c[2], c[3])));
+            }
+        bf16x4_t h2[2][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                f32x4_t c = {F.b2[mt][0], F.b2[mt][1], F.b2[mt][2], F.b2[mt][3]};
+                c = mfma32(F.a2[mt][0], cat8(h1[q][0], h1[q][1]), c);
+                c = mfma32(F.a2[mt][1], cat8(h1[q][2], h1[q][3]), c);
+                h2[q][mt] = bf4(relu_bf2(pack_bf2(c[0], c[1])), relu_bf2(pack_bf2(c[2], c[3])));
+            }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            f32x4_t z = {0.f, 0.f, 0.f, 0.f};
+            z = mfma32(F.a3[0], cat8(h2[q][0], h2[q][1]), z);
+            z = mfma32(F.a3[1], cat8(h2[q][2], h2[q][3]), z);
+            zsel = g == np + q ? z[0] + F.b3 : zsel;
         }
-        f32x4_t z = {0.f, 0.f, 0.f, 0.f};
-        z = mfma32(F.a3[0], cat8(h2[0], h2[1]), z);
-        z = mfma32(F.a3[1], cat8(h2[2], h2[3]), z);
-        zsel = g == nt ? z[0] + F.b3 : zsel;
     }
     __builtin_amdgcn_wave_barrier();
     return zsel;
