@@ -112,6 +112,9 @@ def lib():
         L.orc_sdf_extract.argtypes = [_D, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D,
                                       ctypes.c_double, ctypes.c_double, _D, ctypes.c_int64]
         L.orc_sdf_extract.restype = ctypes.c_int64
+        L.orc_sdf_activate.argtypes = [S, ctypes.c_int, _F, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       _I32, ctypes.c_int64]
+        L.orc_sdf_activate.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -226,6 +229,25 @@ def sdf_fuse(sensor, ranges: np.ndarray, poses: np.ndarray, pts: np.ndarray, tru
     lib().orc_sdf_fuse(ctypes.byref(h.s), int(r.shape[0]), _p(r, _F), _p(T, _D), n, _p(p, _D),
                        float(trunc), float(r_clip), _p(s, _D), _p(w, _D))
     return s, w
+
+
+def sdf_activate(sensor, ranges: np.ndarray, poses: np.ndarray, radius: float, r_clip: float, voxel: float):
+    """Sec. 4.2 block activation (orc_sdf_activate): the distinct 16^3-voxel
+    blocks (edge 16 voxel) that the returns of the scans ranges [F, H, W]
+    (poses [F, 4, 4], world -> sensor) activate within `radius`, sorted, as
+    int [n, 4] rows (bx, by, bz, first activating scan)."""
+    h = _SensorHolder(sensor)
+    r = np.ascontiguousarray(ranges, dtype=np.float32).reshape(-1, h.H, h.W)
+    T = np.ascontiguousarray(poses, dtype=np.float64).reshape(-1, 4, 4)
+    assert T.shape[0] == r.shape[0]
+    args = (ctypes.byref(h.s), int(r.shape[0]), _p(r, _F), _p(T, _D), float(radius), float(r_clip),
+            16.0 * float(voxel))
+    n = lib().orc_sdf_activate(*args, None, 0)
+    if n < 0:
+        raise MemoryError("oracle allocation failed")
+    out = np.zeros((max(n, 1), 4), np.int32)
+    lib().orc_sdf_activate(*args, _p(out, _I32), n)
+    return out[:n]
 
 
 def normals_pca(sensor, rng_img: np.ndarray, half: int = 1, edge_rel: float = 0.1):

@@ -1111,6 +1111,99 @@ void orc_sdf_fuse(const orc_sensor *s, int n_frames, const float *ranges, const 
     }
 }
 
+/* ------------------------------------------------------------------ Sec. 4.2 block activation */
+
+/* Voxel-block activation of Sec. 4.2 (sparse volume of 16^3-voxel blocks):
+ * every return of scan f (range r, finite and > 0, and r <= r_clip when
+ * r_clip > 0) is unprojected (Eq. (1)) and moved to the world frame,
+ * x = R^T (x_s - t) for the scan's world -> sensor pose (R, t); it activates
+ * every block whose cell [E b, E (b + 1)) (E = block_edge, per axis) meets
+ * the cube [x - radius, x + radius] (reading of "the blocks within a certain
+ * radius of the point": an axis-aligned cube, which is what a block grid
+ * tests cheaply), i.e. b from floor((x - radius) / E) to floor((x + radius) / E)
+ * on each axis.  A block's activation frame is the first scan that activates
+ * it (the paper activates with each scan's points before fusing that scan, so
+ * a block takes the scans from that one on).
+ * Output: the distinct blocks sorted by (bx, by, bz), as 4 int32 each (bx,
+ * by, bz, activation frame), at most max_out of them; returns how many there
+ * are (-1 if memory runs out). */
+typedef struct {
+    int32_t b[3];
+    int32_t f;
+} orc_act;
+
+static int act_cmp(const void *pa, const void *pb)
+{
+    const orc_act *a = (const orc_act *)pa, *b = (const orc_act *)pb;
+    for (int i = 0; i < 3; ++i)
+        if (a->b[i] != b->b[i])
+            return a->b[i] < b->b[i] ? -1 : 1;
+    return (a->f > b->f) - (a->f < b->f);
+}
+
+int64_t orc_sdf_activate(const orc_sensor *s, int n_frames, const float *ranges, const double *poses,
+                         double radius, double r_clip, double block_edge, int32_t *out, int64_t max_out)
+{
+    size_t hw = (size_t)s->H * s->W, n = 0, cap = 1024;
+    orc_act *all = (orc_act *)malloc(cap * sizeof(orc_act));
+    if (!all)
+        return -1;
+    for (int f = 0; f < n_frames; ++f) {
+        const double *T = poses + 16 * (size_t)f;
+        for (int v = 0; v < s->H; ++v)
+            for (int u = 0; u < s->W; ++u) {
+                double r = ranges[(size_t)f * hw + (size_t)v * s->W + u];
+                if (!range_ok(r) || (r_clip > 0.0 && r > r_clip))
+                    continue;
+                double xs[3], x[3], d[3];
+                orc_unproject(s, u, v, r, xs);
+                for (int i = 0; i < 3; ++i)
+                    d[i] = xs[i] - T[4 * i + 3];
+                for (int j = 0; j < 3; ++j)  /* x = R^T d */
+                    x[j] = T[j] * d[0] + T[4 + j] * d[1] + T[8 + j] * d[2];
+                int64_t lo[3], hi[3];
+                for (int i = 0; i < 3; ++i) {
+                    lo[i] = (int64_t)floor((x[i] - radius) / block_edge);
+                    hi[i] = (int64_t)floor((x[i] + radius) / block_edge);
+                }
+                for (int64_t bz = lo[2]; bz <= hi[2]; ++bz)
+                    for (int64_t by = lo[1]; by <= hi[1]; ++by)
+                        for (int64_t bx = lo[0]; bx <= hi[0]; ++bx) {
+                            if (n == cap) {
+                                orc_act *g = (orc_act *)realloc(all, 2 * cap * sizeof(orc_act));
+                                if (!g) {
+                                    free(all);
+                                    return -1;
+                                }
+                                all = g;
+                                cap *= 2;
+                            }
+                            all[n].b[0] = (int32_t)bx;
+                            all[n].b[1] = (int32_t)by;
+                            all[n].b[2] = (int32_t)bz;
+                            all[n].f = f;
+                            ++n;
+                        }
+            }
+    }
+    qsort(all, n, sizeof(orc_act), act_cmp);
+    int64_t m = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (i > 0 && all[i].b[0] == all[i - 1].b[0] && all[i].b[1] == all[i - 1].b[1] &&
+            all[i].b[2] == all[i - 1].b[2])
+            continue;  /* sorted by frame within a block: the first is the earliest */
+        if (m < max_out) {
+            out[4 * m] = all[i].b[0];
+            out[4 * m + 1] = all[i].b[1];
+            out[4 * m + 2] = all[i].b[2];
+            out[4 * m + 3] = all[i].f;
+        }
+        ++m;
+    }
+    free(all);
+    return m;
+}
+
 /* ------------------------------------------------------------------ PCA normals */
 
 /* Eigenvalues (ascending) and unit eigenvectors (columns of V) of a symmetric

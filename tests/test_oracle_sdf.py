@@ -239,3 +239,88 @@ def test_extract_sphere_weights_and_jumps(orc):
     assert np.max(np.abs(d3)) <= vx * vx / R
     p4 = oracle.sdf_extract(origin, vx, s3, w)
     assert len(p4) > len(p3)
+
+
+# ----------------------------------------------------------------------------- block activation
+
+def _activation_scans(seed, F=3, H=8, W=32):
+    sm = synth.staggered_sensor(H, W, r0=0.02)
+    rng = np.random.default_rng(seed)
+    ranges = rng.uniform(0.5, 12.0, size=(F, H, W)).astype(np.float32)
+    ranges[rng.random(ranges.shape) < 0.1] = 0.0            # no return
+    ranges[0, 0, :4] = np.nan
+    rots = [synth.rot_axis_angle(synth.unit_vector(rng), rng.uniform(0.0, 1.0)) for _ in range(F)]
+    centres = rng.uniform(-3.0, 3.0, size=(F, 3))
+    poses = np.stack([_world_to_sensor(R, c) for R, c in zip(rots, centres)])
+    return sm, ranges, poses
+
+
+def _brute_activation(orc, sm, ranges, poses, radius, r_clip, voxel):
+    """Every block whose cell [E b, E (b + 1)) overlaps [x - radius, x + radius]
+    on all three axes, by explicit interval tests over a candidate range, and
+    the first scan that does so."""
+    E = 16.0 * voxel
+    first = {}
+    for f in range(ranges.shape[0]):
+        xyz, valid = orc.unproject_image(sm, ranges[f])
+        ok = valid & np.isfinite(ranges[f])
+        if r_clip > 0:
+            ok &= ranges[f] <= r_clip
+        xs = xyz[ok]
+        R, t = poses[f][:3, :3], poses[f][:3, 3]
+        xw = (xs - t) @ R                                    # R^T (x_s - t) row-wise
+        for x in xw:
+            cand = [range(int(np.floor(c / E)) - 2, int(np.floor(c / E)) + 3) for c in x]
+            for bx in cand[0]:
+                if not (E * bx <= x[0] + radius and x[0] - radius < E * (bx + 1)):
+                    continue
+                for by in cand[1]:
+                    if not (E * by <= x[1] + radius and x[1] - radius < E * (by + 1)):
+                        continue
+                    for bz in cand[2]:
+                        if E * bz <= x[2] + radius and x[2] - radius < E * (bz + 1):
+                            first.setdefault((bx, by, bz), f)
+    return np.array(sorted((k[0], k[1], k[2], v) for k, v in first.items()), np.int64).reshape(-1, 4)
+
+
+def test_activation_matches_interval_overlap_brute_force(orc):
+    """Sec. 4.2 activation: the blocks whose cells meet the cube around each
+    return (explicit overlap tests, not the floor formula), with the first
+    activating scan, on a staggered sensor with a receiver offset, NaN and
+    missing returns, rotated poses; radius above and below a block edge."""
+    sm, ranges, poses = _activation_scans(5)
+    for radius, r_clip, voxel in [(0.3, 0.0, 0.1), (0.3, 8.0, 0.05), (2.5, 0.0, 0.1)]:
+        got = orc.sdf_activate(sm, ranges, poses, radius, r_clip, voxel)
+        ref = _brute_activation(orc, sm, ranges, poses, radius, r_clip, voxel)
+        assert len(ref) > 10
+        np.testing.assert_array_equal(got, ref)
+
+
+def test_activation_radius_zero_and_frames(orc):
+    """Radius 0 activates exactly the block holding each return; a scan seen
+    again activates nothing new (every block keeps its first scan); blocks
+    only the second scan reaches get that scan's index; the set grows with the
+    radius."""
+    sm, ranges, poses = _activation_scans(6, F=1)
+    E = 1.6
+    xyz, valid = orc.unproject_image(sm, ranges[0])
+    ok = valid & np.isfinite(ranges[0])
+    R, t = poses[0][:3, :3], poses[0][:3, 3]
+    own = np.unique(np.floor(((xyz[ok] - t) @ R) / E).astype(np.int64), axis=0)
+    a0 = orc.sdf_activate(sm, ranges, poses, 0.0, 0.0, 0.1)
+    np.testing.assert_array_equal(a0[:, :3], own)
+    assert np.all(a0[:, 3] == 0)
+    twice = orc.sdf_activate(sm, np.concatenate([ranges, ranges]), np.concatenate([poses, poses]), 0.3, 0.0, 0.1)
+    once = orc.sdf_activate(sm, ranges, poses, 0.3, 0.0, 0.1)
+    np.testing.assert_array_equal(twice, once)
+    moved = poses.copy()
+    moved[0][:3, 3] += np.array([10.0, 0.0, 0.0])            # the same scan 10 m away
+    both = orc.sdf_activate(sm, np.concatenate([ranges, ranges]), np.concatenate([poses, moved]), 0.3, 0.0, 0.1)
+    second = orc.sdf_activate(sm, ranges, moved, 0.3, 0.0, 0.1)
+    first_keys = {tuple(k) for k in once[:, :3]}
+    for row in both:
+        k = tuple(row[:3])
+        assert row[3] == (0 if k in first_keys else 1)
+    assert {tuple(k) for k in both[:, :3]} == first_keys | {tuple(k) for k in second[:, :3]}
+    big = orc.sdf_activate(sm, ranges, poses, 1.0, 0.0, 0.1)
+    assert {tuple(k) for k in once[:, :3]} < {tuple(k) for k in big[:, :3]}
