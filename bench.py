@@ -494,8 +494,6 @@ def reconstruction_quality(rir, vol, vox, seq, r_clip, radius, n_sample=200000):
     ground-truth points (noise-free returns within the clip range of every
     scan, sampled) within the radius of an extracted point."""
     import torch
-    from scipy.spatial import cKDTree
-    import synth
     import ctypes
     stream = torch.cuda.current_stream()
     pts, n = rir.sdf_extract(vol, vox, min_weight=1.0, max_jump=0.45, stream=stream)
@@ -513,7 +511,15 @@ def reconstruction_quality(rir, vol, vox, seq, r_clip, radius, n_sample=200000):
         assert st == 0 and int(cnt.item()) == n
         ts.append(e0.elapsed_time(e1))
     ms = float(np.median(ts))
-    P = pts.cpu().numpy().astype(np.float64)
+    out = surface_scores(pts.cpu().numpy().astype(np.float64), seq, r_clip, radius, n_sample)
+    return {"extract_ms": round(ms, 4), "surface_points": n, **out}
+
+
+def surface_scores(P, seq, r_clip, radius, n_sample=200000):
+    """Precision, recall and F-score of surface points P [n, 3] against the
+    synthetic scene (the paper's protocol, see reconstruction_quality)."""
+    from scipy.spatial import cKDTree
+    import synth
     rng = np.random.default_rng(3)
     sub = P[rng.choice(len(P), min(n_sample, len(P)), replace=False)] if len(P) else P
     prec = float(np.mean(_scene_distance(seq["scene"], sub) <= radius)) if len(sub) else 0.0
@@ -534,8 +540,7 @@ def reconstruction_quality(rir, vol, vox, seq, r_clip, radius, n_sample=200000):
     gt = np.concatenate(gt)
     rec = float(np.mean(cKDTree(P).query(gt, distance_upper_bound=radius)[0] <= radius)) if len(P) else 0.0
     f = 2 * prec * rec / (prec + rec) if prec + rec > 0 else 0.0
-    return {"extract_ms": round(ms, 4), "surface_points": n, "precision": round(prec, 4), "recall": round(rec, 4),
-            "f_score": round(f, 4), "radius_m": radius,
+    return {"precision": round(prec, 4), "recall": round(rec, 4), "f_score": round(f, 4), "radius_m": radius,
             "protocol": "zero crossings (min weight 1, max step 0.45 m) vs exact scene surfaces; recall over "
                         f"{len(gt)} sampled noise-free returns within the clip range"}
 
@@ -636,7 +641,46 @@ def sdf_fusion(rir, seq, oracle_sample, repeats=5):
                              "scans_per_s_whole_volume": round(len(pick) / dt / nvox, 6)}
     log(f"sdf fusion: {F} scans in {ms:.3f} ms ({res['scans_per_s']:.0f} scans/s), "
         f"{res['evals_per_s'] / 1e9:.1f} G evals/s, {res['hbm_gbps']} GB/s algorithmic")
+    res["sparse"] = sparse_sdf(rir, seq, sen, ranges, poses, trunc, r_clip, repeats)
     return res
+
+
+def sparse_sdf(rir, seq, sen, ranges, poses, trunc, r_clip, repeats):
+    """The same sequence into the sparse volume (Sec. 4.2: blocks activated
+    within the truncation distance of each return, hash table, only active
+    blocks fused), at 0.1 m and at the paper's 0.2 m outdoor voxels: one
+    rir_bvol_integrate call over the whole sequence (activation, the count
+    read-back, fusion), timed with HIP events around the call after a reset;
+    surface points and F-score as for the dense volume."""
+    import torch
+    stream = torch.cuda.current_stream()
+    F = ranges.shape[0]
+    out = {}
+    for vx in (0.1, 0.2):
+        vol = rir.BlockVolume(vx, 200000)
+        times = []
+        for k in range(repeats + 1):
+            vol.reset(stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            vol.integrate(sen, ranges, poses, trunc, r_clip, trunc, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if k > 0:
+                times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        nb, _ = vol.size()
+        pts, n = vol.extract(min_weight=1.0, max_jump=0.45, stream=stream)
+        sc = surface_scores(pts.cpu().numpy().astype(np.float64), seq, r_clip, 3 * vx)
+        out[f"voxel_{vx}"] = {"ms_per_sequence": round(ms, 4), "scans_per_s": round(F / (ms * 1e-3), 1),
+                              "active_blocks": int(nb), "block_memory_gb": round(nb * 32768 / 1e9, 3),
+                              "surface_points": n, **sc}
+        log(f"sparse sdf {vx} m: {F} scans in {ms:.3f} ms ({F / (ms * 1e-3):.0f} scans/s), {nb} blocks, "
+            f"F-score {sc['f_score']}")
+        del vol
+    out["workload"] = (f"{F} scans, blocks activated within {trunc} m (the truncation) of every return within "
+                       f"{r_clip} m, truncation {trunc} m; one call per sequence")
+    return out
 
 
 def normals_pca_timing(rir, seq, repeats=5):

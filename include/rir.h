@@ -385,6 +385,62 @@ rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volume_desc *vo
 rir_status rir_sdf_extract(const rir_volume_desc *vol, const float *voxels, double min_weight, double max_jump,
                            float *points, int64_t max_points, uint64_t *count, void *stream);
 
+/* ---------------------------------------------------------------- sparse SDF volume */
+
+/* Sparse SDF volume of Sec. 4.2: the 16^3-voxel blocks near the returns of
+ * each scan are activated in a hash table keyed by block coordinates, and
+ * only activated blocks are fused.  Voxel (i, j, k) (any integers) sits at
+ * voxel * (i, j, k) in world coordinates (metres); block (bx, by, bz) holds
+ * voxels 16 bx .. 16 bx + 15 along i, and so on, |bx|, |by|, |bz| < 2^20.
+ * The volume owns its device memory on `device`: a pool of max_blocks
+ * blocks (32 KiB each: (sdf, weight) FP32 per voxel in the rir_sdf_integrate
+ * block layout, voxels in (z, y, x) order, x fastest) and an open-addressing
+ * table of at least 2 max_blocks entries.  Calls on one volume run in the
+ * order they are made and must not overlap.  Errors: RIR_E_INVALID (null,
+ * voxel not finite or <= 0, max_blocks outside 1..2^26), RIR_E_OOM, RIR_E_HIP.
+ * *out is owned by the caller and released with rir_bvol_destroy. */
+typedef struct rir_bvol rir_bvol;
+rir_status rir_bvol_create(int device, double voxel, int32_t max_blocks, rir_bvol **out);
+void rir_bvol_destroy(rir_bvol *vol);
+/* Empties the volume (no blocks, no scans); enqueued on `stream`. */
+rir_status rir_bvol_reset(rir_bvol *vol, void *stream);
+
+/* Fuses n_frames scans (Sec. 4.2).  For each scan, in order: every return
+ * (range finite and > 0, and <= r_clip when r_clip > 0) is unprojected
+ * (Eq. (1)) and moved to the world frame, x = R^T (x_s - t); every block
+ * whose cell [E b, E (b + 1)) (E = 16 voxel, per axis) meets the cube
+ * [x - radius, x + radius] is activated (decided in FP64); then the scan is
+ * fused into every active block (the blocks this scan or an earlier one
+ * activated) with the arithmetic, trunc and r_clip of rir_sdf_integrate
+ * (Eq. (8)-(10); with both limits set, a block the scan cannot reach is
+ * skipped).  ranges: device, n_frames * H * W FP32 scans of `sensor`; poses:
+ * host, n_frames * 16 FP64 world -> sensor, read before the call returns.
+ * Enqueued on `stream`; the call waits for the activation (to size the
+ * fusion launches).  Errors: RIR_E_INVALID (null, n_frames < 0, radius
+ * outside 0 .. 64 voxels, non-finite trunc, r_clip or pose, sensor on another
+ * device),
+ * RIR_E_SHAPE (16 scans of H x W at or above 2 GiB), RIR_E_OOM (more active
+ * blocks than max_blocks, or a return beyond the block coordinate range: the
+ * volume is then incomplete and must be reset), RIR_E_HIP. */
+rir_status rir_bvol_integrate(rir_bvol *vol, const rir_sensor *sensor, int32_t n_frames, const float *ranges,
+                              const double *poses, double trunc, double r_clip, double radius, void *stream);
+
+/* Active blocks and scans fused so far (host values, no device work). */
+rir_status rir_bvol_size(const rir_bvol *vol, int64_t *n_blocks, int64_t *n_frames);
+
+/* Copies the active blocks out in pool order (not defined across runs):
+ * blocks (device, n_blocks * 4 int32: bx, by, bz and the index, over the
+ * volume's history, of the first scan that activated the block) and voxels
+ * (device, n_blocks * 8192 FP32, block layout above); either may be NULL.
+ * Enqueued on `stream`. */
+rir_status rir_bvol_export(const rir_bvol *vol, int32_t *blocks, float *voxels, void *stream);
+
+/* Zero crossings of the sparse volume, as rir_sdf_extract (edges between
+ * voxels of active blocks; world coordinates).  Errors: RIR_E_INVALID (null,
+ * max_points < 0, non-finite min_weight, max_jump < 0 or NaN), RIR_E_HIP. */
+rir_status rir_bvol_extract(rir_bvol *vol, double min_weight, double max_jump, float *points, int64_t max_points,
+                            uint64_t *count, void *stream);
+
 /* ---------------------------------------------------------------- learned weight */
 
 /* Per-pixel robust-weight network 14-64-64-1 (ReLU, ReLU, sigmoid) replacing

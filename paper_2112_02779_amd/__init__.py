@@ -31,7 +31,8 @@ EXPORTS = [
     "rir_normals", "rir_icp_batch", "rir_debug_associate", "rir_autotune", "rir_mlp_create", "rir_mlp_destroy",
     "rir_mlp_get_params", "rir_mlp_set_params", "rir_mlp_forward", "rir_mlp_train_step", "rir_last_error",
     "rir_elevation_table", "rir_sdf_integrate", "rir_normals_pca", "rir_deskew",
-    "rir_sdf_extract", "rir_mlp_train_step_noalloc",
+    "rir_sdf_extract", "rir_mlp_train_step_noalloc", "rir_bvol_create", "rir_bvol_destroy", "rir_bvol_reset",
+    "rir_bvol_integrate", "rir_bvol_size", "rir_bvol_export", "rir_bvol_extract",
 ]
 
 
@@ -132,6 +133,13 @@ def lib():
         "rir_deskew": [vp, i32, vp, ctypes.POINTER(f64), vp, vp],
         "rir_normals_pca": [vp, i32, vp, i32, f64, vp, vp, vp],
         "rir_sdf_integrate": [vp, ctypes.POINTER(VolumeDesc), vp, i32, vp, ctypes.POINTER(f64), f64, f64, vp],
+        "rir_bvol_create": [ctypes.c_int, f64, i32, pvp],
+        "rir_bvol_destroy": [vp],
+        "rir_bvol_reset": [vp, vp],
+        "rir_bvol_integrate": [vp, vp, i32, vp, ctypes.POINTER(f64), f64, f64, f64, vp],
+        "rir_bvol_size": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "rir_bvol_export": [vp, vp, vp, vp],
+        "rir_bvol_extract": [vp, f64, f64, vp, i64, vp, vp],
         "rir_last_error": [],
         "rir_elevation_table": [ctypes.POINTER(SensorDesc), i32, i32, vp, i64, ctypes.POINTER(i64),
                                 ctypes.POINTER(f64), ctypes.POINTER(f64)],
@@ -143,6 +151,7 @@ def lib():
     L.rir_sensor_destroy.restype = None
     L.rir_ctx_destroy.restype = None
     L.rir_mlp_destroy.restype = None
+    L.rir_bvol_destroy.restype = None
     L.rir_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
@@ -395,6 +404,78 @@ def sdf_extract(vol: Volume, voxels, min_weight=1.0, max_jump=float("inf"), max_
     pts = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=voxels.device)
     n = run(pts, cap)
     return pts[:min(n, cap)], n
+
+
+class BlockVolume:
+    """Sparse SDF volume of 16^3-voxel blocks activated around the returns of
+    each scan (hash table keyed by block coordinates); voxel (i, j, k) sits at
+    voxel * (i, j, k) (world, metres)."""
+
+    EDGE = 16
+
+    def __init__(self, voxel: float, max_blocks: int, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().rir_bvol_create(int(device), float(voxel), int(max_blocks), ctypes.byref(h)))
+        self.handle = h
+        self.voxel = float(voxel)
+        self.max_blocks = int(max_blocks)
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rir_bvol_destroy(self.handle)
+            self.handle = None
+
+    def reset(self, stream=None):
+        _check(lib().rir_bvol_reset(self.handle, _stream(stream)))
+
+    def integrate(self, sensor: Sensor, ranges, poses, trunc: float, r_clip: float, radius: float, stream=None):
+        """Activates and fuses scans ranges [F, H, W] (device FP32) taken at
+        poses [F, 4, 4] (host FP64, world -> sensor)."""
+        import torch
+        P = np.ascontiguousarray(poses, dtype=np.float64).reshape(-1, 16)
+        F = P.shape[0]
+        if F > 0:
+            _require(ranges, torch.float32, "ranges", F * sensor.H * sensor.W)
+        _check(lib().rir_bvol_integrate(self.handle, sensor.handle, F, _ptr(ranges) if F > 0 else None,
+                                        P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(trunc),
+                                        float(r_clip), float(radius), _stream(stream)))
+
+    def size(self):
+        """(active blocks, scans fused)."""
+        nb, nf = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().rir_bvol_size(self.handle, ctypes.byref(nb), ctypes.byref(nf)))
+        return nb.value, nf.value
+
+    def export(self, stream=None):
+        """(blocks int32 [n, 4]: bx, by, bz, first activating scan; voxels
+        FP32 [n, 16 (z), 16 (y), 16 (x), 2]) as device tensors, pool order."""
+        import torch
+        n = self.size()[0]
+        dev = torch.device("cuda", self.device)
+        blocks = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
+        vox = torch.empty((max(n, 1), 16, 16, 16, 2), dtype=torch.float32, device=dev)
+        _check(lib().rir_bvol_export(self.handle, _ptr(blocks), _ptr(vox), _stream(stream)))
+        return blocks[:n], vox[:n]
+
+    def extract(self, min_weight=1.0, max_jump=float("inf"), max_points=None, stream=None):
+        """Zero-crossing surface points: (points [n, 3] FP32 device tensor,
+        total crossings), as sdf_extract."""
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        dev = torch.device("cuda", self.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def run(pts, cap):
+            _check(lib().rir_bvol_extract(self.handle, float(min_weight), float(max_jump), _ptr(pts), cap,
+                                          _ptr(cnt), _stream(s)))
+            s.synchronize()
+            return int(cnt.item())
+
+        cap = run(None, 0) if max_points is None else int(max_points)
+        pts = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+        n = run(pts, cap)
+        return pts[:min(n, cap)], n
 
 
 def deskew(sensor: Sensor, rng, twists, stream=None):

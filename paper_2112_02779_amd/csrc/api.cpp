@@ -19,6 +19,7 @@
 #include "rir_internal.h"
 #include "rir_ops.h"
 #include "sdf_extract.h"
+#include "sdf_hash.h"
 
 using namespace rir;
 
@@ -1556,6 +1557,42 @@ extern "C" rir_status rir_deskew(const rir_sensor *sensor, int32_t n_images, con
 
 // ============================================================================ projective SDF fusion
 
+// Fusion arguments shared by the dense and the sparse volume: the sensor's
+// FP32 tables, the truncation band, the range clip and the cull distance.
+static void sdf_common_args(const rir_sensor *sensor, double trunc, double r_clip, SdfArgs &a)
+{
+    a.tab = sensor->d_tf;
+    a.xcd_remap = 1;
+    a.trunc = trunc > 0.0 ? (float)trunc : std::numeric_limits<float>::infinity();
+    if (r_clip > 0.0) {
+        // the largest float not above r_clip: the FP32 test om <= clip then
+        // decides exactly as om <= r_clip in real arithmetic
+        float c = (float)r_clip;
+        if ((double)c > r_clip)
+            c = std::nextafter(c, 0.0f);
+        a.clip = c;
+    } else {
+        a.clip = std::numeric_limits<float>::infinity();
+    }
+    // A voxel is updated only if Omega <= r_clip and Omega - r >= -trunc, so its
+    // distance to the sensor origin is at most r_clip + trunc + r0; the margin
+    // covers the FP32 rounding of r.
+    a.cull = (trunc > 0.0 && r_clip > 0.0) ? r_clip + trunc + sensor->r0 + 1e-3 + 1e-4 * (r_clip + trunc) : -1.0;
+}
+
+// World -> sensor poses of k scans (row-major 4x4) as fusion frames.
+static void sdf_frames(const double *poses, int k, SdfFrame *f)
+{
+    for (int j = 0; j < k; ++j) {
+        const double *T = poses + 16 * (size_t)j;
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c)
+                f[j].R[3 * r + c] = T[4 * r + c];
+            f[j].t[r] = T[4 * r + 3];
+        }
+    }
+}
+
 extern "C" rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volume_desc *vol, float *voxels,
                                         int32_t n_frames, const float *ranges, const double *poses, double trunc,
                                         double r_clip, void *stream)
@@ -1589,27 +1626,11 @@ extern "C" rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volu
     HIP_TRY(hipSetDevice(sensor->device));
 
     SdfArgs a{};
-    a.tab = sensor->d_tf;
+    sdf_common_args(sensor, trunc, r_clip, a);
     a.vox = voxels;
     a.nbx = vol->nbx;
     a.nby = vol->nby;
     a.nbz = vol->nbz;
-    a.xcd_remap = 1;
-    a.trunc = trunc > 0.0 ? (float)trunc : std::numeric_limits<float>::infinity();
-    if (r_clip > 0.0) {
-        // the largest float not above r_clip: the FP32 test om <= clip then
-        // decides exactly as om <= r_clip in real arithmetic
-        float c = (float)r_clip;
-        if ((double)c > r_clip)
-            c = std::nextafter(c, 0.0f);
-        a.clip = c;
-    } else {
-        a.clip = std::numeric_limits<float>::infinity();
-    }
-    // A voxel is updated only if Omega <= r_clip and Omega - r >= -trunc, so its
-    // distance to the sensor origin is at most r_clip + trunc + r0; the margin
-    // covers the FP32 rounding of r.
-    a.cull = (trunc > 0.0 && r_clip > 0.0) ? r_clip + trunc + sensor->r0 + 1e-3 + 1e-4 * (r_clip + trunc) : -1.0;
     for (int i = 0; i < 3; ++i)
         a.origin[i] = vol->origin[i];
     a.voxel = vol->voxel;
@@ -1620,18 +1641,12 @@ extern "C" rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volu
         const int k = std::min<int32_t>(kSdfFrames, n_frames - f0);
         a.n_frames = k;
         a.ranges = ranges + (size_t)f0 * (size_t)(img_bytes / (int64_t)sizeof(float));
-        for (int j = 0; j < k; ++j) {
-            const double *T = poses + 16 * (size_t)(f0 + j);
-            for (int r = 0; r < 3; ++r) {
-                for (int c = 0; c < 3; ++c)
-                    a.f[j].R[3 * r + c] = T[4 * r + c];
-                a.f[j].t[r] = T[4 * r + 3];
-            }
-        }
-        HIP_TRY(launch_sdf_fuse(a, r0, pow2, st));
+        sdf_frames(poses + 16 * (size_t)f0, k, a.f);
+        HIP_TRY(launch_sdf_fuse(a, r0, pow2, false, st));
     }
     return RIR_OK;
 }
+
 
 extern "C" rir_status rir_sdf_extract(const rir_volume_desc *vol, const float *voxels, double min_weight,
                                       double max_jump, float *points, int64_t max_points, uint64_t *count,
@@ -1667,7 +1682,230 @@ extern "C" rir_status rir_sdf_extract(const rir_volume_desc *vol, const float *v
     a.pts = points;
     a.max_pts = max_points;
     a.count = reinterpret_cast<unsigned long long *>(count);
-    HIP_TRY(launch_sdf_extract(a, static_cast<hipStream_t>(stream)));
+    HIP_TRY(launch_sdf_extract(a, false, static_cast<hipStream_t>(stream)));
+    return RIR_OK;
+}
+
+// ============================================================================ sparse SDF volume
+
+struct rir_bvol {
+    int device = 0;
+    double voxel = 0.0;
+    int max_blocks = 0;
+    uint32_t cap = 0;       // hash table entries (power of two, >= 2 max_blocks)
+    void *dmem = nullptr;
+    BvolDev t{};
+    int *d_nbr = nullptr;   // [max_blocks][3]
+    float *d_vox = nullptr; // [max_blocks][4096][2]
+    int64_t n_blocks = 0;   // host copies
+    int64_t n_frames = 0;
+    ~rir_bvol()
+    {
+        if (dmem) {
+            hipSetDevice(device);
+            hipFree(dmem);
+        }
+    }
+};
+
+constexpr size_t kBvolBlockBytes = (size_t)kSdfEdge * kSdfEdge * kSdfEdge * 2 * sizeof(float);
+
+// Clears the table, the counters and the voxels of the first `used` slots.
+static rir_status bvol_clear(rir_bvol *v, int64_t used, hipStream_t st)
+{
+    HIP_TRY(hipMemsetAsync(v->t.keys, 0xff, (size_t)v->cap * sizeof(unsigned long long), st));
+    HIP_TRY(hipMemsetAsync(v->t.vals, 0xff, (size_t)v->cap * sizeof(int), st));
+    HIP_TRY(hipMemsetAsync(v->t.act, 0x7f, (size_t)v->cap * sizeof(int), st));  // 0x7f7f7f7f: never
+    HIP_TRY(hipMemsetAsync(v->t.count, 0, 2 * sizeof(int), st));
+    if (used > 0)
+        HIP_TRY(hipMemsetAsync(v->d_vox, 0, (size_t)used * kBvolBlockBytes, st));
+    v->n_blocks = 0;
+    v->n_frames = 0;
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_bvol_create(int device, double voxel, int32_t max_blocks, rir_bvol **out)
+{
+    if (!out)
+        return fail(RIR_E_INVALID, "rir_bvol_create: null argument");
+    *out = nullptr;
+    if (!(voxel > 0.0) || !std::isfinite(voxel))
+        return fail(RIR_E_INVALID, "rir_bvol_create: voxel size must be finite and > 0");
+    if (max_blocks < 1 || max_blocks > (1 << 26))
+        return fail(RIR_E_INVALID, "rir_bvol_create: max_blocks must be in 1..2^26");
+    HIP_TRY(hipSetDevice(device));
+    std::unique_ptr<rir_bvol> v(new rir_bvol());
+    v->device = device;
+    v->voxel = voxel;
+    v->max_blocks = max_blocks;
+    v->cap = 1;
+    while (v->cap < 2u * (uint32_t)max_blocks)
+        v->cap <<= 1;
+    Layout lay;
+    const size_t o_keys = lay.add((size_t)v->cap * sizeof(unsigned long long));
+    const size_t o_vals = lay.add((size_t)v->cap * sizeof(int));
+    const size_t o_act = lay.add((size_t)v->cap * sizeof(int));
+    const size_t o_blocks = lay.add((size_t)max_blocks * sizeof(int4));
+    const size_t o_nbr = lay.add((size_t)max_blocks * 3 * sizeof(int));
+    const size_t o_ctr = lay.add(2 * sizeof(int));
+    const size_t o_vox = lay.add((size_t)max_blocks * kBvolBlockBytes);
+    HIP_TRY(hipMalloc(&v->dmem, lay.bytes));
+    char *base = static_cast<char *>(v->dmem);
+    v->t.keys = reinterpret_cast<unsigned long long *>(base + o_keys);
+    v->t.vals = reinterpret_cast<int *>(base + o_vals);
+    v->t.act = reinterpret_cast<int *>(base + o_act);
+    v->t.blocks = reinterpret_cast<int4 *>(base + o_blocks);
+    v->t.count = reinterpret_cast<int *>(base + o_ctr);
+    v->t.flags = v->t.count + 1;
+    v->t.mask = v->cap - 1;
+    v->t.max_blocks = max_blocks;
+    v->d_nbr = reinterpret_cast<int *>(base + o_nbr);
+    v->d_vox = reinterpret_cast<float *>(base + o_vox);
+    rir_status s = bvol_clear(v.get(), max_blocks, nullptr);
+    if (s != RIR_OK)
+        return s;
+    HIP_TRY(hipDeviceSynchronize());
+    *out = v.release();
+    return RIR_OK;
+}
+
+extern "C" void rir_bvol_destroy(rir_bvol *vol) { delete vol; }
+
+extern "C" rir_status rir_bvol_reset(rir_bvol *vol, void *stream)
+{
+    if (!vol)
+        return fail(RIR_E_INVALID, "rir_bvol_reset: null argument");
+    HIP_TRY(hipSetDevice(vol->device));
+    return bvol_clear(vol, vol->n_blocks, static_cast<hipStream_t>(stream));
+}
+
+extern "C" rir_status rir_bvol_integrate(rir_bvol *vol, const rir_sensor *sensor, int32_t n_frames,
+                                         const float *ranges, const double *poses, double trunc, double r_clip,
+                                         double radius, void *stream)
+{
+    if (!vol || !sensor)
+        return fail(RIR_E_INVALID, "rir_bvol_integrate: null argument");
+    if (n_frames < 0)
+        return fail(RIR_E_INVALID, "rir_bvol_integrate: n_frames < 0");
+    if (n_frames > 0 && (!ranges || !poses))
+        return fail(RIR_E_INVALID, "rir_bvol_integrate: null argument");
+    if (!std::isfinite(trunc) || !std::isfinite(r_clip))
+        return fail(RIR_E_INVALID, "rir_bvol_integrate: trunc and r_clip must be finite");
+    if (!(radius >= 0.0) || !(radius <= 64.0 * vol->voxel))
+        return fail(RIR_E_INVALID, "rir_bvol_integrate: radius must be in 0 .. 64 voxels");
+    if (sensor->device != vol->device)
+        return fail(RIR_E_INVALID, "rir_bvol_integrate: sensor and volume on different devices");
+    for (int64_t i = 0; i < 16 * (int64_t)n_frames; ++i)
+        if (!std::isfinite(poses[i]))
+            return fail(RIR_E_INVALID, "rir_bvol_integrate: non-finite pose");
+    const int64_t hw = (int64_t)sensor->H * sensor->W;
+    if (hw * (int64_t)sizeof(float) * kSdfFrames >= ((int64_t)1 << 31))
+        return fail(RIR_E_SHAPE, "rir_bvol_integrate: range images too large for one launch");
+    if (vol->n_frames + n_frames > (int64_t)std::numeric_limits<int32_t>::max() / 2)
+        return fail(RIR_E_SHAPE, "rir_bvol_integrate: too many scans in the volume's history");
+    if (n_frames == 0)
+        return RIR_OK;
+    HIP_TRY(hipSetDevice(vol->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // activation of every scan of the call, each entry keeping its first scan
+    BvolActArgs b{};
+    b.tab = sensor->d_td;
+    b.H = sensor->H;
+    b.W = sensor->W;
+    b.radius = radius;
+    b.clip = r_clip;
+    b.edge = (double)kSdfEdge * vol->voxel;
+    b.t = vol->t;
+    for (int32_t f0 = 0; f0 < n_frames; f0 += kSdfFrames) {
+        const int k = std::min<int32_t>(kSdfFrames, n_frames - f0);
+        b.n_frames = k;
+        b.frame0 = (int)(vol->n_frames + f0);
+        b.ranges = ranges + (size_t)f0 * (size_t)hw;
+        sdf_frames(poses + 16 * (size_t)f0, k, b.f);
+        HIP_TRY(launch_bvol_activate(b, st));
+    }
+    int ctr[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(ctr, vol->t.count, sizeof(ctr), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    vol->n_blocks = std::min<int64_t>(ctr[0], vol->max_blocks);
+    if (ctr[1] & kBvolFull)
+        return fail(RIR_E_OOM, "rir_bvol_integrate: more active blocks than max_blocks (reset the volume)");
+    if (ctr[1] & kBvolRange)
+        return fail(RIR_E_OOM, "rir_bvol_integrate: a return beyond the block coordinate range (reset the volume)");
+    // fusion of every active block; scan j of a launch skips the blocks
+    // activated after it
+    SdfArgs a{};
+    sdf_common_args(sensor, trunc, r_clip, a);
+    a.vox = vol->d_vox;
+    a.voxel = vol->voxel;
+    a.blocks = vol->t.blocks;
+    a.act = vol->t.act;
+    a.n_blocks = (int)vol->n_blocks;
+    const bool r0 = sensor->r0 > 0.0;
+    const bool pow2 = (sensor->W & (sensor->W - 1)) == 0;
+    for (int32_t f0 = 0; f0 < n_frames; f0 += kSdfFrames) {
+        const int k = std::min<int32_t>(kSdfFrames, n_frames - f0);
+        a.n_frames = k;
+        a.frame0 = (int)(vol->n_frames + f0);
+        a.ranges = ranges + (size_t)f0 * (size_t)hw;
+        sdf_frames(poses + 16 * (size_t)f0, k, a.f);
+        HIP_TRY(launch_sdf_fuse(a, r0, pow2, true, st));
+    }
+    vol->n_frames += n_frames;
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_bvol_size(const rir_bvol *vol, int64_t *n_blocks, int64_t *n_frames)
+{
+    if (!vol)
+        return fail(RIR_E_INVALID, "rir_bvol_size: null argument");
+    if (n_blocks)
+        *n_blocks = vol->n_blocks;
+    if (n_frames)
+        *n_frames = vol->n_frames;
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_bvol_export(const rir_bvol *vol, int32_t *blocks, float *voxels, void *stream)
+{
+    if (!vol)
+        return fail(RIR_E_INVALID, "rir_bvol_export: null argument");
+    HIP_TRY(hipSetDevice(vol->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (blocks)
+        HIP_TRY(launch_bvol_export(vol->t, (int)vol->n_blocks, reinterpret_cast<int4 *>(blocks), st));
+    if (voxels && vol->n_blocks > 0)
+        HIP_TRY(hipMemcpyAsync(voxels, vol->d_vox, (size_t)vol->n_blocks * kBvolBlockBytes, hipMemcpyDeviceToDevice,
+                               st));
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_bvol_extract(rir_bvol *vol, double min_weight, double max_jump, float *points,
+                                       int64_t max_points, uint64_t *count, void *stream)
+{
+    if (!vol || !count || (max_points > 0 && !points))
+        return fail(RIR_E_INVALID, "rir_bvol_extract: null argument");
+    if (max_points < 0)
+        return fail(RIR_E_INVALID, "rir_bvol_extract: max_points < 0");
+    if (!std::isfinite(min_weight) || std::isnan(max_jump) || !(max_jump >= 0.0))
+        return fail(RIR_E_INVALID, "rir_bvol_extract: min_weight must be finite and max_jump >= 0");
+    HIP_TRY(hipSetDevice(vol->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_bvol_neighbors(vol->t, (int)vol->n_blocks, vol->d_nbr, st));
+    SdfExtractArgs a{};
+    a.vox = vol->d_vox;
+    a.min_weight = (float)min_weight;
+    if ((double)a.min_weight < min_weight)
+        a.min_weight = std::nextafter(a.min_weight, std::numeric_limits<float>::infinity());
+    a.max_jump = max_jump;
+    a.voxel = vol->voxel;
+    a.pts = points;
+    a.max_pts = max_points;
+    a.count = reinterpret_cast<unsigned long long *>(count);
+    a.blocks = vol->t.blocks;
+    a.nbr = vol->d_nbr;
+    a.n_blocks = (int)vol->n_blocks;
+    HIP_TRY(launch_sdf_extract(a, true, st));
     return RIR_OK;
 }
 

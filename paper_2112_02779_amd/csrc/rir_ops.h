@@ -32,10 +32,18 @@ struct SdfArgs {
     double origin[3];      // world position of voxel (0, 0, 0)
     double voxel;          // voxel edge (m)
     SdfFrame f[kSdfFrames];
+    // sparse volume (hashed launches): block b of the launch is pool slot b,
+    // at block coordinates blocks[b].xyz, activated first by scan
+    // act[blocks[b].w]; scan j of the launch (index frame0 + j in the
+    // volume's history) updates only blocks activated by it or earlier
+    const int4 *blocks;
+    const int *act;
+    int n_blocks;
+    int frame0;
 };
 
-// One fusion launch over every block of the grid.
-hipError_t launch_sdf_fuse(const SdfArgs &a, bool r0, bool pow2, hipStream_t stream);
+// One fusion launch over every block of the grid (hashed: of the pool).
+hipError_t launch_sdf_fuse(const SdfArgs &a, bool r0, bool pow2, bool hashed, hipStream_t stream);
 
 // PCA normals of n_images contiguous H x W range images; half = 1, 2 or 3
 // (window 3x3, 5x5, 7x7), hipErrorInvalidValue otherwise.

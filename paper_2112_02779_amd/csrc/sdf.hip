@@ -28,13 +28,13 @@ constexpr int kSdfXcdRun = 8;
 
 }  // namespace
 
-template <bool R0, bool POW2>
+template <bool R0, bool POW2, bool HASHED>
 __global__ __launch_bounds__(256) void k_sdf_fuse(const SdfArgs a)
 {
     __shared__ __align__(16) float s_fr[kSdfFrames][kFrameWords];
     __shared__ uint32_t s_mask;
 
-    const int nblk = a.nbx * a.nby * a.nbz;
+    const int nblk = HASHED ? a.n_blocks : a.nbx * a.nby * a.nbz;
     int b = blockIdx.x;
     // XCD-aware order: workgroups go to the 8 XCDs round robin by id; give
     // each XCD runs of kSdfXcdRun consecutive blocks (neighbouring blocks read
@@ -49,13 +49,24 @@ __global__ __launch_bounds__(256) void k_sdf_fuse(const SdfArgs a)
         if (b >= nblk)
             return;
     }
-    const int bx = b % a.nbx, byz = b / a.nbx;
-    const int by = byz % a.nby, bz = byz / a.nby;
+    int bx, by, bz, first = 0;
+    if constexpr (HASHED) {
+        const int *B = reinterpret_cast<const int *>(a.blocks + b);
+        bx = cload(B);
+        by = cload(B + 1);
+        bz = cload(B + 2);
+        first = cload(a.act + cload(B + 3)) - a.frame0;  // the launch's first scan that may update it
+    } else {
+        bx = b % a.nbx;
+        const int byz = b / a.nbx;
+        by = byz % a.nby;
+        bz = byz / a.nby;
+    }
     const int tid = threadIdx.x;
 
     if (tid < 64) {
         bool act = false;
-        if (tid < a.n_frames) {
+        if (tid < a.n_frames && (!HASHED || tid >= first)) {
             const SdfFrame &F = a.f[tid];
             const double s = a.voxel;
             const double o[3] = {a.origin[0] + (double)(kSdfEdge * bx) * s, a.origin[1] + (double)(kSdfEdge * by) * s,
@@ -151,16 +162,27 @@ __global__ __launch_bounds__(256) void k_sdf_fuse(const SdfArgs a)
     }
 }
 
-hipError_t launch_sdf_fuse(const SdfArgs &a, bool r0, bool pow2, hipStream_t stream)
+template <bool HASHED>
+static void launch_sdf_fuse_h(const SdfArgs &a, bool r0, bool pow2, int nblk, hipStream_t stream)
 {
-    const int n = a.nbx * a.nby * a.nbz, run = 8 * kSdfXcdRun;
-    const int nblk = a.xcd_remap ? (n + run - 1) / run * run : n;
     if (r0)
-        hipLaunchKernelGGL((k_sdf_fuse<true, false>), dim3(nblk), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((k_sdf_fuse<true, false, HASHED>), dim3(nblk), dim3(256), 0, stream, a);
     else if (pow2)
-        hipLaunchKernelGGL((k_sdf_fuse<false, true>), dim3(nblk), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((k_sdf_fuse<false, true, HASHED>), dim3(nblk), dim3(256), 0, stream, a);
     else
-        hipLaunchKernelGGL((k_sdf_fuse<false, false>), dim3(nblk), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((k_sdf_fuse<false, false, HASHED>), dim3(nblk), dim3(256), 0, stream, a);
+}
+
+hipError_t launch_sdf_fuse(const SdfArgs &a, bool r0, bool pow2, bool hashed, hipStream_t stream)
+{
+    const int n = hashed ? a.n_blocks : a.nbx * a.nby * a.nbz, run = 8 * kSdfXcdRun;
+    if (n <= 0)
+        return hipSuccess;
+    const int nblk = a.xcd_remap ? (n + run - 1) / run * run : n;
+    if (hashed)
+        launch_sdf_fuse_h<true>(a, r0, pow2, nblk, stream);
+    else
+        launch_sdf_fuse_h<false>(a, r0, pow2, nblk, stream);
     return hipGetLastError();
 }
 

@@ -15,9 +15,14 @@ struct SdfExtractArgs {
     float *pts;                  // [max_pts][3]
     long long max_pts;
     unsigned long long *count;   // crossings found (may exceed max_pts)
+    // sparse volume: block b is pool slot b at blocks[b].xyz; nbr[3 b + a]
+    // the slot of its +x / +y / +z neighbour (a = 0, 1, 2; -1: none)
+    const int4 *blocks;
+    const int *nbr;
+    int n_blocks;
 };
 
 // Zero crossings of a fused volume (count zeroed first, then one launch).
-hipError_t launch_sdf_extract(const SdfExtractArgs &a, hipStream_t stream);
+hipError_t launch_sdf_extract(const SdfExtractArgs &a, bool hashed, hipStream_t stream);
 
 }  // namespace rir

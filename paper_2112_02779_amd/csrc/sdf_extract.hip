@@ -31,14 +31,25 @@ __device__ __forceinline__ bool crossing(const SdfExtractArgs &a, float2 A, floa
     return B.y >= a.min_weight && (A.x > 0.f) != (B.x > 0.f) && !(fabs((double)A.x - (double)B.x) > a.max_jump);
 }
 
+template <bool HASHED>
 __global__ __launch_bounds__(256) void k_sdf_extract(const SdfExtractArgs a)
 {
     __shared__ float2 s_v[kE1][kE1][kE1];  // [z][y][x]
     __shared__ int s_scan[256];
     __shared__ unsigned long long s_base;
     const int b = blockIdx.x;
-    const int bx = b % a.nbx, byz = b / a.nbx;
-    const int by = byz % a.nby, bz = byz / a.nby;
+    int bx, by, bz;
+    if constexpr (HASHED) {
+        const int4 B = a.blocks[b];
+        bx = B.x;
+        by = B.y;
+        bz = B.z;
+    } else {
+        bx = b % a.nbx;
+        const int byz = b / a.nbx;
+        by = byz % a.nby;
+        bz = byz / a.nby;
+    }
     const int tid = threadIdx.x;
     const float2 *vox = reinterpret_cast<const float2 *>(a.vox);
     const float2 none = make_float2(0.f, -INFINITY);
@@ -57,12 +68,24 @@ __global__ __launch_bounds__(256) void k_sdf_extract(const SdfExtractArgs a)
         const int u = tid & 15, w = tid >> 4;
         const int i0 = bx * kSdfEdge, j0 = by * kSdfEdge, k0 = bz * kSdfEdge;
         float2 fx = none, fy = none, fz = none;
-        if (bx + 1 < a.nbx)
-            fx = vox[vox_index(a.nbx, a.nby, i0 + kSdfEdge, j0 + u, k0 + w)];
-        if (by + 1 < a.nby)
-            fy = vox[vox_index(a.nbx, a.nby, i0 + u, j0 + kSdfEdge, k0 + w)];
-        if (bz + 1 < a.nbz)
-            fz = vox[vox_index(a.nbx, a.nby, i0 + u, j0 + w, k0 + kSdfEdge)];
+        if constexpr (HASHED) {
+            // the neighbour's first plane: (0, u, w), (u, 0, w), (u, w, 0)
+            constexpr size_t kB = kSdfEdge * kSdfEdge * kSdfEdge;
+            const int nx = a.nbr[3 * b], ny = a.nbr[3 * b + 1], nz = a.nbr[3 * b + 2];
+            if (nx >= 0)
+                fx = vox[(size_t)nx * kB + (size_t)((w * kSdfEdge + u) * kSdfEdge)];
+            if (ny >= 0)
+                fy = vox[(size_t)ny * kB + (size_t)(w * kSdfEdge * kSdfEdge + u)];
+            if (nz >= 0)
+                fz = vox[(size_t)nz * kB + (size_t)(w * kSdfEdge + u)];
+        } else {
+            if (bx + 1 < a.nbx)
+                fx = vox[vox_index(a.nbx, a.nby, i0 + kSdfEdge, j0 + u, k0 + w)];
+            if (by + 1 < a.nby)
+                fy = vox[vox_index(a.nbx, a.nby, i0 + u, j0 + kSdfEdge, k0 + w)];
+            if (bz + 1 < a.nbz)
+                fz = vox[vox_index(a.nbx, a.nby, i0 + u, j0 + w, k0 + kSdfEdge)];
+        }
         s_v[w][u][kSdfEdge] = fx;
         s_v[w][kSdfEdge][u] = fy;
         s_v[kSdfEdge][w][u] = fz;
@@ -117,13 +140,18 @@ __global__ __launch_bounds__(256) void k_sdf_extract(const SdfExtractArgs a)
     }
 }
 
-hipError_t launch_sdf_extract(const SdfExtractArgs &a, hipStream_t stream)
+hipError_t launch_sdf_extract(const SdfExtractArgs &a, bool hashed, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, a.count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_sdf_extract, dim3(a.nbx * a.nby * a.nbz), dim3(256), 0, stream, a);
+    if (hashed) {
+        if (a.n_blocks > 0)
+            hipLaunchKernelGGL(k_sdf_extract<true>, dim3(a.n_blocks), dim3(256), 0, stream, a);
+    } else {
+        hipLaunchKernelGGL(k_sdf_extract<false>, dim3(a.nbx * a.nby * a.nbz), dim3(256), 0, stream, a);
+    }
     return hipGetLastError();
 }
 
