@@ -112,8 +112,8 @@ def lib():
         L.orc_sdf_extract.argtypes = [_D, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D,
                                       ctypes.c_double, ctypes.c_double, _D, ctypes.c_int64]
         L.orc_sdf_extract.restype = ctypes.c_int64
-        L.orc_sdf_activate.argtypes = [S, ctypes.c_int, _F, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                       _I32, ctypes.c_int64]
+        L.orc_sdf_activate.argtypes = [S, ctypes.c_int, _F, _D, _D, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, _I32, ctypes.c_int64]
         L.orc_sdf_activate.restype = ctypes.c_int64
         _lib = L
     return _lib
@@ -231,16 +231,19 @@ def sdf_fuse(sensor, ranges: np.ndarray, poses: np.ndarray, pts: np.ndarray, tru
     return s, w
 
 
-def sdf_activate(sensor, ranges: np.ndarray, poses: np.ndarray, radius: float, r_clip: float, voxel: float):
+def sdf_activate(sensor, ranges: np.ndarray, poses: np.ndarray, radius: float, r_clip: float, voxel: float,
+                 origin=(0.0, 0.0, 0.0)):
     """Sec. 4.2 block activation (orc_sdf_activate): the distinct 16^3-voxel
-    blocks (edge 16 voxel) that the returns of the scans ranges [F, H, W]
-    (poses [F, 4, 4], world -> sensor) activate within `radius`, sorted, as
-    int [n, 4] rows (bx, by, bz, first activating scan)."""
+    blocks (edge 16 voxel, voxel (0, 0, 0) at `origin`) that the returns of
+    the scans ranges [F, H, W] (poses [F, 4, 4], world -> sensor) activate
+    within `radius`, sorted, as int [n, 4] rows (bx, by, bz, first activating
+    scan)."""
     h = _SensorHolder(sensor)
     r = np.ascontiguousarray(ranges, dtype=np.float32).reshape(-1, h.H, h.W)
     T = np.ascontiguousarray(poses, dtype=np.float64).reshape(-1, 4, 4)
     assert T.shape[0] == r.shape[0]
-    args = (ctypes.byref(h.s), int(r.shape[0]), _p(r, _F), _p(T, _D), float(radius), float(r_clip),
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    args = (ctypes.byref(h.s), int(r.shape[0]), _p(r, _F), _p(T, _D), _p(o, _D), float(radius), float(r_clip),
             16.0 * float(voxel))
     n = lib().orc_sdf_activate(*args, None, 0)
     if n < 0:

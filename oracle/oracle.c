@@ -1117,11 +1117,12 @@ void orc_sdf_fuse(const orc_sensor *s, int n_frames, const float *ranges, const 
  * every return of scan f (range r, finite and > 0, and r <= r_clip when
  * r_clip > 0) is unprojected (Eq. (1)) and moved to the world frame,
  * x = R^T (x_s - t) for the scan's world -> sensor pose (R, t); it activates
- * every block whose cell [E b, E (b + 1)) (E = block_edge, per axis) meets
- * the cube [x - radius, x + radius] (reading of "the blocks within a certain
- * radius of the point": an axis-aligned cube, which is what a block grid
- * tests cheaply), i.e. b from floor((x - radius) / E) to floor((x + radius) / E)
- * on each axis.  A block's activation frame is the first scan that activates
+ * every block whose cell o + [E b, E (b + 1)) (E = block_edge, per axis;
+ * o the volume origin, where voxel (0, 0, 0) sits) meets the cube
+ * [x - radius, x + radius] (reading of "the blocks within a certain radius of
+ * the point": an axis-aligned cube, which is what a block grid tests
+ * cheaply), i.e. b from floor((x - o - radius) / E) to
+ * floor((x - o + radius) / E) on each axis.  A block's activation frame is the first scan that activates
  * it (the paper activates with each scan's points before fusing that scan, so
  * a block takes the scans from that one on).
  * Output: the distinct blocks sorted by (bx, by, bz), as 4 int32 each (bx,
@@ -1142,7 +1143,8 @@ static int act_cmp(const void *pa, const void *pb)
 }
 
 int64_t orc_sdf_activate(const orc_sensor *s, int n_frames, const float *ranges, const double *poses,
-                         double radius, double r_clip, double block_edge, int32_t *out, int64_t max_out)
+                         const double origin[3], double radius, double r_clip, double block_edge, int32_t *out,
+                         int64_t max_out)
 {
     size_t hw = (size_t)s->H * s->W, n = 0, cap = 1024;
     orc_act *all = (orc_act *)malloc(cap * sizeof(orc_act));
@@ -1163,8 +1165,9 @@ int64_t orc_sdf_activate(const orc_sensor *s, int n_frames, const float *ranges,
                     x[j] = T[j] * d[0] + T[4 + j] * d[1] + T[8 + j] * d[2];
                 int64_t lo[3], hi[3];
                 for (int i = 0; i < 3; ++i) {
-                    lo[i] = (int64_t)floor((x[i] - radius) / block_edge);
-                    hi[i] = (int64_t)floor((x[i] + radius) / block_edge);
+                    const double c = x[i] - origin[i];
+                    lo[i] = (int64_t)floor((c - radius) / block_edge);
+                    hi[i] = (int64_t)floor((c + radius) / block_edge);
                 }
                 for (int64_t bz = lo[2]; bz <= hi[2]; ++bz)
                     for (int64_t by = lo[1]; by <= hi[1]; ++by)

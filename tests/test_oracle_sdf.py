@@ -255,10 +255,10 @@ def _activation_scans(seed, F=3, H=8, W=32):
     return sm, ranges, poses
 
 
-def _brute_activation(orc, sm, ranges, poses, radius, r_clip, voxel):
-    """Every block whose cell [E b, E (b + 1)) overlaps [x - radius, x + radius]
-    on all three axes, by explicit interval tests over a candidate range, and
-    the first scan that does so."""
+def _brute_activation(orc, sm, ranges, poses, radius, r_clip, voxel, origin=(0.0, 0.0, 0.0)):
+    """Every block whose cell o + [E b, E (b + 1)) overlaps [x - radius,
+    x + radius] on all three axes, by explicit interval tests over a candidate
+    range, and the first scan that does so."""
     E = 16.0 * voxel
     first = {}
     for f in range(ranges.shape[0]):
@@ -268,7 +268,7 @@ def _brute_activation(orc, sm, ranges, poses, radius, r_clip, voxel):
             ok &= ranges[f] <= r_clip
         xs = xyz[ok]
         R, t = poses[f][:3, :3], poses[f][:3, 3]
-        xw = (xs - t) @ R                                    # R^T (x_s - t) row-wise
+        xw = (xs - t) @ R - np.asarray(origin)               # R^T (x_s - t) - o row-wise
         for x in xw:
             cand = [range(int(np.floor(c / E)) - 2, int(np.floor(c / E)) + 3) for c in x]
             for bx in cand[0]:
@@ -289,9 +289,10 @@ def test_activation_matches_interval_overlap_brute_force(orc):
     activating scan, on a staggered sensor with a receiver offset, NaN and
     missing returns, rotated poses; radius above and below a block edge."""
     sm, ranges, poses = _activation_scans(5)
-    for radius, r_clip, voxel in [(0.3, 0.0, 0.1), (0.3, 8.0, 0.05), (2.5, 0.0, 0.1)]:
-        got = orc.sdf_activate(sm, ranges, poses, radius, r_clip, voxel)
-        ref = _brute_activation(orc, sm, ranges, poses, radius, r_clip, voxel)
+    for radius, r_clip, voxel, o in [(0.3, 0.0, 0.1, (0.0, 0.0, 0.0)), (0.3, 8.0, 0.05, (0.03, -1.2, 0.05)),
+                                     (2.5, 0.0, 0.1, (0.0, 0.0, 0.0))]:
+        got = orc.sdf_activate(sm, ranges, poses, radius, r_clip, voxel, o)
+        ref = _brute_activation(orc, sm, ranges, poses, radius, r_clip, voxel, o)
         assert len(ref) > 10
         np.testing.assert_array_equal(got, ref)
 
