@@ -390,17 +390,19 @@ rir_status rir_sdf_extract(const rir_volume_desc *vol, const float *voxels, doub
 /* Sparse SDF volume of Sec. 4.2: the 16^3-voxel blocks near the returns of
  * each scan are activated in a hash table keyed by block coordinates, and
  * only activated blocks are fused.  Voxel (i, j, k) (any integers) sits at
- * voxel * (i, j, k) in world coordinates (metres); block (bx, by, bz) holds
+ * origin + voxel * (i, j, k) in world coordinates (metres; origin host,
+ * 3 FP64, read before the call returns); block (bx, by, bz) holds
  * voxels 16 bx .. 16 bx + 15 along i, and so on, |bx|, |by|, |bz| < 2^20.
  * The volume owns its device memory on `device`: a pool of max_blocks
  * blocks (32 KiB each: (sdf, weight) FP32 per voxel in the rir_sdf_integrate
  * block layout, voxels in (z, y, x) order, x fastest) and an open-addressing
  * table of at least 2 max_blocks entries.  Calls on one volume run in the
  * order they are made and must not overlap.  Errors: RIR_E_INVALID (null,
- * voxel not finite or <= 0, max_blocks outside 1..2^26), RIR_E_OOM, RIR_E_HIP.
+ * non-finite origin, voxel not finite or <= 0, max_blocks outside 1..2^26),
+ * RIR_E_OOM, RIR_E_HIP.
  * *out is owned by the caller and released with rir_bvol_destroy. */
 typedef struct rir_bvol rir_bvol;
-rir_status rir_bvol_create(int device, double voxel, int32_t max_blocks, rir_bvol **out);
+rir_status rir_bvol_create(int device, const double origin[3], double voxel, int32_t max_blocks, rir_bvol **out);
 void rir_bvol_destroy(rir_bvol *vol);
 /* Empties the volume (no blocks, no scans); enqueued on `stream`. */
 rir_status rir_bvol_reset(rir_bvol *vol, void *stream);
@@ -408,7 +410,7 @@ rir_status rir_bvol_reset(rir_bvol *vol, void *stream);
 /* Fuses n_frames scans (Sec. 4.2).  For each scan, in order: every return
  * (range finite and > 0, and <= r_clip when r_clip > 0) is unprojected
  * (Eq. (1)) and moved to the world frame, x = R^T (x_s - t); every block
- * whose cell [E b, E (b + 1)) (E = 16 voxel, per axis) meets the cube
+ * whose cell origin + [E b, E (b + 1)) (E = 16 voxel, per axis) meets the cube
  * [x - radius, x + radius] is activated (decided in FP64); then the scan is
  * fused into every active block (the blocks this scan or an earlier one
  * activated) with the arithmetic, trunc and r_clip of rir_sdf_integrate

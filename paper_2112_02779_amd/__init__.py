@@ -133,7 +133,7 @@ def lib():
         "rir_deskew": [vp, i32, vp, ctypes.POINTER(f64), vp, vp],
         "rir_normals_pca": [vp, i32, vp, i32, f64, vp, vp, vp],
         "rir_sdf_integrate": [vp, ctypes.POINTER(VolumeDesc), vp, i32, vp, ctypes.POINTER(f64), f64, f64, vp],
-        "rir_bvol_create": [ctypes.c_int, f64, i32, pvp],
+        "rir_bvol_create": [ctypes.c_int, ctypes.POINTER(f64), f64, i32, pvp],
         "rir_bvol_destroy": [vp],
         "rir_bvol_reset": [vp, vp],
         "rir_bvol_integrate": [vp, vp, i32, vp, ctypes.POINTER(f64), f64, f64, f64, vp],
@@ -409,14 +409,16 @@ def sdf_extract(vol: Volume, voxels, min_weight=1.0, max_jump=float("inf"), max_
 class BlockVolume:
     """Sparse SDF volume of 16^3-voxel blocks activated around the returns of
     each scan (hash table keyed by block coordinates); voxel (i, j, k) sits at
-    voxel * (i, j, k) (world, metres)."""
+    origin + voxel * (i, j, k) (world, metres)."""
 
     EDGE = 16
 
-    def __init__(self, voxel: float, max_blocks: int, device: int = 0):
+    def __init__(self, voxel: float, max_blocks: int, origin=(0.0, 0.0, 0.0), device: int = 0):
         h = ctypes.c_void_p()
-        _check(lib().rir_bvol_create(int(device), float(voxel), int(max_blocks), ctypes.byref(h)))
+        o = (ctypes.c_double * 3)(*(float(x) for x in origin))
+        _check(lib().rir_bvol_create(int(device), o, float(voxel), int(max_blocks), ctypes.byref(h)))
         self.handle = h
+        self.origin = tuple(float(x) for x in origin)
         self.voxel = float(voxel)
         self.max_blocks = int(max_blocks)
         self.device = device

@@ -1690,6 +1690,7 @@ extern "C" rir_status rir_sdf_extract(const rir_volume_desc *vol, const float *v
 
 struct rir_bvol {
     int device = 0;
+    double origin[3] = {0.0, 0.0, 0.0};
     double voxel = 0.0;
     int max_blocks = 0;
     uint32_t cap = 0;       // hash table entries (power of two, >= 2 max_blocks)
@@ -1724,18 +1725,24 @@ static rir_status bvol_clear(rir_bvol *v, int64_t used, hipStream_t st)
     return RIR_OK;
 }
 
-extern "C" rir_status rir_bvol_create(int device, double voxel, int32_t max_blocks, rir_bvol **out)
+extern "C" rir_status rir_bvol_create(int device, const double origin[3], double voxel, int32_t max_blocks,
+                                      rir_bvol **out)
 {
-    if (!out)
+    if (!out || !origin)
         return fail(RIR_E_INVALID, "rir_bvol_create: null argument");
     *out = nullptr;
     if (!(voxel > 0.0) || !std::isfinite(voxel))
         return fail(RIR_E_INVALID, "rir_bvol_create: voxel size must be finite and > 0");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(origin[i]))
+            return fail(RIR_E_INVALID, "rir_bvol_create: origin must be finite");
     if (max_blocks < 1 || max_blocks > (1 << 26))
         return fail(RIR_E_INVALID, "rir_bvol_create: max_blocks must be in 1..2^26");
     HIP_TRY(hipSetDevice(device));
     std::unique_ptr<rir_bvol> v(new rir_bvol());
     v->device = device;
+    for (int i = 0; i < 3; ++i)
+        v->origin[i] = origin[i];
     v->voxel = voxel;
     v->max_blocks = max_blocks;
     v->cap = 1;
@@ -1812,6 +1819,8 @@ extern "C" rir_status rir_bvol_integrate(rir_bvol *vol, const rir_sensor *sensor
     b.tab = sensor->d_td;
     b.H = sensor->H;
     b.W = sensor->W;
+    for (int i = 0; i < 3; ++i)
+        b.origin[i] = vol->origin[i];
     b.radius = radius;
     b.clip = r_clip;
     b.edge = (double)kSdfEdge * vol->voxel;
@@ -1837,6 +1846,8 @@ extern "C" rir_status rir_bvol_integrate(rir_bvol *vol, const rir_sensor *sensor
     SdfArgs a{};
     sdf_common_args(sensor, trunc, r_clip, a);
     a.vox = vol->d_vox;
+    for (int i = 0; i < 3; ++i)
+        a.origin[i] = vol->origin[i];
     a.voxel = vol->voxel;
     a.blocks = vol->t.blocks;
     a.act = vol->t.act;
@@ -1898,6 +1909,8 @@ extern "C" rir_status rir_bvol_extract(rir_bvol *vol, double min_weight, double 
     if ((double)a.min_weight < min_weight)
         a.min_weight = std::nextafter(a.min_weight, std::numeric_limits<float>::infinity());
     a.max_jump = max_jump;
+    for (int i = 0; i < 3; ++i)
+        a.origin[i] = vol->origin[i];
     a.voxel = vol->voxel;
     a.pts = points;
     a.max_pts = max_points;

@@ -35,6 +35,7 @@ struct BvolActArgs {
     const float *ranges;  // n_frames images of H x W, contiguous
     int n_frames, H, W;
     int frame0;           // index of the launch's first scan in the volume's history
+    double origin[3];     // world position of voxel (0, 0, 0)
     double radius;        // half edge of the activation cube (m)
     double clip;          // > 0: returns beyond it activate nothing
     double edge;          // block edge (16 voxels, m)

@@ -6,7 +6,8 @@
 //
 // Activation: one thread per return.  The return is unprojected in FP64
 // (Eq. (1)) and moved to the world frame, x = R^T (x_s - t); every block whose
-// cell [E b, E (b + 1)) meets the cube [x - radius, x + radius] is looked up
+// cell o + [E b, E (b + 1)) (o: the volume origin) meets the cube
+// [x - radius, x + radius] is looked up
 // and, if absent, inserted (64-bit compare-and-swap on the key, then a slot of
 // the block pool from a counter).  Each table entry keeps the first scan that
 // activated it (atomic minimum), so that fusion can apply a scan only to the
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(256) void k_bvol_activate(const BvolActArgs a)
                 const SdfFrame &F = a.f[f];
                 const double d[3] = {xs.x - F.t[0], xs.y - F.t[1], xs.z - F.t[2]};
                 for (int j = 0; j < 3; ++j) {
-                    const double x = F.R[j] * d[0] + F.R[3 + j] * d[1] + F.R[6 + j] * d[2];
+                    const double x = F.R[j] * d[0] + F.R[3 + j] * d[1] + F.R[6 + j] * d[2] - a.origin[j];
                     const double l = floor((x - a.radius) / a.edge), h = floor((x + a.radius) / a.edge);
                     if (!(l > (double)-kBvolBias && h < (double)kBvolBias)) {
                         on = false;  // outside the table's coordinate range

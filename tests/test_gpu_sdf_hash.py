@@ -33,9 +33,10 @@ def rir():
     return rir
 
 
-def _integrate(rir, sm, ranges, poses, trunc, r_clip, radius, voxel=0.1, max_blocks=20000, vol=None):
+def _integrate(rir, sm, ranges, poses, trunc, r_clip, radius, voxel=0.1, max_blocks=20000, vol=None,
+               origin=(0.0, 0.0, 0.0)):
     import torch
-    vol = rir.BlockVolume(voxel, max_blocks) if vol is None else vol
+    vol = rir.BlockVolume(voxel, max_blocks, origin) if vol is None else vol
     vol.integrate(rir.Sensor.from_model(sm), to_dev(ranges), poses, trunc, r_clip, radius)
     torch.cuda.synchronize()
     return vol
@@ -52,11 +53,11 @@ def _key_map(rows):
     return {tuple(int(x) for x in r[:3]): int(r[3]) for r in rows}
 
 
-def _block_points(key, voxel):
+def _block_points(key, voxel, origin):
     E = 16
     k, j, i = np.meshgrid(np.arange(E), np.arange(E), np.arange(E), indexing="ij")
     idx = np.stack([i, j, k], axis=-1).reshape(-1, 3) + E * np.asarray(key)
-    return voxel * idx.astype(np.float64)
+    return np.asarray(origin) + voxel * idx.astype(np.float64)
 
 
 SENSORS = {
@@ -65,21 +66,25 @@ SENSORS = {
 }
 
 
+ORIGIN = (0.03, -1.2, 0.05)
+
+
 @pytest.mark.parametrize("name", list(SENSORS))
-@pytest.mark.parametrize("radius,r_clip", [(0.3, 30.0), (0.0, 0.0), (1.7, 20.0)])
-def test_activation_matches_oracle(rir, name, radius, r_clip):
+@pytest.mark.parametrize("radius,r_clip,origin", [(0.3, 30.0, ORIGIN), (0.0, 0.0, (0.0, 0.0, 0.0)),
+                                                  (1.7, 20.0, ORIGIN)])
+def test_activation_matches_oracle(rir, name, radius, r_clip, origin):
     """Activated blocks and first activating scans: 20 scans (two launches of
     activation), radius 0 (each return's own block), below and above one
-    block edge (1.6 m)."""
+    block edge (1.6 m), with and without an origin offset."""
     sm = SENSORS[name]()
     ranges, poses, _ = sequence(sm, 20, seed=11)
-    vol = _integrate(rir, sm, ranges, poses, 0.3, r_clip, radius)
+    vol = _integrate(rir, sm, ranges, poses, 0.3, r_clip, radius, origin=origin)
     rows, _ = _export(vol)
     assert vol.size() == (len(rows), 20)
     got = _key_map(rows)
     assert len(got) == len(rows)  # no block twice
-    inner = _key_map(oracle.sdf_activate(sm, ranges, poses, max(radius - EPS, 0.0), r_clip, 0.1))
-    outer = _key_map(oracle.sdf_activate(sm, ranges, poses, radius + EPS, r_clip, 0.1))
+    inner = _key_map(oracle.sdf_activate(sm, ranges, poses, max(radius - EPS, 0.0), r_clip, 0.1, origin))
+    outer = _key_map(oracle.sdf_activate(sm, ranges, poses, radius + EPS, r_clip, 0.1, origin))
     assert len(inner) > 50
     assert set(inner) <= set(got) <= set(outer), (len(set(inner) - set(got)), len(set(got) - set(outer)))
     for k, f in got.items():
@@ -96,7 +101,7 @@ def test_fusion_matches_oracle(rir, name, trunc, r_clip):
     sm = SENSORS[name]()
     ranges, poses, _ = sequence(sm, 20, seed=12)
     voxel = 0.1
-    vol = _integrate(rir, sm, ranges, poses, trunc, r_clip, 0.3, voxel=voxel)
+    vol = _integrate(rir, sm, ranges, poses, trunc, r_clip, 0.3, voxel=voxel, origin=ORIGIN)
     rows, vox = _export(vol)
     rng = np.random.default_rng(3)
     late = np.flatnonzero(rows[:, 3] > 0)
@@ -107,7 +112,7 @@ def test_fusion_matches_oracle(rir, name, trunc, r_clip):
     n_obs, n_amb, amb_bound, err_max = 0, 0, 0.0, 0.0
     for b in pick:
         key, f0 = rows[b, :3], int(rows[b, 3])
-        pts = _block_points(key, voxel)
+        pts = _block_points(key, voxel, ORIGIN)
         g = vox[b].reshape(-1, 2).astype(np.float64)
         s_ref, w_ref = oracle.sdf_fuse(sm, ranges[f0:], poses[f0:], pts, trunc, r_clip)
         amb = sdf_ambiguous(sm, ranges[f0:], poses[f0:], pts, trunc, r_clip)
@@ -137,7 +142,7 @@ def test_extract_matches_oracle_on_the_blocks(rir):
     sm = synth.uniform_sensor(32, 512)
     ranges, poses, _ = sequence(sm, 12, seed=13)
     voxel = 0.1
-    vol = _integrate(rir, sm, ranges, poses, 0.3, 30.0, 0.3, voxel=voxel)
+    vol = _integrate(rir, sm, ranges, poses, 0.3, 30.0, 0.3, voxel=voxel, origin=ORIGIN)
     rows, vox = _export(vol)
     lo = rows[:, :3].min(axis=0)
     nb = rows[:, :3].max(axis=0) - lo + 1
@@ -146,7 +151,8 @@ def test_extract_matches_oracle_on_the_blocks(rir):
         x, y, z = (r[:3] - lo) * 16
         dense[z:z + 16, y:y + 16, x:x + 16] = v
     for mw, mj in [(1.0, 0.45), (3.0, np.inf)]:
-        ref = oracle.sdf_extract(tuple(voxel * 16 * lo.astype(np.float64)), voxel, dense[..., 0], dense[..., 1],
+        ref = oracle.sdf_extract(tuple(np.asarray(ORIGIN) + voxel * 16 * lo.astype(np.float64)), voxel,
+                                 dense[..., 0], dense[..., 1],
                                  min_weight=mw, max_jump=mj)
         pts, n = vol.extract(min_weight=mw, max_jump=mj)
         torch.cuda.synchronize()
@@ -211,5 +217,7 @@ def test_errors_and_empty_calls(rir):
         vol.integrate(sen, to_dev(ranges[:1]), poses[:1], 0.3, 30.0, -1.0)
     with pytest.raises(rir.RirError):
         rir.BlockVolume(0.0, 10)
+    with pytest.raises(rir.RirError):
+        rir.BlockVolume(0.1, 10, (0.0, np.nan, 0.0))
     with pytest.raises(rir.RirError):
         rir.BlockVolume(0.1, 0)
