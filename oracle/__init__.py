@@ -112,6 +112,9 @@ def lib():
         L.orc_sdf_extract.argtypes = [_D, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D,
                                       ctypes.c_double, ctypes.c_double, _D, ctypes.c_int64]
         L.orc_sdf_extract.restype = ctypes.c_int64
+        L.orc_sdf_mesh.argtypes = [_D, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D,
+                                   ctypes.c_double, ctypes.c_double, _D, ctypes.c_int64]
+        L.orc_sdf_mesh.restype = ctypes.c_int64
         L.orc_sdf_activate.argtypes = [S, ctypes.c_int, _F, _D, _D, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, _I32, ctypes.c_int64]
         L.orc_sdf_activate.restype = ctypes.c_int64
@@ -307,6 +310,21 @@ def sdf_extract(origin, voxel: float, sdf: np.ndarray, weight: np.ndarray, min_w
     lib().orc_sdf_extract(_p(o, _D), float(voxel), nx, ny, nz, _p(s, _D), _p(w, _D), float(min_weight),
                           float(max_jump), _p(pts, _D), n)
     return pts[:n]
+
+
+def sdf_mesh(origin, voxel: float, sdf: np.ndarray, weight: np.ndarray, min_weight: float = 1.0,
+             max_jump: float = np.inf) -> np.ndarray:
+    """Level-set triangles of an SDF grid sdf/weight [nz, ny, nx] by the
+    tetrahedral split of every cube: triangles [n, 3, 3] (see orc_sdf_mesh)."""
+    s = np.ascontiguousarray(sdf, dtype=np.float64)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    nz, ny, nx = s.shape
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    args = (_p(o, _D), float(voxel), nx, ny, nz, _p(s, _D), _p(w, _D), float(min_weight), float(max_jump))
+    n = lib().orc_sdf_mesh(*args, None, 0)
+    t = np.zeros((max(n, 1), 3, 3))
+    lib().orc_sdf_mesh(*args, _p(t, _D), n)
+    return t[:n]
 
 
 def bf16(x: float) -> float:

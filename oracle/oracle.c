@@ -1417,6 +1417,134 @@ void orc_deskew(const orc_sensor *s, const float *range, const double xi[6], dou
 }
 
 /*
+ * Level-set triangles of an SDF volume (Sec. 4.2 meshes the fused SDF with
+ * marching cubes; this is its tetrahedral form, consistent without the
+ * ambiguous cube cases).  Grid as in orc_sdf_extract.  Every cube of 8
+ * voxels (i..i+1, j..j+1, k..k+1) is split into the six tetrahedra that
+ * share its diagonal from corner (0, 0, 0) to (1, 1, 1): for each order of
+ * the axes (x y z, x z y, y x z, y z x, z x y, z y x) the path 000 -> one
+ * axis -> two axes -> 111.  A tetrahedron is meshed when its four voxels have
+ * weight >= min_weight and every edge whose ends lie on different sides of
+ * zero (s > 0 against s <= 0) has |s_a - s_b| <= max_jump.  With one vertex
+ * on its own side (the other three on the other) it gives the triangle
+ * through the crossings of that vertex's three edges, taken in the order of
+ * the other vertices; with two on each side, positive a, b and non-positive
+ * c, d (tetrahedron order), the quadrilateral ac, ad, bd, bc as the
+ * triangles (ac, ad, bd) and (ac, bd, bc).  A crossing is a + t (b - a),
+ * t = s_a / (s_a - s_b).  Each triangle is turned so that its normal
+ * (v1 - v0) x (v2 - v0) points from the tetrahedron's non-positive vertices
+ * towards its positive ones (mean against mean).  Order: cubes in index
+ * order of their (0, 0, 0) voxel, then tetrahedra, then triangles.  Writes
+ * at most max_tris triangles (9 doubles each) and returns how many there are.
+ */
+static const int orc_tet_axes[6][2] = {{0, 1}, {0, 2}, {1, 0}, {1, 2}, {2, 0}, {2, 1}};
+
+int64_t orc_sdf_mesh(const double origin[3], double voxel, int nx, int ny, int nz, const double *sdf,
+                     const double *weight, double min_weight, double max_jump, double *tris, int64_t max_tris)
+{
+    int64_t n = 0;
+    for (int k = 0; k + 1 < nz; ++k)
+        for (int j = 0; j + 1 < ny; ++j)
+            for (int i = 0; i + 1 < nx; ++i)
+                for (int t = 0; t < 6; ++t) {
+                    int c[4][3] = {{i, j, k}, {i, j, k}, {i, j, k}, {i + 1, j + 1, k + 1}};
+                    c[1][orc_tet_axes[t][0]] += 1;
+                    c[2][orc_tet_axes[t][0]] += 1;
+                    c[2][orc_tet_axes[t][1]] += 1;
+                    double sv[4], x[4][3];
+                    int pos[4], np = 0, ok = 1;
+                    for (int q = 0; q < 4; ++q) {
+                        size_t idx = ((size_t)c[q][2] * ny + c[q][1]) * nx + c[q][0];
+                        if (!(weight[idx] >= min_weight))
+                            ok = 0;
+                        sv[q] = sdf[idx];
+                        pos[q] = sv[q] > 0.0;
+                        np += pos[q];
+                        for (int a = 0; a < 3; ++a)
+                            x[q][a] = origin[a] + voxel * (double)c[q][a];
+                    }
+                    if (!ok || np == 0 || np == 4)
+                        continue;
+                    for (int a = 0; a < 4; ++a)
+                        for (int b = a + 1; b < 4; ++b)
+                            if (pos[a] != pos[b] && fabs(sv[a] - sv[b]) > max_jump)
+                                ok = 0;
+                    if (!ok)
+                        continue;
+                    /* edges (as vertex pairs) of the triangles */
+                    int e[2][3][2], ntri = 0;
+                    if (np == 1 || np == 3) {
+                        int lone = -1, o[3], m = 0;
+                        for (int q = 0; q < 4; ++q)
+                            if (pos[q] == (np == 1))
+                                lone = q;
+                        for (int q = 0; q < 4; ++q)
+                            if (q != lone)
+                                o[m++] = q;
+                        for (int v = 0; v < 3; ++v) {
+                            e[0][v][0] = lone;
+                            e[0][v][1] = o[v];
+                        }
+                        ntri = 1;
+                    } else {
+                        int P[2], N[2], mp = 0, mn = 0;
+                        for (int q = 0; q < 4; ++q) {
+                            if (pos[q])
+                                P[mp++] = q;
+                            else
+                                N[mn++] = q;
+                        }
+                        int quad[4][2] = {{P[0], N[0]}, {P[0], N[1]}, {P[1], N[1]}, {P[1], N[0]}};
+                        int tri_of[2][3] = {{0, 1, 2}, {0, 2, 3}};
+                        for (int tr = 0; tr < 2; ++tr)
+                            for (int v = 0; v < 3; ++v) {
+                                e[tr][v][0] = quad[tri_of[tr][v]][0];
+                                e[tr][v][1] = quad[tri_of[tr][v]][1];
+                            }
+                        ntri = 2;
+                    }
+                    /* direction from the non-positive towards the positive vertices */
+                    double gp[3] = {0, 0, 0}, gn[3] = {0, 0, 0}, g[3];
+                    for (int q = 0; q < 4; ++q)
+                        for (int a = 0; a < 3; ++a) {
+                            if (pos[q])
+                                gp[a] += x[q][a] / np;
+                            else
+                                gn[a] += x[q][a] / (4 - np);
+                        }
+                    for (int a = 0; a < 3; ++a)
+                        g[a] = gp[a] - gn[a];
+                    for (int tr = 0; tr < ntri; ++tr) {
+                        double v[3][3];
+                        for (int w = 0; w < 3; ++w) {
+                            int a = e[tr][w][0], b = e[tr][w][1];
+                            double tt = sv[a] / (sv[a] - sv[b]);
+                            for (int d = 0; d < 3; ++d)
+                                v[w][d] = x[a][d] + tt * (x[b][d] - x[a][d]);
+                        }
+                        double u1[3], u2[3], nn[3];
+                        for (int d = 0; d < 3; ++d) {
+                            u1[d] = v[1][d] - v[0][d];
+                            u2[d] = v[2][d] - v[0][d];
+                        }
+                        nn[0] = u1[1] * u2[2] - u1[2] * u2[1];
+                        nn[1] = u1[2] * u2[0] - u1[0] * u2[2];
+                        nn[2] = u1[0] * u2[1] - u1[1] * u2[0];
+                        int flip = nn[0] * g[0] + nn[1] * g[1] + nn[2] * g[2] < 0.0;
+                        if (n < max_tris) {
+                            double *o = tris + 9 * n;
+                            int order[3] = {0, flip ? 2 : 1, flip ? 1 : 2};
+                            for (int w = 0; w < 3; ++w)
+                                for (int d = 0; d < 3; ++d)
+                                    o[3 * w + d] = v[order[w]][d];
+                        }
+                        ++n;
+                    }
+                }
+    return n;
+}
+
+/*
  * Surface points of an SDF volume: the zero crossings of the fused SDF along
  * the grid edges (the level set that Sec. 4.2 extracts with marching cubes;
  * this returns its vertices, without the triangles).  Grid of nx * ny * nz

@@ -325,3 +325,81 @@ def test_activation_radius_zero_and_frames(orc):
     assert {tuple(k) for k in both[:, :3]} == first_keys | {tuple(k) for k in second[:, :3]}
     big = orc.sdf_activate(sm, ranges, poses, 1.0, 0.0, 0.1)
     assert {tuple(k) for k in once[:, :3]} < {tuple(k) for k in big[:, :3]}
+
+
+# ----------------------------------------------------------------------------- level-set triangles
+
+def _field(nx, ny, nz, voxel, origin, f):
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x = np.asarray(origin)[0] + voxel * i
+    y = np.asarray(origin)[1] + voxel * j
+    z = np.asarray(origin)[2] + voxel * k
+    return f(x, y, z)
+
+
+def _area_normals(t):
+    n = np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    return 0.5 * np.linalg.norm(n, axis=1), n
+
+
+def test_mesh_of_a_plane_is_the_plane(orc):
+    """A linear SDF (tilted plane, positive above): every vertex on the plane,
+    the triangles cover exactly the plane over the grid's xy extent (area
+    (nx - 1)(ny - 1) voxel^2 sqrt(1 + a^2 + b^2)), every normal points to the
+    positive side."""
+    a, b, c, v = 0.3, -0.2, 0.77, 0.1
+    nx, ny, nz = 12, 9, 20
+    s = _field(nx, ny, nz, v, (0.0, 0.0, 0.0), lambda x, y, z: (z - (a * x + b * y + c)) / np.sqrt(1 + a * a + b * b))
+    w = np.ones_like(s)
+    t = orc.sdf_mesh((0.0, 0.0, 0.0), v, s, w)
+    assert len(t) > 100
+    p = t.reshape(-1, 3)
+    np.testing.assert_allclose(p[:, 2], a * p[:, 0] + b * p[:, 1] + c, atol=1e-12)
+    area, nrm = _area_normals(t)
+    assert abs(area.sum() - (nx - 1) * (ny - 1) * v * v * np.sqrt(1 + a * a + b * b)) < 1e-10
+    up = nrm @ np.array([-a, -b, 1.0])
+    assert np.all(up[area > 1e-14] > 0)
+
+
+def test_mesh_of_a_sphere_is_closed_and_oriented(orc):
+    """Positive outside a sphere: the mesh is closed and consistently turned
+    (every directed edge once, its reverse once), its enclosed volume
+    (divergence theorem) is within 1.5% of 4/3 pi R^3, and every vertex lies
+    within voxel^2 / R of the sphere."""
+    v, R, c = 0.1, 0.8, np.array([1.03, 0.98, 1.01])
+    n = 21
+    s = _field(n, n, n, v, (0.0, 0.0, 0.0), lambda x, y, z: np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) - R)
+    t = orc.sdf_mesh((0.0, 0.0, 0.0), v, s, np.ones_like(s))
+    key = np.round(t.reshape(-1, 3) / 1e-9).astype(np.int64).reshape(-1, 3, 3)
+    ids = {}
+    tri = np.array([[ids.setdefault(tuple(p), len(ids)) for p in tr] for tr in key])
+    directed = {}
+    for a, b, cc in tri:
+        for e in ((a, b), (b, cc), (cc, a)):
+            directed[e] = directed.get(e, 0) + 1
+    assert all(m == 1 for m in directed.values())
+    assert all((b, a) in directed for a, b in directed)
+    vol = np.einsum("ij,ij->i", t[:, 0], np.cross(t[:, 1], t[:, 2])).sum() / 6.0
+    assert abs(vol / (4.0 / 3.0 * np.pi * R ** 3) - 1.0) < 0.015, vol
+    r = np.linalg.norm(t.reshape(-1, 3) - c, axis=1)
+    assert np.max(np.abs(r - R)) < v * v / R
+
+
+def test_mesh_weight_and_step_gates(orc):
+    """Unobserved voxels (weight below min_weight) and steps above max_jump
+    leave no triangle on a tetrahedron that holds them."""
+    v = 0.1
+    nx = ny = nz = 8
+    s = _field(nx, ny, nz, v, (0.0, 0.0, 0.0), lambda x, y, z: z - 0.33)
+    w = np.full_like(s, 2.0)
+    full = orc.sdf_mesh((0.0, 0.0, 0.0), v, s, w, min_weight=2.0)
+    w2 = w.copy()
+    w2[:, :, 4:] = 1.0                                     # x >= 0.4 observed once
+    part = orc.sdf_mesh((0.0, 0.0, 0.0), v, s, w2, min_weight=2.0)
+    assert 0 < len(part) < len(full)
+    assert np.all(part[:, :, 0] <= 0.3 + 1e-12)
+    s2 = s.copy()
+    s2[:, 4:, :] *= 10.0                                   # steep half: |s_a - s_b| up to 1 m
+    cut = orc.sdf_mesh((0.0, 0.0, 0.0), v, s2, w, max_jump=0.5)
+    assert 0 < len(cut) < len(full)
+    assert np.all(cut[:, :, 1] <= 0.4 + 1e-12)
