@@ -385,6 +385,30 @@ rir_status rir_sdf_integrate(const rir_sensor *sensor, const rir_volume_desc *vo
 rir_status rir_sdf_extract(const rir_volume_desc *vol, const float *voxels, double min_weight, double max_jump,
                            float *points, int64_t max_points, uint64_t *count, void *stream);
 
+/* Level-set triangles of a fused volume (Sec. 4.2 meshes the fused SDF with
+ * marching cubes; this is its tetrahedral form, which needs no resolution
+ * of ambiguous cube cases).  Every cube of 8 voxels (i..i+1, j..j+1, k..k+1)
+ * is split into the six tetrahedra around its diagonal from voxel (0, 0, 0)
+ * to (1, 1, 1), one for each order of the axes (x y z, x z y, y x z, y z x,
+ * z x y, z y x: 000 -> one axis -> two axes -> 111).  A tetrahedron whose four
+ * voxels have weight >= min_weight and whose edges with values on different
+ * sides of zero (s > 0 against s <= 0) step by at most max_jump gives: with
+ * one vertex on its own side, the triangle through the crossings of its
+ * three edges (in the order of the other vertices); with positive a, b and
+ * non-positive c, d (tetrahedron order), the triangles (ac, ad, bd) and
+ * (ac, bd, bc).  A crossing is a + t (b - a), t = s_a / (s_a - s_b), formed
+ * in FP64 in world coordinates and stored as FP32; each triangle is turned so
+ * that (v1 - v0) x (v2 - v0) points from the tetrahedron's non-positive
+ * vertices towards its positive ones.
+ *   voxels      device volume (rir_sdf_integrate layout), read only.
+ *   triangles   device max_triangles * 9 FP32 (three vertices of x, y, z),
+ *               order not defined.
+ *   count       device uint64: number of triangles (may exceed
+ *               max_triangles; only the first max_triangles are stored).
+ * Runs asynchronously on `stream`.  Errors as rir_sdf_extract. */
+rir_status rir_sdf_mesh(const rir_volume_desc *vol, const float *voxels, double min_weight, double max_jump,
+                        float *triangles, int64_t max_triangles, uint64_t *count, void *stream);
+
 /* ---------------------------------------------------------------- sparse SDF volume */
 
 /* Sparse SDF volume of Sec. 4.2: the 16^3-voxel blocks near the returns of
@@ -442,6 +466,12 @@ rir_status rir_bvol_export(const rir_bvol *vol, int32_t *blocks, float *voxels, 
  * max_points < 0, non-finite min_weight, max_jump < 0 or NaN), RIR_E_HIP. */
 rir_status rir_bvol_extract(rir_bvol *vol, double min_weight, double max_jump, float *points, int64_t max_points,
                             uint64_t *count, void *stream);
+
+/* Level-set triangles of the sparse volume, as rir_sdf_mesh (cubes whose
+ * eight voxels lie in active blocks; world coordinates).  Errors as
+ * rir_bvol_extract. */
+rir_status rir_bvol_mesh(rir_bvol *vol, double min_weight, double max_jump, float *triangles, int64_t max_triangles,
+                         uint64_t *count, void *stream);
 
 /* ---------------------------------------------------------------- learned weight */
 

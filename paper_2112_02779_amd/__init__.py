@@ -32,7 +32,7 @@ EXPORTS = [
     "rir_mlp_get_params", "rir_mlp_set_params", "rir_mlp_forward", "rir_mlp_train_step", "rir_last_error",
     "rir_elevation_table", "rir_sdf_integrate", "rir_normals_pca", "rir_deskew",
     "rir_sdf_extract", "rir_mlp_train_step_noalloc", "rir_bvol_create", "rir_bvol_destroy", "rir_bvol_reset",
-    "rir_bvol_integrate", "rir_bvol_size", "rir_bvol_export", "rir_bvol_extract",
+    "rir_bvol_integrate", "rir_bvol_size", "rir_bvol_export", "rir_bvol_extract", "rir_sdf_mesh", "rir_bvol_mesh",
 ]
 
 
@@ -140,6 +140,8 @@ def lib():
         "rir_bvol_size": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "rir_bvol_export": [vp, vp, vp, vp],
         "rir_bvol_extract": [vp, f64, f64, vp, i64, vp, vp],
+        "rir_bvol_mesh": [vp, f64, f64, vp, i64, vp, vp],
+        "rir_sdf_mesh": [ctypes.POINTER(VolumeDesc), vp, f64, f64, vp, i64, vp, vp],
         "rir_last_error": [],
         "rir_elevation_table": [ctypes.POINTER(SensorDesc), i32, i32, vp, i64, ctypes.POINTER(i64),
                                 ctypes.POINTER(f64), ctypes.POINTER(f64)],
@@ -478,6 +480,47 @@ class BlockVolume:
         pts = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
         n = run(pts, cap)
         return pts[:min(n, cap)], n
+
+    def mesh(self, min_weight=1.0, max_jump=float("inf"), max_triangles=None, stream=None):
+        """Level-set triangles: (triangles [n, 3, 3] FP32 device tensor, total
+        triangles), as sdf_mesh."""
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        dev = torch.device("cuda", self.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def run(tri, cap):
+            _check(lib().rir_bvol_mesh(self.handle, float(min_weight), float(max_jump), _ptr(tri), cap, _ptr(cnt),
+                                       _stream(s)))
+            s.synchronize()
+            return int(cnt.item())
+
+        cap = run(None, 0) if max_triangles is None else int(max_triangles)
+        tri = torch.empty((max(cap, 1), 3, 3), dtype=torch.float32, device=dev)
+        n = run(tri, cap)
+        return tri[:min(n, cap)], n
+
+
+def sdf_mesh(vol: Volume, voxels, min_weight=1.0, max_jump=float("inf"), max_triangles=None, stream=None):
+    """Level-set triangles of a fused volume (the tetrahedral form of marching
+    cubes): (triangles [n, 3, 3] FP32 device tensor, total triangles).
+    Synchronises the stream to read the count; with max_triangles None a
+    counting pass sizes the result exactly."""
+    import torch
+    _require(voxels, torch.float32, "voxels", 2 * 4096 * vol.nb[0] * vol.nb[1] * vol.nb[2])
+    s = torch.cuda.current_stream() if stream is None else stream
+    cnt = torch.zeros(1, dtype=torch.int64, device=voxels.device)
+
+    def run(tri, cap):
+        _check(lib().rir_sdf_mesh(ctypes.byref(vol.desc), _ptr(voxels), float(min_weight), float(max_jump),
+                                  _ptr(tri), cap, _ptr(cnt), _stream(s)))
+        s.synchronize()
+        return int(cnt.item())
+
+    cap = run(None, 0) if max_triangles is None else int(max_triangles)
+    tri = torch.empty((max(cap, 1), 3, 3), dtype=torch.float32, device=voxels.device)
+    n = run(tri, cap)
+    return tri[:min(n, cap)], n
 
 
 def deskew(sensor: Sensor, rng, twists, stream=None):

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librir.so")
-SOURCES = ["kernels.hip", "mlp.hip", "sdf.hip", "sdf_extract.hip", "sdf_hash.hip", "normals_pca.hip", "deskew.hip",
+SOURCES = ["kernels.hip", "mlp.hip", "sdf.hip", "sdf_extract.hip", "sdf_hash.hip", "sdf_mesh.hip",
+           "normals_pca.hip", "deskew.hip",
            "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1686,6 +1686,44 @@ extern "C" rir_status rir_sdf_extract(const rir_volume_desc *vol, const float *v
     return RIR_OK;
 }
 
+extern "C" rir_status rir_sdf_mesh(const rir_volume_desc *vol, const float *voxels, double min_weight,
+                                   double max_jump, float *triangles, int64_t max_triangles, uint64_t *count,
+                                   void *stream)
+{
+    if (!vol || !voxels || !count || (max_triangles > 0 && !triangles))
+        return fail(RIR_E_INVALID, "rir_sdf_mesh: null argument");
+    if (max_triangles < 0)
+        return fail(RIR_E_INVALID, "rir_sdf_mesh: max_triangles < 0");
+    if (vol->nbx < 1 || vol->nby < 1 || vol->nbz < 1)
+        return fail(RIR_E_SHAPE, "rir_sdf_mesh: block counts must be >= 1");
+    if ((int64_t)vol->nbx * vol->nby * vol->nbz > (int64_t)std::numeric_limits<int32_t>::max())
+        return fail(RIR_E_SHAPE, "rir_sdf_mesh: more than 2^31 - 1 blocks");
+    if (!(vol->voxel > 0.0) || !std::isfinite(vol->voxel))
+        return fail(RIR_E_INVALID, "rir_sdf_mesh: voxel size must be finite and > 0");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(vol->origin[i]))
+            return fail(RIR_E_INVALID, "rir_sdf_mesh: origin must be finite");
+    if (!std::isfinite(min_weight) || std::isnan(max_jump) || !(max_jump >= 0.0))
+        return fail(RIR_E_INVALID, "rir_sdf_mesh: min_weight must be finite and max_jump >= 0");
+    SdfExtractArgs a{};
+    a.vox = voxels;
+    a.nbx = vol->nbx;
+    a.nby = vol->nby;
+    a.nbz = vol->nbz;
+    a.min_weight = (float)min_weight;
+    if ((double)a.min_weight < min_weight)
+        a.min_weight = std::nextafter(a.min_weight, std::numeric_limits<float>::infinity());
+    a.max_jump = max_jump;
+    for (int i = 0; i < 3; ++i)
+        a.origin[i] = vol->origin[i];
+    a.voxel = vol->voxel;
+    a.pts = triangles;
+    a.max_pts = max_triangles;
+    a.count = reinterpret_cast<unsigned long long *>(count);
+    HIP_TRY(launch_sdf_mesh(a, false, static_cast<hipStream_t>(stream)));
+    return RIR_OK;
+}
+
 // ============================================================================ sparse SDF volume
 
 struct rir_bvol {
@@ -1696,7 +1734,7 @@ struct rir_bvol {
     uint32_t cap = 0;       // hash table entries (power of two, >= 2 max_blocks)
     void *dmem = nullptr;
     BvolDev t{};
-    int *d_nbr = nullptr;   // [max_blocks][3]
+    int *d_nbr = nullptr;   // [max_blocks][kNbrPerBlock]
     float *d_vox = nullptr; // [max_blocks][4096][2]
     int64_t n_blocks = 0;   // host copies
     int64_t n_frames = 0;
@@ -1753,7 +1791,7 @@ extern "C" rir_status rir_bvol_create(int device, const double origin[3], double
     const size_t o_vals = lay.add((size_t)v->cap * sizeof(int));
     const size_t o_act = lay.add((size_t)v->cap * sizeof(int));
     const size_t o_blocks = lay.add((size_t)max_blocks * sizeof(int4));
-    const size_t o_nbr = lay.add((size_t)max_blocks * 3 * sizeof(int));
+    const size_t o_nbr = lay.add((size_t)max_blocks * kNbrPerBlock * sizeof(int));
     const size_t o_ctr = lay.add(2 * sizeof(int));
     const size_t o_vox = lay.add((size_t)max_blocks * kBvolBlockBytes);
     HIP_TRY(hipMalloc(&v->dmem, lay.bytes));
@@ -1919,6 +1957,37 @@ extern "C" rir_status rir_bvol_extract(rir_bvol *vol, double min_weight, double 
     a.nbr = vol->d_nbr;
     a.n_blocks = (int)vol->n_blocks;
     HIP_TRY(launch_sdf_extract(a, true, st));
+    return RIR_OK;
+}
+
+extern "C" rir_status rir_bvol_mesh(rir_bvol *vol, double min_weight, double max_jump, float *triangles,
+                                    int64_t max_triangles, uint64_t *count, void *stream)
+{
+    if (!vol || !count || (max_triangles > 0 && !triangles))
+        return fail(RIR_E_INVALID, "rir_bvol_mesh: null argument");
+    if (max_triangles < 0)
+        return fail(RIR_E_INVALID, "rir_bvol_mesh: max_triangles < 0");
+    if (!std::isfinite(min_weight) || std::isnan(max_jump) || !(max_jump >= 0.0))
+        return fail(RIR_E_INVALID, "rir_bvol_mesh: min_weight must be finite and max_jump >= 0");
+    HIP_TRY(hipSetDevice(vol->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_bvol_neighbors(vol->t, (int)vol->n_blocks, vol->d_nbr, st));
+    SdfExtractArgs a{};
+    a.vox = vol->d_vox;
+    a.min_weight = (float)min_weight;
+    if ((double)a.min_weight < min_weight)
+        a.min_weight = std::nextafter(a.min_weight, std::numeric_limits<float>::infinity());
+    a.max_jump = max_jump;
+    for (int i = 0; i < 3; ++i)
+        a.origin[i] = vol->origin[i];
+    a.voxel = vol->voxel;
+    a.pts = triangles;
+    a.max_pts = max_triangles;
+    a.count = reinterpret_cast<unsigned long long *>(count);
+    a.blocks = vol->t.blocks;
+    a.nbr = vol->d_nbr;
+    a.n_blocks = (int)vol->n_blocks;
+    HIP_TRY(launch_sdf_mesh(a, true, st));
     return RIR_OK;
 }
 

@@ -71,7 +71,8 @@ __global__ __launch_bounds__(256) void k_sdf_extract(const SdfExtractArgs a)
         if constexpr (HASHED) {
             // the neighbour's first plane: (0, u, w), (u, 0, w), (u, w, 0)
             constexpr size_t kB = kSdfEdge * kSdfEdge * kSdfEdge;
-            const int nx = a.nbr[3 * b], ny = a.nbr[3 * b + 1], nz = a.nbr[3 * b + 2];
+            const int nx = a.nbr[kNbrPerBlock * b], ny = a.nbr[kNbrPerBlock * b + 1],
+                      nz = a.nbr[kNbrPerBlock * b + 2];
             if (nx >= 0)
                 fx = vox[(size_t)nx * kB + (size_t)((w * kSdfEdge + u) * kSdfEdge)];
             if (ny >= 0)
@@ -140,10 +141,15 @@ __global__ __launch_bounds__(256) void k_sdf_extract(const SdfExtractArgs a)
     }
 }
 
+hipError_t launch_zero_count(unsigned long long *count, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_sdf_extract(const SdfExtractArgs &a, bool hashed, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, a.count);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_zero_count(a.count, stream);
     if (e != hipSuccess)
         return e;
     if (hashed) {

@@ -15,6 +15,7 @@
 // activated and then fused in turn.  Neighbouring lanes mostly produce the
 // same cube: a lane whose scan and block range equal those of the lane below
 // it leaves the inserts to that lane.
+#include "sdf_extract.h"
 #include "sdf_hash.h"
 
 namespace rir {
@@ -143,15 +144,18 @@ __global__ __launch_bounds__(256) void k_bvol_activate(const BvolActArgs a)
     }
 }
 
-// Slots of the +x, +y and +z neighbours of every block (-1: not active).
+// Slots of the +x, +y, +z, +x+y, +x+z, +y+z and +x+y+z neighbours of every
+// block (-1: not active).
 __global__ __launch_bounds__(256) void k_bvol_neighbors(const BvolDev t, int n_blocks, int *nbr)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 3 * n_blocks)
+    if (i >= kNbrPerBlock * n_blocks)
         return;
-    const int b = i / 3, ax = i - 3 * b;
+    const int b = i / kNbrPerBlock, d = i - kNbrPerBlock * b;
+    constexpr int kDx[kNbrPerBlock] = {1, 0, 0, 1, 1, 0, 1}, kDy[kNbrPerBlock] = {0, 1, 0, 1, 0, 1, 1},
+                  kDz[kNbrPerBlock] = {0, 0, 1, 0, 1, 1, 1};
     const int4 B = t.blocks[b];
-    nbr[i] = bvol_find(t, B.x + (ax == 0), B.y + (ax == 1), B.z + (ax == 2));
+    nbr[i] = bvol_find(t, B.x + kDx[d], B.y + kDy[d], B.z + kDz[d]);
 }
 
 // Block coordinates and activation scans of the pool, in slot order.
@@ -176,7 +180,8 @@ hipError_t launch_bvol_neighbors(const BvolDev &t, int n_blocks, int *nbr, hipSt
 {
     if (n_blocks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_bvol_neighbors, dim3((3 * n_blocks + 255) / 256), dim3(256), 0, stream, t, n_blocks, nbr);
+    hipLaunchKernelGGL(k_bvol_neighbors, dim3((kNbrPerBlock * n_blocks + 255) / 256), dim3(256), 0, stream, t,
+                       n_blocks, nbr);
     return hipGetLastError();
 }
 
