@@ -512,7 +512,32 @@ def reconstruction_quality(rir, vol, vox, seq, r_clip, radius, n_sample=200000):
         ts.append(e0.elapsed_time(e1))
     ms = float(np.median(ts))
     out = surface_scores(pts.cpu().numpy().astype(np.float64), seq, r_clip, radius, n_sample)
-    return {"extract_ms": round(ms, 4), "surface_points": n, **out}
+    mesh = mesh_stats(rir, lambda tri, cap, c, st: rir.lib().rir_sdf_mesh(
+        ctypes.byref(vol.desc), vox.data_ptr(), 1.0, 0.45, tri, cap, c, st),
+        rir.sdf_mesh(vol, vox, min_weight=1.0, max_jump=0.45, stream=stream), stream)
+    return {"extract_ms": round(ms, 4), "surface_points": n, **out, "mesh": mesh}
+
+
+def mesh_stats(rir, launch, result, stream):
+    """Triangle count, total area and the median time of one mesh launch
+    (HIP events around the launch alone; launch(tri_ptr, cap, count_ptr,
+    stream) enqueues it)."""
+    import torch
+    import ctypes
+    tri, n = result
+    cnt = torch.zeros(1, dtype=torch.int64, device=tri.device)
+    ts = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st = launch(tri.data_ptr(), n, cnt.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        assert st == 0 and int(cnt.item()) == n
+        ts.append(e0.elapsed_time(e1))
+    t = tri.double()
+    area = float(0.5 * torch.linalg.norm(torch.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0], dim=1), dim=1).sum())
+    return {"triangles": n, "mesh_ms": round(float(np.median(ts)), 4), "area_m2": round(area, 1)}
 
 
 def surface_scores(P, seq, r_clip, radius, n_sample=200000):
@@ -682,6 +707,8 @@ def sparse_sdf(rir, seq, sen, ranges, poses, r_clip, repeats):
         sc = surface_scores(pts.cpu().numpy().astype(np.float64), seq, r_clip, 3 * vx)
         if not np.isfinite(max_jump):
             sc["protocol"] = sc["protocol"].replace("max step 0.45 m", "no step limit")
+        sc["mesh"] = mesh_stats(rir, lambda tri, cap, c, st, v=vol, mj=max_jump: rir.lib().rir_bvol_mesh(
+            v.handle, 1.0, mj, tri, cap, c, st), vol.mesh(min_weight=1.0, max_jump=max_jump, stream=stream), stream)
         out[f"voxel_{vx}"] = {"ms_per_sequence": round(ms, 4), "scans_per_s": round(F / (ms * 1e-3), 1),
                               "truncation_m": round(trunc, 3),
                               "active_blocks": int(nb), "block_memory_gb": round(nb * 32768 / 1e9, 3),
