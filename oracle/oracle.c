@@ -270,8 +270,9 @@ void orc_project_points(const orc_sensor *s, int level, const double *xyz, int64
 
 /*
  * Target normals by the cross product of neighbour-pixel differences
- * (Sec. 4.1: "simply a cross product of two neighbor pixels"; Sec. 6.1 notes
- * the normal map can be computed directly from the range image).
+ * (Sec. 4.1 forms the normal from two neighbouring pixels by a cross
+ * product; Sec. 6.1 notes the normal map comes straight from the range
+ * image).
  *
  * Readings: central differences n = (P(u+1,v) - P(u-1,v)) x (P(u,v+1) -
  * P(u,v-1)); u wraps around the cylinder, v does not (rows 0 and H-1 are
