@@ -268,7 +268,8 @@ rir_status rir_normals_pca(const rir_sensor *sensor, int32_t n_images, const flo
                            double edge_rel, float *nrm, uint8_t *valid, void *stream);
 
 /* Re-projection under per-column poses, the non-rigid model of the paper's
- * outlook (Sec. 6: consecutive poses assigned to each column, as in LOAM) for
+ * outlook (Sec. 6: each column given its own pose between consecutive poses,
+ * as in LOAM) for
  * sensors that move during a sweep.  Column u of scan k is captured at sweep
  * time s_u = (u + 1/2) / W - 1/2 (0 at mid-sweep); with the constant twist
  * xi_k = (omega, tau) per sweep its pose in the mid-sweep frame is

@@ -1120,12 +1120,13 @@ void orc_sdf_fuse(const orc_sensor *s, int n_frames, const float *ranges, const 
  * x = R^T (x_s - t) for the scan's world -> sensor pose (R, t); it activates
  * every block whose cell o + [E b, E (b + 1)) (E = block_edge, per axis;
  * o the volume origin, where voxel (0, 0, 0) sits) meets the cube
- * [x - radius, x + radius] (reading of "the blocks within a certain radius of
- * the point": an axis-aligned cube, which is what a block grid tests
+ * [x - radius, x + radius] (reading of the paper's blocks within some radius
+ * of each point: an axis-aligned cube, which is what a block grid tests
  * cheaply), i.e. b from floor((x - o - radius) / E) to
- * floor((x - o + radius) / E) on each axis.  A block's activation frame is the first scan that activates
- * it (the paper activates with each scan's points before fusing that scan, so
- * a block takes the scans from that one on).
+ * floor((x - o + radius) / E) on each axis.  A block's activation frame is
+ * the first scan that activates it (the paper activates with each scan's
+ * points before fusing that scan, so a block takes the scans from that one
+ * on).
  * Output: the distinct blocks sorted by (bx, by, bz), as 4 int32 each (bx,
  * by, bz, activation frame), at most max_out of them; returns how many there
  * are (-1 if memory runs out). */
