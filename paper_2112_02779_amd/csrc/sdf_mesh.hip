@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
             // neighbour order: +x, +y, +z, +x+y, +x+z, +y+z, +x+y+z
             const int dir = dx + dy + dz == 1 ? (dx ? 0 : (dy ? 1 : 2))
                                               : (dx + dy + dz == 3 ? 6 : (!dz ? 3 : (!dy ? 4 : 5)));
-            const int slot = a.nbr[7 * b + dir];
+            const int slot = a.nbr[kNbrPerBlock * b + dir];
             if (slot < 0)
                 return none;
             return vox[(size_t)slot * kB + (size_t)((((lz & 15) * kSdfEdge) + (ly & 15)) * kSdfEdge + (lx & 15))];
@@ -206,21 +206,29 @@ __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
     __syncthreads();
     const int x = tid & 15, y = tid >> 4;
     int g[3] = {bx * kSdfEdge + x, by * kSdfEdge + y, 0};
+    // the cube's 8 voxels; false when all lie on one side of zero (no
+    // tetrahedron of it has a triangle: most cubes, away from the surfaces)
     auto cube = [&](int z, float2 (&c)[2][2][2]) {
+        int npos = 0;
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
             for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-                for (int dx = 0; dx < 2; ++dx)
+                for (int dx = 0; dx < 2; ++dx) {
                     c[dz][dy][dx] = s_v[z + dz][y + dy][x + dx];
+                    npos += c[dz][dy][dx].x > 0.f ? 1 : 0;
+                }
+        return npos != 0 && npos != 8;
     };
     // pass 1: this thread's triangles
     int cnt = 0;
     for (int z = 0; z < kSdfEdge; ++z) {
         float2 c[2][2][2];
-        cube(z, c);
+        if (!cube(z, c))
+            continue;
         g[2] = bz * kSdfEdge + z;
+#pragma unroll
         for (int t = 0; t < 6; ++t)
             cnt += tet_triangles(a, c, g, t, nullptr);
     }
@@ -242,7 +250,8 @@ __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
     unsigned long long n = s_base + (unsigned long long)(s_scan[tid] - cnt);
     for (int z = 0; z < kSdfEdge; ++z) {
         float2 c[2][2][2];
-        cube(z, c);
+        if (!cube(z, c))
+            continue;
         g[2] = bz * kSdfEdge + z;
         for (int t = 0; t < 6; ++t) {
             const int k = tet_triangles(a, c, g, t, nullptr);
