@@ -6,9 +6,11 @@
 // One workgroup per block: the block's 16^3 voxels and the first planes,
 // edges and corner of its +x, +y, +z neighbours (17^3 voxels) are staged in
 // shared memory with independent loads (outside the volume or in a block
-// that is not active: weight -inf, no triangle).  Thread (x, y) takes the 16
-// cubes of its column whose (0, 0, 0) voxel lies in the block; each cube is
-// split into the six tetrahedra around its 000-111 diagonal, and each
+// that is not active: weight -inf, no triangle).  The cubes whose (0, 0, 0)
+// voxel lies in the block and whose voxels lie on both sides of zero (the
+// only ones with triangles) are compacted into a work list that the 256
+// threads share out evenly; each cube is split into the six tetrahedra around
+// its 000-111 diagonal, and each
 // tetrahedron whose four voxels are observed (weight >= min_weight) and whose
 // sign-changing edges step by at most max_jump gives one triangle (one
 // vertex on its own side) or two (two and two), turned so that its normal
@@ -101,17 +103,19 @@ __device__ __forceinline__ int tet_triangles(const SdfExtractArgs &a, const floa
     for (int q = 0; q < 4; ++q)
         for (int k = 0; k < 3; ++k)
             x[q][k] = a.origin[k] + a.voxel * (double)(g[k] + v[q].d[k]);
-    // from the non-positive towards the positive vertices (mean against mean)
+    // from the non-positive towards the positive vertices: mean against mean,
+    // scaled by np (4 - np) > 0 (only the sign of its product with the
+    // normal is used)
     double gdir[3];
     for (int k = 0; k < 3; ++k) {
         double sp = 0.0, sn = 0.0;
         for (int q = 0; q < 4; ++q) {
             if (v[q].s > 0.f)
-                sp += x[q][k] / np;
+                sp += x[q][k];
             else
-                sn += x[q][k] / (4 - np);
+                sn += x[q][k];
         }
-        gdir[k] = sp - sn;
+        gdir[k] = (double)(4 - np) * sp - (double)np * sn;
     }
     for (int tr = 0; tr < ntri; ++tr) {
         double p[3][3];
@@ -136,6 +140,23 @@ __device__ __forceinline__ int tet_triangles(const SdfExtractArgs &a, const floa
     return ntri;
 }
 
+// Exclusive prefix sum of v over the 256 threads of the workgroup
+// (Hillis-Steele in shared memory); s_scan then holds the inclusive sums.
+__device__ __forceinline__ int block_exclusive_scan(int *s_scan, int v)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();
+    s_scan[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int u = tid >= off ? s_scan[tid - off] : 0;
+        __syncthreads();
+        s_scan[tid] += u;
+        __syncthreads();
+    }
+    return s_scan[tid] - v;
+}
+
 }  // namespace
 
 template <bool HASHED>
@@ -143,6 +164,7 @@ __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
 {
     __shared__ float2 s_v[kM1][kM1][kM1];  // [z][y][x]
     __shared__ int s_scan[256];
+    __shared__ uint16_t s_list[kSdfEdge * kSdfEdge * kSdfEdge];
     __shared__ unsigned long long s_base;
     const int b = blockIdx.x;
     int bx, by, bz;
@@ -204,55 +226,67 @@ __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
             s_v[kSdfEdge][kSdfEdge][kSdfEdge] = far(kSdfEdge, kSdfEdge, kSdfEdge);
     }
     __syncthreads();
+    // the cubes with voxels on both sides of zero (the only ones with
+    // triangles) as a work list in shared memory: thread (x, y) marks those of
+    // its column, then the workgroup compacts them (cube index z << 8 | y << 4
+    // | x, in thread order, then z)
     const int x = tid & 15, y = tid >> 4;
-    int g[3] = {bx * kSdfEdge + x, by * kSdfEdge + y, 0};
-    // the cube's 8 voxels; false when all lie on one side of zero (no
-    // tetrahedron of it has a triangle: most cubes, away from the surfaces)
-    auto cube = [&](int z, float2 (&c)[2][2][2]) {
+    uint32_t mask = 0;
+    for (int z = 0; z < kSdfEdge; ++z) {
         int npos = 0;
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
             for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
-                    c[dz][dy][dx] = s_v[z + dz][y + dy][x + dx];
-                    npos += c[dz][dy][dx].x > 0.f ? 1 : 0;
-                }
-        return npos != 0 && npos != 8;
+                for (int dx = 0; dx < 2; ++dx)
+                    npos += s_v[z + dz][y + dy][x + dx].x > 0.f ? 1 : 0;
+        if (npos != 0 && npos != 8)
+            mask |= 1u << z;
+    }
+    const int nmine = __builtin_popcount(mask);
+    const int first = block_exclusive_scan(s_scan, nmine);
+    const int n_cubes = s_scan[255];  // inclusive total, left by the scan
+    __syncthreads();
+    for (int z = 0, k = first; z < kSdfEdge; ++z)
+        if (mask & (1u << z))
+            s_list[k++] = (uint16_t)((z << 8) | (y << 4) | x);
+    __syncthreads();
+    auto load_cube = [&](int id, float2 (&c)[2][2][2], int (&g)[3]) {
+        const int cx = id & 15, cy = (id >> 4) & 15, cz = id >> 8;
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx)
+                    c[dz][dy][dx] = s_v[cz + dz][cy + dy][cx + dx];
+        g[0] = bx * kSdfEdge + cx;
+        g[1] = by * kSdfEdge + cy;
+        g[2] = bz * kSdfEdge + cz;
     };
-    // pass 1: this thread's triangles
+    // pass 1: triangles of this thread's cubes (list entries tid, tid + 256, ...)
     int cnt = 0;
-    for (int z = 0; z < kSdfEdge; ++z) {
+    for (int i = tid; i < n_cubes; i += 256) {
         float2 c[2][2][2];
-        if (!cube(z, c))
-            continue;
-        g[2] = bz * kSdfEdge + z;
+        int g[3];
+        load_cube(s_list[i], c, g);
 #pragma unroll
         for (int t = 0; t < 6; ++t)
             cnt += tet_triangles(a, c, g, t, nullptr);
     }
-    // exclusive scan over the workgroup (Hillis-Steele in shared memory)
-    s_scan[tid] = cnt;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int v = tid >= off ? s_scan[tid - off] : 0;
-        __syncthreads();
-        s_scan[tid] += v;
-        __syncthreads();
-    }
+    const int before = block_exclusive_scan(s_scan, cnt);
     if (tid == 255)
         s_base = s_scan[255] > 0 ? atomicAdd(a.count, (unsigned long long)s_scan[255]) : 0ull;
     __syncthreads();
     if (cnt == 0)
         return;
-    // pass 2: write the triangles
-    unsigned long long n = s_base + (unsigned long long)(s_scan[tid] - cnt);
-    for (int z = 0; z < kSdfEdge; ++z) {
+    // pass 2: write them
+    unsigned long long n = s_base + (unsigned long long)before;
+    for (int i = tid; i < n_cubes; i += 256) {
         float2 c[2][2][2];
-        if (!cube(z, c))
-            continue;
-        g[2] = bz * kSdfEdge + z;
+        int g[3];
+        load_cube(s_list[i], c, g);
         for (int t = 0; t < 6; ++t) {
             const int k = tet_triangles(a, c, g, t, nullptr);
             if (k == 0)
