@@ -429,7 +429,8 @@ rir_status rir_sdf_mesh(const rir_volume_desc *vol, const float *voxels, double 
 typedef struct rir_bvol rir_bvol;
 rir_status rir_bvol_create(int device, const double origin[3], double voxel, int32_t max_blocks, rir_bvol **out);
 void rir_bvol_destroy(rir_bvol *vol);
-/* Empties the volume (no blocks, no scans); enqueued on `stream`. */
+/* Empties the volume (no blocks, no scans); enqueued on `stream` as device
+ * memsets (not for a stream under graph capture). */
 rir_status rir_bvol_reset(rir_bvol *vol, void *stream);
 
 /* Fuses n_frames scans (Sec. 4.2).  For each scan, in order: every return
@@ -443,7 +444,7 @@ rir_status rir_bvol_reset(rir_bvol *vol, void *stream);
  * skipped).  ranges: device, n_frames * H * W FP32 scans of `sensor`; poses:
  * host, n_frames * 16 FP64 world -> sensor, read before the call returns.
  * Enqueued on `stream`; the call waits for the activation (to size the
- * fusion launches).  Errors: RIR_E_INVALID (null, n_frames < 0, radius
+ * fusion launches), so it cannot run on a stream under graph capture.  Errors: RIR_E_INVALID (null, n_frames < 0, radius
  * outside 0 .. 64 voxels, non-finite trunc, r_clip or pose, sensor on another
  * device),
  * RIR_E_SHAPE (16 scans of H x W at or above 2 GiB), RIR_E_OOM (more active
