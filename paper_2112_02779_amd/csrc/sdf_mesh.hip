@@ -28,115 +28,107 @@ constexpr int kM1 = kSdfEdge + 1;
 constexpr int kTetP[6] = {0, 0, 1, 1, 2, 2};
 constexpr int kTetQ[6] = {1, 2, 0, 2, 0, 1};
 
-struct Corner {
-    float s, w;
-    int d[3];  // offset in the cube
+struct D3 {
+    double x, y, z;
 };
 
-// Triangles (0, 1 or 2) of tetrahedron t of the cube whose (0, 0, 0) voxel is
-// g (global voxel index); with out != nullptr also writes them, 9 floats each.
-__device__ __forceinline__ int tet_triangles(const SdfExtractArgs &a, const float2 (&c)[2][2][2], const int (&g)[3],
-                                             int t, float *out)
+template <typename V>
+__device__ __forceinline__ V sel4(int i, V v0, V v1, V v2, V v3)
 {
-    Corner v[4];
-    int off[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
-    off[1][kTetP[t]] = 1;
-    off[2][kTetP[t]] = 1;
-    off[2][kTetQ[t]] = 1;
-    int np = 0;
-    bool ok = true;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float2 cv = c[off[q][2]][off[q][1]][off[q][0]];
-        v[q].s = cv.x;
-        v[q].w = cv.y;
-        v[q].d[0] = off[q][0];
-        v[q].d[1] = off[q][1];
-        v[q].d[2] = off[q][2];
-        ok = ok && cv.y >= a.min_weight;
-        np += cv.x > 0.f ? 1 : 0;
-    }
-    if (!ok || np == 0 || np == 4)
+    return i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3));
+}
+
+// Triangles (0, 1 or 2) of tetrahedron t (0..5; unrolled by the callers, so
+// that its vertex offsets are constants) of the cube c whose (0, 0, 0) voxel
+// is g (global voxel index).  With out != nullptr also writes them, 9 floats
+// each, triangle k at out + 9 k if first + k < cap.  Everything stays in
+// registers: vertex data is picked by index with selects.
+__device__ __forceinline__ int tet_triangles(const SdfExtractArgs &a, const float2 (&c)[2][2][2], const int (&g)[3],
+                                             int t, float *out, unsigned long long first, unsigned long long cap)
+{
+    const int P = kTetP[t], Q = kTetQ[t];
+    const int o1[3] = {P == 0, P == 1, P == 2};
+    const int o2[3] = {P == 0 || Q == 0, P == 1 || Q == 1, P == 2 || Q == 2};
+    const float2 v0 = c[0][0][0], v1 = c[o1[2]][o1[1]][o1[0]], v2 = c[o2[2]][o2[1]][o2[0]], v3 = c[1][1][1];
+    if (!(v0.y >= a.min_weight && v1.y >= a.min_weight && v2.y >= a.min_weight && v3.y >= a.min_weight))
         return 0;
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = p + 1; q < 4; ++q)
-            if ((v[p].s > 0.f) != (v[q].s > 0.f) && fabs((double)v[p].s - (double)v[q].s) > a.max_jump)
-                return 0;
-    // edges (vertex pairs) of the triangles
-    int e[2][3][2];
-    int ntri;
-    if (np == 1 || np == 3) {
-        int lone = 0;
-        for (int q = 0; q < 4; ++q)
-            if ((v[q].s > 0.f) == (np == 1))
-                lone = q;
-        int m = 0;
-        for (int q = 0; q < 4; ++q)
-            if (q != lone) {
-                e[0][m][0] = lone;
-                e[0][m][1] = q;
-                ++m;
-            }
-        ntri = 1;
-    } else {
-        int P[2], N[2], mp = 0, mn = 0;
-        for (int q = 0; q < 4; ++q) {
-            if (v[q].s > 0.f)
-                P[mp++] = q;
-            else
-                N[mn++] = q;
-        }
-        // quadrilateral P0N0, P0N1, P1N1, P1N0 as (0, 1, 2) and (0, 2, 3)
-        e[0][0][0] = P[0], e[0][0][1] = N[0];
-        e[0][1][0] = P[0], e[0][1][1] = N[1];
-        e[0][2][0] = P[1], e[0][2][1] = N[1];
-        e[1][0][0] = P[0], e[1][0][1] = N[0];
-        e[1][1][0] = P[1], e[1][1][1] = N[1];
-        e[1][2][0] = P[1], e[1][2][1] = N[0];
-        ntri = 2;
-    }
+    const bool b0 = v0.x > 0.f, b1 = v1.x > 0.f, b2 = v2.x > 0.f, b3 = v3.x > 0.f;
+    const int np = (int)b0 + (int)b1 + (int)b2 + (int)b3;
+    if (np == 0 || np == 4)
+        return 0;
+    auto jump = [&](bool ba, float sa, bool bb, float sb) {
+        return ba != bb && fabs((double)sa - (double)sb) > a.max_jump;
+    };
+    if (jump(b0, v0.x, b1, v1.x) || jump(b0, v0.x, b2, v2.x) || jump(b0, v0.x, b3, v3.x) ||
+        jump(b1, v1.x, b2, v2.x) || jump(b1, v1.x, b3, v3.x) || jump(b2, v2.x, b3, v3.x))
+        return 0;
+    const int ntri = np == 2 ? 2 : 1;
     if (!out)
         return ntri;
-    double x[4][3];
-    for (int q = 0; q < 4; ++q)
-        for (int k = 0; k < 3; ++k)
-            x[q][k] = a.origin[k] + a.voxel * (double)(g[k] + v[q].d[k]);
+    // edges (vertex pairs) of the triangles: triangle k has (ea[k][w], eb[k][w])
+    int ea0, eb0, ea1, eb1, ea2, eb2, fa1, fb1, fa2, fb2;  // second triangle: (ea0, eb0), (fa1, fb1), (fa2, fb2)
+    if (np != 2) {
+        const bool want = np == 1;  // the lone vertex is the positive one
+        const int lone = b0 == want ? 0 : (b1 == want ? 1 : (b2 == want ? 2 : 3));
+        ea0 = ea1 = ea2 = lone;
+        eb0 = lone == 0 ? 1 : 0;
+        eb1 = lone <= 1 ? 2 : 1;
+        eb2 = lone <= 2 ? 3 : 2;
+        fa1 = fb1 = fa2 = fb2 = 0;
+    } else {
+        // positive p0 < p1 and non-positive n0 < n1 (tetrahedron order)
+        const int p0 = b0 ? 0 : (b1 ? 1 : 2);
+        const int p1 = b3 ? 3 : (b2 ? 2 : 1);
+        const int n0 = !b0 ? 0 : (!b1 ? 1 : 2);
+        const int n1 = !b3 ? 3 : (!b2 ? 2 : 1);
+        // quadrilateral p0n0, p0n1, p1n1, p1n0 as (0, 1, 2) and (0, 2, 3)
+        ea0 = p0, eb0 = n0;
+        ea1 = p0, eb1 = n1;
+        ea2 = p1, eb2 = n1;
+        fa1 = p1, fb1 = n1;
+        fa2 = p1, fb2 = n0;
+    }
+    auto pos = [&](int q) -> D3 {
+        const int dx = q == 3 ? 1 : (q == 1 ? o1[0] : (q == 2 ? o2[0] : 0));
+        const int dy = q == 3 ? 1 : (q == 1 ? o1[1] : (q == 2 ? o2[1] : 0));
+        const int dz = q == 3 ? 1 : (q == 1 ? o1[2] : (q == 2 ? o2[2] : 0));
+        return {a.origin[0] + a.voxel * (double)(g[0] + dx), a.origin[1] + a.voxel * (double)(g[1] + dy),
+                a.origin[2] + a.voxel * (double)(g[2] + dz)};
+    };
+    const D3 x0 = pos(0), x1 = pos(1), x2 = pos(2), x3 = pos(3);
+    auto crossing = [&](int i0, int i1) -> D3 {
+        const double sa = (double)sel4(i0, v0.x, v1.x, v2.x, v3.x), sb = (double)sel4(i1, v0.x, v1.x, v2.x, v3.x);
+        const D3 xa = sel4(i0, x0, x1, x2, x3), xb = sel4(i1, x0, x1, x2, x3);
+        const double tt = sa / (sa - sb);
+        return {xa.x + tt * (xb.x - xa.x), xa.y + tt * (xb.y - xa.y), xa.z + tt * (xb.z - xa.z)};
+    };
     // from the non-positive towards the positive vertices: mean against mean,
     // scaled by np (4 - np) > 0 (only the sign of its product with the
     // normal is used)
-    double gdir[3];
-    for (int k = 0; k < 3; ++k) {
-        double sp = 0.0, sn = 0.0;
-        for (int q = 0; q < 4; ++q) {
-            if (v[q].s > 0.f)
-                sp += x[q][k];
-            else
-                sn += x[q][k];
-        }
-        gdir[k] = (double)(4 - np) * sp - (double)np * sn;
-    }
-    for (int tr = 0; tr < ntri; ++tr) {
-        double p[3][3];
-        for (int w = 0; w < 3; ++w) {
-            const int i0 = e[tr][w][0], i1 = e[tr][w][1];
-            const double sa = (double)v[i0].s, sb = (double)v[i1].s;
-            const double tt = sa / (sa - sb);
-            for (int k = 0; k < 3; ++k)
-                p[w][k] = x[i0][k] + tt * (x[i1][k] - x[i0][k]);
-        }
-        const double u1[3] = {p[1][0] - p[0][0], p[1][1] - p[0][1], p[1][2] - p[0][2]};
-        const double u2[3] = {p[2][0] - p[0][0], p[2][1] - p[0][1], p[2][2] - p[0][2]};
-        const double nn[3] = {u1[1] * u2[2] - u1[2] * u2[1], u1[2] * u2[0] - u1[0] * u2[2],
-                              u1[0] * u2[1] - u1[1] * u2[0]};
-        const bool flip = nn[0] * gdir[0] + nn[1] * gdir[1] + nn[2] * gdir[2] < 0.0;
-        float *o = out + 9 * tr;
-        const int order[3] = {0, flip ? 2 : 1, flip ? 1 : 2};
-        for (int w = 0; w < 3; ++w)
-            for (int k = 0; k < 3; ++k)
-                o[3 * w + k] = (float)p[order[w]][k];
-    }
+    const double wp = (double)(4 - np), wn = (double)np;
+    const D3 gd = {wp * ((b0 ? x0.x : 0.0) + (b1 ? x1.x : 0.0) + (b2 ? x2.x : 0.0) + (b3 ? x3.x : 0.0)) -
+                       wn * ((b0 ? 0.0 : x0.x) + (b1 ? 0.0 : x1.x) + (b2 ? 0.0 : x2.x) + (b3 ? 0.0 : x3.x)),
+                   wp * ((b0 ? x0.y : 0.0) + (b1 ? x1.y : 0.0) + (b2 ? x2.y : 0.0) + (b3 ? x3.y : 0.0)) -
+                       wn * ((b0 ? 0.0 : x0.y) + (b1 ? 0.0 : x1.y) + (b2 ? 0.0 : x2.y) + (b3 ? 0.0 : x3.y)),
+                   wp * ((b0 ? x0.z : 0.0) + (b1 ? x1.z : 0.0) + (b2 ? x2.z : 0.0) + (b3 ? x3.z : 0.0)) -
+                       wn * ((b0 ? 0.0 : x0.z) + (b1 ? 0.0 : x1.z) + (b2 ? 0.0 : x2.z) + (b3 ? 0.0 : x3.z))};
+    auto emit = [&](int k, const D3 &p0, const D3 &p1, const D3 &p2) {
+        if (first + (unsigned long long)k >= cap)
+            return;
+        const double u1x = p1.x - p0.x, u1y = p1.y - p0.y, u1z = p1.z - p0.z;
+        const double u2x = p2.x - p0.x, u2y = p2.y - p0.y, u2z = p2.z - p0.z;
+        const double nx = u1y * u2z - u1z * u2y, ny = u1z * u2x - u1x * u2z, nz = u1x * u2y - u1y * u2x;
+        const bool flip = nx * gd.x + ny * gd.y + nz * gd.z < 0.0;
+        const D3 q1 = flip ? p2 : p1, q2 = flip ? p1 : p2;
+        float *o = out + 9 * k;
+        o[0] = (float)p0.x, o[1] = (float)p0.y, o[2] = (float)p0.z;
+        o[3] = (float)q1.x, o[4] = (float)q1.y, o[5] = (float)q1.z;
+        o[6] = (float)q2.x, o[7] = (float)q2.y, o[8] = (float)q2.z;
+    };
+    const D3 c0 = crossing(ea0, eb0), c1 = crossing(ea1, eb1), c2 = crossing(ea2, eb2);
+    emit(0, c0, c1, c2);
+    if (ntri == 2)
+        emit(1, c0, crossing(fa1, fb1), crossing(fa2, fb2));
     return ntri;
 }
 
@@ -273,7 +265,7 @@ __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
         load_cube(s_list[i], c, g);
 #pragma unroll
         for (int t = 0; t < 6; ++t)
-            cnt += tet_triangles(a, c, g, t, nullptr);
+            cnt += tet_triangles(a, c, g, t, nullptr, 0, 0);
     }
     const int before = block_exclusive_scan(s_scan, cnt);
     if (tid == 255)
@@ -287,20 +279,10 @@ __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
         float2 c[2][2][2];
         int g[3];
         load_cube(s_list[i], c, g);
-        for (int t = 0; t < 6; ++t) {
-            const int k = tet_triangles(a, c, g, t, nullptr);
-            if (k == 0)
-                continue;
-            if (n + (unsigned long long)k <= (unsigned long long)a.max_pts) {
-                tet_triangles(a, c, g, t, a.pts + 9 * n);
-            } else if (n < (unsigned long long)a.max_pts) {
-                float tmp[18];
-                tet_triangles(a, c, g, t, tmp);
-                for (int q = 0; q < 9; ++q)
-                    a.pts[9 * n + q] = tmp[q];
-            }
-            n += (unsigned long long)k;
-        }
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+            n += (unsigned long long)tet_triangles(a, c, g, t, a.max_pts > 0 ? a.pts + 9 * n : nullptr, n,
+                                                   (unsigned long long)a.max_pts);
     }
 }
 
