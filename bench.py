@@ -666,11 +666,52 @@ def sdf_fusion(rir, seq, oracle_sample, repeats=5):
                              "scans_per_s_whole_volume": round(len(pick) / dt / nvox, 6)}
     log(f"sdf fusion: {F} scans in {ms:.3f} ms ({res['scans_per_s']:.0f} scans/s), "
         f"{res['evals_per_s'] / 1e9:.1f} G evals/s, {res['hbm_gbps']} GB/s algorithmic")
-    res["sparse"] = sparse_sdf(rir, seq, sen, ranges, poses, r_clip, repeats)
+    res["sparse"] = sparse_sdf(rir, seq, sen, ranges, poses, r_clip, repeats,
+                               oracle_sample=oracle_sample // 2, scans=scans)
     return res
 
 
-def sparse_sdf(rir, seq, sen, ranges, poses, r_clip, repeats):
+def sparse_oracle_check(vol, seq, scans, poses, trunc, r_clip, n_sample):
+    """Sampled voxels of active blocks against the oracle fusing the scans
+    from each block's first activating scan on (weights equal and SDF within
+    the dense check's bound outside the ambiguity band)."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity_util import sdf_ambiguous
+    b, v = vol.export()
+    rows = b.cpu().numpy().astype(np.int64)
+    vox = v.cpu().numpy().reshape(len(rows), -1, 2)
+    rng = np.random.default_rng(23)
+    blk = rng.integers(0, len(rows), n_sample)
+    loc = rng.integers(0, 4096, n_sample)
+    got = vox[blk, loc].astype(np.float64)
+    k, rem = np.divmod(loc, 256)
+    j, i = np.divmod(rem, 16)
+    idx = 16 * rows[blk, :3] + np.stack([i, j, k], axis=1)
+    pts = np.asarray(vol.origin) + vol.voxel * idx.astype(np.float64)
+    sm = seq["sensor"]
+    first = rows[blk, 3]
+    s_ref, w_ref = np.zeros(n_sample), np.zeros(n_sample)
+    t0 = time.perf_counter()
+    for f0 in np.unique(first):
+        m = first == f0
+        s_ref[m], w_ref[m] = oracle.sdf_fuse(sm, scans[f0:], poses[f0:], pts[m], trunc, r_clip)
+    dt = time.perf_counter() - t0
+    # a voxel is ambiguous when some scan it fuses (from its block's first
+    # activating scan on) leaves it in the band
+    amb = np.zeros(n_sample, bool)
+    for f in range(len(scans)):
+        amb |= (first <= f) & sdf_ambiguous(sm, scans[f:f + 1], poses[f:f + 1], pts, trunc, r_clip)
+    clear = ~amb
+    tol = 5e-7 * (r_clip + trunc) + 1e-6
+    ok_w = got[clear, 1] == w_ref[clear]
+    err = np.abs(got[clear, 0] - s_ref[clear])
+    return {"voxels": int(n_sample), "clear": int(clear.sum()), "observed": int((w_ref > 0).sum()),
+            "weights_equal": int(ok_w.sum()), "max_sdf_err_m": float(err.max(initial=0.0)), "tol_m": tol,
+            "within_tol": bool(ok_w.all() and err.max(initial=0.0) <= tol), "oracle_s": round(dt, 2)}
+
+
+def sparse_sdf(rir, seq, sen, ranges, poses, r_clip, repeats, oracle_sample=0, scans=None):
     """The same sequence into the sparse volume (Sec. 4.2: blocks activated
     within the truncation distance of each return, hash table, only active
     blocks fused), at 0.1 m and at the paper's 0.2 m outdoor voxels with a
@@ -709,6 +750,8 @@ def sparse_sdf(rir, seq, sen, ranges, poses, r_clip, repeats):
             sc["protocol"] = sc["protocol"].replace("max step 0.45 m", "no step limit")
         sc["mesh"] = mesh_stats(rir, lambda tri, cap, c, st, v=vol, mj=max_jump: rir.lib().rir_bvol_mesh(
             v.handle, 1.0, mj, tri, cap, c, st), vol.mesh(min_weight=1.0, max_jump=max_jump, stream=stream), stream)
+        if oracle_sample > 0 and vx < 0.15:
+            sc["oracle_check"] = sparse_oracle_check(vol, seq, scans, poses, trunc, r_clip, oracle_sample)
         out[f"voxel_{vx}"] = {"ms_per_sequence": round(ms, 4), "scans_per_s": round(F / (ms * 1e-3), 1),
                               "truncation_m": round(trunc, 3),
                               "active_blocks": int(nb), "block_memory_gb": round(nb * 32768 / 1e9, 3),
