@@ -25,6 +25,34 @@ struct SdfExtractArgs {
 
 constexpr int kNbrPerBlock = 7;
 
+// Exclusive prefix sum of v over a workgroup of 256 threads in thread order,
+// and the workgroup's total: inclusive sums within each wavefront by lane
+// exchanges, then the totals of the wavefronts before (s_wsum: 4 ints of
+// shared memory; two barriers, all threads must call).
+__device__ __forceinline__ int block_scan256(int *s_wsum, int v, int &total)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(inc, off, 64);
+        inc += lane >= off ? u : 0;
+    }
+    __syncthreads();  // earlier readers of s_wsum are done
+    if (lane == 63)
+        s_wsum[wv] = inc;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int t = s_wsum[w];
+        before += w < wv ? t : 0;
+        total += t;
+    }
+    return before + inc - v;
+}
+
 // Zeroes a device counter (a kernel, so that the call can be captured).
 hipError_t launch_zero_count(unsigned long long *count, hipStream_t stream);
 // Zero crossings of a fused volume (count zeroed first, then one launch).

@@ -13,9 +13,9 @@ namespace rir {
 // weights >= min_weight, SDF values on different sides of zero (s_a > 0 >=
 // s_b or the reverse) and |s_a - s_b| <= max_jump; its point
 // a + t (b - a), t = s_a / (s_a - s_b), is formed in FP64.  The workgroup
-// counts its crossings, takes one range of the output with one atomic add,
-// and writes its points there (so the order of the points across blocks is
-// not defined).
+// counts its crossings (a block without any stops there), takes one range of
+// the output with one atomic add, and writes its points there in thread
+// order (so the order of the points across blocks is not defined).
 __device__ __forceinline__ size_t vox_index(int nbx, int nby, int i, int j, int k)
 {
     const size_t blk = ((size_t)(k >> 4) * nby + (j >> 4)) * nbx + (i >> 4);
@@ -35,7 +35,7 @@ template <bool HASHED>
 __global__ __launch_bounds__(256) void k_sdf_extract(const SdfExtractArgs a)
 {
     __shared__ float2 s_v[kE1][kE1][kE1];  // [z][y][x]
-    __shared__ int s_scan[256];
+    __shared__ int s_wsum[4];
     __shared__ unsigned long long s_base;
     const int b = blockIdx.x;
     int bx, by, bz;
@@ -103,22 +103,18 @@ __global__ __launch_bounds__(256) void k_sdf_extract(const SdfExtractArgs a)
         cnt += crossing(a, A, s_v[z][y + 1][x]) ? 1 : 0;
         cnt += crossing(a, A, s_v[z + 1][y][x]) ? 1 : 0;
     }
-    // exclusive scan over the workgroup (Hillis-Steele in shared memory)
-    s_scan[tid] = cnt;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int v = tid >= off ? s_scan[tid - off] : 0;
-        __syncthreads();
-        s_scan[tid] += v;
-        __syncthreads();
-    }
-    if (tid == 255)
-        s_base = s_scan[255] > 0 ? atomicAdd(a.count, (unsigned long long)s_scan[255]) : 0ull;
+    // a block without crossings (most of the volume) ends here
+    if (!__syncthreads_or(cnt))
+        return;
+    int total;
+    const int before = block_scan256(s_wsum, cnt, total);
+    if (tid == 0)
+        s_base = atomicAdd(a.count, (unsigned long long)total);
     __syncthreads();
     if (cnt == 0)
         return;
     // pass 2: write the points
-    unsigned long long n = s_base + (unsigned long long)(s_scan[tid] - cnt);
+    unsigned long long n = s_base + (unsigned long long)before;
     const int i = bx * kSdfEdge + x, j = by * kSdfEdge + y;
     for (int z = 0; z < kSdfEdge; ++z) {
         const float2 A = s_v[z][y][x];

@@ -132,30 +132,13 @@ __device__ __forceinline__ int tet_triangles(const SdfExtractArgs &a, const floa
     return ntri;
 }
 
-// Exclusive prefix sum of v over the 256 threads of the workgroup
-// (Hillis-Steele in shared memory); s_scan then holds the inclusive sums.
-__device__ __forceinline__ int block_exclusive_scan(int *s_scan, int v)
-{
-    const int tid = threadIdx.x;
-    __syncthreads();
-    s_scan[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int u = tid >= off ? s_scan[tid - off] : 0;
-        __syncthreads();
-        s_scan[tid] += u;
-        __syncthreads();
-    }
-    return s_scan[tid] - v;
-}
-
 }  // namespace
 
 template <bool HASHED>
 __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
 {
     __shared__ float2 s_v[kM1][kM1][kM1];  // [z][y][x]
-    __shared__ int s_scan[256];
+    __shared__ int s_wsum[4];
     __shared__ uint16_t s_list[kSdfEdge * kSdfEdge * kSdfEdge];
     __shared__ unsigned long long s_base;
     const int b = blockIdx.x;
@@ -237,9 +220,10 @@ __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
             mask |= 1u << z;
     }
     const int nmine = __builtin_popcount(mask);
-    const int first = block_exclusive_scan(s_scan, nmine);
-    const int n_cubes = s_scan[255];  // inclusive total, left by the scan
-    __syncthreads();
+    if (!__syncthreads_or(nmine))
+        return;  // no surface in this block (most of the volume)
+    int n_cubes;
+    const int first = block_scan256(s_wsum, nmine, n_cubes);
     for (int z = 0, k = first; z < kSdfEdge; ++z)
         if (mask & (1u << z))
             s_list[k++] = (uint16_t)((z << 8) | (y << 4) | x);
@@ -267,9 +251,10 @@ __global__ __launch_bounds__(256) void k_sdf_mesh(const SdfExtractArgs a)
         for (int t = 0; t < 6; ++t)
             cnt += tet_triangles(a, c, g, t, nullptr, 0, 0);
     }
-    const int before = block_exclusive_scan(s_scan, cnt);
-    if (tid == 255)
-        s_base = s_scan[255] > 0 ? atomicAdd(a.count, (unsigned long long)s_scan[255]) : 0ull;
+    int total;
+    const int before = block_scan256(s_wsum, cnt, total);
+    if (tid == 0)
+        s_base = total > 0 ? atomicAdd(a.count, (unsigned long long)total) : 0ull;
     __syncthreads();
     if (cnt == 0)
         return;
