@@ -681,6 +681,10 @@ def sparse_oracle_check(vol, seq, scans, poses, trunc, r_clip, n_sample):
     b, v = vol.export()
     rows = b.cpu().numpy().astype(np.int64)
     vox = v.cpu().numpy().reshape(len(rows), -1, 2)
+    # blocks in key order (the export follows the order of the table's
+    # inserts, which varies between runs), so that the sample is repeatable
+    order = np.lexsort(rows[:, :3].T[::-1])
+    rows, vox = rows[order], vox[order]
     rng = np.random.default_rng(23)
     blk = rng.integers(0, len(rows), n_sample)
     loc = rng.integers(0, 4096, n_sample)
