@@ -822,22 +822,38 @@ __global__ __launch_bounds__(256) void k_icp_step(StepArgs a)
     auto tile = [&](int cur) {
         const int2 tl = cload(a.tiles + cur);
         const int pair = tl.x;
-        if (!dbg) {
-            const int *fl = a.flags + (size_t)pair * kFlagStride;
-            if (cload(fl + l) & 1)
-                return;
-            if (a.mode == kStepFallback && !(cload(fl + kMaxLevels) & 1))
-                return;
-        }
+        const int *fl = a.flags + (size_t)pair * kFlagStride;
         const PairDesc<T> *P = pairs + pair;
         const double *Tp = a.poses + 16 * (size_t)pair;
+        // What the tile reads that depends on the pair alone is loaded before
+        // the flag tests and waited for once (the empty asm takes it all), so
+        // that these loads go out together rather than as a chain of
+        // dependent round trips behind the early exits.
+        const int f_lvl = cload(fl + l), f_fb = cload(fl + kMaxLevels);
+        double Td[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            Td[k] = cload(Tp + k);
+        const int Hp = cload(&P->H), Wp = cload(&P->W);
+        const SensorTab<T> *ptab = cload(&P->tab);
+        const float *psrc = cload(&P->src[l]), *pdstr = cload(&P->dstr[l]);
+        const T *pdst4 = cload(&P->dst4[l]), *pfr = cload(&P->frames);
+        asm volatile("" ::"s"(f_lvl), "s"(f_fb), "s"(Hp), "s"(Wp), "s"(ptab), "s"(psrc), "s"(pdstr), "s"(pdst4),
+                     "s"(pfr), "s"(Td[0]), "s"(Td[1]), "s"(Td[2]), "s"(Td[3]), "s"(Td[4]), "s"(Td[5]), "s"(Td[6]),
+                     "s"(Td[7]), "s"(Td[8]), "s"(Td[9]), "s"(Td[10]), "s"(Td[11]));
+        if (!dbg) {
+            if (f_lvl & 1)
+                return;
+            if (a.mode == kStepFallback && !(f_fb & 1))
+                return;
+        }
         T pose[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k)
-            pose[k] = (T)cload(Tp + k);
-        const int Hl = cload(&P->H) >> l, spr = ((cload(&P->W) >> l) + kSegPx - 1) / kSegPx;
+            pose[k] = (T)Td[k];
+        const int Hl = Hp >> l, spr = ((Wp >> l) + kSegPx - 1) / kSegPx;
         step_segments<T, WMODE, CHUNK, LEAN, false>(a, F, pair, tl.y, min(tl.y + a.tile_seg, Hl * spr),
-                                                    a.stats_pass != 0, pose, cload(&P->frames), s_wave, s_wcnt);
+                                                    a.stats_pass != 0, pose, pfr, s_wave, s_wcnt);
         __syncthreads();
         if (tid < kAccum) {
             T sum = (T)0;
